@@ -1,0 +1,199 @@
+/*
+ * nep.h: C-ABI of the MI355X (gfx950) NEP molecular-dynamics library.
+ *
+ * The problem (Section III.B and Section VI.A of the paper): given species and
+ * positions of atoms in a periodic box, evaluate the neuroevolution potential
+ *   U = sum_i U_i,  U_i = sum_mu w1_mu tanh(sum_nu W0_mu,nu q~_nu^i - b0_mu) - b1,
+ * its forces and virial, and advance molecular dynamics with neighbour lists
+ * that are rebuilt periodically. q^i are radial descriptors (Chebyshev radial
+ * functions summed over neighbours inside the radial cutoff) and angular
+ * descriptors (radial functions times spherical harmonics, contracted over m,
+ * inside the shorter angular cutoff), plus the l = 2 four-body invariant.
+ *
+ * Conventions for every call:
+ *   - Every call returns an int status (enum nep_status) and never aborts or
+ *     throws across the ABI. nep_last_error() gives a message for the last
+ *     failing call on that system.
+ *   - Units: angstrom, femtosecond, eV, amu, kelvin.
+ *   - Atom arrays at the boundary are in the caller's ORIGINAL atom order,
+ *     row-major [N][3] for vectors. Internally atoms are kept sorted by cell.
+ *   - Ownership: the caller owns every host array and the device workspace
+ *     (allocated by the caller, e.g. as a torch tensor). The library never
+ *     allocates device memory; it only carves the workspace. Pointers are
+ *     borrowed for the duration of the call. The system object itself is a
+ *     small host allocation freed by nep_system_destroy.
+ *   - Ordering: all device work of a system runs in order on the HIP stream
+ *     given at creation. Calls that return host values synchronise that
+ *     stream before returning; calls whose outputs are device pointers
+ *     (on_device = 1) do not synchronise.
+ *   - A system handle is not thread-safe.
+ *   - Box: orthorhombic and periodic; every side must be at least
+ *     2 * (radial cutoff + skin), otherwise NEP_ERR_BOX_TOO_SMALL.
+ */
+#ifndef NEP_MI355X_H
+#define NEP_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nep_model nep_model;
+typedef struct nep_system nep_system;
+
+enum nep_status {
+  NEP_OK = 0,
+  NEP_ERR_ARG = -1,                /* null pointer, bad size or bad value          */
+  NEP_ERR_BOX_TOO_SMALL = -2,      /* a side shorter than 2 (cutoff + skin)        */
+  NEP_ERR_NEIGHBOR_OVERFLOW = -3,  /* a list exceeded its capacity (results void)  */
+  NEP_ERR_TYPE = -4,               /* an atom type outside [0, n_types)            */
+  NEP_ERR_NONFINITE = -5,          /* NaN or Inf in positions, forces or energy    */
+  NEP_ERR_HIP = -6,                /* a HIP runtime call failed                    */
+  NEP_ERR_WORKSPACE = -7,          /* workspace missing, too small or misaligned   */
+  NEP_ERR_STALE_LIST = -8,         /* evaluation requested before any list build   */
+  NEP_ERR_UNSUPPORTED = -9         /* model shape without a compiled kernel        */
+};
+
+enum nep_precision {
+  NEP_FP32 = 0,  /* descriptors, forces FP32; network FP32 MFMA, FP32 accumulate   */
+  NEP_BF16 = 1   /* as FP32, but the network's matrix operands are bfloat16        */
+};
+
+/* Model hyperparameters (Section VI.A: n_max 4, basis size 8, three-body
+ * l_max 4, four-body l_max 2, 30 hidden neurons; two cutoffs, Fig. 1).
+ * n_max_* counts channels 0..n_max, basis_* counts functions 0..basis.
+ * l_max_4b is 0 (no four-body term) or 2.
+ * Compiled shapes: (n_max 4, basis 8) with either (l_max_3b 4, l_max_4b 2,
+ * n_hidden 30) or (l_max_3b 2, l_max_4b 0, n_hidden 8); n_types 1 or 2. */
+typedef struct nep_hparams {
+  int32_t n_types;
+  int32_t n_max_radial, n_max_angular;
+  int32_t basis_radial, basis_angular;
+  int32_t l_max_3b, l_max_4b;
+  int32_t n_hidden;
+  double rc_radial, rc_angular;  /* rc_angular <= rc_radial */
+} nep_hparams;
+
+/* Packed FP64 parameter vector, in this order:
+ *   cR    [T][T][n_max_R+1][basis_R+1]  radial coefficients, (center type, neighbour type)
+ *   cA    [T][T][n_max_A+1][basis_A+1]  angular coefficients
+ *   sigma [D]                           descriptor scaler, q~ = q * sigma
+ *   W0    [H][D]                        hidden weights, row = hidden unit
+ *   b0    [H], w1 [H], b1 [1]
+ * with D = (n_max_R+1) + (n_max_A+1) l_max_3b + (l_max_4b == 2 ? n_max_A+1 : 0) and
+ * descriptor order [radial n | angular l = 1..l_max_3b, each n | four-body n]. */
+int nep_param_count(const nep_hparams* hp, int64_t* n_params, int32_t* n_desc);
+
+/* Create a host-side model (validated copy of hp and params). */
+int nep_model_create(const nep_hparams* hp, const double* params, int64_t n_params,
+                     nep_model** out);
+void nep_model_destroy(nep_model* m);
+
+/* Bytes of device workspace a system needs. surrogate may be NULL.
+ * cap_radial / cap_angular: per-atom capacities of the lists with skin
+ * (radial cutoff + skin, angular cutoff + skin). */
+int nep_system_workspace_bytes(const nep_model* full, const nep_model* surrogate,
+                               int64_t n_atoms, const double box[3], int32_t cap_radial,
+                               int32_t cap_angular, int64_t* bytes);
+
+/* Create a system on the current HIP device. workspace: device pointer,
+ * 256-byte aligned, at least nep_system_workspace_bytes long, owned by the
+ * caller and kept alive until nep_system_destroy. hip_stream: a hipStream_t
+ * (NULL = default stream). The models' parameters are copied into the
+ * workspace; the models may be destroyed afterwards. */
+int nep_system_create(const nep_model* full, const nep_model* surrogate, int64_t n_atoms,
+                      const double box[3], int32_t cap_radial, int32_t cap_angular,
+                      void* workspace, int64_t workspace_bytes, void* hip_stream,
+                      nep_system** out);
+void nep_system_destroy(nep_system* s);
+
+/* Replace one model's parameters (slot 0 = full, 1 = surrogate) from host FP64,
+ * same hyperparameters as at creation. */
+int nep_system_set_params(nep_system* s, int32_t slot, const double* params, int64_t n_params);
+
+/* Set positions x [N][3] (inside [0, L) per axis), velocities v [N][3] (NULL = zero),
+ * types [N] and masses per type [n_types] (amu, host). on_device = 1: x, v,
+ * types are device pointers. Invalidates the neighbour lists. */
+int nep_set_state(nep_system* s, const double* x, const double* v, const int32_t* types,
+                  const double* masses, int32_t on_device);
+
+/* Sort atoms by cell and build the lists with skin (Section VI.A neighbour
+ * buffer; 27-cell stencil): radial r^2 < (rc_radial+skin)^2, angular
+ * r^2 < (rc_angular+skin)^2, FP64 minimum-image distances. Synchronises.
+ * Returns NEP_ERR_NEIGHBOR_OVERFLOW (message gives the needed capacities). */
+int nep_build_neighbors(nep_system* s, double skin);
+
+/* Copy a list out (which 0 = radial, 1 = angular) as CSR over ORIGINAL ids,
+ * each row ascending: offsets [N+1] and idx [cap_total] (host). */
+int nep_export_neighbors(nep_system* s, int32_t which, int64_t* offsets, int32_t* idx,
+                         int64_t cap_total);
+
+/* Energy, virial and (optionally) forces and per-atom energies at the current
+ * positions, for model slot 0 (full) or 1 (surrogate), with precision
+ * NEP_FP32 or NEP_BF16. energy, virial9 (row-major 3x3,
+ * W_ab = -sum_i sum_j (r_ij)_a (dU_i/dr_ij)_b) are host pointers and always
+ * written (FP64 reductions on the device). forces [N][3] and per_atom_energy
+ * [N] (FP64, original order) may be NULL; on_device says whether they are
+ * device pointers. Requires a built list whose skin still covers the current
+ * positions (nep_step keeps it so). Synchronises. */
+int nep_compute_energy_forces_virial(nep_system* s, int32_t slot, int32_t precision,
+                                     double* energy, double* virial9, double* forces,
+                                     double* per_atom_energy, int32_t on_device);
+
+/* Advance n_steps of FP64 velocity Verlet with step dt_fs (Section VI.A uses
+ * 1 fs). Lists are rebuilt at every rebuild_every-th step and early whenever
+ * any atom moved more than skin/2 since the last build. mts_k = 0: plain
+ * velocity Verlet with the full model. mts_k >= 1: multiple time stepping with
+ * the surrogate as the fast force and the full model applied every mts_k
+ * steps (n_steps must be a multiple of mts_k); when the surrogate's force
+ * error against the full model exceeds fallback_rms or fallback_max (eV/A),
+ * the next blocks fall back to the full model. thermo (host, nullable):
+ * rows of 8 doubles {step, potential, kinetic, temperature, pressure (eV/A^3),
+ * surrogate rms error, surrogate max error, fallback flag} every thermo_every
+ * steps (and the final step), at most max_rows rows. Synchronises at the end,
+ * after each MTS block and when the thermo buffer fills. */
+int nep_step(nep_system* s, int64_t n_steps, double dt_fs, int32_t rebuild_every, double skin,
+             int32_t mts_k, double fallback_rms, double fallback_max, int32_t precision,
+             double* thermo, int32_t thermo_every, int64_t max_rows, int64_t* rows_written);
+
+/* Positions and velocities [N][3] in original order, and the step counter. */
+int nep_get_state(nep_system* s, double* x, double* v, int64_t* step, int32_t on_device);
+
+/* Counters since creation: {list builds, MTS blocks, fallback blocks, steps}. */
+int nep_get_stats(nep_system* s, int64_t* stats4);
+
+/* ---------------------------------------------------------------- training
+ * Differentiation of E and F with respect to the network parameters
+ * theta = (W0 [H][D], b0 [H], w1 [H], b1), packed FP32 in that order on the
+ * device (H*D + 2H + 1 values). These calls use the descriptor coefficients
+ * and scaler of the model in the given slot and the current positions and
+ * lists; the network parameters come from theta.
+ *
+ * nep_train_forward: E (host FP64) and forces F [N][3] (device FP32, original
+ * order) for theta.
+ * nep_train_backward: grad = dL/dtheta (device FP32, FP64 accumulation) for
+ * L = gE * E + sum_i gF_i . F_i, with gF [N][3] device FP32 in original order
+ * (NULL = no force term). */
+int nep_train_forward(nep_system* s, int32_t slot, const float* theta, double* energy,
+                      float* forces);
+int nep_train_backward(nep_system* s, int32_t slot, const float* theta, double gE,
+                       const float* gF, float* grad);
+
+/* One Adam step on device FP32 arrays theta, grad, m1, m2 of length n
+ * (t = 1-based step count), on the system's stream. */
+int nep_adam_update(nep_system* s, float* theta, const float* grad, float* m1, float* m2,
+                    int64_t n, int64_t t, double lr, double beta1, double beta2, double eps);
+
+/* Force error of the surrogate against the full model at the current positions:
+ * err2 = {rms, max} over atoms of |F_full - F_surrogate| (host). */
+int nep_surrogate_error(nep_system* s, int32_t precision, double* err2);
+
+const char* nep_status_string(int status);
+const char* nep_last_error(const nep_system* s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NEP_MI355X_H */

@@ -1,0 +1,791 @@
+// C-ABI entry points and the host runtime of one simulated system: workspace
+// layout, model upload, the step driver (velocity Verlet and multiple time
+// stepping) and error reporting. All device work is enqueued on the system's
+// stream; the library allocates no device memory.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/nep.h"
+#include "nep_common.h"
+
+using namespace nep;
+
+struct nep_model {
+  nep_hparams hp;
+  std::vector<double> params;
+  int D = 0;
+  int64_t n_params = 0;
+};
+
+namespace {
+
+constexpr double kXi = 103.642697;          // eV per (amu A^2 / fs^2)
+constexpr double kBoltzmann = 8.617333262e-5;  // eV / K
+constexpr int kResults = 32;                // doubles of device scalar results
+
+int64_t count_params(const nep_hparams& hp, int* D_out) {
+  const int64_t T = hp.n_types, nR = hp.n_max_radial + 1, nA = hp.n_max_angular + 1;
+  const int64_t kR = hp.basis_radial + 1, kA = hp.basis_angular + 1;
+  const int64_t D = nR + nA * hp.l_max_3b + (hp.l_max_4b == 2 ? nA : 0);
+  const int64_t H = hp.n_hidden;
+  if (D_out) *D_out = (int)D;
+  return T * T * nR * kR + T * T * nA * kA + D + H * D + H + H + 1;
+}
+
+bool hp_valid(const nep_hparams* hp) {
+  if (!hp) return false;
+  return hp->n_types >= 1 && hp->n_types <= kMaxTypes && hp->n_max_radial >= 0 && hp->n_max_angular >= 0 &&
+         hp->basis_radial >= 1 && hp->basis_angular >= 1 && hp->l_max_3b >= 1 && hp->l_max_3b <= 4 &&
+         (hp->l_max_4b == 0 || hp->l_max_4b == 2) && hp->n_hidden >= 1 && hp->rc_radial > 0 &&
+         hp->rc_angular > 0 && hp->rc_angular <= hp->rc_radial && std::isfinite(hp->rc_radial);
+}
+
+// Round an FP64 value to bfloat16 bits, nearest-even, directly from FP64.
+uint16_t f64_to_bf16_bits(double v) {
+  if (v == 0.0) return std::signbit(v) ? 0x8000u : 0u;
+  int e = 0;
+  const double mant = std::frexp(v, &e);         // |mant| in [0.5, 1)
+  const double r = std::nearbyint(std::ldexp(mant, 8));  // 8 significant bits
+  const float f = (float)std::ldexp(r, e - 8);   // exactly representable
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  return (uint16_t)(u >> 16);
+}
+
+struct Carver {
+  int64_t off = 0;
+  char* base = nullptr;
+  template <class T>
+  T* take(int64_t count) {
+    off = (off + 255) & ~int64_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * (int64_t)sizeof(T);
+    return p;
+  }
+};
+
+CellGrid make_grid(const double box[3], double cut) {
+  CellGrid g;
+  g.ncell = 1;
+  for (int c = 0; c < 3; ++c) {
+    int n = (int)std::floor(box[c] / cut);
+    while (n > 1 && box[c] / n < cut * (1.0 + 1e-10)) --n;
+    if (n < 1) n = 1;
+    g.nc[c] = n;
+    g.box[c] = box[c];
+    g.ncell *= n;
+  }
+  return g;
+}
+
+}  // namespace
+
+struct nep_system {
+  int device = 0;
+  hipStream_t st = nullptr;
+  int64_t N = 0;
+  double box[3] = {0, 0, 0};
+  int capR = 0, capA = 0;
+  nep_model model[2];
+  bool has_model[2] = {false, false};
+  ModelDev mdev[2];
+  MassTable mt;
+  int n_types = 1;
+  int max_ncell = 1;
+  CellGrid grid;
+  bool have_state = false, have_list = false;
+  double list_skin = 0;
+  bool force_valid[2] = {false, false};
+  int force_prec[2] = {0, 0};
+  int64_t step = 0;
+  int64_t n_mts_blocks = 0, n_fallback_blocks = 0, n_steps_total = 0;
+  std::string err;
+  // device buffers (inside the caller's workspace)
+  double *x, *v, *x_alt, *v_alt, *x_build;
+  int32_t *type, *type_alt, *perm, *perm_alt, *cellid, *cell_sorted, *src, *key;
+  int32_t *cell_count, *cell_start, *cell_fill, *scan_tmp;
+  int32_t *nbrR, *cntR, *nbrA, *cntA, *actR, *nactR, *actA, *nactA;
+  float *F[2], *U, *FpR, *G;
+  float *gF, *vjp, *qs;
+  double *partial, *gpart, *res, *staging;
+  int32_t* flags;
+  float* mparams[2];
+  uint16_t* mbf[2];
+  int nblocks = 1;
+};
+
+namespace {
+
+constexpr int kGradMax = 32 * 32 + 2 * 32 + 1;
+
+// Lays out every buffer; with base == nullptr it only measures.
+int64_t layout(nep_system* s, char* base, int64_t N, int capR, int capA, int max_ncell, const int64_t* np,
+               const int* HD) {
+  Carver c;
+  c.base = base;
+  auto& S = *s;
+  S.x = c.take<double>(3 * N);
+  S.v = c.take<double>(3 * N);
+  S.x_alt = c.take<double>(3 * N);
+  S.v_alt = c.take<double>(3 * N);
+  S.x_build = c.take<double>(3 * N);
+  S.type = c.take<int32_t>(N);
+  S.type_alt = c.take<int32_t>(N);
+  S.perm = c.take<int32_t>(N);
+  S.perm_alt = c.take<int32_t>(N);
+  S.cellid = c.take<int32_t>(N);
+  S.cell_sorted = c.take<int32_t>(N);
+  S.src = c.take<int32_t>(N);
+  S.key = c.take<int32_t>(N);
+  S.cell_count = c.take<int32_t>(max_ncell);
+  S.cell_start = c.take<int32_t>(max_ncell + 1);
+  S.cell_fill = c.take<int32_t>(max_ncell);
+  S.scan_tmp = c.take<int32_t>(max_ncell / 1024 + 2);
+  S.nbrR = c.take<int32_t>((int64_t)capR * N);
+  S.cntR = c.take<int32_t>(N);
+  S.nbrA = c.take<int32_t>((int64_t)capA * N);
+  S.cntA = c.take<int32_t>(N);
+  S.actR = c.take<int32_t>((int64_t)capR * N);
+  S.nactR = c.take<int32_t>(N);
+  S.actA = c.take<int32_t>((int64_t)capA * N);
+  S.nactA = c.take<int32_t>(N);
+  S.F[0] = c.take<float>(3 * N);
+  S.F[1] = c.take<float>(3 * N);
+  S.U = c.take<float>(N);
+  S.FpR = c.take<float>(8 * N);
+  S.G = c.take<float>(5 * 24 * N);
+  S.gF = c.take<float>(3 * N);
+  const int nb = grid_blocks(N);
+  S.partial = c.take<double>((int64_t)nb * kPartialStride);
+  S.gpart = c.take<double>((int64_t)nb * kGradMax);
+  S.res = c.take<double>(kResults);
+  S.staging = c.take<double>(3 * N);
+  S.flags = c.take<int32_t>(FLAG_COUNT);
+  for (int k = 0; k < 2; ++k) {
+    S.mparams[k] = c.take<float>(np[k] > 0 ? np[k] : 1);
+    S.mbf[k] = c.take<uint16_t>(HD[k] > 0 ? HD[k] : 1);
+  }
+  S.vjp = nullptr;
+  S.qs = nullptr;
+  S.nblocks = nb;
+  return (c.off + 255) & ~int64_t(255);
+}
+
+#define HIPCHK(call)                                                            \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess) {                                                     \
+      s->err = std::string(#call) + ": " + hipGetErrorString(e_);               \
+      return NEP_ERR_HIP;                                                       \
+    }                                                                           \
+  } while (0)
+
+int fail(nep_system* s, int code, const std::string& msg) {
+  if (s) s->err = msg;
+  return code;
+}
+
+// Upload one model's parameters (FP32 copy + bfloat16 copy of W0).
+int upload_model(nep_system* s, int slot) {
+  const nep_model& m = s->model[slot];
+  std::vector<float> f(m.params.size());
+  for (size_t k = 0; k < f.size(); ++k) f[k] = (float)m.params[k];
+  const int T = m.hp.n_types, nR = m.hp.n_max_radial + 1, nA = m.hp.n_max_angular + 1;
+  const int kR = m.hp.basis_radial + 1, kA = m.hp.basis_angular + 1, H = m.hp.n_hidden, D = m.D;
+  const int64_t offW0 = (int64_t)T * T * nR * kR + (int64_t)T * T * nA * kA + D;
+  std::vector<uint16_t> bf((size_t)H * D);
+  for (int k = 0; k < H * D; ++k) bf[k] = f64_to_bf16_bits(m.params[offW0 + k]);
+  HIPCHK(hipMemcpyAsync(s->mparams[slot], f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(s->mbf[slot], bf.data(), bf.size() * sizeof(uint16_t), hipMemcpyHostToDevice, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));  // host vectors go out of scope
+  ModelDev& d = s->mdev[slot];
+  d.T = T;
+  d.nR = nR;
+  d.kR = kR;
+  d.nA = nA;
+  d.kA = kA;
+  d.L3 = m.hp.l_max_3b;
+  d.L4 = m.hp.l_max_4b;
+  d.H = H;
+  d.D = D;
+  d.rcR = (float)m.hp.rc_radial;
+  d.rcA = (float)m.hp.rc_angular;
+  d.rcR64 = m.hp.rc_radial;
+  d.rcA64 = m.hp.rc_angular;
+  const float* p = s->mparams[slot];
+  d.cR = p;
+  d.cA = p + (int64_t)T * T * nR * kR;
+  d.sigma = d.cA + (int64_t)T * T * nA * kA;
+  d.W0 = d.sigma + D;
+  d.b0 = d.W0 + (int64_t)H * D;
+  d.w1 = d.b0 + H;
+  d.b1 = d.w1 + H;
+  d.W0bf = s->mbf[slot];
+  s->force_valid[slot] = false;
+  return NEP_OK;
+}
+
+EvalBuffers eval_buffers(nep_system* s, int slot) {
+  EvalBuffers b;
+  b.N = s->N;
+  for (int c = 0; c < 3; ++c) b.box[c] = s->box[c];
+  b.x = s->x;
+  b.type = s->type;
+  b.nbrR = s->nbrR;
+  b.cntR = s->cntR;
+  b.capR = s->capR;
+  b.capA = s->capA;
+  b.actR = s->actR;
+  b.nactR = s->nactR;
+  b.actA = s->actA;
+  b.nactA = s->nactA;
+  b.U = s->U;
+  b.FpR = s->FpR;
+  b.G = s->G;
+  b.F = s->F[slot];
+  b.partial = s->partial;
+  b.flags = s->flags;
+  return b;
+}
+
+int do_eval(nep_system* s, int slot, int prec) {
+  HIPCHK(launch_eval(s->mdev[slot], prec, eval_buffers(s, slot), s->st));
+  s->force_valid[slot] = true;
+  s->force_prec[slot] = prec;
+  return NEP_OK;
+}
+
+// Reduce energy + virial partials into res[base .. base+10).
+int reduce_ew(nep_system* s, int base) {
+  HIPCHK(launch_reduce_partials(s->partial, s->nblocks, P_ENERGY, 10, s->res + base, s->st));
+  return NEP_OK;
+}
+
+int rebuild(nep_system* s, double skin, int force) {
+  const double cutR = s->model[0].hp.rc_radial + skin;
+  const double cutA = s->model[0].hp.rc_angular + skin;
+  HIPCHK(launch_rebuild(s->N, s->grid, cutR, cutA, s->capR, s->capA, s->x, s->v, s->type, s->perm, s->x_alt,
+                        s->v_alt, s->type_alt, s->perm_alt, s->x_build, s->cellid, s->cell_sorted, s->src,
+                        s->key, s->cell_count, s->cell_start, s->cell_fill, s->scan_tmp, s->nbrR, s->cntR,
+                        s->nbrA, s->cntA, s->flags, s->st));
+  (void)force;
+  return NEP_OK;
+}
+
+int read_flags(nep_system* s, int32_t* f) {
+  HIPCHK(hipMemcpyAsync(f, s->flags, FLAG_COUNT * sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  return NEP_OK;
+}
+
+int check_flags(nep_system* s) {
+  int32_t f[FLAG_COUNT];
+  int st = read_flags(s, f);
+  if (st) return st;
+  if (f[FLAG_OVF_R] > 0 || f[FLAG_OVF_A] > 0) {
+    char buf[256];
+    snprintf(buf, sizeof buf, "neighbour list overflow: need radial capacity %d (have %d), angular %d (have %d)",
+             std::max(f[FLAG_OVF_R], 0), s->capR, std::max(f[FLAG_OVF_A], 0), s->capA);
+    s->have_list = false;
+    return fail(s, NEP_ERR_NEIGHBOR_OVERFLOW, buf);
+  }
+  if (f[FLAG_TYPE]) return fail(s, NEP_ERR_TYPE, "atom type out of range");
+  if (f[FLAG_NONFINITE]) return fail(s, NEP_ERR_NONFINITE, "non-finite positions or velocities");
+  return NEP_OK;
+}
+
+int check_model_pair(const nep_model* full, const nep_model* sur) {
+  if (!full) return NEP_ERR_ARG;
+  if (sur) {
+    if (sur->hp.n_types != full->hp.n_types) return NEP_ERR_ARG;
+    if (sur->hp.rc_radial > full->hp.rc_radial || sur->hp.rc_angular > full->hp.rc_angular) return NEP_ERR_ARG;
+  }
+  return NEP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nep_status_string(int status) {
+  switch (status) {
+    case NEP_OK: return "ok";
+    case NEP_ERR_ARG: return "invalid argument";
+    case NEP_ERR_BOX_TOO_SMALL: return "box too small for cutoff + skin";
+    case NEP_ERR_NEIGHBOR_OVERFLOW: return "neighbour list capacity exceeded";
+    case NEP_ERR_TYPE: return "atom type out of range";
+    case NEP_ERR_NONFINITE: return "non-finite value";
+    case NEP_ERR_HIP: return "HIP runtime error";
+    case NEP_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+    case NEP_ERR_STALE_LIST: return "no valid neighbour list";
+    case NEP_ERR_UNSUPPORTED: return "model shape has no compiled kernel";
+    default: return "unknown status";
+  }
+}
+
+const char* nep_last_error(const nep_system* s) { return s ? s->err.c_str() : "null system"; }
+
+int nep_param_count(const nep_hparams* hp, int64_t* n_params, int32_t* n_desc) {
+  if (!hp_valid(hp)) return NEP_ERR_ARG;
+  int D = 0;
+  const int64_t n = count_params(*hp, &D);
+  if (n_params) *n_params = n;
+  if (n_desc) *n_desc = D;
+  return NEP_OK;
+}
+
+int nep_model_create(const nep_hparams* hp, const double* params, int64_t n_params, nep_model** out) {
+  if (!out || !params || !hp_valid(hp)) return NEP_ERR_ARG;
+  int D = 0;
+  const int64_t n = count_params(*hp, &D);
+  if (n != n_params) return NEP_ERR_ARG;
+  for (int64_t k = 0; k < n; ++k)
+    if (!std::isfinite(params[k])) return NEP_ERR_NONFINITE;
+  nep_model* m = new (std::nothrow) nep_model;
+  if (!m) return NEP_ERR_ARG;
+  m->hp = *hp;
+  m->params.assign(params, params + n);
+  m->D = D;
+  m->n_params = n;
+  if (D > 32 || hp->n_hidden > 32) {
+    delete m;
+    return NEP_ERR_UNSUPPORTED;
+  }
+  *out = m;
+  return NEP_OK;
+}
+
+void nep_model_destroy(nep_model* m) { delete m; }
+
+static int max_cells(const double box[3], double rc) {
+  const CellGrid g = make_grid(box, rc);
+  return g.ncell;
+}
+
+int nep_system_workspace_bytes(const nep_model* full, const nep_model* sur, int64_t n_atoms, const double box[3],
+                               int32_t cap_radial, int32_t cap_angular, int64_t* bytes) {
+  if (!bytes || !box || n_atoms < 1 || n_atoms > (int64_t)INT32_MAX || cap_radial < 1 || cap_angular < 1)
+    return NEP_ERR_ARG;
+  if (check_model_pair(full, sur)) return NEP_ERR_ARG;
+  nep_system tmp;
+  const int64_t np[2] = {full->n_params, sur ? sur->n_params : 0};
+  const int HD[2] = {full->hp.n_hidden * full->D, sur ? sur->hp.n_hidden * sur->D : 0};
+  *bytes = layout(&tmp, nullptr, n_atoms, cap_radial, cap_angular, max_cells(box, full->hp.rc_radial), np, HD);
+  return NEP_OK;
+}
+
+int nep_system_create(const nep_model* full, const nep_model* sur, int64_t n_atoms, const double box[3],
+                      int32_t cap_radial, int32_t cap_angular, void* workspace, int64_t workspace_bytes,
+                      void* hip_stream, nep_system** out) {
+  if (!out || !box || n_atoms < 1 || n_atoms > (int64_t)INT32_MAX || cap_radial < 1 || cap_angular < 1)
+    return NEP_ERR_ARG;
+  if (check_model_pair(full, sur)) return NEP_ERR_ARG;
+  for (int c = 0; c < 3; ++c)
+    if (!(box[c] > 0) || !std::isfinite(box[c])) return NEP_ERR_ARG;
+  if (!workspace || ((uintptr_t)workspace & 255)) return NEP_ERR_WORKSPACE;
+  nep_system* s = new (std::nothrow) nep_system;
+  if (!s) return NEP_ERR_ARG;
+  s->N = n_atoms;
+  for (int c = 0; c < 3; ++c) s->box[c] = box[c];
+  s->capR = cap_radial;
+  s->capA = cap_angular;
+  s->model[0] = *full;
+  s->has_model[0] = true;
+  if (sur) {
+    s->model[1] = *sur;
+    s->has_model[1] = true;
+  }
+  s->n_types = full->hp.n_types;
+  s->max_ncell = max_cells(box, full->hp.rc_radial);
+  const int64_t np[2] = {full->n_params, sur ? sur->n_params : 0};
+  const int HD[2] = {full->hp.n_hidden * full->D, sur ? sur->hp.n_hidden * sur->D : 0};
+  const int64_t need = layout(s, nullptr, n_atoms, cap_radial, cap_angular, s->max_ncell, np, HD);
+  if (workspace_bytes < need) {
+    delete s;
+    return NEP_ERR_WORKSPACE;
+  }
+  layout(s, (char*)workspace, n_atoms, cap_radial, cap_angular, s->max_ncell, np, HD);
+  s->st = (hipStream_t)hip_stream;
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return NEP_ERR_HIP;
+  }
+  for (int k = 0; k < 2; ++k) {
+    if (!s->has_model[k]) continue;
+    const int st = upload_model(s, k);
+    if (st) {
+      delete s;
+      return st;
+    }
+    if (!eval_supported(s->mdev[k])) {
+      delete s;
+      return NEP_ERR_UNSUPPORTED;
+    }
+  }
+  if (launch_zero_i32(s->flags, FLAG_COUNT, s->st) != hipSuccess) {
+    delete s;
+    return NEP_ERR_HIP;
+  }
+  for (int t = 0; t < kMaxTypes; ++t) {
+    s->mt.mass[t] = 1.0;
+    s->mt.inv_mxi[t] = 1.0 / kXi;
+  }
+  *out = s;
+  return NEP_OK;
+}
+
+void nep_system_destroy(nep_system* s) {
+  if (s && s->st) (void)hipStreamSynchronize(s->st);
+  delete s;
+}
+
+int nep_system_set_params(nep_system* s, int32_t slot, const double* params, int64_t n_params) {
+  if (!s || slot < 0 || slot > 1 || !s->has_model[slot] || !params) return fail(s, NEP_ERR_ARG, "bad slot or params");
+  if (n_params != s->model[slot].n_params) return fail(s, NEP_ERR_ARG, "parameter count mismatch");
+  for (int64_t k = 0; k < n_params; ++k)
+    if (!std::isfinite(params[k])) return fail(s, NEP_ERR_NONFINITE, "non-finite parameter");
+  s->model[slot].params.assign(params, params + n_params);
+  return upload_model(s, slot);
+}
+
+int nep_set_state(nep_system* s, const double* x, const double* v, const int32_t* types, const double* masses,
+                  int32_t on_device) {
+  if (!s || !x || !types || !masses) return fail(s, NEP_ERR_ARG, "null argument");
+  for (int t = 0; t < s->n_types; ++t) {
+    if (!(masses[t] > 0) || !std::isfinite(masses[t])) return fail(s, NEP_ERR_ARG, "masses must be positive");
+    s->mt.mass[t] = masses[t];
+    s->mt.inv_mxi[t] = 1.0 / (masses[t] * kXi);
+  }
+  const int64_t N = s->N;
+  CellGrid g = make_grid(s->box, s->model[0].hp.rc_radial);
+  HIPCHK(launch_zero_i32(s->flags, FLAG_COUNT, s->st));
+  const double* xd = x;
+  const double* vd = v;
+  const int32_t* td = types;
+  if (!on_device) {
+    // stage host arrays through the device buffers that the rebuild overwrites anyway
+    HIPCHK(hipMemcpyAsync(s->x_alt, x, 3 * N * sizeof(double), hipMemcpyHostToDevice, s->st));
+    xd = s->x_alt;
+    if (v) {
+      HIPCHK(hipMemcpyAsync(s->v_alt, v, 3 * N * sizeof(double), hipMemcpyHostToDevice, s->st));
+      vd = s->v_alt;
+    }
+    HIPCHK(hipMemcpyAsync(s->type_alt, types, N * sizeof(int32_t), hipMemcpyHostToDevice, s->st));
+    td = s->type_alt;
+  }
+  HIPCHK(launch_state_in(N, xd, vd, td, s->n_types, g, s->x, s->v, s->type, s->perm, s->flags, s->st));
+  int32_t f[FLAG_COUNT];
+  int st = read_flags(s, f);
+  if (st) return st;
+  if (f[FLAG_TYPE]) return fail(s, NEP_ERR_TYPE, "atom type out of range");
+  if (f[FLAG_NONFINITE]) return fail(s, NEP_ERR_NONFINITE, "non-finite position or velocity");
+  s->have_state = true;
+  s->have_list = false;
+  s->force_valid[0] = s->force_valid[1] = false;
+  s->step = 0;
+  return NEP_OK;
+}
+
+int nep_build_neighbors(nep_system* s, double skin) {
+  if (!s) return NEP_ERR_ARG;
+  if (!s->have_state) return fail(s, NEP_ERR_ARG, "no state set");
+  if (!(skin >= 0) || !std::isfinite(skin)) return fail(s, NEP_ERR_ARG, "skin must be >= 0");
+  const double cut = s->model[0].hp.rc_radial + skin;
+  for (int c = 0; c < 3; ++c)
+    if (!(s->box[c] >= 2.0 * cut)) return fail(s, NEP_ERR_BOX_TOO_SMALL, "every box side must be >= 2 (rc + skin)");
+  s->grid = make_grid(s->box, cut);
+  HIPCHK(launch_zero_i32(s->flags, FLAG_COUNT, s->st));
+  HIPCHK(launch_set_flag(s->flags, FLAG_REBUILD, 1, s->st));
+  int st = rebuild(s, skin, 1);
+  if (st) return st;
+  st = check_flags(s);
+  if (st) return st;
+  s->have_list = true;
+  s->list_skin = skin;
+  s->force_valid[0] = s->force_valid[1] = false;
+  return NEP_OK;
+}
+
+int nep_export_neighbors(nep_system* s, int32_t which, int64_t* offsets, int32_t* idx, int64_t cap_total) {
+  if (!s || !offsets || !idx || which < 0 || which > 1) return fail(s, NEP_ERR_ARG, "bad argument");
+  if (!s->have_list) return fail(s, NEP_ERR_STALE_LIST, "no list built");
+  const int64_t N = s->N;
+  const int cap = which == 0 ? s->capR : s->capA;
+  int32_t* rows = which == 0 ? s->actR : s->actA;  // scratch, rewritten by every evaluation
+  int32_t* rcnt = which == 0 ? s->nactR : s->nactA;
+  HIPCHK(launch_export(N, s->perm, which == 0 ? s->nbrR : s->nbrA, which == 0 ? s->cntR : s->cntA, cap, rows,
+                       rcnt, s->st));
+  std::vector<int32_t> cnt(N);
+  HIPCHK(hipMemcpyAsync(cnt.data(), rcnt, N * sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
+  std::vector<int32_t> all((size_t)N * cap);
+  HIPCHK(hipMemcpyAsync(all.data(), rows, (size_t)N * cap * sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  s->force_valid[0] = s->force_valid[1] = false;
+  offsets[0] = 0;
+  for (int64_t o = 0; o < N; ++o) offsets[o + 1] = offsets[o] + cnt[o];
+  if (offsets[N] > cap_total) return fail(s, NEP_ERR_ARG, "cap_total too small");
+  for (int64_t o = 0; o < N; ++o)
+    std::memcpy(idx + offsets[o], all.data() + o * cap, cnt[o] * sizeof(int32_t));
+  return NEP_OK;
+}
+
+int nep_compute_energy_forces_virial(nep_system* s, int32_t slot, int32_t precision, double* energy,
+                                     double* virial9, double* forces, double* per_atom_energy,
+                                     int32_t on_device) {
+  if (!s || !energy || !virial9 || slot < 0 || slot > 1 || !s->has_model[slot] || precision < 0 || precision > 1)
+    return fail(s, NEP_ERR_ARG, "bad argument");
+  if (!s->have_list) return fail(s, NEP_ERR_STALE_LIST, "build the neighbour lists first");
+  int st = do_eval(s, slot, precision);
+  if (st) return st;
+  if ((st = reduce_ew(s, 0))) return st;
+  const int64_t N = s->N;
+  if (forces) {
+    double* dst = on_device ? forces : s->staging;
+    HIPCHK(launch_forces_out(N, s->perm, s->F[slot], dst, s->st));
+    if (!on_device) HIPCHK(hipMemcpyAsync(forces, s->staging, 3 * N * sizeof(double), hipMemcpyDeviceToHost, s->st));
+  }
+  if (per_atom_energy) {
+    double* dst = on_device ? per_atom_energy : s->staging;
+    HIPCHK(launch_scalar_out(N, s->perm, s->U, dst, s->st));
+    if (!on_device)
+      HIPCHK(hipMemcpyAsync(per_atom_energy, s->staging, N * sizeof(double), hipMemcpyDeviceToHost, s->st));
+  }
+  double r[10];
+  HIPCHK(hipMemcpyAsync(r, s->res, 10 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  *energy = r[0];
+  for (int k = 0; k < 9; ++k) virial9[k] = r[1 + k];
+  bool finite = std::isfinite(r[0]);
+  for (int k = 1; k < 10; ++k) finite = finite && std::isfinite(r[k]);
+  if (!finite) return fail(s, NEP_ERR_NONFINITE, "non-finite energy or virial");
+  return NEP_OK;
+}
+
+namespace {
+
+// Thermo row {step, PE, KE, T, P, err_rms, err_max, fallback} from res[0..10) (E, W).
+int thermo_row(nep_system* s, double* row, double err_rms, double err_max, int fallback) {
+  HIPCHK(launch_kinetic(s->N, s->v, s->type, s->mt, s->partial, s->st));
+  HIPCHK(launch_reduce_partials(s->partial, s->nblocks, P_KE, 1, s->res + 10, s->st));
+  double r[11];
+  HIPCHK(hipMemcpyAsync(r, s->res, 11 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  const double V = s->box[0] * s->box[1] * s->box[2];
+  const double ke = r[10];
+  row[0] = (double)s->step;
+  row[1] = r[0];
+  row[2] = ke;
+  row[3] = 2.0 * ke / ((3.0 * s->N - 3.0) * kBoltzmann);
+  row[4] = (2.0 * ke + (r[1] + r[5] + r[9])) / (3.0 * V);
+  row[5] = err_rms;
+  row[6] = err_max;
+  row[7] = fallback;
+  return NEP_OK;
+}
+
+// One velocity-Verlet step with model `slot`. The rebuild flag is set on the device
+// for the scheduled steps and raised by the drift kernel when an atom has moved
+// more than skin/2 since the last build.
+int vv_step(nep_system* s, int slot, int prec, double dt, int rebuild_every, double skin) {
+  const int64_t next = s->step + 1;
+  const int scheduled = (rebuild_every > 0 && next % rebuild_every == 0) ? 1 : 0;
+  HIPCHK(launch_set_flag(s->flags, FLAG_REBUILD, scheduled, s->st));
+  HIPCHK(launch_kick_drift(s->N, dt, s->grid, s->F[slot], s->type, s->mt, s->x, s->v, s->x_build,
+                           0.25 * skin * skin, s->flags, s->st));
+  int st = rebuild(s, skin, 0);
+  if (st) return st;
+  if ((st = do_eval(s, slot, prec))) return st;
+  HIPCHK(launch_kick(s->N, dt, s->F[slot], s->type, s->mt, s->v, s->st));
+  s->step = next;
+  s->n_steps_total++;
+  return NEP_OK;
+}
+
+int force_error(nep_system* s, double* rms, double* mx) {
+  HIPCHK(launch_force_error(s->N, s->F[0], s->F[1], s->partial, s->st));
+  HIPCHK(launch_reduce_partials(s->partial, s->nblocks, P_ERR2, 1, s->res + 12, s->st));
+  HIPCHK(launch_max_partials(s->partial, s->nblocks, P_ERRMAX, s->res + 13, s->st));
+  double r[2];
+  HIPCHK(hipMemcpyAsync(r, s->res + 12, 2 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  *rms = std::sqrt(r[0] / (3.0 * s->N));
+  *mx = r[1];
+  return NEP_OK;
+}
+
+}  // namespace
+
+int nep_step(nep_system* s, int64_t n_steps, double dt_fs, int32_t rebuild_every, double skin, int32_t mts_k,
+             double fallback_rms, double fallback_max, int32_t precision, double* thermo, int32_t thermo_every,
+             int64_t max_rows, int64_t* rows_written) {
+  if (!s || n_steps < 0 || !(dt_fs > 0) || rebuild_every < 0 || !(skin >= 0) || mts_k < 0 || precision < 0 ||
+      precision > 1)
+    return fail(s, NEP_ERR_ARG, "bad argument");
+  if (!s->have_state) return fail(s, NEP_ERR_ARG, "no state set");
+  if (mts_k > 0 && (!s->has_model[1] || n_steps % mts_k != 0))
+    return fail(s, NEP_ERR_ARG, "MTS needs a surrogate model and n_steps divisible by mts_k");
+  if (thermo && (thermo_every < 1 || max_rows < 1)) return fail(s, NEP_ERR_ARG, "thermo_every and max_rows must be >= 1");
+  if (rows_written) *rows_written = 0;
+  int st;
+  if (!s->have_list || s->list_skin != skin) {
+    if ((st = nep_build_neighbors(s, skin))) return st;
+  }
+  int64_t rows = 0;
+  auto want_row = [&](bool last) {
+    return thermo && rows < max_rows && (last || (s->step % thermo_every == 0));
+  };
+  if (mts_k == 0) {
+    if (!s->force_valid[0] || s->force_prec[0] != precision)
+      if ((st = do_eval(s, 0, precision))) return st;
+    for (int64_t k = 0; k < n_steps; ++k) {
+      if ((st = vv_step(s, 0, precision, dt_fs, rebuild_every, skin))) return st;
+      if (want_row(k == n_steps - 1)) {
+        if ((st = reduce_ew(s, 0))) return st;
+        if ((st = thermo_row(s, thermo + 8 * rows, 0.0, 0.0, 0))) return st;
+        ++rows;
+      }
+    }
+    s->force_valid[1] = false;
+  } else {
+    // Multiple time stepping (r-RESPA): fast force = surrogate (slot 1), slow force =
+    // full - surrogate applied as impulses every mts_k steps.
+    if (!s->force_valid[0] || s->force_prec[0] != precision)
+      if ((st = do_eval(s, 0, precision))) return st;
+    if ((st = reduce_ew(s, 0))) return st;
+    if (!s->force_valid[1] || s->force_prec[1] != precision)
+      if ((st = do_eval(s, 1, precision))) return st;
+    const double big = mts_k * dt_fs;
+    const int64_t nblk = n_steps / mts_k;
+    int fallback = 0, clean = 0;
+    for (int64_t b = 0; b < nblk; ++b) {
+      double rms = 0, mx = 0;
+      if (!fallback) {
+        HIPCHK(launch_kick_diff(s->N, 0.5 * big, s->F[0], s->F[1], s->type, s->mt, s->v, s->st));
+        for (int k = 0; k < mts_k; ++k)
+          if ((st = vv_step(s, 1, precision, dt_fs, rebuild_every, skin))) return st;
+        if ((st = do_eval(s, 0, precision))) return st;
+        if ((st = reduce_ew(s, 0))) return st;
+        if ((st = force_error(s, &rms, &mx))) return st;
+        HIPCHK(launch_kick_diff(s->N, 0.5 * big, s->F[0], s->F[1], s->type, s->mt, s->v, s->st));
+        s->n_mts_blocks++;
+        if (rms > fallback_rms || mx > fallback_max) {
+          fallback = 1;
+          clean = 0;
+        }
+      } else {
+        for (int k = 0; k < mts_k; ++k)
+          if ((st = vv_step(s, 0, precision, dt_fs, rebuild_every, skin))) return st;
+        if ((st = reduce_ew(s, 0))) return st;
+        if ((st = do_eval(s, 1, precision))) return st;  // shadow surrogate evaluation
+        if ((st = force_error(s, &rms, &mx))) return st;
+        s->n_fallback_blocks++;
+        if (rms <= fallback_rms && mx <= fallback_max) {
+          if (++clean >= 10) fallback = 0;
+        } else {
+          clean = 0;
+        }
+      }
+      if (want_row(b == nblk - 1)) {
+        if ((st = thermo_row(s, thermo + 8 * rows, rms, mx, fallback))) return st;
+        ++rows;
+      }
+    }
+  }
+  if (rows_written) *rows_written = rows;
+  if ((st = check_flags(s))) return st;
+  HIPCHK(hipStreamSynchronize(s->st));
+  return NEP_OK;
+}
+
+int nep_get_state(nep_system* s, double* x, double* v, int64_t* step, int32_t on_device) {
+  if (!s) return NEP_ERR_ARG;
+  if (!s->have_state) return fail(s, NEP_ERR_ARG, "no state set");
+  const int64_t N = s->N;
+  if (x) {
+    double* dst = on_device ? x : s->staging;
+    HIPCHK(launch_state_out(N, s->perm, s->x, dst, s->st));
+    if (!on_device) HIPCHK(hipMemcpyAsync(x, s->staging, 3 * N * sizeof(double), hipMemcpyDeviceToHost, s->st));
+  }
+  if (v) {
+    double* dst = on_device ? v : s->staging;
+    HIPCHK(launch_state_out(N, s->perm, s->v, dst, s->st));
+    if (!on_device) HIPCHK(hipMemcpyAsync(v, s->staging, 3 * N * sizeof(double), hipMemcpyDeviceToHost, s->st));
+  }
+  if (step) *step = s->step;
+  HIPCHK(hipStreamSynchronize(s->st));
+  return NEP_OK;
+}
+
+int nep_get_stats(nep_system* s, int64_t* stats4) {
+  if (!s || !stats4) return NEP_ERR_ARG;
+  int32_t f[FLAG_COUNT];
+  int st = read_flags(s, f);
+  if (st) return st;
+  stats4[0] = f[FLAG_NBUILD];
+  stats4[1] = s->n_mts_blocks;
+  stats4[2] = s->n_fallback_blocks;
+  stats4[3] = s->n_steps_total;
+  return NEP_OK;
+}
+
+int nep_surrogate_error(nep_system* s, int32_t precision, double* err2) {
+  if (!s || !err2 || !s->has_model[1] || precision < 0 || precision > 1) return fail(s, NEP_ERR_ARG, "bad argument");
+  if (!s->have_list) return fail(s, NEP_ERR_STALE_LIST, "build the neighbour lists first");
+  int st;
+  if ((st = do_eval(s, 0, precision))) return st;
+  if ((st = do_eval(s, 1, precision))) return st;
+  return force_error(s, &err2[0], &err2[1]);
+}
+
+int nep_train_forward(nep_system* s, int32_t slot, const float* theta, double* energy, float* forces) {
+  if (!s || !theta || !energy || slot < 0 || slot > 1 || !s->has_model[slot]) return fail(s, NEP_ERR_ARG, "bad argument");
+  if (!s->have_list) return fail(s, NEP_ERR_STALE_LIST, "build the neighbour lists first");
+  HIPCHK(launch_train_forward(s->mdev[slot], theta, eval_buffers(s, slot), s->st));
+  s->force_valid[slot] = false;
+  int st;
+  if ((st = reduce_ew(s, 0))) return st;
+  if (forces) HIPCHK(launch_scatter_vec_f32(s->N, s->perm, s->F[slot], forces, s->st));
+  double r;
+  HIPCHK(hipMemcpyAsync(&r, s->res, sizeof(double), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  *energy = r;
+  if (!std::isfinite(r)) return fail(s, NEP_ERR_NONFINITE, "non-finite energy");
+  return NEP_OK;
+}
+
+int nep_train_backward(nep_system* s, int32_t slot, const float* theta, double gE, const float* gF, float* grad) {
+  if (!s || !theta || !grad || slot < 0 || slot > 1 || !s->has_model[slot]) return fail(s, NEP_ERR_ARG, "bad argument");
+  if (!s->have_list) return fail(s, NEP_ERR_STALE_LIST, "build the neighbour lists first");
+  TrainBuffers t;
+  t.e = eval_buffers(s, slot);
+  t.theta = theta;
+  t.gE = gE;
+  t.gF = nullptr;
+  if (gF) {
+    HIPCHK(launch_gather_vec_f32(s->N, s->perm, gF, s->gF, s->st));
+    t.gF = s->gF;
+  }
+  t.vjp = nullptr;
+  t.qs = nullptr;
+  t.gpart = s->gpart;
+  t.grad = grad;
+  hipError_t e = launch_train_backward(s->mdev[slot], t, s->st);
+  if (e == hipErrorNotSupported) return fail(s, NEP_ERR_UNSUPPORTED, "weight gradients not available");
+  HIPCHK(e);
+  HIPCHK(hipStreamSynchronize(s->st));
+  return NEP_OK;
+}
+
+int nep_adam_update(nep_system* s, float* theta, const float* grad, float* m1, float* m2, int64_t n, int64_t t,
+                    double lr, double beta1, double beta2, double eps) {
+  if (!s || !theta || !grad || !m1 || !m2 || n < 1 || t < 1) return fail(s, NEP_ERR_ARG, "bad argument");
+  HIPCHK(launch_adam(theta, grad, m1, m2, n, t, lr, beta1, beta2, eps, s->st));
+  return NEP_OK;
+}
+
+}  // extern "C"

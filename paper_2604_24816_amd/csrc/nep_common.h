@@ -1,0 +1,170 @@
+// Internal declarations shared by the HIP translation units of libnep.
+// Not part of the public ABI (see include/nep.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace nep {
+
+constexpr int kBlock = 256;          // threads per workgroup for per-atom kernels
+constexpr int kMaxTypes = 2;
+constexpr int kNumXcd = 8;           // MI355X: 8 accelerator complex dies, one L2 each
+constexpr int kPartialStride = 16;   // doubles per workgroup in reduction partials
+
+// Energy/virial partial slots.
+enum { P_ENERGY = 0, P_VIR = 1 /* 9 values */, P_KE = 10, P_ERR2 = 11, P_ERRMAX = 12 };
+
+// Device flag words (int32 unless noted).
+enum {
+  FLAG_OVF_R = 0,      // max radial list length seen (atomicMax)
+  FLAG_OVF_A = 1,      // max angular list length seen
+  FLAG_TYPE = 2,       // type out of range
+  FLAG_NONFINITE = 3,  // NaN/Inf seen
+  FLAG_REBUILD = 4,    // 1 = the current step rebuilds its lists
+  FLAG_NBUILD = 5,     // number of list builds (device counter)
+  FLAG_COUNT = 8
+};
+
+// Orthorhombic cell grid over the box.
+struct CellGrid {
+  int nc[3];
+  int ncell;
+  double box[3];
+};
+
+// Device copy of one model (FP32 parameters, same packed order as the host FP64
+// vector) plus a bfloat16 copy of W0.
+struct ModelDev {
+  int T, nR, kR, nA, kA, L3, L4, H, D;
+  float rcR, rcA;
+  double rcR64, rcA64;
+  const float* cR;
+  const float* cA;
+  const float* sigma;
+  const float* W0;    // [H][D]
+  const float* b0;
+  const float* w1;
+  const float* b1;
+  const uint16_t* W0bf;  // [H][D] bfloat16 bits, rounded from the FP64 parameters
+};
+
+// XCD-aware mapping of a workgroup id to a contiguous tile index: workgroups
+// are dispatched round-robin over the 8 dies, so consecutive tiles (which share
+// neighbour atoms) are given to the same die and its L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int x = b % kNumXcd;
+  const int k = b / kNumXcd;
+  const int per = nb / kNumXcd;
+  const int rem = nb % kNumXcd;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
+// Minimum image of one FP64 component, as d = x_j - x_i; if (d > L/2) d -= L;
+// else if (d < -L/2) d += L.
+__device__ __forceinline__ double min_image(double d, double L) {
+  const double half = 0.5 * L;
+  if (d > half) d -= L;
+  else if (d < -half) d += L;
+  return d;
+}
+
+inline int grid_blocks(int64_t n, int block = kBlock) {
+  return (int)((n + block - 1) / block);
+}
+
+// ---------------------------------------------------------------- launchers
+// Neighbour lists (nep_neighbors.hip)
+hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t st);
+hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st);
+hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st);
+hipError_t launch_rebuild(int64_t N, const CellGrid& g, double cutR, double cutA, int capR, int capA,
+                          double* x, double* v, int32_t* type, int32_t* perm,
+                          double* x_alt, double* v_alt, int32_t* type_alt, int32_t* perm_alt,
+                          double* x_build, int32_t* cellid, int32_t* cell_sorted, int32_t* src,
+                          int32_t* key, int32_t* cell_count, int32_t* cell_start, int32_t* cell_fill,
+                          int32_t* scan_tmp, int32_t* nbrR, int32_t* cntR, int32_t* nbrA,
+                          int32_t* cntA, int32_t* flags, hipStream_t st);
+hipError_t launch_export(int64_t N, const int32_t* perm, const int32_t* nbr, const int32_t* cnt,
+                         int cap, int32_t* rows, int32_t* row_cnt, hipStream_t st);
+
+// Evaluation (nep_eval.hip)
+struct EvalBuffers {
+  int64_t N;
+  double box[3];
+  const double* x;       // [3][N]
+  const int32_t* type;   // [N]
+  const int32_t* nbrR;   // [capR][N] lists with skin
+  const int32_t* cntR;
+  int capR, capA;
+  int32_t* actR;         // [capR][N] pairs with r < rc_radial
+  int32_t* nactR;
+  int32_t* actA;         // [capA][N] pairs with r < rc_angular
+  int32_t* nactA;
+  float* U;              // [N]
+  float* FpR;            // [nR][N] dU/dq for the radial block
+  float* G;              // [nA * ncomp][N] dU/ds for the angular accumulators
+  float* F;              // [3][N] forces (FP32 accumulation)
+  double* partial;       // [nblocks][kPartialStride]
+  int32_t* flags;
+};
+bool eval_supported(const ModelDev& m);
+hipError_t launch_eval(const ModelDev& m, int precision, const EvalBuffers& b, hipStream_t st);
+int eval_partial_blocks(int64_t N);
+
+// MD and reductions (nep_md.hip)
+struct MassTable {
+  double mass[kMaxTypes];     // amu
+  double inv_mxi[kMaxTypes];  // 1 / (m * xi), xi = 103.642697 eV fs^2 / (amu A^2)
+};
+hipError_t launch_reduce_partials(const double* partial, int nblocks, int first, int nvals,
+                                  double* out, hipStream_t st);
+hipError_t launch_max_partials(const double* partial, int nblocks, int slot, double* out,
+                               hipStream_t st);
+hipError_t launch_kick_drift(int64_t N, double dt, CellGrid g, const float* F, const int32_t* type,
+                             MassTable mt, double* x, double* v, const double* x_build,
+                             double half_skin2, int32_t* flags, hipStream_t st);
+hipError_t launch_kick(int64_t N, double dt, const float* F, const int32_t* type, MassTable mt,
+                       double* v, hipStream_t st);
+hipError_t launch_kick_diff(int64_t N, double dt, const float* Fa, const float* Fb,
+                            const int32_t* type, MassTable mt, double* v, hipStream_t st);
+hipError_t launch_kinetic(int64_t N, const double* v, const int32_t* type, MassTable mt,
+                          double* partial, hipStream_t st);
+hipError_t launch_force_error(int64_t N, const float* Fa, const float* Fb, double* partial,
+                              hipStream_t st);
+hipError_t launch_set_flag(int32_t* flags, int idx, int value, hipStream_t st);
+hipError_t launch_state_in(int64_t N, const double* x_aos, const double* v_aos,
+                           const int32_t* type_in, int n_types, CellGrid g, double* x, double* v,
+                           int32_t* type, int32_t* perm, int32_t* flags, hipStream_t st);
+hipError_t launch_state_out(int64_t N, const int32_t* perm, const double* soa, double* aos,
+                            hipStream_t st);
+hipError_t launch_forces_out(int64_t N, const int32_t* perm, const float* F, double* aos,
+                             hipStream_t st);
+hipError_t launch_scalar_out(int64_t N, const int32_t* perm, const float* U, double* out,
+                             hipStream_t st);
+hipError_t launch_gather_vec_f32(int64_t N, const int32_t* perm, const float* aos_orig,
+                                 float* soa_sorted, hipStream_t st);
+hipError_t launch_scatter_vec_f32(int64_t N, const int32_t* perm, const float* soa_sorted,
+                                  float* aos_orig, hipStream_t st);
+
+// Training (nep_train.hip)
+struct TrainBuffers {
+  EvalBuffers e;
+  const float* theta;    // network parameters, packed W0, b0, w1, b1
+  const float* gF;       // [3][N] sorted order, may be null
+  double gE;
+  float* vjp;            // [D][N] scratch
+  float* qs;             // [D][N] scratch
+  double* gpart;         // [nblocks][G] FP64 partial gradients
+  float* grad;           // [G] output
+};
+hipError_t launch_train_forward(const ModelDev& m, const float* theta, const EvalBuffers& b,
+                                hipStream_t st);
+hipError_t launch_train_backward(const ModelDev& m, const TrainBuffers& t, hipStream_t st);
+int train_partial_blocks(int64_t N);
+hipError_t launch_adam(float* theta, const float* g, float* m1, float* m2, int64_t n, int64_t t,
+                       double lr, double b1, double b2, double eps, hipStream_t st);
+
+}  // namespace nep

@@ -1,0 +1,287 @@
+// Velocity-Verlet integration in FP64, the rebuild trigger, FP64 reductions and
+// the conversions between the caller's original atom order ([N][3] rows) and
+// the cell-sorted structure-of-arrays layout ([3][N]) used on the device.
+// Section VI.A: 1 fs steps, neighbour lists refreshed every 10 steps with the
+// displacement check enabled.
+#include "nep_common.h"
+
+namespace nep {
+namespace {
+
+__global__ void k_reduce_partials(const double* __restrict__ partial, int nblocks, int first, int nvals,
+                                  double* __restrict__ out) {
+  __shared__ double sh[kBlock];
+  for (int k = 0; k < nvals; ++k) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) s += partial[(int64_t)b * kPartialStride + first + k];
+    __syncthreads();
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < (unsigned)off) sh[threadIdx.x] += sh[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = sh[0];
+  }
+}
+
+__device__ __forceinline__ double wrap_coord(double xv, double L) {
+  if (xv < 0.0) xv += L;
+  else if (xv >= L) xv -= L;
+  return xv;
+}
+
+// v += dt/2 F/(m xi); x += dt v; wrap; flag a rebuild when |x - x_build| > skin/2.
+__global__ void k_kick_drift(int64_t N, double dt, CellGrid g, const float* __restrict__ F,
+                             const int32_t* __restrict__ type, MassTable mt, double* __restrict__ x,
+                             double* __restrict__ v, const double* __restrict__ xb, double half_skin2,
+                             int32_t* __restrict__ flags) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const double inv = mt.inv_mxi[type[p]];
+  double d2 = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    double vv = v[c * N + p] + 0.5 * dt * (double)F[c * N + p] * inv;
+    double xx = wrap_coord(x[c * N + p] + dt * vv, g.box[c]);
+    v[c * N + p] = vv;
+    x[c * N + p] = xx;
+    const double d = min_image(xx - xb[c * N + p], g.box[c]);
+    d2 += d * d;
+  }
+  if (!(d2 <= half_skin2)) flags[FLAG_REBUILD] = 1;  // also catches NaN
+}
+
+__global__ void k_kick(int64_t N, double dt, const float* __restrict__ F, const int32_t* __restrict__ type,
+                       MassTable mt, double* __restrict__ v) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const double inv = mt.inv_mxi[type[p]];
+  for (int c = 0; c < 3; ++c) v[c * N + p] += 0.5 * dt * (double)F[c * N + p] * inv;
+}
+
+// v += dt (Fa - Fb)/(m xi)
+__global__ void k_kick_diff(int64_t N, double dt, const float* __restrict__ Fa, const float* __restrict__ Fb,
+                            const int32_t* __restrict__ type, MassTable mt, double* __restrict__ v) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const double inv = mt.inv_mxi[type[p]];
+  for (int c = 0; c < 3; ++c)
+    v[c * N + p] += dt * ((double)Fa[c * N + p] - (double)Fb[c * N + p]) * inv;
+}
+
+__device__ __forceinline__ void block_partial(double val, double* sh, double* out) {
+  __syncthreads();
+  sh[threadIdx.x] = val;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < (unsigned)off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+__global__ void k_kinetic(int64_t N, const double* __restrict__ v, const int32_t* __restrict__ type,
+                          MassTable mt, double* __restrict__ partial) {
+  __shared__ double sh[kBlock];
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double ke = 0.0;
+  if (p < N) {
+    const double m = mt.mass[type[p]];
+    for (int c = 0; c < 3; ++c) ke += v[c * N + p] * v[c * N + p];
+    ke *= 0.5 * m * 103.642697;
+  }
+  block_partial(ke, sh, partial + (int64_t)blockIdx.x * kPartialStride + P_KE);
+}
+
+__global__ void k_force_error(int64_t N, const float* __restrict__ Fa, const float* __restrict__ Fb,
+                              double* __restrict__ partial) {
+  __shared__ double sh[kBlock];
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double e2 = 0.0;
+  if (p < N) {
+    for (int c = 0; c < 3; ++c) {
+      const double d = (double)Fa[c * N + p] - (double)Fb[c * N + p];
+      e2 += d * d;
+    }
+  }
+  block_partial(e2, sh, partial + (int64_t)blockIdx.x * kPartialStride + P_ERR2);
+  // maximum |e| over the block
+  __syncthreads();
+  sh[threadIdx.x] = sqrt(e2);
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < (unsigned)off) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * kPartialStride + P_ERRMAX] = sh[0];
+}
+
+__global__ void k_max_partials(const double* __restrict__ partial, int nblocks, int slot,
+                               double* __restrict__ out) {
+  __shared__ double sh[kBlock];
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kBlock) m = fmax(m, partial[(int64_t)b * kPartialStride + slot]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < (unsigned)off) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+__global__ void k_set_flag(int32_t* flags, int idx, int value) {
+  if (threadIdx.x == 0) flags[idx] = value;
+}
+
+__global__ void k_state_in(int64_t N, const double* __restrict__ xa, const double* __restrict__ va,
+                           const int32_t* __restrict__ tin, int n_types, CellGrid g, double* __restrict__ x,
+                           double* __restrict__ v, int32_t* __restrict__ type, int32_t* __restrict__ perm,
+                           int32_t* __restrict__ flags) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  for (int c = 0; c < 3; ++c) {
+    double xv = xa[3 * p + c];
+    if (!isfinite(xv)) flags[FLAG_NONFINITE] = 1;
+    else if (xv < 0.0 || xv >= g.box[c]) {
+      xv = xv - g.box[c] * floor(xv / g.box[c]);
+      if (xv >= g.box[c]) xv -= g.box[c];
+    }
+    x[c * N + p] = xv;
+    const double vv = va ? va[3 * p + c] : 0.0;
+    if (!isfinite(vv)) flags[FLAG_NONFINITE] = 1;
+    v[c * N + p] = vv;
+  }
+  const int t = tin[p];
+  if (t < 0 || t >= n_types) flags[FLAG_TYPE] = 1;
+  type[p] = (t < 0 || t >= n_types) ? 0 : t;
+  perm[p] = (int32_t)p;
+}
+
+__global__ void k_state_out(int64_t N, const int32_t* __restrict__ perm, const double* __restrict__ soa,
+                            double* __restrict__ aos) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const int64_t o = perm[p];
+  for (int c = 0; c < 3; ++c) aos[3 * o + c] = soa[c * N + p];
+}
+
+__global__ void k_forces_out(int64_t N, const int32_t* __restrict__ perm, const float* __restrict__ F,
+                             double* __restrict__ aos) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const int64_t o = perm[p];
+  for (int c = 0; c < 3; ++c) aos[3 * o + c] = (double)F[c * N + p];
+}
+
+__global__ void k_scalar_out(int64_t N, const int32_t* __restrict__ perm, const float* __restrict__ U,
+                             double* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  out[perm[p]] = (double)U[p];
+}
+
+__global__ void k_gather_vec_f32(int64_t N, const int32_t* __restrict__ perm, const float* __restrict__ a,
+                                 float* __restrict__ s) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const int64_t o = perm[p];
+  for (int c = 0; c < 3; ++c) s[c * N + p] = a[3 * o + c];
+}
+
+__global__ void k_scatter_vec_f32(int64_t N, const int32_t* __restrict__ perm, const float* __restrict__ s,
+                                  float* __restrict__ a) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const int64_t o = perm[p];
+  for (int c = 0; c < 3; ++c) a[3 * o + c] = s[c * N + p];
+}
+
+}  // namespace
+
+hipError_t launch_reduce_partials(const double* partial, int nblocks, int first, int nvals, double* out,
+                                  hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, st, partial, nblocks, first, nvals, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_max_partials(const double* partial, int nblocks, int slot, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(kBlock), 0, st, partial, nblocks, slot, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_kick_drift(int64_t N, double dt, CellGrid g, const float* F, const int32_t* type,
+                             MassTable mt, double* x, double* v, const double* x_build, double half_skin2,
+                             int32_t* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_kick_drift, dim3(grid_blocks(N)), dim3(kBlock), 0, st, N, dt, g, F, type, mt, x, v,
+                     x_build, half_skin2, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_kick(int64_t N, double dt, const float* F, const int32_t* type, MassTable mt, double* v,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_kick, dim3(grid_blocks(N)), dim3(kBlock), 0, st, N, dt, F, type, mt, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_kick_diff(int64_t N, double dt, const float* Fa, const float* Fb, const int32_t* type,
+                            MassTable mt, double* v, hipStream_t st) {
+  hipLaunchKernelGGL(k_kick_diff, dim3(grid_blocks(N)), dim3(kBlock), 0, st, N, dt, Fa, Fb, type, mt, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_kinetic(int64_t N, const double* v, const int32_t* type, MassTable mt, double* partial,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_kinetic, dim3(grid_blocks(N)), dim3(kBlock), 0, st, N, v, type, mt, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_force_error(int64_t N, const float* Fa, const float* Fb, double* partial,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_force_error, dim3(grid_blocks(N)), dim3(kBlock), 0, st, N, Fa, Fb, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_flag(int32_t* flags, int idx, int value, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(64), 0, st, flags, idx, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_in(int64_t N, const double* x_aos, const double* v_aos, const int32_t* type_in,
+                           int n_types, CellGrid g, double* x, double* v, int32_t* type, int32_t* perm,
+                           int32_t* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_state_in, dim3(grid_blocks(N)), dim3(kBlock), 0, st, N, x_aos, v_aos, type_in,
+                     n_types, g, x, v, type, perm, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_out(int64_t N, const int32_t* perm, const double* soa, double* aos, hipStream_t st) {
+  hipLaunchKernelGGL(k_state_out, dim3(grid_blocks(N)), dim3(kBlock), 0, st, N, perm, soa, aos);
+  return hipGetLastError();
+}
+
+hipError_t launch_forces_out(int64_t N, const int32_t* perm, const float* F, double* aos, hipStream_t st) {
+  hipLaunchKernelGGL(k_forces_out, dim3(grid_blocks(N)), dim3(kBlock), 0, st, N, perm, F, aos);
+  return hipGetLastError();
+}
+
+hipError_t launch_scalar_out(int64_t N, const int32_t* perm, const float* U, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_scalar_out, dim3(grid_blocks(N)), dim3(kBlock), 0, st, N, perm, U, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_vec_f32(int64_t N, const int32_t* perm, const float* aos_orig, float* soa_sorted,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_vec_f32, dim3(grid_blocks(N)), dim3(kBlock), 0, st, N, perm, aos_orig,
+                     soa_sorted);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_vec_f32(int64_t N, const int32_t* perm, const float* soa_sorted, float* aos_orig,
+                                  hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter_vec_f32, dim3(grid_blocks(N)), dim3(kBlock), 0, st, N, perm, soa_sorted,
+                     aos_orig);
+  return hipGetLastError();
+}
+
+}  // namespace nep

@@ -1,0 +1,335 @@
+// Cell binning, stable sort of atoms by cell, and neighbour-list construction.
+//
+// Atoms are kept sorted by (cell, original id) so that the atoms one wavefront
+// handles, and their neighbours, are contiguous in HBM. Lists are stored
+// slot-major ([slot][N]) so that lane i of a wavefront reads the list entry of
+// atom i: consecutive lanes touch consecutive words.
+//
+// Pair membership is decided by r^2 < (cutoff + skin)^2 with FP64 minimum-image
+// differences and r^2 = (dx*dx + dy*dy) + dz*dz, evaluated without fused
+// multiply-add so that the set is reproducible bit for bit (Section VI.A
+// neighbour-list buffer; Fig. 1 radial and angular cutoffs).
+#include "nep_common.h"
+
+namespace nep {
+namespace {
+
+__global__ void k_zero_i32(int32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+__global__ void k_zero_f32(float* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+__global__ void k_zero_f64(double* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+__device__ __forceinline__ int cell_coord(double xv, double L, int n) {
+  int c = (int)(xv * ((double)n / L));
+  if (c < 0) c = 0;
+  if (c > n - 1) c = n - 1;
+  return c;
+}
+
+__global__ void k_bin(int64_t N, CellGrid g, const double* __restrict__ x, int32_t* __restrict__ cellid,
+                      int32_t* __restrict__ count, const int32_t* __restrict__ flags) {
+  if (flags[FLAG_REBUILD] == 0) return;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const int cx = cell_coord(x[p], g.box[0], g.nc[0]);
+  const int cy = cell_coord(x[N + p], g.box[1], g.nc[1]);
+  const int cz = cell_coord(x[2 * N + p], g.box[2], g.nc[2]);
+  const int c = (cz * g.nc[1] + cy) * g.nc[0] + cx;
+  cellid[p] = c;
+  atomicAdd(&count[c], 1);
+}
+
+// Exclusive scan, phase 1: each 256-thread block scans 1024 elements.
+constexpr int kScanPer = 4;
+constexpr int kScanTile = kBlock * kScanPer;
+
+__global__ void k_scan_tiles(const int32_t* __restrict__ in, int32_t* __restrict__ out, int n,
+                             int32_t* __restrict__ tile_sums, const int32_t* __restrict__ flags) {
+  if (flags[FLAG_REBUILD] == 0) return;
+  __shared__ int32_t s[kBlock];
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+  int32_t v[kScanPer];
+  int32_t sum = 0;
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0;
+    sum += v[k];
+  }
+  s[threadIdx.x] = sum;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    int32_t t = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0;
+    __syncthreads();
+    s[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int32_t run = s[threadIdx.x] - sum;  // exclusive prefix of this thread
+  for (int k = 0; k < kScanPer; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == kBlock - 1) tile_sums[blockIdx.x] = s[kBlock - 1];
+}
+
+// Phase 2: one block scans the tile sums (any count) in chunks, exclusive.
+__global__ void k_scan_sums(int32_t* __restrict__ sums, int nt, int32_t* __restrict__ total,
+                            const int32_t* __restrict__ flags) {
+  if (flags[FLAG_REBUILD] == 0) return;
+  __shared__ int32_t s[kBlock];
+  int32_t carry = 0;
+  for (int base = 0; base < nt; base += kBlock) {
+    const int i = base + threadIdx.x;
+    const int32_t v = (i < nt) ? sums[i] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+      int32_t t = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0;
+      __syncthreads();
+      s[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < nt) sums[i] = carry + s[threadIdx.x] - v;
+    const int32_t chunk = s[kBlock - 1];
+    __syncthreads();
+    carry += chunk;
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void k_scan_add(int32_t* __restrict__ out, int n, const int32_t* __restrict__ sums,
+                           const int32_t* __restrict__ flags) {
+  if (flags[FLAG_REBUILD] == 0) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] += sums[i / kScanTile];
+}
+
+__global__ void k_scatter(int64_t N, const int32_t* __restrict__ cellid, const int32_t* __restrict__ start,
+                          int32_t* __restrict__ fill, const int32_t* __restrict__ perm,
+                          int32_t* __restrict__ src, int32_t* __restrict__ key,
+                          const int32_t* __restrict__ flags) {
+  if (flags[FLAG_REBUILD] == 0) return;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const int c = cellid[p];
+  const int pos = start[c] + atomicAdd(&fill[c], 1);
+  src[pos] = (int32_t)p;
+  key[pos] = perm[p];
+}
+
+// Within each cell, order atoms by original id (insertion sort; cells hold tens of atoms).
+__global__ void k_cell_sort(int ncell, const int32_t* __restrict__ start, int32_t* __restrict__ key,
+                            int32_t* __restrict__ src, const int32_t* __restrict__ flags) {
+  if (flags[FLAG_REBUILD] == 0) return;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const int a = start[c], b = start[c + 1];
+  for (int i = a + 1; i < b; ++i) {
+    const int32_t k = key[i], s = src[i];
+    int j = i - 1;
+    while (j >= a && key[j] > k) {
+      key[j + 1] = key[j];
+      src[j + 1] = src[j];
+      --j;
+    }
+    key[j + 1] = k;
+    src[j + 1] = s;
+  }
+}
+
+__global__ void k_permute(int64_t N, const int32_t* __restrict__ src, const int32_t* __restrict__ cellid,
+                          const double* __restrict__ x, const double* __restrict__ v,
+                          const int32_t* __restrict__ type, const int32_t* __restrict__ perm,
+                          double* __restrict__ x2, double* __restrict__ v2, int32_t* __restrict__ type2,
+                          int32_t* __restrict__ perm2, double* __restrict__ xb,
+                          int32_t* __restrict__ cell_sorted, const int32_t* __restrict__ flags) {
+  if (flags[FLAG_REBUILD] == 0) return;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const int64_t s = src[p];
+  for (int c = 0; c < 3; ++c) {
+    const double xv = x[c * N + s];
+    x2[c * N + p] = xv;
+    xb[c * N + p] = xv;
+    v2[c * N + p] = v[c * N + s];
+  }
+  type2[p] = type[s];
+  perm2[p] = perm[s];
+  cell_sorted[p] = cellid[s];
+}
+
+// Copy the permuted arrays back to the primary buffers.
+__global__ void k_copy_back(int64_t N, const double* __restrict__ x2, const double* __restrict__ v2,
+                            const int32_t* __restrict__ type2, const int32_t* __restrict__ perm2,
+                            double* __restrict__ x, double* __restrict__ v, int32_t* __restrict__ type,
+                            int32_t* __restrict__ perm, const int32_t* __restrict__ flags) {
+  if (flags[FLAG_REBUILD] == 0) return;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  for (int c = 0; c < 3; ++c) {
+    x[c * N + p] = x2[c * N + p];
+    v[c * N + p] = v2[c * N + p];
+  }
+  type[p] = type2[p];
+  perm[p] = perm2[p];
+}
+
+// r^2 of the FP64 minimum-image pair vector, with no contraction into FMA so that
+// the result equals (dx*dx + dy*dy) + dz*dz rounded after every operation.
+__device__ __attribute__((noinline)) double pair_r2_exact(double xi, double yi, double zi, double xj,
+                                                          double yj, double zj, double Lx, double Ly,
+                                                          double Lz) {
+#pragma clang fp contract(off)
+  const double dx = min_image(xj - xi, Lx);
+  const double dy = min_image(yj - yi, Ly);
+  const double dz = min_image(zj - zi, Lz);
+  const double sxx = dx * dx;
+  const double syy = dy * dy;
+  const double szz = dz * dz;
+  const double s = sxx + syy;
+  return s + szz;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t* __restrict__ start,
+              const int32_t* __restrict__ cell_sorted, double cutR2, double cutA2, int capR, int capA,
+              int32_t* __restrict__ nbrR, int32_t* __restrict__ cntR, int32_t* __restrict__ nbrA,
+              int32_t* __restrict__ cntA, int32_t* __restrict__ flags) {
+  if (flags[FLAG_REBUILD] == 0) return;
+  const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const double xi = x[p], yi = x[N + p], zi = x[2 * N + p];
+  const int c = cell_sorted[p];
+  const int cx = c % g.nc[0];
+  const int cy = (c / g.nc[0]) % g.nc[1];
+  const int cz = c / (g.nc[0] * g.nc[1]);
+  int lo[3], nof[3];
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = g.nc[d] >= 3 ? -1 : 0;
+    nof[d] = g.nc[d] >= 3 ? 3 : g.nc[d];
+  }
+  int nr = 0, na = 0;
+  for (int a = 0; a < nof[2]; ++a) {
+    const int zc = (cz + lo[2] + a + g.nc[2]) % g.nc[2];
+    for (int b = 0; b < nof[1]; ++b) {
+      const int yc = (cy + lo[1] + b + g.nc[1]) % g.nc[1];
+      for (int e = 0; e < nof[0]; ++e) {
+        const int xc = (cx + lo[0] + e + g.nc[0]) % g.nc[0];
+        const int cc = (zc * g.nc[1] + yc) * g.nc[0] + xc;
+        const int q0 = start[cc], q1 = start[cc + 1];
+        for (int q = q0; q < q1; ++q) {
+          if (q == p) continue;
+          const double r2 = pair_r2_exact(xi, yi, zi, x[q], x[N + q], x[2 * N + q], g.box[0],
+                                          g.box[1], g.box[2]);
+          if (r2 < cutR2) {
+            if (nr < capR) nbrR[(int64_t)nr * N + p] = q;
+            ++nr;
+            if (r2 < cutA2) {
+              if (na < capA) nbrA[(int64_t)na * N + p] = q;
+              ++na;
+            }
+          }
+        }
+      }
+    }
+  }
+  cntR[p] = nr < capR ? nr : capR;
+  cntA[p] = na < capA ? na : capA;
+  if (nr > capR) atomicMax(&flags[FLAG_OVF_R], nr);
+  if (na > capA) atomicMax(&flags[FLAG_OVF_A], na);
+}
+
+__global__ void k_count_build(int32_t* flags) {
+  if (flags[FLAG_REBUILD] != 0 && threadIdx.x == 0) flags[FLAG_NBUILD] += 1;
+}
+
+// Lists in original ids, one row per original atom, ascending.
+__global__ void k_export(int64_t N, const int32_t* __restrict__ perm, const int32_t* __restrict__ nbr,
+                         const int32_t* __restrict__ cnt, int cap, int32_t* __restrict__ rows,
+                         int32_t* __restrict__ row_cnt) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  const int64_t o = perm[p];
+  const int n = cnt[p];
+  int32_t* row = rows + o * cap;
+  for (int k = 0; k < n; ++k) {
+    const int32_t val = perm[nbr[(int64_t)k * N + p]];
+    int j = k - 1;
+    while (j >= 0 && row[j] > val) {
+      row[j + 1] = row[j];
+      --j;
+    }
+    row[j + 1] = val;
+  }
+  row_cnt[o] = n;
+}
+
+}  // namespace
+
+hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_i32, dim3(grid_blocks(n)), dim3(kBlock), 0, st, p, n);
+  return hipGetLastError();
+}
+hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_f32, dim3(grid_blocks(n)), dim3(kBlock), 0, st, p, n);
+  return hipGetLastError();
+}
+hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_f64, dim3(grid_blocks(n)), dim3(kBlock), 0, st, p, n);
+  return hipGetLastError();
+}
+
+// Every kernel below returns at once when flags[FLAG_REBUILD] == 0, so the whole
+// rebuild can be enqueued each step and skipped on the device without a host sync.
+hipError_t launch_rebuild(int64_t N, const CellGrid& g, double cutR, double cutA, int capR, int capA,
+                          double* x, double* v, int32_t* type, int32_t* perm, double* x_alt,
+                          double* v_alt, int32_t* type_alt, int32_t* perm_alt, double* x_build,
+                          int32_t* cellid, int32_t* cell_sorted, int32_t* src, int32_t* key,
+                          int32_t* cell_count, int32_t* cell_start, int32_t* cell_fill,
+                          int32_t* scan_tmp, int32_t* nbrR, int32_t* cntR, int32_t* nbrA,
+                          int32_t* cntA, int32_t* flags, hipStream_t st) {
+  const int nb = grid_blocks(N);
+  const int ncell = g.ncell;
+  hipError_t e;
+  if ((e = launch_zero_i32(cell_count, ncell, st)) != hipSuccess) return e;
+  if ((e = launch_zero_i32(cell_fill, ncell, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bin, dim3(nb), dim3(kBlock), 0, st, N, g, x, cellid, cell_count, flags);
+  const int ntiles = (ncell + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kBlock), 0, st, cell_count, cell_start, ncell,
+                     scan_tmp, flags);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, st, scan_tmp, ntiles, cell_start + ncell,
+                     flags);
+  hipLaunchKernelGGL(k_scan_add, dim3(grid_blocks(ncell)), dim3(kBlock), 0, st, cell_start, ncell,
+                     scan_tmp, flags);
+  hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, st, N, cellid, cell_start, cell_fill, perm,
+                     src, key, flags);
+  hipLaunchKernelGGL(k_cell_sort, dim3(grid_blocks(ncell)), dim3(kBlock), 0, st, ncell, cell_start,
+                     key, src, flags);
+  hipLaunchKernelGGL(k_permute, dim3(nb), dim3(kBlock), 0, st, N, src, cellid, x, v, type, perm,
+                     x_alt, v_alt, type_alt, perm_alt, x_build, cell_sorted, flags);
+  hipLaunchKernelGGL(k_copy_back, dim3(nb), dim3(kBlock), 0, st, N, x_alt, v_alt, type_alt, perm_alt,
+                     x, v, type, perm, flags);
+  const double cr2 = cutR * cutR, ca2 = cutA * cutA;
+  hipLaunchKernelGGL(k_build_lists, dim3(nb), dim3(kBlock), 0, st, N, g, x, cell_start, cell_sorted,
+                     cr2, ca2, capR, capA, nbrR, cntR, nbrA, cntA, flags);
+  hipLaunchKernelGGL(k_count_build, dim3(1), dim3(64), 0, st, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_export(int64_t N, const int32_t* perm, const int32_t* nbr, const int32_t* cnt,
+                         int cap, int32_t* rows, int32_t* row_cnt, hipStream_t st) {
+  hipLaunchKernelGGL(k_export, dim3(grid_blocks(N)), dim3(kBlock), 0, st, N, perm, nbr, cnt, cap,
+                     rows, row_cnt);
+  return hipGetLastError();
+}
+
+}  // namespace nep

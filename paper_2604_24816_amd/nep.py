@@ -1,0 +1,284 @@
+"""Python binding of the NEP C-ABI library (``libnep.so``, declared in ``include/nep.h``).
+
+Argument marshalling only: every step of the evaluation and of the integrator
+runs in the HIP kernels of the library. PyTorch provides device memory (the
+workspace and device-side arrays) and the HIP stream. There is no fallback:
+if the library is missing or no GPU is present, these classes raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import inputs
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnep.so")
+
+NEP_FP32 = 0
+NEP_BF16 = 1
+_PREC = {"fp32": NEP_FP32, "bf16": NEP_BF16, NEP_FP32: NEP_FP32, NEP_BF16: NEP_BF16}
+
+EXPORTED = [
+    "nep_param_count", "nep_model_create", "nep_model_destroy", "nep_system_workspace_bytes",
+    "nep_system_create", "nep_system_destroy", "nep_system_set_params", "nep_set_state",
+    "nep_build_neighbors", "nep_export_neighbors", "nep_compute_energy_forces_virial", "nep_step",
+    "nep_get_state", "nep_get_stats", "nep_train_forward", "nep_train_backward", "nep_adam_update",
+    "nep_surrogate_error", "nep_status_string", "nep_last_error",
+]
+
+
+class NEPError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"NEP status {status}: {message}")
+        self.status = status
+
+
+class _HParams(ctypes.Structure):
+    _fields_ = [("n_types", ctypes.c_int32), ("n_max_radial", ctypes.c_int32),
+                ("n_max_angular", ctypes.c_int32), ("basis_radial", ctypes.c_int32),
+                ("basis_angular", ctypes.c_int32), ("l_max_3b", ctypes.c_int32),
+                ("l_max_4b", ctypes.c_int32), ("n_hidden", ctypes.c_int32),
+                ("rc_radial", ctypes.c_double), ("rc_angular", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libnep.so (built in-tree by ``__graft_entry__.build()``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "nep_param_count": [vp, vp, vp],
+        "nep_model_create": [vp, vp, i64, vp],
+        "nep_system_workspace_bytes": [vp, vp, i64, vp, i32, i32, vp],
+        "nep_system_create": [vp, vp, i64, vp, i32, i32, vp, i64, vp, vp],
+        "nep_system_set_params": [vp, i32, vp, i64],
+        "nep_set_state": [vp, vp, vp, vp, vp, i32],
+        "nep_build_neighbors": [vp, f64],
+        "nep_export_neighbors": [vp, i32, vp, vp, i64],
+        "nep_compute_energy_forces_virial": [vp, i32, i32, vp, vp, vp, vp, i32],
+        "nep_step": [vp, i64, f64, i32, f64, i32, f64, f64, i32, vp, i32, i64, vp],
+        "nep_get_state": [vp, vp, vp, vp, i32],
+        "nep_get_stats": [vp, vp],
+        "nep_train_forward": [vp, i32, vp, vp, vp],
+        "nep_train_backward": [vp, i32, vp, f64, vp, vp],
+        "nep_adam_update": [vp, vp, vp, vp, vp, i64, i64, f64, f64, f64, f64],
+        "nep_surrogate_error": [vp, i32, vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.nep_model_destroy.argtypes = [vp]
+    lib.nep_model_destroy.restype = None
+    lib.nep_system_destroy.argtypes = [vp]
+    lib.nep_system_destroy.restype = None
+    lib.nep_status_string.argtypes = [ctypes.c_int]
+    lib.nep_status_string.restype = ctypes.c_char_p
+    lib.nep_last_error.argtypes = [vp]
+    lib.nep_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _hp_struct(hp: inputs.HParams) -> _HParams:
+    return _HParams(hp.n_types, hp.n_max_radial, hp.n_max_angular, hp.basis_radial, hp.basis_angular,
+                    hp.l_max_3b, hp.l_max_4b, hp.n_hidden, hp.rc_radial, hp.rc_angular)
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _t_ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class NEPModel:
+    """Host-side model handle (hyperparameters + packed FP64 parameters)."""
+
+    def __init__(self, hp: inputs.HParams, params: np.ndarray):
+        lib = load_library()
+        self.hp = hp
+        self.params = np.ascontiguousarray(params, dtype=np.float64)
+        self._hps = _hp_struct(hp)
+        h = ctypes.c_void_p()
+        st = lib.nep_model_create(ctypes.byref(self._hps), _np_ptr(self.params),
+                                  self.params.size, ctypes.byref(h))
+        if st != 0:
+            raise NEPError(st, lib.nep_status_string(st).decode())
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.nep_model_destroy(self.handle)
+            self.handle = None
+
+
+class NEPSystem:
+    """One periodic system on one GPU: workspace, state, neighbour lists, models."""
+
+    def __init__(self, full: NEPModel, n_atoms: int, box, surrogate: Optional[NEPModel] = None,
+                 cap_radial: int = 160, cap_angular: int = 96, device: str = "cuda:0",
+                 stream: Optional[torch.cuda.Stream] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("NEPSystem needs a HIP GPU; none is visible")
+        self.lib = load_library()
+        self.device = torch.device(device)
+        self.full = full
+        self.surrogate = surrogate
+        self.n = int(n_atoms)
+        self.box = np.ascontiguousarray(box, dtype=np.float64)
+        self.cap_radial, self.cap_angular = cap_radial, cap_angular
+        torch.cuda.set_device(self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nb = ctypes.c_int64()
+        self._check(self.lib.nep_system_workspace_bytes(
+            full.handle, surrogate.handle if surrogate else None, self.n, _np_ptr(self.box),
+            cap_radial, cap_angular, ctypes.byref(nb)), None)
+        self.workspace_bytes = nb.value
+        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        self._check(self.lib.nep_system_create(
+            full.handle, surrogate.handle if surrogate else None, self.n, _np_ptr(self.box),
+            cap_radial, cap_angular, _t_ptr(self.workspace), nb.value,
+            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), None)
+        self.handle = h
+
+    def _check(self, st, handle="self"):
+        if st != 0:
+            h = self.handle if handle == "self" else None
+            msg = self.lib.nep_last_error(h).decode() if h else ""
+            raise NEPError(st, f"{self.lib.nep_status_string(st).decode()}: {msg}")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.nep_system_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+    # ------------------------------------------------------------------ state
+    def set_params(self, slot: int, params: np.ndarray):
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        self._check(self.lib.nep_system_set_params(self.handle, slot, _np_ptr(p), p.size))
+
+    def set_state(self, x, types, masses, v=None):
+        masses = np.ascontiguousarray(masses, dtype=np.float64)
+        if isinstance(x, torch.Tensor):
+            xt = x.to(self.device, torch.float64).contiguous()
+            tt = torch.as_tensor(types, device=self.device, dtype=torch.int32).contiguous()
+            vt = None if v is None else v.to(self.device, torch.float64).contiguous()
+            self._check(self.lib.nep_set_state(self.handle, _t_ptr(xt), _t_ptr(vt) if vt is not None else None,
+                                               _t_ptr(tt), _np_ptr(masses), 1))
+            torch.cuda.synchronize(self.device)
+            return
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        t = np.ascontiguousarray(types, dtype=np.int32)
+        vv = None if v is None else np.ascontiguousarray(v, dtype=np.float64)
+        assert x.shape == (self.n, 3) and t.shape == (self.n,)
+        self._check(self.lib.nep_set_state(self.handle, _np_ptr(x), _np_ptr(vv) if vv is not None else None,
+                                           _np_ptr(t), _np_ptr(masses), 0))
+
+    def get_state(self):
+        x = np.zeros((self.n, 3))
+        v = np.zeros((self.n, 3))
+        step = ctypes.c_int64()
+        self._check(self.lib.nep_get_state(self.handle, _np_ptr(x), _np_ptr(v), ctypes.byref(step), 0))
+        return x, v, step.value
+
+    def build_neighbors(self, skin: float = 1.0):
+        self._check(self.lib.nep_build_neighbors(self.handle, float(skin)))
+
+    def export_neighbors(self, which: int = 0):
+        cap = self.cap_radial if which == 0 else self.cap_angular
+        offsets = np.zeros(self.n + 1, np.int64)
+        idx = np.zeros(self.n * cap, np.int32)
+        self._check(self.lib.nep_export_neighbors(self.handle, which, _np_ptr(offsets), _np_ptr(idx),
+                                                  idx.size))
+        return offsets, idx[: offsets[-1]].copy()
+
+    # ------------------------------------------------------------------ evaluation
+    def compute(self, slot: int = 0, precision="fp32", forces: bool = True, per_atom: bool = False,
+                on_device: bool = False):
+        """(E, W[3][3], F[N][3] or None, U[N] or None), FP64, original atom order."""
+        E = ctypes.c_double()
+        W = np.zeros(9)
+        if on_device:
+            F = torch.empty((self.n, 3), dtype=torch.float64, device=self.device) if forces else None
+            U = torch.empty(self.n, dtype=torch.float64, device=self.device) if per_atom else None
+            fp = _t_ptr(F) if F is not None else None
+            up = _t_ptr(U) if U is not None else None
+        else:
+            F = np.zeros((self.n, 3)) if forces else None
+            U = np.zeros(self.n) if per_atom else None
+            fp = _np_ptr(F) if F is not None else None
+            up = _np_ptr(U) if U is not None else None
+        self._check(self.lib.nep_compute_energy_forces_virial(
+            self.handle, slot, _PREC[precision], ctypes.byref(E), _np_ptr(W), fp, up, 1 if on_device else 0))
+        return E.value, W.reshape(3, 3), F, U
+
+    def step(self, n_steps: int, dt: float = 1.0, rebuild_every: int = 10, skin: float = 1.0,
+             mts_k: int = 0, fallback_rms: float = 0.05, fallback_max: float = 1.0, precision="fp32",
+             thermo_every: int = 0, max_rows: int = 4096):
+        """Advance n_steps; returns thermo rows [k][8] (step, PE, KE, T, P, err_rms, err_max, fallback)."""
+        rows = ctypes.c_int64()
+        th = np.zeros((max_rows, 8)) if thermo_every > 0 else None
+        self._check(self.lib.nep_step(self.handle, int(n_steps), float(dt), int(rebuild_every), float(skin),
+                                      int(mts_k), float(fallback_rms), float(fallback_max), _PREC[precision],
+                                      _np_ptr(th) if th is not None else None, int(max(thermo_every, 1)),
+                                      int(max_rows), ctypes.byref(rows)))
+        return th[: rows.value].copy() if th is not None else None
+
+    def stats(self) -> dict:
+        s = np.zeros(4, np.int64)
+        self._check(self.lib.nep_get_stats(self.handle, _np_ptr(s)))
+        return {"list_builds": int(s[0]), "mts_blocks": int(s[1]), "fallback_blocks": int(s[2]),
+                "steps": int(s[3])}
+
+    def surrogate_error(self, precision="fp32"):
+        e = np.zeros(2)
+        self._check(self.lib.nep_surrogate_error(self.handle, _PREC[precision], _np_ptr(e)))
+        return float(e[0]), float(e[1])
+
+    # ------------------------------------------------------------------ training
+    def train_forward(self, slot: int, theta: torch.Tensor):
+        """(E float, F torch [N][3] float32) with network parameters theta (device FP32)."""
+        theta = theta.detach().to(self.device, torch.float32).contiguous()
+        F = torch.empty((self.n, 3), dtype=torch.float32, device=self.device)
+        E = ctypes.c_double()
+        self._check(self.lib.nep_train_forward(self.handle, slot, _t_ptr(theta), ctypes.byref(E), _t_ptr(F)))
+        return E.value, F
+
+    def train_backward(self, slot: int, theta: torch.Tensor, gE: float, gF: Optional[torch.Tensor]):
+        theta = theta.detach().to(self.device, torch.float32).contiguous()
+        grad = torch.empty_like(theta)
+        gFc = None if gF is None else gF.detach().to(self.device, torch.float32).contiguous()
+        self._check(self.lib.nep_train_backward(self.handle, slot, _t_ptr(theta), float(gE),
+                                                _t_ptr(gFc) if gFc is not None else None, _t_ptr(grad)))
+        return grad
+
+    def adam(self, theta: torch.Tensor, grad: torch.Tensor, m1: torch.Tensor, m2: torch.Tensor, t: int,
+             lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        for a in (theta, grad, m1, m2):
+            assert a.dtype == torch.float32 and a.is_contiguous() and a.device == self.device
+        self._check(self.lib.nep_adam_update(self.handle, _t_ptr(theta), _t_ptr(grad), _t_ptr(m1), _t_ptr(m2),
+                                             theta.numel(), int(t), lr, beta1, beta2, eps))
+
+
+def network_params(hp: inputs.HParams, params: np.ndarray) -> np.ndarray:
+    """The network block (W0, b0, w1, b1) of a packed parameter vector, as one array."""
+    b = inputs.unpack(hp, params)
+    return np.concatenate([b["W0"], b["b0"], b["w1"], b["b1"]])

@@ -1,0 +1,205 @@
+"""Parity of the HIP path (through the C-ABI) against the FP64 oracle.
+
+Bars: neighbour lists bit-exact as sorted index sets; FP32 energies within
+1e-6 eV per atom (max over atoms and total / N), forces within 1e-4 eV/A,
+virial within 1e-6 eV per atom per component; bfloat16 network against the
+oracle's bfloat16 model within the FP32-accumulation slack derived in the design doc.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_24816_amd import inputs as I
+from tests.gpu_helpers import lists_equal, make_system, min_image_diff, say
+
+pytestmark = pytest.mark.gpu
+
+E_ATOM_TOL = 1e-6    # eV per atom
+F_TOL = 1e-4         # eV / A
+W_ATOM_TOL = 1e-6    # eV per atom, per virial component
+
+
+@pytest.fixture(scope="module")
+def full():
+    hp = I.FULL_HPARAMS
+    params = I.random_model(hp, 0)
+    return hp, params, oracle.Model.from_hparams(hp, params)
+
+
+def _check_efw(s, m, at, precision="fp32", bf16_oracle=False, e_tol=E_ATOM_TOL, f_tol=F_TOL):
+    E, W, F, U = s.compute(precision=precision, per_atom=True)
+    Eo, Wo, Uo, Fo = oracle.evaluate(m, at.x, at.types, at.box, bf16=bf16_oracle)
+    du = np.abs(U - Uo).max()
+    de = abs(E - Eo) / at.n
+    df = np.abs(F - Fo).max()
+    dw = np.abs(W - Wo).max() / at.n
+    say(f"  N={at.n} {precision}: max|dU|={du:.2e} |dE|/N={de:.2e} max|dF|={df:.2e} max|dW|/N={dw:.2e}")
+    assert du < e_tol and de < e_tol, (du, de)
+    assert df < f_tol, df
+    assert dw < W_ATOM_TOL, dw
+    return E, W, F, U
+
+
+def test_mfma_network_and_forces_small_box(full):
+    hp, params, m = full
+    at = I.fcc_box(4, 0.1, 5)
+    say("case: FCC 4^3 cells, fp32, full model")
+    s = make_system(at, hp, params)
+    _check_efw(s, m, at)
+
+
+def test_neighbor_lists_bit_exact_4000_atoms(full):
+    hp, params, m = full
+    at = I.workload_small()
+    say("case: lists, FCC 10^3 cells, skin 1.0")
+    s = make_system(at, hp, params)
+    for which, cut in [(0, hp.rc_radial + 1.0), (1, hp.rc_angular + 1.0)]:
+        off, idx = s.export_neighbors(which)
+        cnt, oidx = oracle.neighbors(at.x, at.box, cut, cap=200)
+        ok, msg = lists_equal(off, idx, cnt, oidx)
+        assert ok, (which, msg)
+
+
+@pytest.mark.parametrize("box,n,seed", [((14.5, 14.5, 14.5), 300, 1), ((14.2, 21.7, 30.1), 700, 2),
+                                        ((28.3, 14.1, 15.2), 520, 3)])
+def test_neighbor_lists_bit_exact_random_tiny_boxes(full, box, n, seed):
+    hp, params, m = full
+    rng = np.random.default_rng(seed)
+    box = np.array(box)
+    x = I.wrap(rng.uniform(0, 1, size=(n, 3)) * box, box)
+    at = I.Atoms(x=x, types=np.zeros(n, np.int32), box=box, masses=np.array([63.546]))
+    say(f"case: lists, random box {box} n={n}")
+    s = make_system(at, hp, params, cap_radial=256, cap_angular=200)
+    for which, cut in [(0, 7.0), (1, 6.0)]:
+        off, idx = s.export_neighbors(which)
+        cnt, oidx = oracle.neighbors(x, box, cut, cap=300)
+        ok, msg = lists_equal(off, idx, cnt, oidx)
+        assert ok, (which, msg)
+
+
+def test_energy_forces_virial_4000_atoms(full):
+    hp, params, m = full
+    at = I.workload_small()
+    say("case: E/F/W, FCC 10^3 cells (4000 atoms), fp32")
+    s = make_system(at, hp, params)
+    _check_efw(s, m, at)
+
+
+def test_two_species_alloy_with_vacancies():
+    hp = I.HParams(n_types=2)
+    params = I.random_model(hp, 7)
+    m = oracle.Model.from_hparams(hp, params)
+    at = I.alloy_box(8, 31, 102, 32, 0.05, 33)
+    say(f"case: two-species alloy 8^3 cells with vacancies (N={at.n}), fp32")
+    s = make_system(at, hp, params)
+    _check_efw(s, m, at)
+    off, idx = s.export_neighbors(1)
+    cnt, oidx = oracle.neighbors(at.x, at.box, hp.rc_angular + 1.0, cap=200)
+    ok, msg = lists_equal(off, idx, cnt, oidx)
+    assert ok, msg
+
+
+def test_surrogate_shape(full):
+    hp, params, m = full
+    shp = I.SURROGATE_HPARAMS
+    sp = I.surrogate_from_teacher(hp, params, shp, 1)
+    ms = oracle.Model.from_hparams(shp, sp)
+    at = I.fcc_box(5, 0.12, 9)
+    say("case: surrogate (hidden 8, l_max 2, no four-body), fp32")
+    s = make_system(at, hp, params, shp, sp)
+    E, W, F, U = s.compute(slot=1, per_atom=True)
+    Eo, Wo, Uo, Fo = oracle.evaluate(ms, at.x, at.types, at.box)
+    assert np.abs(U - Uo).max() < E_ATOM_TOL and np.abs(F - Fo).max() < F_TOL
+    assert np.abs(W - Wo).max() / at.n < W_ATOM_TOL
+
+
+def test_bf16_network_against_oracle_bf16_model(full):
+    """BF16 MFMA network: against the oracle's bfloat16 model (same rounding points).
+
+    Both sides round q~ and w1*(1 - tanh^2) to bfloat16, the GPU from FP32 values and
+    the oracle from FP64 values, so an element sitting within FP32 error of a rounding
+    boundary can round differently; such flips move U_i by at most one bfloat16 step of
+    one product. The bar: mean |dU| and |dE|/N at FP32 level, and every atom within
+    the one-flip bound.
+    """
+    hp, params, m = full
+    at = I.workload_small()
+    say("case: bf16 network, 4000 atoms")
+    s = make_system(at, hp, params)
+    E, W, F, U = s.compute(precision="bf16", per_atom=True)
+    Eb, Wb, Ub, Fb = oracle.evaluate(m, at.x, at.types, at.box, bf16=True)
+    E64, W64, U64, F64 = oracle.evaluate(m, at.x, at.types, at.box)
+    du = np.abs(U - Ub)
+    dF = np.abs(F - Fb)
+    say(f"  vs bf16 model: max|dU|={du.max():.2e} mean|dU|={du.mean():.2e} max|dF|={dF.max():.2e}")
+    say(f"  vs FP64: max|dU|={np.abs(U - U64).max():.2e} |dE|/N={abs(E - E64) / at.n:.2e} "
+        f"max|dF|={np.abs(F - F64).max():.2e} rms dF={np.sqrt(np.mean((F - F64) ** 2)):.2e}")
+    assert du.mean() < 2e-6 and abs(E - Eb) / at.n < 2e-6
+    assert du.max() < 5e-4 and dF.max() < 5e-3
+    # and the bf16 form is a bf16-sized approximation of FP64
+    assert np.abs(U - U64).max() < 5e-2
+
+
+def test_md_ten_steps_against_oracle_velocity_verlet(full):
+    hp, params, m = full
+    at = I.workload_small()
+    say("case: 10 velocity-Verlet steps, 4000 atoms, dt 1 fs, rebuild every 10, skin 1")
+    s = make_system(at, hp, params)
+    th = s.step(10, dt=1.0, rebuild_every=10, skin=1.0, thermo_every=5)
+    x, v, step = s.get_state()
+    xo, vo, tho = oracle.velocity_verlet(m, at.x, at.v, at.types, at.masses, at.box, 1.0, 10)
+    dx = np.abs(min_image_diff(x, xo, at.box)).max()
+    dv = np.abs(v - vo).max()
+    say(f"  max|dx|={dx:.2e} A max|dv|={dv:.2e} A/fs rows={th.shape[0]}")
+    assert step == 10
+    assert dx < 1e-6 and dv < 1e-7
+    assert th.shape[0] == 2 and th[-1, 0] == 10
+    assert abs(th[-1, 1] - tho[10, 0]) / at.n < E_ATOM_TOL
+    assert abs(th[-1, 2] - tho[10, 1]) / at.n < 1e-9
+    assert abs(th[-1, 3] - tho[10, 2]) < 1e-6
+    st = s.stats()
+    assert st["list_builds"] == 2 and st["steps"] == 10
+
+
+def test_early_rebuild_when_an_atom_moves_more_than_half_skin(full):
+    hp, params, m = full
+    at = I.fcc_box(5, 0.05, 41)
+    at.v = I.maxwell_boltzmann(at, 300.0, 42)
+    at.v[17] = [0.31, 0.0, 0.0]  # 0.31 A/fs: more than skin/2 = 0.3 A in the first step
+    say("case: early rebuild (one fast atom), 500 atoms")
+    s = make_system(at, hp, params, skin=0.6)
+    s.step(3, dt=1.0, rebuild_every=100, skin=0.6)
+    st = s.stats()
+    assert st["list_builds"] >= 2
+    x, v, _ = s.get_state()
+    xo, vo, _ = oracle.velocity_verlet(m, at.x, at.v, at.types, at.masses, at.box, 1.0, 3)
+    assert np.abs(min_image_diff(x, xo, at.box)).max() < 1e-6
+
+
+def test_error_paths(full):
+    from paper_2604_24816_amd import nep
+    hp, params, m = full
+    at = I.fcc_box(4, 0.05, 1)
+    say("case: error paths")
+    s = make_system(at, hp, params, build=False)
+    with pytest.raises(nep.NEPError) as e:
+        s.compute()
+    assert e.value.status == -8  # stale list
+    s2 = make_system(at, hp, params, cap_radial=8, build=False)
+    with pytest.raises(nep.NEPError) as e:
+        s2.build_neighbors(1.0)
+    assert e.value.status == -3 and "capacity" in str(e.value)
+    x = at.x.copy()
+    x[3, 1] = np.nan
+    with pytest.raises(nep.NEPError) as e:
+        s.set_state(x, at.types, at.masses)
+    assert e.value.status == -5
+    t = at.types.copy()
+    t[5] = 3
+    with pytest.raises(nep.NEPError) as e:
+        s.set_state(at.x, t, at.masses)
+    assert e.value.status == -4
+    s.set_state(at.x, at.types, at.masses)
+    with pytest.raises(nep.NEPError) as e:
+        s.build_neighbors(2.0)  # 14.46 A box < 2 (6 + 2)
+    assert e.value.status == -2
