@@ -1,0 +1,147 @@
+"""Benchmark of the NEP molecular-dynamics step on one MI355X.
+
+Default workload: FCC Cu-like box of 100 x 100 x 100 unit cells (4,000,000 atoms,
+a = 3.615 A, Gaussian displacements sigma = 0.08 A, 600 K Maxwell-Boltzmann
+velocities), the full NEP (radial 6 A / angular 5 A cutoffs, n_max 4, basis 8,
+l_max 4 + four-body, 30 hidden units) with random N(0, 0.1) weights, FP32
+descriptors and forces, FP32 MFMA network, FP64 integration; velocity Verlet at
+1 fs, neighbour lists rebuilt every 10 steps with a 1 A skin, thermo output
+every 100 steps. One "step" is one MD step of the whole path (integration,
+conditional list rebuild, descriptors, network, forces, virial, reductions).
+
+Prints one JSON line: atom-steps/s on one GPU, the roofline of the dominant
+kernel (the force kernel, timed with HIP events on the library's stream over
+the timed region) and the FP64 CPU oracle timed on this host's cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published FP32 vector peak (packed FMA)
+PEAK_HBM_GBS = 8000.0
+
+# Static FLOP counts per unit (FMA = 2 flops), from the kernel source of the full
+# model (n_max 4, basis 8, l_max 4 + four-body, 30 hidden): see the kernel notes
+# in the design doc. Units are pairs inside the true cutoffs and atoms.
+FLOPS = {
+    "force_radial_pair": 346,
+    "force_angular_pair": 1222,
+    "desc_candidate_pair": 8,        # FP64 distance test of each skin-list entry
+    "desc_radial_pair": 160,
+    "desc_angular_pair": 460,
+    "desc_per_atom": 5000,           # q_nl, four-body, network (2 x 2 x 30 x 30) and dU/ds
+}
+
+
+def flops_per_atom(pairs_r, pairs_a, skin_entries):
+    force = FLOPS["force_radial_pair"] * pairs_r + FLOPS["force_angular_pair"] * pairs_a
+    desc = (FLOPS["desc_candidate_pair"] * skin_entries + FLOPS["desc_radial_pair"] * pairs_r +
+            FLOPS["desc_angular_pair"] * pairs_a + FLOPS["desc_per_atom"])
+    return desc, force
+
+
+def cpu_baseline(hp, params, at, seconds):
+    import oracle
+    m = oracle.Model.from_hparams(hp, params)
+    k0 = 2000
+    t = time.perf_counter()
+    oracle.center_work(m, at.x, at.types, at.box, 0, k0)
+    dt0 = time.perf_counter() - t
+    k = int(min(at.n - k0, max(k0, k0 * seconds / max(dt0, 1e-3))))
+    t = time.perf_counter()
+    oracle.center_work(m, at.x, at.types, at.box, k0, k)
+    dt = time.perf_counter() - t
+    return {"value": k / dt, "unit": "atom-steps/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"per-center work of one force evaluation (descriptors, network, every pair "
+                      f"derivative) for {k} consecutive atoms of the same {at.n}-atom box, FP64 C++ "
+                      f"oracle with OpenMP, {dt:.1f} s; cell-list setup of the whole box included"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cells", type=int, default=100, help="FCC cells per side")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(the path shards by spatial decomposition, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2604_24816_amd import inputs as I
+    from paper_2604_24816_amd import nep
+
+    hp = I.FULL_HPARAMS
+    params = I.random_model(hp, 0)
+    at = I.workload_4m(args.cells)
+    s = nep.NEPSystem(nep.NEPModel(hp, params), at.n, at.box)
+    s.set_state(at.x, at.types, at.masses, at.v)
+    s.build_neighbors(1.0)
+    s.step(args.warmup, dt=1.0, rebuild_every=10, skin=1.0, precision=args.precision)
+    # timed region
+    s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(args.steps, dt=1.0, rebuild_every=10, skin=1.0, precision=args.precision, thermo_every=100)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = s.profile_read()
+    s.profile(False)
+    elapsed = t1 - t0
+    n = at.n
+    value = n * args.steps / elapsed
+    pairs_r, pairs_a, skin_total = s.pair_counts()
+    skin_entries = skin_total / n
+    desc_f, force_f = flops_per_atom(pairs_r / n, pairs_a / n, skin_entries)
+    force_ms, force_cnt = prof["force"]
+    desc_ms, desc_cnt = prof["desc_net"]
+    avg_force_s = force_ms / force_cnt / 1e3
+    achieved = force_f * n / avg_force_s / 1e12
+    out = {
+        "metric": "atom-steps/s per GPU (s/step/atom): plain FP32 NEP vs BF16/MTS surrogate",
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "s_per_step_per_atom": elapsed / (n * args.steps),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32" if args.precision == "fp32" else "fp32+bf16-mfma",
+        "data": "synthetic (seeded FCC box, random-weight NEP)",
+        "config": {"workload": f"fcc_cu_{args.cells}x{args.cells}x{args.cells}_cells_{n}_atoms_nve",
+                   "n_atoms": n, "model": "NEP rc 6/5 A, n_max 4, basis 8, l_max 4 + 4-body, 30 hidden",
+                   "precision": args.precision, "dt_fs": 1.0, "rebuild_every": 10, "skin_A": 1.0,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "kernel": "k_force", "achieved": achieved,
+                     "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                     "flops_per_atom": force_f, "avg_launch_ms": avg_force_s * 1e3},
+        "kernels_ms_per_launch": {k: (v[0] / v[1] if v[1] else None) for k, v in prof.items()},
+        "pairs_per_atom": {"radial": pairs_r / n, "angular": pairs_a / n, "skin_list": skin_entries},
+        "flops_per_atom_step": desc_f + force_f,
+        "sustained_tflops": (desc_f + force_f) * value / 1e12,
+        "paper_context": {"note": "Table 5, CNIS GPGPU, trained Cu model, 4,499,456 atoms, FP32",
+                          "atom_steps_per_s": 46.19e6},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(hp, params, at, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

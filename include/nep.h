@@ -189,6 +189,19 @@ int nep_adam_update(nep_system* s, float* theta, const float* grad, float* m1, f
  * err2 = {rms, max} over atoms of |F_full - F_surrogate| (host). */
 int nep_surrogate_error(nep_system* s, int32_t precision, double* err2);
 
+/* ---------------------------------------------------------------- measurement
+ * nep_profile(s, 1) starts timing kernels with HIP events recorded on the
+ * system's stream; nep_profile(s, 0) stops. nep_profile_read returns, since
+ * enabling, the summed milliseconds and the number of timed launches of four
+ * groups: {descriptor + network kernel, force kernel, list rebuild
+ * (conditional kernels included), integrator kernels}. Reading synchronises. */
+int nep_profile(nep_system* s, int32_t enable);
+int nep_profile_read(nep_system* s, double* ms4, int64_t* count4);
+
+/* Pair counts summed over atoms at the last evaluation: counts3 = {radial pairs
+ * (r < rc_radial), angular pairs (r < rc_angular), radial list entries with skin}. */
+int nep_pair_counts(nep_system* s, int64_t* counts3);
+
 const char* nep_status_string(int status);
 const char* nep_last_error(const nep_system* s);
 

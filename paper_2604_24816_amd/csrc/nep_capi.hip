@@ -117,6 +117,13 @@ struct nep_system {
   float* mparams[2];
   uint16_t* mbf[2];
   int nblocks = 1;
+  // kernel timing with events (off unless nep_profile enables it)
+  bool prof = false;
+  std::vector<hipEvent_t> pool;
+  int pool_next = 0;
+  std::vector<int> pending;  // triples (start index, stop index, group)
+  double prof_ms[4] = {0, 0, 0, 0};
+  int64_t prof_cnt[4] = {0, 0, 0, 0};
 };
 
 namespace {
@@ -253,8 +260,16 @@ EvalBuffers eval_buffers(nep_system* s, int slot) {
   return b;
 }
 
+hipEvent_t* prof_take(nep_system* s, int n);
+void prof_pair(nep_system* s, hipEvent_t* base, int a, int b, int group);
+
 int do_eval(nep_system* s, int slot, int prec) {
-  HIPCHK(launch_eval(s->mdev[slot], prec, eval_buffers(s, slot), s->st));
+  hipEvent_t* ev = prof_take(s, 3);
+  HIPCHK(launch_eval(s->mdev[slot], prec, eval_buffers(s, slot), s->st, ev));
+  if (ev) {
+    prof_pair(s, ev, 0, 1, 0);
+    prof_pair(s, ev, 1, 2, 1);
+  }
   s->force_valid[slot] = true;
   s->force_prec[slot] = prec;
   return NEP_OK;
@@ -306,6 +321,42 @@ int check_model_pair(const nep_model* full, const nep_model* sur) {
     if (sur->hp.rc_radial > full->hp.rc_radial || sur->hp.rc_angular > full->hp.rc_angular) return NEP_ERR_ARG;
   }
   return NEP_OK;
+}
+
+constexpr int kPoolEvents = 1024;
+
+int prof_drain(nep_system* s) {
+  if (s->pending.empty()) {
+    s->pool_next = 0;
+    return NEP_OK;
+  }
+  HIPCHK(hipStreamSynchronize(s->st));
+  for (size_t k = 0; k + 3 <= s->pending.size(); k += 3) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, s->pool[s->pending[k]], s->pool[s->pending[k + 1]]));
+    s->prof_ms[s->pending[k + 2]] += ms;
+    s->prof_cnt[s->pending[k + 2]] += 1;
+  }
+  s->pending.clear();
+  s->pool_next = 0;
+  return NEP_OK;
+}
+
+// n consecutive events from the pool (nullptr when profiling is off).
+hipEvent_t* prof_take(nep_system* s, int n) {
+  if (!s->prof) return nullptr;
+  if (s->pool_next + n > (int)s->pool.size())
+    if (prof_drain(s) != NEP_OK) return nullptr;
+  hipEvent_t* e = &s->pool[s->pool_next];
+  s->pool_next += n;
+  return e;
+}
+
+void prof_pair(nep_system* s, hipEvent_t* base, int a, int b, int group) {
+  const int i0 = (int)(base - s->pool.data());
+  s->pending.push_back(i0 + a);
+  s->pending.push_back(i0 + b);
+  s->pending.push_back(group);
 }
 
 }  // namespace
@@ -440,7 +491,9 @@ int nep_system_create(const nep_model* full, const nep_model* sur, int64_t n_ato
 }
 
 void nep_system_destroy(nep_system* s) {
-  if (s && s->st) (void)hipStreamSynchronize(s->st);
+  if (!s) return;
+  (void)hipStreamSynchronize(s->st);
+  for (hipEvent_t e : s->pool) (void)hipEventDestroy(e);
   delete s;
 }
 
@@ -594,13 +647,27 @@ int thermo_row(nep_system* s, double* row, double err_rms, double err_max, int f
 int vv_step(nep_system* s, int slot, int prec, double dt, int rebuild_every, double skin) {
   const int64_t next = s->step + 1;
   const int scheduled = (rebuild_every > 0 && next % rebuild_every == 0) ? 1 : 0;
+  hipEvent_t* ev = prof_take(s, 4);
+  if (ev) HIPCHK(hipEventRecord(ev[0], s->st));
   HIPCHK(launch_set_flag(s->flags, FLAG_REBUILD, scheduled, s->st));
   HIPCHK(launch_kick_drift(s->N, dt, s->grid, s->F[slot], s->type, s->mt, s->x, s->v, s->x_build,
                            0.25 * skin * skin, s->flags, s->st));
+  if (ev) HIPCHK(hipEventRecord(ev[1], s->st));
   int st = rebuild(s, skin, 0);
   if (st) return st;
+  if (ev) {
+    HIPCHK(hipEventRecord(ev[2], s->st));
+    prof_pair(s, ev, 0, 1, 3);
+    prof_pair(s, ev, 1, 2, 2);
+  }
   if ((st = do_eval(s, slot, prec))) return st;
+  hipEvent_t* ev2 = prof_take(s, 2);
+  if (ev2) HIPCHK(hipEventRecord(ev2[0], s->st));
   HIPCHK(launch_kick(s->N, dt, s->F[slot], s->type, s->mt, s->v, s->st));
+  if (ev2) {
+    HIPCHK(hipEventRecord(ev2[1], s->st));
+    prof_pair(s, ev2, 0, 1, 3);
+  }
   s->step = next;
   s->n_steps_total++;
   return NEP_OK;
@@ -785,6 +852,55 @@ int nep_adam_update(nep_system* s, float* theta, const float* grad, float* m1, f
                     double lr, double beta1, double beta2, double eps) {
   if (!s || !theta || !grad || !m1 || !m2 || n < 1 || t < 1) return fail(s, NEP_ERR_ARG, "bad argument");
   HIPCHK(launch_adam(theta, grad, m1, m2, n, t, lr, beta1, beta2, eps, s->st));
+  return NEP_OK;
+}
+
+int nep_profile(nep_system* s, int32_t enable) {
+  if (!s) return NEP_ERR_ARG;
+  if (enable) {
+    if (s->pool.empty()) {
+      s->pool.resize(kPoolEvents);
+      for (auto& e : s->pool) HIPCHK(hipEventCreate(&e));
+    }
+    int st = prof_drain(s);
+    if (st) return st;
+    for (int k = 0; k < 4; ++k) {
+      s->prof_ms[k] = 0;
+      s->prof_cnt[k] = 0;
+    }
+    s->prof = true;
+  } else {
+    int st = prof_drain(s);
+    if (st) return st;
+    s->prof = false;
+  }
+  return NEP_OK;
+}
+
+int nep_profile_read(nep_system* s, double* ms4, int64_t* count4) {
+  if (!s || !ms4 || !count4) return NEP_ERR_ARG;
+  int st = prof_drain(s);
+  if (st) return st;
+  for (int k = 0; k < 4; ++k) {
+    ms4[k] = s->prof_ms[k];
+    count4[k] = s->prof_cnt[k];
+  }
+  return NEP_OK;
+}
+
+int nep_pair_counts(nep_system* s, int64_t* counts3) {
+  if (!s || !counts3) return NEP_ERR_ARG;
+  if (!s->force_valid[0] && !s->force_valid[1]) return fail(s, NEP_ERR_STALE_LIST, "no evaluation yet");
+  HIPCHK(launch_sum_i32(s->N, s->nactR, s->partial, P_ERR2, s->st));
+  HIPCHK(launch_reduce_partials(s->partial, s->nblocks, P_ERR2, 1, s->res + 14, s->st));
+  HIPCHK(launch_sum_i32(s->N, s->nactA, s->partial, P_ERR2, s->st));
+  HIPCHK(launch_reduce_partials(s->partial, s->nblocks, P_ERR2, 1, s->res + 15, s->st));
+  HIPCHK(launch_sum_i32(s->N, s->cntR, s->partial, P_ERR2, s->st));
+  HIPCHK(launch_reduce_partials(s->partial, s->nblocks, P_ERR2, 1, s->res + 16, s->st));
+  double r[3];
+  HIPCHK(hipMemcpyAsync(r, s->res + 14, 3 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  for (int k = 0; k < 3; ++k) counts3[k] = (int64_t)r[k];
   return NEP_OK;
 }
 

@@ -111,7 +111,10 @@ struct EvalBuffers {
   int32_t* flags;
 };
 bool eval_supported(const ModelDev& m);
-hipError_t launch_eval(const ModelDev& m, int precision, const EvalBuffers& b, hipStream_t st);
+// ev (nullable): three events recorded before the descriptor kernel, between the
+// two kernels and after the force kernel.
+hipError_t launch_eval(const ModelDev& m, int precision, const EvalBuffers& b, hipStream_t st,
+                       hipEvent_t* ev = nullptr);
 int eval_partial_blocks(int64_t N);
 
 // MD and reductions (nep_md.hip)
@@ -135,6 +138,7 @@ hipError_t launch_kinetic(int64_t N, const double* v, const int32_t* type, MassT
 hipError_t launch_force_error(int64_t N, const float* Fa, const float* Fb, double* partial,
                               hipStream_t st);
 hipError_t launch_set_flag(int32_t* flags, int idx, int value, hipStream_t st);
+hipError_t launch_sum_i32(int64_t N, const int32_t* a, double* partial, int slot, hipStream_t st);
 hipError_t launch_state_in(int64_t N, const double* x_aos, const double* v_aos,
                            const int32_t* type_in, int n_types, CellGrid g, double* x, double* v,
                            int32_t* type, int32_t* perm, int32_t* flags, hipStream_t st);

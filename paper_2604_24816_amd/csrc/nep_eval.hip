@@ -559,19 +559,23 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
 }
 
 template <class S, int PREC, bool MULTI>
-hipError_t launch_pair(const ModelDev& m, const EvalBuffers& b, hipStream_t st) {
+hipError_t launch_pair(const ModelDev& m, const EvalBuffers& b, hipStream_t st, hipEvent_t* ev) {
   const int nb = grid_blocks(b.N);
+  if (ev) (void)hipEventRecord(ev[0], st);
   hipLaunchKernelGGL((k_desc_net<S, PREC, MULTI>), dim3(nb), dim3(kBlock), 0, st, m, b);
+  if (ev) (void)hipEventRecord(ev[1], st);
   hipLaunchKernelGGL((k_force<S, MULTI>), dim3(nb), dim3(kBlock), 0, st, m, b);
+  if (ev) (void)hipEventRecord(ev[2], st);
   return hipGetLastError();
 }
 
 template <class S>
-hipError_t launch_shape(const ModelDev& m, int precision, const EvalBuffers& b, hipStream_t st) {
+hipError_t launch_shape(const ModelDev& m, int precision, const EvalBuffers& b, hipStream_t st,
+                        hipEvent_t* ev) {
   const bool multi = m.T > 1;
   if (precision == 0)
-    return multi ? launch_pair<S, 0, true>(m, b, st) : launch_pair<S, 0, false>(m, b, st);
-  return multi ? launch_pair<S, 1, true>(m, b, st) : launch_pair<S, 1, false>(m, b, st);
+    return multi ? launch_pair<S, 0, true>(m, b, st, ev) : launch_pair<S, 0, false>(m, b, st, ev);
+  return multi ? launch_pair<S, 1, true>(m, b, st, ev) : launch_pair<S, 1, false>(m, b, st, ev);
 }
 
 template <class S>
@@ -586,9 +590,10 @@ bool eval_supported(const ModelDev& m) { return is_shape<FullShape>(m) || is_sha
 
 int eval_partial_blocks(int64_t N) { return grid_blocks(N); }
 
-hipError_t launch_eval(const ModelDev& m, int precision, const EvalBuffers& b, hipStream_t st) {
-  if (is_shape<FullShape>(m)) return launch_shape<FullShape>(m, precision, b, st);
-  if (is_shape<SurShape>(m)) return launch_shape<SurShape>(m, precision, b, st);
+hipError_t launch_eval(const ModelDev& m, int precision, const EvalBuffers& b, hipStream_t st,
+                       hipEvent_t* ev) {
+  if (is_shape<FullShape>(m)) return launch_shape<FullShape>(m, precision, b, st, ev);
+  if (is_shape<SurShape>(m)) return launch_shape<SurShape>(m, precision, b, st, ev);
   return hipErrorInvalidValue;
 }
 

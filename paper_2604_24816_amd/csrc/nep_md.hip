@@ -130,6 +130,12 @@ __global__ void k_max_partials(const double* __restrict__ partial, int nblocks, 
   if (threadIdx.x == 0) *out = sh[0];
 }
 
+__global__ void k_sum_i32(int64_t N, const int32_t* __restrict__ a, double* __restrict__ partial, int slot) {
+  __shared__ double sh[kBlock];
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  block_partial(p < N ? (double)a[p] : 0.0, sh, partial + (int64_t)blockIdx.x * kPartialStride + slot);
+}
+
 __global__ void k_set_flag(int32_t* flags, int idx, int value) {
   if (threadIdx.x == 0) flags[idx] = value;
 }
@@ -239,6 +245,11 @@ hipError_t launch_kinetic(int64_t N, const double* v, const int32_t* type, MassT
 hipError_t launch_force_error(int64_t N, const float* Fa, const float* Fb, double* partial,
                               hipStream_t st) {
   hipLaunchKernelGGL(k_force_error, dim3(grid_blocks(N)), dim3(kBlock), 0, st, N, Fa, Fb, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_i32(int64_t N, const int32_t* a, double* partial, int slot, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_i32, dim3(grid_blocks(N)), dim3(kBlock), 0, st, N, a, partial, slot);
   return hipGetLastError();
 }
 

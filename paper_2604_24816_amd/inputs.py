@@ -190,8 +190,8 @@ SURROGATE_HPARAMS = HParams(l_max_3b=2, l_max_4b=0, n_hidden=8)
 # scaled descriptors are of order one for thermally disordered FCC boxes at the
 # cutoffs above; they are part of the model definition, not derived at run time.
 SIGMA_RADIAL = 0.3
-SIGMA_ANGULAR = (20.0, 20.0, 20.0, 20.0)
-SIGMA_FOURBODY = 2000.0
+SIGMA_ANGULAR = (2.0, 2.0, 2.0, 2.0)
+SIGMA_FOURBODY = 10.0
 
 
 def default_sigma(hp: HParams) -> np.ndarray:

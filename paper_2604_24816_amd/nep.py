@@ -28,7 +28,8 @@ EXPORTED = [
     "nep_system_create", "nep_system_destroy", "nep_system_set_params", "nep_set_state",
     "nep_build_neighbors", "nep_export_neighbors", "nep_compute_energy_forces_virial", "nep_step",
     "nep_get_state", "nep_get_stats", "nep_train_forward", "nep_train_backward", "nep_adam_update",
-    "nep_surrogate_error", "nep_status_string", "nep_last_error",
+    "nep_surrogate_error", "nep_status_string", "nep_last_error", "nep_profile", "nep_profile_read",
+    "nep_pair_counts",
 ]
 
 
@@ -75,6 +76,9 @@ def load_library(path: str = LIB_PATH):
         "nep_train_backward": [vp, i32, vp, f64, vp, vp],
         "nep_adam_update": [vp, vp, vp, vp, vp, i64, i64, f64, f64, f64, f64],
         "nep_surrogate_error": [vp, i32, vp],
+        "nep_profile": [vp, i32],
+        "nep_profile_read": [vp, vp, vp],
+        "nep_pair_counts": [vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -247,6 +251,23 @@ class NEPSystem:
         self._check(self.lib.nep_get_stats(self.handle, _np_ptr(s)))
         return {"list_builds": int(s[0]), "mts_blocks": int(s[1]), "fallback_blocks": int(s[2]),
                 "steps": int(s[3])}
+
+    def profile(self, enable: bool):
+        self._check(self.lib.nep_profile(self.handle, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        """Summed ms and launch counts: desc_net, force, rebuild, integrate."""
+        ms = np.zeros(4)
+        cnt = np.zeros(4, np.int64)
+        self._check(self.lib.nep_profile_read(self.handle, _np_ptr(ms), _np_ptr(cnt)))
+        names = ["desc_net", "force", "rebuild", "integrate"]
+        return {n: (float(ms[k]), int(cnt[k])) for k, n in enumerate(names)}
+
+    def pair_counts(self):
+        """(radial pairs, angular pairs, radial skin-list entries) summed over atoms."""
+        c = np.zeros(3, np.int64)
+        self._check(self.lib.nep_pair_counts(self.handle, _np_ptr(c)))
+        return int(c[0]), int(c[1]), int(c[2])
 
     def surrogate_error(self, precision="fp32"):
         e = np.zeros(2)

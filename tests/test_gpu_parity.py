@@ -203,3 +203,40 @@ def test_error_paths(full):
     with pytest.raises(nep.NEPError) as e:
         s.build_neighbors(2.0)  # 14.46 A box < 2 (6 + 2)
     assert e.value.status == -2
+
+
+def _block_model(hp, block, seed=5):
+    p = I.random_model(hp, seed)
+    b = I.unpack(hp, p)
+    nr, na = hp.n_max_radial + 1, hp.n_max_angular + 1
+    W0 = b["W0"].reshape(hp.n_hidden, hp.n_desc)
+    keep = np.zeros(hp.n_desc, bool)
+    if block == "radial":
+        keep[:nr] = True
+    elif block == "fourbody":
+        keep[nr + na * hp.l_max_3b:] = True
+    else:
+        l = int(block)
+        keep[nr + (l - 1) * na: nr + l * na] = True
+    W0[:, ~keep] = 0.0
+    return p
+
+
+@pytest.mark.parametrize("block", ["radial", "1", "2", "3", "4", "fourbody"])
+def test_each_descriptor_block_separately(block):
+    """Each descriptor block alone drives the network, on a disordered two-species box with
+    vacancies, so that an error in any one block's forces cannot hide behind the others."""
+    hp = I.HParams(n_types=2)
+    p = _block_model(hp, block)
+    m = oracle.Model.from_hparams(hp, p)
+    at = I.alloy_box(6, 1, 40, 2, 0.15, 3)
+    say(f"case: block {block} only, alloy 6^3 with vacancies, N={at.n}")
+    s = make_system(at, hp, p)
+    E, W, F, U = s.compute(per_atom=True)
+    Eo, Wo, Uo, Fo = oracle.evaluate(m, at.x, at.types, at.box)
+    rel = np.abs(F - Fo).max() / np.abs(Fo).max()
+    say(f"  max|F|={np.abs(Fo).max():.3e} rel dF={rel:.2e} max|dU|={np.abs(U - Uo).max():.2e}")
+    assert np.abs(Fo).max() > 1e-3
+    assert rel < 2e-5
+    assert np.abs(U - Uo).max() < E_ATOM_TOL
+    assert np.abs(W - Wo).max() < 2e-5 * np.abs(Wo).max() + 1e-9
