@@ -172,13 +172,15 @@ int nep_get_stats(nep_system* s, int64_t* stats4);
  *
  * nep_train_forward: E (host FP64) and forces F [N][3] (device FP32, original
  * order) for theta.
- * nep_train_backward: grad = dL/dtheta (device FP32, FP64 accumulation) for
- * L = gE * E + sum_i gF_i . F_i, with gF [N][3] device FP32 in original order
- * (NULL = no force term). */
+ * nep_train_backward: grad = dL/dtheta (device FP32, FP64 reduction over atoms)
+ * for L = gE * E + sum_i gF_i . F_i, with gF [N][3] device FP32 in original order
+ * (NULL = no force term); accumulate = 1 adds to grad instead of overwriting it.
+ * It must follow nep_train_forward (or an evaluation) of the same slot at the
+ * same positions, whose pair lists it reuses. Does not synchronise. */
 int nep_train_forward(nep_system* s, int32_t slot, const float* theta, double* energy,
                       float* forces);
 int nep_train_backward(nep_system* s, int32_t slot, const float* theta, double gE,
-                       const float* gF, float* grad);
+                       const float* gF, float* grad, int32_t accumulate);
 
 /* One Adam step on device FP32 arrays theta, grad, m1, m2 of length n
  * (t = 1-based step count), on the system's stream. */

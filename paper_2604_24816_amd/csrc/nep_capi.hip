@@ -128,7 +128,7 @@ struct nep_system {
 
 namespace {
 
-constexpr int kGradMax = 32 * 32 + 2 * 32 + 1;
+constexpr int kGradMax = 32 * 32 + 2 * 32 + 1;  // equals train_grad_stride()
 
 // Lays out every buffer; with base == nullptr it only measures.
 int64_t layout(nep_system* s, char* base, int64_t N, int capR, int capA, int max_ncell, const int64_t* np,
@@ -825,7 +825,8 @@ int nep_train_forward(nep_system* s, int32_t slot, const float* theta, double* e
   return NEP_OK;
 }
 
-int nep_train_backward(nep_system* s, int32_t slot, const float* theta, double gE, const float* gF, float* grad) {
+int nep_train_backward(nep_system* s, int32_t slot, const float* theta, double gE, const float* gF, float* grad,
+                       int32_t accumulate) {
   if (!s || !theta || !grad || slot < 0 || slot > 1 || !s->has_model[slot]) return fail(s, NEP_ERR_ARG, "bad argument");
   if (!s->have_list) return fail(s, NEP_ERR_STALE_LIST, "build the neighbour lists first");
   TrainBuffers t;
@@ -841,10 +842,9 @@ int nep_train_backward(nep_system* s, int32_t slot, const float* theta, double g
   t.qs = nullptr;
   t.gpart = s->gpart;
   t.grad = grad;
-  hipError_t e = launch_train_backward(s->mdev[slot], t, s->st);
-  if (e == hipErrorNotSupported) return fail(s, NEP_ERR_UNSUPPORTED, "weight gradients not available");
-  HIPCHK(e);
-  HIPCHK(hipStreamSynchronize(s->st));
+  t.accumulate = accumulate ? 1 : 0;
+  HIPCHK(launch_train_backward(s->mdev[slot], t, s->st));
+  s->force_valid[slot] = false;
   return NEP_OK;
 }
 

@@ -161,13 +161,15 @@ struct TrainBuffers {
   double gE;
   float* vjp;            // [D][N] scratch
   float* qs;             // [D][N] scratch
-  double* gpart;         // [nblocks][G] FP64 partial gradients
+  double* gpart;         // [nblocks][train_grad_stride()] FP64 partial gradients
   float* grad;           // [G] output
+  int accumulate;        // 1: grad += result
 };
 hipError_t launch_train_forward(const ModelDev& m, const float* theta, const EvalBuffers& b,
                                 hipStream_t st);
 hipError_t launch_train_backward(const ModelDev& m, const TrainBuffers& t, hipStream_t st);
 int train_partial_blocks(int64_t N);
+int train_grad_stride();
 hipError_t launch_adam(float* theta, const float* g, float* m1, float* m2, int64_t n, int64_t t,
                        double lr, double b1, double b2, double eps, hipStream_t st);
 

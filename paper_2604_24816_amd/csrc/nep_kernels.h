@@ -1,0 +1,237 @@
+// Device helpers shared by the evaluation and training kernels: radial basis,
+// pair vectors, workgroup reductions, model shapes, and the descriptor
+// accumulation of one center (radial q_n, angular s_nlm, q_nl, four-body).
+#pragma once
+
+#include "nep_common.h"
+#include "nep_poly.h"
+
+namespace nep {
+namespace kern {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr float kPiF = 3.14159265358979323846f;
+
+// Round-to-nearest-even conversion of an FP32 value to bfloat16 bits.
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ __bf16 bits_to_bf16(uint16_t b) { return __builtin_bit_cast(__bf16, b); }
+
+// Chebyshev-based radial basis f_k(r) = (T_k(x) + 1) f_c(r) / 2 with
+// x = 2 (r/rc - 1)^2 - 1 and f_c = (1 + cos(pi r / rc)) / 2 (published NEP form).
+// Returns g_n = sum_k c_nk f_k.
+template <int N, int K>
+__device__ __forceinline__ void radial_g(float r, float rc_inv, const float* __restrict__ c, float* g) {
+  float sn, cs;
+  sincospif(r * rc_inv, &sn, &cs);
+  const float fc = 0.5f * (1.f + cs);
+  const float y = r * rc_inv - 1.f;
+  const float x = 2.f * y * y - 1.f;
+  float Tm1 = 1.f, T = x;
+  float fk[K];
+  fk[0] = 1.f;
+  fk[1] = 0.5f * (x + 1.f);
+#pragma unroll
+  for (int k = 2; k < K; ++k) {
+    const float Tn = 2.f * x * T - Tm1;
+    Tm1 = T;
+    T = Tn;
+    fk[k] = 0.5f * (Tn + 1.f);
+  }
+#pragma unroll
+  for (int n = 0; n < N; ++n) {
+    float a = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) a = fmaf(c[n * K + k], fk[k], a);
+    g[n] = a * fc;
+  }
+}
+
+// g_n and dg_n/dr.
+template <int N, int K>
+__device__ __forceinline__ void radial_g_dg(float r, float rc_inv, const float* __restrict__ c, float* g,
+                                            float* dg) {
+  float sn, cs;
+  sincospif(r * rc_inv, &sn, &cs);
+  const float fc = 0.5f * (1.f + cs);
+  const float dfc = -0.5f * kPiF * rc_inv * sn;
+  const float y = r * rc_inv - 1.f;
+  const float x = 2.f * y * y - 1.f;
+  const float dx = 4.f * y * rc_inv;
+  float hk[K], dk[K];  // (T_k + 1)/2 and T_k'/2
+  float Tm1 = 1.f, T = x, dTm1 = 0.f, dT = 1.f;
+  hk[0] = 1.f;
+  dk[0] = 0.f;
+  hk[1] = 0.5f * (x + 1.f);
+  dk[1] = 0.5f;
+#pragma unroll
+  for (int k = 2; k < K; ++k) {
+    const float Tn = 2.f * x * T - Tm1;
+    const float dTn = 2.f * T + 2.f * x * dT - dTm1;
+    Tm1 = T;
+    T = Tn;
+    dTm1 = dT;
+    dT = dTn;
+    hk[k] = 0.5f * (Tn + 1.f);
+    dk[k] = 0.5f * dTn;
+  }
+  const float fcdx = fc * dx;
+#pragma unroll
+  for (int n = 0; n < N; ++n) {
+    float a = 0.f, b = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      a = fmaf(c[n * K + k], hk[k], a);
+      b = fmaf(c[n * K + k], dk[k], b);
+    }
+    g[n] = a * fc;
+    dg[n] = fmaf(b, fcdx, a * dfc);
+  }
+}
+
+// FP64 minimum-image pair vector, rounded to FP32 after the subtraction.
+__device__ __forceinline__ void pair_vec(const double* __restrict__ x, int64_t N, int64_t j, double xi,
+                                         double yi, double zi, double Lx, double Ly, double Lz, float& dx,
+                                         float& dy, float& dz) {
+  dx = (float)min_image(x[j] - xi, Lx);
+  dy = (float)min_image(x[N + j] - yi, Ly);
+  dz = (float)min_image(x[2 * N + j] - zi, Lz);
+}
+
+// Deterministic FP64 sum over a 256-thread workgroup (fixed tree order).
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  __syncthreads();
+  sh[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < (unsigned)off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+template <int NR_, int KR_, int NA_, int KA_, int L3_, bool FB_, int H_>
+struct Shape {
+  static constexpr int NR = NR_, KR = KR_, NA = NA_, KA = KA_, L3 = L3_, H = H_;
+  static constexpr bool FB = FB_;
+  static constexpr int NC = L3 * (L3 + 2);
+  static constexpr int D = NR + NA * L3 + (FB ? NA : 0);
+  static_assert(D <= 32 && H <= 32, "network tiles hold at most 32 descriptors and 32 hidden units");
+  static_assert(!FB || L3 >= 2, "the four-body term uses the l = 2 accumulators");
+};
+
+using FullShape = Shape<5, 9, 5, 9, 4, true, 30>;
+using SurShape = Shape<5, 9, 5, 9, 2, false, 8>;
+
+constexpr int kLdsStride = 33;  // 32 columns + 1 pad word against bank conflicts
+
+
+// Radial descriptors q[0..NR) and angular accumulators s[NA][NC] of center i over
+// its active lists (pairs inside the true cutoffs), all channels in one pass over
+// the neighbours (geometry computed once per pair and reused for every n).
+template <class S, bool MULTI>
+__device__ __forceinline__ void desc_accumulate(const ModelDev& m, const EvalBuffers& b, int64_t i, int ti,
+                                                double xi, double yi, double zi, double Lx, double Ly,
+                                                double Lz, int nr, int na, float* q, float* s) {
+  constexpr int NR = S::NR, NA = S::NA, NC = S::NC;
+  const int64_t N = b.N;
+  const double* __restrict__ x = b.x;
+  const float rcR_inv = 1.f / m.rcR, rcA_inv = 1.f / m.rcA;
+  for (int p = 0; p < nr; ++p) {
+    const int32_t j = b.actR[(int64_t)p * N + i];
+    float dx, dy, dz;
+    pair_vec(x, N, j, xi, yi, zi, Lx, Ly, Lz, dx, dy, dz);
+    const float r = sqrtf(dx * dx + dy * dy + dz * dz);
+    const int tj = MULTI ? b.type[j] : 0;
+    float g[NR];
+    radial_g<NR, S::KR>(r, rcR_inv, m.cR + (ti * m.T + tj) * NR * S::KR, g);
+#pragma unroll
+    for (int n = 0; n < NR; ++n) q[n] += g[n];
+  }
+  for (int p = 0; p < na; ++p) {
+    const int32_t j = b.actA[(int64_t)p * N + i];
+    float dx, dy, dz;
+    pair_vec(x, N, j, xi, yi, zi, Lx, Ly, Lz, dx, dy, dz);
+    const float r = sqrtf(dx * dx + dy * dy + dz * dz);
+    const float rinv = 1.f / r;
+    const int tj = MULTI ? b.type[j] : 0;
+    float g[NA];
+    radial_g<NA, S::KA>(r, rcA_inv, m.cA + (ti * m.T + tj) * NA * S::KA, g);
+    for_each_poly<NC>(dx * rinv, dy * rinv, dz * rinv, [&](int lm, float P) {
+#pragma unroll
+      for (int n = 0; n < NA; ++n) s[n * NC + lm] = fmaf(g[n], P, s[n * NC + lm]);
+    });
+  }
+}
+
+// The 3x3 traceless matrix S = sum_j g (u u^T - I/3) of one channel from its
+// l = 2 accumulators (xy, yz, 3z^2 - r^2, xz, x^2 - y^2).
+struct Sym3 {
+  float xx, yy, zz, xy, yz, xz;
+};
+__device__ __forceinline__ Sym3 s_matrix(const float* sl) {
+  Sym3 a;
+  a.xy = sl[3];
+  a.yz = sl[4];
+  a.zz = sl[5] * (1.f / 3.f);
+  a.xz = sl[6];
+  a.xx = 0.5f * (sl[7] - a.zz);
+  a.yy = 0.5f * (-sl[7] - a.zz);
+  return a;
+}
+
+// q_nl = sum_m W_lm s_nlm^2 and the four-body invariant tr(S^3) = 3 det S.
+template <class S>
+__device__ __forceinline__ void desc_finish(const float* s, float* q) {
+  constexpr int NR = S::NR, NA = S::NA, NC = S::NC;
+#pragma unroll
+  for (int n = 0; n < NA; ++n)
+#pragma unroll
+    for (int lm = 0; lm < NC; ++lm) {
+      const int l = comp_l(lm);
+      q[NR + (l - 1) * NA + n] = fmaf(kW[lm], s[n * NC + lm] * s[n * NC + lm], q[NR + (l - 1) * NA + n]);
+    }
+  if constexpr (S::FB) {
+#pragma unroll
+    for (int n = 0; n < NA; ++n) {
+      const Sym3 a = s_matrix(s + n * NC);
+      const float det = a.xx * (a.yy * a.zz - a.yz * a.yz) - a.xy * (a.xy * a.zz - a.yz * a.xz) +
+                        a.xz * (a.xy * a.yz - a.yy * a.xz);
+      q[NR + S::L3 * NA + n] = 3.f * det;
+    }
+  }
+}
+
+// d tr(S^3) / d s for the l = 2 accumulators (xy, yz, 3z^2 - r^2, xz, x^2 - y^2)
+// of one channel: 3 S^2 contracted with dS/ds.
+__device__ __forceinline__ void fourbody_ds(const float* sl, float* d5) {
+  const Sym3 a = s_matrix(sl);
+  const float Qxx = a.xx * a.xx + a.xy * a.xy + a.xz * a.xz;
+  const float Qyy = a.xy * a.xy + a.yy * a.yy + a.yz * a.yz;
+  const float Qzz = a.xz * a.xz + a.yz * a.yz + a.zz * a.zz;
+  const float Qxy = a.xx * a.xy + a.xy * a.yy + a.xz * a.yz;
+  const float Qyz = a.xy * a.xz + a.yy * a.yz + a.yz * a.zz;
+  const float Qxz = a.xx * a.xz + a.xy * a.yz + a.xz * a.zz;
+  d5[0] = 6.f * Qxy;
+  d5[1] = 6.f * Qyz;
+  d5[2] = Qzz - 0.5f * (Qxx + Qyy);
+  d5[3] = 6.f * Qxz;
+  d5[4] = 1.5f * (Qxx - Qyy);
+}
+
+template <class S>
+__host__ __device__ inline bool is_shape(const ModelDev& m) {
+  return m.nR == S::NR && m.kR == S::KR && m.nA == S::NA && m.kA == S::KA && m.L3 == S::L3 &&
+         (m.L4 == 2) == S::FB && m.H == S::H && m.T >= 1 && m.T <= kMaxTypes;
+}
+
+}  // namespace kern
+}  // namespace nep

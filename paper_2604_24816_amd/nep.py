@@ -73,7 +73,7 @@ def load_library(path: str = LIB_PATH):
         "nep_get_state": [vp, vp, vp, vp, i32],
         "nep_get_stats": [vp, vp],
         "nep_train_forward": [vp, i32, vp, vp, vp],
-        "nep_train_backward": [vp, i32, vp, f64, vp, vp],
+        "nep_train_backward": [vp, i32, vp, f64, vp, vp, i32],
         "nep_adam_update": [vp, vp, vp, vp, vp, i64, i64, f64, f64, f64, f64],
         "nep_surrogate_error": [vp, i32, vp],
         "nep_profile": [vp, i32],
@@ -159,6 +159,9 @@ class NEPSystem:
             cap_radial, cap_angular, _t_ptr(self.workspace), nb.value,
             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), None)
         self.handle = h
+        self.generation = 0      # bumped by every call that changes positions, lists or buffers
+        self._types = None
+        self._masses = None
 
     def _check(self, st, handle="self"):
         if st != 0:
@@ -180,7 +183,10 @@ class NEPSystem:
         self._check(self.lib.nep_system_set_params(self.handle, slot, _np_ptr(p), p.size))
 
     def set_state(self, x, types, masses, v=None):
+        self.generation += 1
         masses = np.ascontiguousarray(masses, dtype=np.float64)
+        self._types = types
+        self._masses = masses
         if isinstance(x, torch.Tensor):
             xt = x.to(self.device, torch.float64).contiguous()
             tt = torch.as_tensor(types, device=self.device, dtype=torch.int32).contiguous()
@@ -203,7 +209,14 @@ class NEPSystem:
         self._check(self.lib.nep_get_state(self.handle, _np_ptr(x), _np_ptr(v), ctypes.byref(step), 0))
         return x, v, step.value
 
+    def set_positions(self, x):
+        """New positions with the types and masses of the last set_state (velocities zero)."""
+        if self._types is None:
+            raise RuntimeError("set_state first")
+        self.set_state(x, self._types, self._masses)
+
     def build_neighbors(self, skin: float = 1.0):
+        self.generation += 1
         self._check(self.lib.nep_build_neighbors(self.handle, float(skin)))
 
     def export_neighbors(self, which: int = 0):
@@ -218,6 +231,7 @@ class NEPSystem:
     def compute(self, slot: int = 0, precision="fp32", forces: bool = True, per_atom: bool = False,
                 on_device: bool = False):
         """(E, W[3][3], F[N][3] or None, U[N] or None), FP64, original atom order."""
+        self.generation += 1
         E = ctypes.c_double()
         W = np.zeros(9)
         if on_device:
@@ -238,6 +252,7 @@ class NEPSystem:
              mts_k: int = 0, fallback_rms: float = 0.05, fallback_max: float = 1.0, precision="fp32",
              thermo_every: int = 0, max_rows: int = 4096):
         """Advance n_steps; returns thermo rows [k][8] (step, PE, KE, T, P, err_rms, err_max, fallback)."""
+        self.generation += 1
         rows = ctypes.c_int64()
         th = np.zeros((max_rows, 8)) if thermo_every > 0 else None
         self._check(self.lib.nep_step(self.handle, int(n_steps), float(dt), int(rebuild_every), float(skin),
@@ -277,18 +292,23 @@ class NEPSystem:
     # ------------------------------------------------------------------ training
     def train_forward(self, slot: int, theta: torch.Tensor):
         """(E float, F torch [N][3] float32) with network parameters theta (device FP32)."""
+        self.generation += 1
         theta = theta.detach().to(self.device, torch.float32).contiguous()
         F = torch.empty((self.n, 3), dtype=torch.float32, device=self.device)
         E = ctypes.c_double()
         self._check(self.lib.nep_train_forward(self.handle, slot, _t_ptr(theta), ctypes.byref(E), _t_ptr(F)))
         return E.value, F
 
-    def train_backward(self, slot: int, theta: torch.Tensor, gE: float, gF: Optional[torch.Tensor]):
+    def train_backward(self, slot: int, theta: torch.Tensor, gE: float, gF: Optional[torch.Tensor],
+                       out: Optional[torch.Tensor] = None):
+        """dL/dtheta for L = gE*E + sum gF.F (FP32, device); adds into ``out`` when given."""
         theta = theta.detach().to(self.device, torch.float32).contiguous()
-        grad = torch.empty_like(theta)
+        acc = out is not None
+        grad = out if acc else torch.empty_like(theta)
         gFc = None if gF is None else gF.detach().to(self.device, torch.float32).contiguous()
         self._check(self.lib.nep_train_backward(self.handle, slot, _t_ptr(theta), float(gE),
-                                                _t_ptr(gFc) if gFc is not None else None, _t_ptr(grad)))
+                                                _t_ptr(gFc) if gFc is not None else None, _t_ptr(grad),
+                                                1 if acc else 0))
         return grad
 
     def adam(self, theta: torch.Tensor, grad: torch.Tensor, m1: torch.Tensor, m2: torch.Tensor, t: int,

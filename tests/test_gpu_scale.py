@@ -52,3 +52,34 @@ def test_nve_run_4m_conserves_momentum_and_energy(big):
     assert np.abs(p).max() < 1e-6 * at.n
     assert abs(etot[-1] - etot[0]) / at.n < 1e-5
     assert np.isfinite(x).all()
+
+
+def test_alloy_820k_fp32_and_bf16_errors_against_fp64():
+    """Two-species 60^3-cell alloy with 5% vacancies (820,800 atoms): FP32 and BF16 forms
+    against the FP64 oracle over every atom; the errors are printed (stated) and bounded."""
+    hp = I.HParams(n_types=2)
+    params = I.random_model(hp, 0)
+    m = oracle.Model.from_hparams(hp, params)
+    at = I.workload_alloy()
+    say(f"case: alloy 60^3 cells, 5% vacancies, N={at.n}")
+    s = make_system(at, hp, params)
+    Eo, Wo, Uo, Fo = oracle.evaluate(m, at.x, at.types, at.box)
+    _, _, Ub, Fb = oracle.evaluate(m, at.x, at.types, at.box, bf16=True)
+    off, _ = s.export_neighbors(1)
+    cnt = np.diff(off)
+    say(f"  angular list (skin) counts p50={np.percentile(cnt, 50):.0f} p90={np.percentile(cnt, 90):.0f} "
+        f"max={cnt.max()}; rms|F|={np.sqrt(np.mean(Fo ** 2)):.3e} eV/A")
+    res = {}
+    for prec in ("fp32", "bf16"):
+        E, W, F, U = s.compute(precision=prec, per_atom=True)
+        dU = np.abs(U - Uo)
+        dF = np.abs(F - Fo)
+        res[prec] = (dU.max(), dU.mean(), abs(E - Eo) / at.n, dF.max(), np.sqrt(np.mean((F - Fo) ** 2)),
+                     np.abs(W - Wo).max() / at.n)
+        say(f"  {prec} vs FP64: max|dU|={res[prec][0]:.2e} mean|dU|={res[prec][1]:.2e} |dE|/N={res[prec][2]:.2e} "
+            f"max|dF|={res[prec][3]:.2e} rms dF={res[prec][4]:.2e} max|dW|/N={res[prec][5]:.2e}")
+        if prec == "bf16":
+            say(f"  bf16 vs oracle bf16 model: max|dU|={np.abs(U - Ub).max():.2e} "
+                f"mean|dU|={np.abs(U - Ub).mean():.2e} max|dF|={np.abs(F - Fb).max():.2e}")
+    assert res["fp32"][0] < 1e-6 and res["fp32"][2] < 1e-6 and res["fp32"][3] < 1e-4
+    assert res["bf16"][0] < 5e-2 and res["bf16"][3] < 5e-2
