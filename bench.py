@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -30,19 +32,30 @@ PEAK_HBM_GBS = 8000.0
 # model (n_max 4, basis 8, l_max 4 + four-body, 30 hidden): see the kernel notes
 # in the design doc. Units are pairs inside the true cutoffs and atoms.
 FLOPS = {
-    "force_radial_pair": 346,
-    "force_angular_pair": 1222,
-    "desc_candidate_pair": 8,        # FP64 distance test of each skin-list entry
-    "desc_radial_pair": 160,
-    "desc_angular_pair": 460,
-    "desc_per_atom": 5000,           # q_nl, four-body, network (2 x 2 x 30 x 30) and dU/ds
+    "full": {
+        "force_radial_pair": 346,
+        "force_angular_pair": 1222,
+        "desc_candidate_pair": 8,        # FP64 distance test of each skin-list entry
+        "desc_radial_pair": 160,
+        "desc_angular_pair": 460,
+        "desc_per_atom": 5000,           # q_nl, four-body, network (2 x 2 x 30 x 30) and dU/ds
+    },
+    "surrogate": {                       # l_max 2 (8 harmonics), no four-body, 8 hidden units
+        "force_radial_pair": 346,
+        "force_angular_pair": 615,
+        "desc_candidate_pair": 8,
+        "desc_radial_pair": 160,
+        "desc_angular_pair": 270,
+        "desc_per_atom": 1000,
+    },
 }
 
 
-def flops_per_atom(pairs_r, pairs_a, skin_entries):
-    force = FLOPS["force_radial_pair"] * pairs_r + FLOPS["force_angular_pair"] * pairs_a
-    desc = (FLOPS["desc_candidate_pair"] * skin_entries + FLOPS["desc_radial_pair"] * pairs_r +
-            FLOPS["desc_angular_pair"] * pairs_a + FLOPS["desc_per_atom"])
+def flops_per_atom(pairs_r, pairs_a, skin_entries, model="full"):
+    f = FLOPS[model]
+    force = f["force_radial_pair"] * pairs_r + f["force_angular_pair"] * pairs_a
+    desc = (f["desc_candidate_pair"] * skin_entries + f["desc_radial_pair"] * pairs_r +
+            f["desc_angular_pair"] * pairs_a + f["desc_per_atom"])
     return desc, force
 
 
@@ -63,6 +76,99 @@ def cpu_baseline(hp, params, at, seconds):
                       f"oracle with OpenMP, {dt:.1f} s; cell-list setup of the whole box included"}
 
 
+def run_form(form, hp, params, at, steps, warmup, sur=None, judge_fraction=0.75):
+    """Time one form on one box: 'fp32', 'bf16' or 'mts' (surrogate inner steps, k = 4)."""
+    import torch
+    from paper_2604_24816_amd import nep
+    from paper_2604_24816_amd import surrogate as SG
+    shp, sp = sur if sur is not None else (None, None)
+    s = nep.NEPSystem(nep.NEPModel(hp, params), at.n, at.box,
+                      surrogate=nep.NEPModel(shp, sp) if form == "mts" else None)
+    s.set_state(at.x, at.types, at.masses, at.v)
+    s.build_neighbors(1.0)
+    prec = "bf16" if form == "bf16" else "fp32"
+    k = 4 if form == "mts" else 0
+    kw = dict(dt=1.0, rebuild_every=10, skin=1.0, precision=prec, mts_k=k)
+    extra = {}
+    if form == "mts":
+        tau_rms, tau_max, rms = SG.judge_thresholds(s, judge_fraction)
+        kw.update(fallback_rms=tau_rms, fallback_max=tau_max)
+        extra["judge"] = {"tau_rms": tau_rms, "tau_max": tau_max, "rms_force_full": rms,
+                          "fraction": judge_fraction}
+    s.step(warmup, **kw)
+    s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th = s.step(steps, thermo_every=k if k else 100, **kw)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = s.profile_read()
+    s.profile(False)
+    n = at.n
+    pr, pa, sk = s.pair_counts()
+    model_name = "surrogate" if form == "mts" else "full"
+    grp = "force_surrogate" if form == "mts" else "force"
+    desc_f, force_f = flops_per_atom(pr / n, pa / n, sk / n, model_name)
+    fms, fcnt = prof[grp]
+    out = {"atom_steps_per_s": n * steps / elapsed, "s_per_step_per_atom": elapsed / (n * steps),
+           "ms_per_step": 1e3 * elapsed / steps, "n_atoms": n, "steps": steps,
+           "kernels_ms_per_launch": {kk: (v[0] / v[1] if v[1] else None) for kk, v in prof.items()},
+           "roofline": {"bound": "alu", "kernel": "k_force" + ("<surrogate>" if form == "mts" else ""),
+                        "achieved": force_f * n / (fms / fcnt / 1e3) / 1e12, "peak": PEAK_FP32_VECTOR_TFLOPS,
+                        "unit": "TFLOP/s"},
+           "energy_drift_per_atom": float((th[-1, 1] + th[-1, 2] - th[0, 1] - th[0, 2]) / n) if len(th) > 1 else None}
+    out["roofline"]["frac"] = out["roofline"]["achieved"] / PEAK_FP32_VECTOR_TFLOPS
+    if form == "mts":
+        st = s.stats()
+        out.update(extra)
+        out["surrogate_force_error_rms_mean"] = float(np.mean(th[:, 5]))
+        out["surrogate_force_error_max"] = float(np.max(th[:, 6]))
+        out["mts_blocks"] = st["mts_blocks"]
+        out["fallback_blocks"] = st["fallback_blocks"]
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_forms(args):
+    """32M-atom box: FP32, BF16 and MTS with a surrogate trained here on the GPU, plus the
+    untrained-surrogate MTS run that shows what training gains."""
+    import torch
+    from paper_2604_24816_amd import inputs as I
+    from paper_2604_24816_amd import surrogate as SG
+    hp = I.FULL_HPARAMS
+    params = I.random_model(hp, 0)
+    shp = I.SURROGATE_HPARAMS
+    sur0 = I.surrogate_from_teacher(hp, params, shp, 1)
+    t = time.perf_counter()
+    fr = SG.generate_frames(hp, params, n_traj=20, cells=10, steps=1000, every=10)
+    t_frames = time.perf_counter() - t
+    n_frames = int(fr.x.shape[0])
+    res = SG.train_surrogate(fr, shp, sur0, epochs=args.epochs, batch=8, lr=1e-2)
+    del fr
+    torch.cuda.empty_cache()
+    at = I.workload_32m(args.cells)
+    forms = {}
+    for form in ("fp32", "bf16"):
+        forms[form] = run_form(form, hp, params, at, args.steps, args.warmup)
+    forms["mts_trained"] = run_form("mts", hp, params, at, args.steps, 4 * max(1, args.warmup // 4),
+                                    sur=(shp, res.params))
+    forms["mts_untrained"] = run_form("mts", hp, params, at, args.steps, 4 * max(1, args.warmup // 4),
+                                      sur=(shp, sur0))
+    out = {"metric": "atom-steps/s per GPU (s/step/atom): plain FP32 NEP vs BF16/MTS surrogate",
+           "value": forms["mts_trained"]["atom_steps_per_s"], "unit": "atom-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "data": "synthetic (seeded FCC box, random-weight NEP)",
+           "config": {"workload": f"fcc_cu_{args.cells}^3_cells_{at.n}_atoms_forms", "n_atoms": at.n},
+           "training": {"frames": n_frames, "frame_generation_s": t_frames,
+                        "epochs": args.epochs, "seconds": res.seconds, "loss_history": res.history,
+                        "val_force_rmse_init": res.val_force_rmse_init, "val_force_rmse": res.val_force_rmse,
+                        "val_energy_mae_init": res.val_energy_mae_init, "val_energy_mae": res.val_energy_mae},
+           "forms": forms}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,13 +178,21 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", action="store_true",
+                    help="time FP32, BF16 and surrogate MTS on the 200^3-cell (32M-atom) box instead")
+    ap.add_argument("--epochs", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               f"(the path shards by spatial decomposition, see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
+    if args.forms:
+        if args.cells == 100:
+            args.cells = 200
+        run_forms(args)
+        return
+
     import torch
     from paper_2604_24816_amd import inputs as I
     from paper_2604_24816_amd import nep

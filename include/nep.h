@@ -194,11 +194,12 @@ int nep_surrogate_error(nep_system* s, int32_t precision, double* err2);
 /* ---------------------------------------------------------------- measurement
  * nep_profile(s, 1) starts timing kernels with HIP events recorded on the
  * system's stream; nep_profile(s, 0) stops. nep_profile_read returns, since
- * enabling, the summed milliseconds and the number of timed launches of four
- * groups: {descriptor + network kernel, force kernel, list rebuild
- * (conditional kernels included), integrator kernels}. Reading synchronises. */
+ * enabling, the summed milliseconds and the number of timed launches of six
+ * groups: {descriptor + network kernel of slot 0, force kernel of slot 0, list
+ * rebuild (conditional kernels included), integrator kernels, descriptor +
+ * network kernel of slot 1, force kernel of slot 1}. Reading synchronises. */
 int nep_profile(nep_system* s, int32_t enable);
-int nep_profile_read(nep_system* s, double* ms4, int64_t* count4);
+int nep_profile_read(nep_system* s, double* ms6, int64_t* count6);
 
 /* Pair counts summed over atoms at the last evaluation: counts3 = {radial pairs
  * (r < rc_radial), angular pairs (r < rc_angular), radial list entries with skin}. */

@@ -122,8 +122,8 @@ struct nep_system {
   std::vector<hipEvent_t> pool;
   int pool_next = 0;
   std::vector<int> pending;  // triples (start index, stop index, group)
-  double prof_ms[4] = {0, 0, 0, 0};
-  int64_t prof_cnt[4] = {0, 0, 0, 0};
+  double prof_ms[6] = {0, 0, 0, 0, 0, 0};
+  int64_t prof_cnt[6] = {0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -267,8 +267,8 @@ int do_eval(nep_system* s, int slot, int prec) {
   hipEvent_t* ev = prof_take(s, 3);
   HIPCHK(launch_eval(s->mdev[slot], prec, eval_buffers(s, slot), s->st, ev));
   if (ev) {
-    prof_pair(s, ev, 0, 1, 0);
-    prof_pair(s, ev, 1, 2, 1);
+    prof_pair(s, ev, 0, 1, slot == 0 ? 0 : 4);
+    prof_pair(s, ev, 1, 2, slot == 0 ? 1 : 5);
   }
   s->force_valid[slot] = true;
   s->force_prec[slot] = prec;
@@ -864,7 +864,7 @@ int nep_profile(nep_system* s, int32_t enable) {
     }
     int st = prof_drain(s);
     if (st) return st;
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 6; ++k) {
       s->prof_ms[k] = 0;
       s->prof_cnt[k] = 0;
     }
@@ -877,13 +877,13 @@ int nep_profile(nep_system* s, int32_t enable) {
   return NEP_OK;
 }
 
-int nep_profile_read(nep_system* s, double* ms4, int64_t* count4) {
-  if (!s || !ms4 || !count4) return NEP_ERR_ARG;
+int nep_profile_read(nep_system* s, double* ms6, int64_t* count6) {
+  if (!s || !ms6 || !count6) return NEP_ERR_ARG;
   int st = prof_drain(s);
   if (st) return st;
-  for (int k = 0; k < 4; ++k) {
-    ms4[k] = s->prof_ms[k];
-    count4[k] = s->prof_cnt[k];
+  for (int k = 0; k < 6; ++k) {
+    ms6[k] = s->prof_ms[k];
+    count6[k] = s->prof_cnt[k];
   }
   return NEP_OK;
 }

@@ -271,11 +271,11 @@ class NEPSystem:
         self._check(self.lib.nep_profile(self.handle, 1 if enable else 0))
 
     def profile_read(self) -> dict:
-        """Summed ms and launch counts: desc_net, force, rebuild, integrate."""
-        ms = np.zeros(4)
-        cnt = np.zeros(4, np.int64)
+        """Summed ms and launch counts per kernel group (slot 0 = full model, slot 1 = surrogate)."""
+        ms = np.zeros(6)
+        cnt = np.zeros(6, np.int64)
         self._check(self.lib.nep_profile_read(self.handle, _np_ptr(ms), _np_ptr(cnt)))
-        names = ["desc_net", "force", "rebuild", "integrate"]
+        names = ["desc_net", "force", "rebuild", "integrate", "desc_net_surrogate", "force_surrogate"]
         return {n: (float(ms[k]), int(cnt[k])) for k, n in enumerate(names)}
 
     def pair_counts(self):
