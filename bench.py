@@ -142,7 +142,7 @@ def run_forms(args):
     shp = I.SURROGATE_HPARAMS
     sur0 = I.surrogate_from_teacher(hp, params, shp, 1)
     t = time.perf_counter()
-    fr = SG.generate_frames(hp, params, n_traj=20, cells=10, steps=1000, every=10)
+    fr = SG.generate_frames(hp, params, n_traj=200, cells=10, steps=100, every=10)
     t_frames = time.perf_counter() - t
     n_frames = int(fr.x.shape[0])
     res = SG.train_surrogate(fr, shp, sur0, epochs=args.epochs, batch=8, lr=1e-2)

@@ -32,12 +32,14 @@ class Frames:
     temps: np.ndarray      # [F] target temperature of the trajectory each frame came from
 
 
-def generate_frames(full_hp: I.HParams, full_params: np.ndarray, n_traj: int = 20, cells: int = 10,
-                    steps: int = 1000, every: int = 10, t_min: float = 300.0, t_max: float = 1200.0,
+def generate_frames(full_hp: I.HParams, full_params: np.ndarray, n_traj: int = 200, cells: int = 10,
+                    steps: int = 100, every: int = 10, t_min: float = 300.0, t_max: float = 1200.0,
                     seed: int = 100, skin: float = 1.0, cap_radial: int = 256,
                     cap_angular: int = 160) -> Frames:
     """Full-NEP FP32 MD: n_traj trajectories at T_j = t_min + (t_max - t_min) j/(n_traj - 1), each
-    started from displacements 0.083 sqrt(T/300) A and MB(T) velocities; a frame every `every` steps."""
+    started from an FCC box with displacements 0.083 sqrt(T/300) A and MB(T) velocities (the
+    production workload's recipe); a frame every `every` steps. Many short trajectories keep the
+    frames in the near-lattice regime the production runs sample (the default gives 2,000 frames)."""
     xs, es, fs, ts = [], [], [], []
     box = types = masses = None
     model = NEPModel(full_hp, full_params)

@@ -71,8 +71,8 @@ def test_surrogate_training_and_gain(models):
     and an MTS run whose judge accepts the trained surrogate but falls back for the untrained."""
     from paper_2604_24816_amd import surrogate as SG
     hp, teacher, shp, sur0 = models
-    say("case: frames from full-NEP MD (4 trajectories x 40 frames, 4000 atoms) and GPU training")
-    fr = SG.generate_frames(hp, teacher, n_traj=4, cells=10, steps=400, every=10)
+    say("case: frames from full-NEP MD (40 trajectories x 10 frames, 4000 atoms) and GPU training")
+    fr = SG.generate_frames(hp, teacher, n_traj=40, cells=10, steps=100, every=10)
     res = SG.train_surrogate(fr, shp, sur0, epochs=6, batch=8, lr=1e-2, log=say)
     say(f"  val force RMSE {res.val_force_rmse_init:.4e} -> {res.val_force_rmse:.4e} eV/A; "
         f"energy MAE {res.val_energy_mae_init:.3e} -> {res.val_energy_mae:.3e} eV/atom; {res.seconds:.1f} s")
