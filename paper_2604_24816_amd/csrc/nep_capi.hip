@@ -109,7 +109,7 @@ struct nep_system {
   double *x, *v, *x_alt, *v_alt, *x_build;
   int32_t *type, *type_alt, *perm, *perm_alt, *cellid, *cell_sorted, *src, *key;
   int32_t *cell_count, *cell_start, *cell_fill, *scan_tmp;
-  int32_t *nbrR, *cntR, *nbrA, *cntA, *actR, *nactR, *actA, *nactA;
+  int32_t *nbrR, *cntR, *nbrA, *cntA, *bpR, *bpA, *nactR, *nactA;
   float *F[2], *U, *FpR, *G;
   float *gF, *vjp, *qs;
   double *partial, *gpart, *res, *staging;
@@ -157,9 +157,9 @@ int64_t layout(nep_system* s, char* base, int64_t N, int capR, int capA, int max
   S.cntR = c.take<int32_t>(N);
   S.nbrA = c.take<int32_t>((int64_t)capA * N);
   S.cntA = c.take<int32_t>(N);
-  S.actR = c.take<int32_t>((int64_t)capR * N);
+  S.bpR = c.take<int32_t>((int64_t)kNumBins * N);
+  S.bpA = c.take<int32_t>((int64_t)kNumBins * N);
   S.nactR = c.take<int32_t>(N);
-  S.actA = c.take<int32_t>((int64_t)capA * N);
   S.nactA = c.take<int32_t>(N);
   S.F[0] = c.take<float>(3 * N);
   S.F[1] = c.take<float>(3 * N);
@@ -244,12 +244,10 @@ EvalBuffers eval_buffers(nep_system* s, int slot) {
   b.x = s->x;
   b.type = s->type;
   b.nbrR = s->nbrR;
-  b.cntR = s->cntR;
-  b.capR = s->capR;
-  b.capA = s->capA;
-  b.actR = s->actR;
+  b.nbrA = s->nbrA;
+  b.bpR = s->bpR;
+  b.bpA = s->bpA;
   b.nactR = s->nactR;
-  b.actA = s->actA;
   b.nactA = s->nactA;
   b.U = s->U;
   b.FpR = s->FpR;
@@ -282,12 +280,11 @@ int reduce_ew(nep_system* s, int base) {
 }
 
 int rebuild(nep_system* s, double skin, int force) {
-  const double cutR = s->model[0].hp.rc_radial + skin;
-  const double cutA = s->model[0].hp.rc_angular + skin;
-  HIPCHK(launch_rebuild(s->N, s->grid, cutR, cutA, s->capR, s->capA, s->x, s->v, s->type, s->perm, s->x_alt,
-                        s->v_alt, s->type_alt, s->perm_alt, s->x_build, s->cellid, s->cell_sorted, s->src,
-                        s->key, s->cell_count, s->cell_start, s->cell_fill, s->scan_tmp, s->nbrR, s->cntR,
-                        s->nbrA, s->cntA, s->flags, s->st));
+  HIPCHK(launch_rebuild(s->N, s->grid, s->model[0].hp.rc_radial, s->model[0].hp.rc_angular, skin, s->capR,
+                        s->capA, s->x, s->v, s->type, s->perm, s->x_alt, s->v_alt, s->type_alt, s->perm_alt,
+                        s->x_build, s->cellid, s->cell_sorted, s->src, s->key, s->cell_count, s->cell_start,
+                        s->cell_fill, s->scan_tmp, s->nbrR, s->cntR, s->nbrA, s->cntA, s->bpR, s->bpA,
+                        s->flags, s->st));
   (void)force;
   return NEP_OK;
 }
@@ -569,16 +566,21 @@ int nep_export_neighbors(nep_system* s, int32_t which, int64_t* offsets, int32_t
   if (!s->have_list) return fail(s, NEP_ERR_STALE_LIST, "no list built");
   const int64_t N = s->N;
   const int cap = which == 0 ? s->capR : s->capA;
-  int32_t* rows = which == 0 ? s->actR : s->actA;  // scratch, rewritten by every evaluation
-  int32_t* rcnt = which == 0 ? s->nactR : s->nactA;
-  HIPCHK(launch_export(N, s->perm, which == 0 ? s->nbrR : s->nbrA, which == 0 ? s->cntR : s->cntA, cap, rows,
-                       rcnt, s->st));
+  // rows of original ids are produced in chunks that fit the staging buffer (3N doubles)
+  const int64_t chunk = std::max<int64_t>(1, (3 * N * (int64_t)sizeof(double)) / ((int64_t)cap * 4 + 4));
+  int32_t* rows = reinterpret_cast<int32_t*>(s->staging);
+  int32_t* rcnt = rows + chunk * cap;
   std::vector<int32_t> cnt(N);
-  HIPCHK(hipMemcpyAsync(cnt.data(), rcnt, N * sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
   std::vector<int32_t> all((size_t)N * cap);
-  HIPCHK(hipMemcpyAsync(all.data(), rows, (size_t)N * cap * sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
-  HIPCHK(hipStreamSynchronize(s->st));
-  s->force_valid[0] = s->force_valid[1] = false;
+  for (int64_t o0 = 0; o0 < N; o0 += chunk) {
+    const int64_t o1 = std::min(N, o0 + chunk);
+    HIPCHK(launch_export(N, s->perm, which == 0 ? s->nbrR : s->nbrA, which == 0 ? s->cntR : s->cntA, cap, o0, o1,
+                         rows, rcnt, s->st));
+    HIPCHK(hipMemcpyAsync(cnt.data() + o0, rcnt, (o1 - o0) * sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipMemcpyAsync(all.data() + o0 * cap, rows, (size_t)(o1 - o0) * cap * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s->st));
+    HIPCHK(hipStreamSynchronize(s->st));
+  }
   offsets[0] = 0;
   for (int64_t o = 0; o < N; ++o) offsets[o + 1] = offsets[o] + cnt[o];
   if (offsets[N] > cap_total) return fail(s, NEP_ERR_ARG, "cap_total too small");
@@ -651,7 +653,8 @@ int vv_step(nep_system* s, int slot, int prec, double dt, int rebuild_every, dou
   if (ev) HIPCHK(hipEventRecord(ev[0], s->st));
   HIPCHK(launch_set_flag(s->flags, FLAG_REBUILD, scheduled, s->st));
   HIPCHK(launch_kick_drift(s->N, dt, s->grid, s->F[slot], s->type, s->mt, s->x, s->v, s->x_build,
-                           0.25 * skin * skin, s->flags, s->st));
+                           0.25 * skin * skin, s->flags, s->partial, s->st));
+  HIPCHK(launch_select_bin(s->partial, s->nblocks, s->flags, skin, s->st));
   if (ev) HIPCHK(hipEventRecord(ev[1], s->st));
   int st = rebuild(s, skin, 0);
   if (st) return st;

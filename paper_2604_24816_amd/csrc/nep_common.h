@@ -15,9 +15,9 @@ constexpr int kNumXcd = 8;           // MI355X: 8 accelerator complex dies, one 
 constexpr int kPartialStride = 16;   // doubles per workgroup in reduction partials
 
 // Energy/virial partial slots.
-enum { P_ENERGY = 0, P_VIR = 1 /* 9 values */, P_KE = 10, P_ERR2 = 11, P_ERRMAX = 12 };
+enum { P_ENERGY = 0, P_VIR = 1 /* 9 values */, P_KE = 10, P_ERR2 = 11, P_ERRMAX = 12, P_MAXD2 = 13 };
 
-// Device flag words (int32 unless noted).
+// Device flag words (int32).
 enum {
   FLAG_OVF_R = 0,      // max radial list length seen (atomicMax)
   FLAG_OVF_A = 1,      // max angular list length seen
@@ -25,8 +25,21 @@ enum {
   FLAG_NONFINITE = 3,  // NaN/Inf seen
   FLAG_REBUILD = 4,    // 1 = the current step rebuilds its lists
   FLAG_NBUILD = 5,     // number of list builds (device counter)
+  FLAG_SPARE = 6,
+  FLAG_BIN = 7,        // distance bin the evaluation kernels read up to (see kBinFrac)
   FLAG_COUNT = 8
 };
+
+// The lists with skin are stored partitioned into distance bins (by the distance
+// at build time): bin k holds pairs with rc + kBinFrac[k-1] skin <= r < rc + kBinFrac[k] skin
+// (bin 0: r < rc). Between rebuilds a pair distance changes by at most twice the
+// largest displacement d since the build, so an evaluation only needs the bins up
+// to the first k with kBinFrac[k] skin >= 2 d; every pair there is still tested
+// against the true cutoff. bp[k][i] = number of entries of atom i in bins 0..k.
+constexpr int kNumBins = 8;
+__host__ __device__ constexpr float bin_frac(int k) {
+  return k == 0 ? 0.f : (k == 1 ? 0.05f : (k == 2 ? 0.1f : (k == 3 ? 0.2f : (k == 4 ? 0.3f : (k == 5 ? 0.45f : (k == 6 ? 0.7f : 1.0f))))));
+}
 
 // Orthorhombic cell grid over the box.
 struct CellGrid {
@@ -80,15 +93,17 @@ inline int grid_blocks(int64_t n, int block = kBlock) {
 hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t st);
 hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st);
 hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st);
-hipError_t launch_rebuild(int64_t N, const CellGrid& g, double cutR, double cutA, int capR, int capA,
-                          double* x, double* v, int32_t* type, int32_t* perm,
+hipError_t launch_rebuild(int64_t N, const CellGrid& g, double rcR, double rcA, double skin, int capR,
+                          int capA, double* x, double* v, int32_t* type, int32_t* perm,
                           double* x_alt, double* v_alt, int32_t* type_alt, int32_t* perm_alt,
                           double* x_build, int32_t* cellid, int32_t* cell_sorted, int32_t* src,
                           int32_t* key, int32_t* cell_count, int32_t* cell_start, int32_t* cell_fill,
                           int32_t* scan_tmp, int32_t* nbrR, int32_t* cntR, int32_t* nbrA,
-                          int32_t* cntA, int32_t* flags, hipStream_t st);
+                          int32_t* cntA, int32_t* bpR, int32_t* bpA, int32_t* flags, hipStream_t st);
+// Rows of original ids [o_lo, o_hi), ascending, into rows[(o - o_lo) * cap + k].
 hipError_t launch_export(int64_t N, const int32_t* perm, const int32_t* nbr, const int32_t* cnt,
-                         int cap, int32_t* rows, int32_t* row_cnt, hipStream_t st);
+                         int cap, int64_t o_lo, int64_t o_hi, int32_t* rows, int32_t* row_cnt,
+                         hipStream_t st);
 
 // Evaluation (nep_eval.hip)
 struct EvalBuffers {
@@ -96,13 +111,12 @@ struct EvalBuffers {
   double box[3];
   const double* x;       // [3][N]
   const int32_t* type;   // [N]
-  const int32_t* nbrR;   // [capR][N] lists with skin
-  const int32_t* cntR;
-  int capR, capA;
-  int32_t* actR;         // [capR][N] pairs with r < rc_radial
-  int32_t* nactR;
-  int32_t* actA;         // [capA][N] pairs with r < rc_angular
-  int32_t* nactA;
+  const int32_t* nbrR;   // [capR][N] radial list with skin, in distance bins
+  const int32_t* nbrA;   // [capA][N] angular list with skin, in distance bins
+  const int32_t* bpR;    // [kNumBins][N] bin breakpoints of the radial list
+  const int32_t* bpA;    // [kNumBins][N] bin breakpoints of the angular list
+  int32_t* nactR;        // [N] pairs inside rc_radial at this evaluation
+  int32_t* nactA;        // [N] pairs inside rc_angular
   float* U;              // [N]
   float* FpR;            // [nR][N] dU/dq for the radial block
   float* G;              // [nA * ncomp][N] dU/ds for the angular accumulators
@@ -128,7 +142,10 @@ hipError_t launch_max_partials(const double* partial, int nblocks, int slot, dou
                                hipStream_t st);
 hipError_t launch_kick_drift(int64_t N, double dt, CellGrid g, const float* F, const int32_t* type,
                              MassTable mt, double* x, double* v, const double* x_build,
-                             double half_skin2, int32_t* flags, hipStream_t st);
+                             double half_skin2, int32_t* flags, double* partial, hipStream_t st);
+// FLAG_BIN from the per-workgroup displacement maxima the drift kernel left in partial.
+hipError_t launch_select_bin(const double* partial, int nblocks, int32_t* flags, double skin,
+                             hipStream_t st);
 hipError_t launch_kick(int64_t N, double dt, const float* F, const int32_t* type, MassTable mt,
                        double* v, hipStream_t st);
 hipError_t launch_kick_diff(int64_t N, double dt, const float* Fa, const float* Fb,

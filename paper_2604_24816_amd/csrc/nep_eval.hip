@@ -195,28 +195,10 @@ __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers 
 
   if (valid) {
     const double xi = x[i], yi = x[N + i], zi = x[2 * N + i];
-    // 0. compaction of the skin list to the true cutoffs
-    const int cnt = b.cntR[i];
-    const double rcR2 = m.rcR64 * m.rcR64, rcA2 = m.rcA64 * m.rcA64;
     int nr = 0, na = 0;
-    for (int p = 0; p < cnt; ++p) {
-      const int32_t j = b.nbrR[(int64_t)p * N + i];
-      const double dx = min_image(x[j] - xi, Lx);
-      const double dy = min_image(x[N + j] - yi, Ly);
-      const double dz = min_image(x[2 * N + j] - zi, Lz);
-      const double r2 = dx * dx + dy * dy + dz * dz;
-      if (r2 < rcR2) {
-        b.actR[(int64_t)nr * N + i] = j;
-        ++nr;
-        if (r2 < rcA2) {
-          b.actA[(int64_t)na * N + i] = j;
-          ++na;
-        }
-      }
-    }
+    desc_accumulate<S, MULTI>(m, b, i, ti, xi, yi, zi, Lx, Ly, Lz, q, s, nr, na);
     b.nactR[i] = nr;
     b.nactA[i] = na;
-    desc_accumulate<S, MULTI>(m, b, i, ti, xi, yi, zi, Lx, Ly, Lz, nr, na, q, s);
     desc_finish<S>(s, q);
   }
   // 3. network (whole wavefronts take part; inactive lanes carry zeros)
@@ -283,11 +265,12 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
 #pragma unroll
     for (int n = 0; n < NR; ++n) fpi[n] = b.FpR[(int64_t)n * N + i];
     // radial: gather, F_i += (Fp_i . g'^{ij} + Fp_j . g'^{ji}) u
-    const int nr = b.nactR[i];
-    for (int p = 0; p < nr; ++p) {
-      const int32_t j = b.actR[(int64_t)p * N + i];
+    const double rcR2 = m.rcR64 * m.rcR64, rcA2 = m.rcA64 * m.rcA64;
+    const int kR = list_bound(b.bpR, b.flags, N, i);
+    for (int p = 0; p < kR; ++p) {
+      const int32_t j = b.nbrR[(int64_t)p * N + i];
       float dx, dy, dz;
-      pair_vec(x, N, j, xi, yi, zi, Lx, Ly, Lz, dx, dy, dz);
+      if (!pair_inside(x, N, j, xi, yi, zi, Lx, Ly, Lz, rcR2, dx, dy, dz)) continue;
       const float r = sqrtf(dx * dx + dy * dy + dz * dz);
       const float rinv = 1.f / r;
       const int tj = MULTI ? b.type[j] : 0;
@@ -326,11 +309,11 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
     float G[NA * NC];
 #pragma unroll
     for (int k = 0; k < NA * NC; ++k) G[k] = b.G[(int64_t)k * N + i];
-    const int na = b.nactA[i];
-    for (int p = 0; p < na; ++p) {
-      const int32_t j = b.actA[(int64_t)p * N + i];
+    const int kA = list_bound(b.bpA, b.flags, N, i);
+    for (int p = 0; p < kA; ++p) {
+      const int32_t j = b.nbrA[(int64_t)p * N + i];
       float dx, dy, dz;
-      pair_vec(x, N, j, xi, yi, zi, Lx, Ly, Lz, dx, dy, dz);
+      if (!pair_inside(x, N, j, xi, yi, zi, Lx, Ly, Lz, rcA2, dx, dy, dz)) continue;
       const float r = sqrtf(dx * dx + dy * dy + dz * dz);
       const float rinv = 1.f / r;
       const int tj = MULTI ? b.type[j] : 0;

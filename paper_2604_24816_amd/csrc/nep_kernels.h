@@ -134,21 +134,48 @@ using SurShape = Shape<5, 9, 5, 9, 2, false, 8>;
 constexpr int kLdsStride = 33;  // 32 columns + 1 pad word against bank conflicts
 
 
+// Pair test for one entry of a list with skin: FP64 minimum-image vector, kept when
+// r^2 < cut2 (the true cutoff); the vector is rounded to FP32 after the subtraction.
+__device__ __forceinline__ bool pair_inside(const double* __restrict__ x, int64_t N, int32_t j, double xi,
+                                            double yi, double zi, double Lx, double Ly, double Lz, double cut2,
+                                            float& dx, float& dy, float& dz) {
+  const double ex = min_image(x[j] - xi, Lx);
+  const double ey = min_image(x[N + j] - yi, Ly);
+  const double ez = min_image(x[2 * N + j] - zi, Lz);
+  if (!(ex * ex + ey * ey + ez * ez < cut2)) return false;
+  dx = (float)ex;
+  dy = (float)ey;
+  dz = (float)ez;
+  return true;
+}
+
+// Number of list entries of atom i the current evaluation must visit: the entries
+// of the distance bins that pairs can have reached since the last build.
+__device__ __forceinline__ int list_bound(const int32_t* __restrict__ bp, const int32_t* __restrict__ flags,
+                                          int64_t N, int64_t i) {
+  return bp[(int64_t)flags[FLAG_BIN] * N + i];
+}
+
 // Radial descriptors q[0..NR) and angular accumulators s[NA][NC] of center i over
-// its active lists (pairs inside the true cutoffs), all channels in one pass over
-// the neighbours (geometry computed once per pair and reused for every n).
+// the pairs inside the true cutoffs, all channels in one pass over the neighbours
+// (geometry computed once per pair and reused for every n). Returns the pair counts.
 template <class S, bool MULTI>
 __device__ __forceinline__ void desc_accumulate(const ModelDev& m, const EvalBuffers& b, int64_t i, int ti,
                                                 double xi, double yi, double zi, double Lx, double Ly,
-                                                double Lz, int nr, int na, float* q, float* s) {
+                                                double Lz, float* q, float* s, int& nr, int& na) {
   constexpr int NR = S::NR, NA = S::NA, NC = S::NC;
   const int64_t N = b.N;
   const double* __restrict__ x = b.x;
   const float rcR_inv = 1.f / m.rcR, rcA_inv = 1.f / m.rcA;
-  for (int p = 0; p < nr; ++p) {
-    const int32_t j = b.actR[(int64_t)p * N + i];
+  const double rcR2 = m.rcR64 * m.rcR64, rcA2 = m.rcA64 * m.rcA64;
+  nr = 0;
+  na = 0;
+  const int kR = list_bound(b.bpR, b.flags, N, i);
+  for (int p = 0; p < kR; ++p) {
+    const int32_t j = b.nbrR[(int64_t)p * N + i];
     float dx, dy, dz;
-    pair_vec(x, N, j, xi, yi, zi, Lx, Ly, Lz, dx, dy, dz);
+    if (!pair_inside(x, N, j, xi, yi, zi, Lx, Ly, Lz, rcR2, dx, dy, dz)) continue;
+    ++nr;
     const float r = sqrtf(dx * dx + dy * dy + dz * dz);
     const int tj = MULTI ? b.type[j] : 0;
     float g[NR];
@@ -156,10 +183,12 @@ __device__ __forceinline__ void desc_accumulate(const ModelDev& m, const EvalBuf
 #pragma unroll
     for (int n = 0; n < NR; ++n) q[n] += g[n];
   }
-  for (int p = 0; p < na; ++p) {
-    const int32_t j = b.actA[(int64_t)p * N + i];
+  const int kA = list_bound(b.bpA, b.flags, N, i);
+  for (int p = 0; p < kA; ++p) {
+    const int32_t j = b.nbrA[(int64_t)p * N + i];
     float dx, dy, dz;
-    pair_vec(x, N, j, xi, yi, zi, Lx, Ly, Lz, dx, dy, dz);
+    if (!pair_inside(x, N, j, xi, yi, zi, Lx, Ly, Lz, rcA2, dx, dy, dz)) continue;
+    ++na;
     const float r = sqrtf(dx * dx + dy * dy + dz * dz);
     const float rinv = 1.f / r;
     const int tj = MULTI ? b.type[j] : 0;

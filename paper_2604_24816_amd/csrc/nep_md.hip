@@ -35,11 +35,12 @@ __device__ __forceinline__ double wrap_coord(double xv, double L) {
 __global__ void k_kick_drift(int64_t N, double dt, CellGrid g, const float* __restrict__ F,
                              const int32_t* __restrict__ type, MassTable mt, double* __restrict__ x,
                              double* __restrict__ v, const double* __restrict__ xb, double half_skin2,
-                             int32_t* __restrict__ flags) {
+                             int32_t* __restrict__ flags, double* __restrict__ partial) {
+  __shared__ double sh[kBlock];
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= N) return;
-  const double inv = mt.inv_mxi[type[p]];
   double d2 = 0.0;
+  if (p < N) {
+  const double inv = mt.inv_mxi[type[p]];
   for (int c = 0; c < 3; ++c) {
     double vv = v[c * N + p] + 0.5 * dt * (double)F[c * N + p] * inv;
     double xx = wrap_coord(x[c * N + p] + dt * vv, g.box[c]);
@@ -49,6 +50,37 @@ __global__ void k_kick_drift(int64_t N, double dt, CellGrid g, const float* __re
     d2 += d * d;
   }
   if (!(d2 <= half_skin2)) flags[FLAG_REBUILD] = 1;  // also catches NaN
+  if (!(d2 == d2)) d2 = 1e300;
+  }
+  // largest squared displacement since the build, per workgroup
+  __syncthreads();
+  sh[threadIdx.x] = d2;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < (unsigned)off) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * kPartialStride + P_MAXD2] = sh[0];
+}
+
+// FLAG_BIN = first bin k with bin_frac(k) * skin >= 2 * (largest displacement since the build);
+// a rebuild later in the same step resets it to 0.
+__global__ void k_select_bin(const double* __restrict__ partial, int nblocks, int32_t* flags, double skin) {
+  __shared__ double sh[kBlock];
+  double m = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kBlock) m = fmax(m, partial[(int64_t)b * kPartialStride + P_MAXD2]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < (unsigned)off) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double d = sqrt(sh[0]);
+  int k = kNumBins - 1;
+  for (int j = kNumBins - 1; j >= 0; --j)
+    if ((double)bin_frac(j) * skin >= 2.0 * d * (1.0 + 1e-12)) k = j;
+  flags[FLAG_BIN] = k;
 }
 
 __global__ void k_kick(int64_t N, double dt, const float* __restrict__ F, const int32_t* __restrict__ type,
@@ -218,9 +250,14 @@ hipError_t launch_max_partials(const double* partial, int nblocks, int slot, dou
 
 hipError_t launch_kick_drift(int64_t N, double dt, CellGrid g, const float* F, const int32_t* type,
                              MassTable mt, double* x, double* v, const double* x_build, double half_skin2,
-                             int32_t* flags, hipStream_t st) {
+                             int32_t* flags, double* partial, hipStream_t st) {
   hipLaunchKernelGGL(k_kick_drift, dim3(grid_blocks(N)), dim3(kBlock), 0, st, N, dt, g, F, type, mt, x, v,
-                     x_build, half_skin2, flags);
+                     x_build, half_skin2, flags, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_bin(const double* partial, int nblocks, int32_t* flags, double skin, hipStream_t st) {
+  hipLaunchKernelGGL(k_select_bin, dim3(1), dim3(kBlock), 0, st, partial, nblocks, flags, skin);
   return hipGetLastError();
 }
 

@@ -182,7 +182,7 @@ __global__ void k_copy_back(int64_t N, const double* __restrict__ x2, const doub
 
 // r^2 of the FP64 minimum-image pair vector, with no contraction into FMA so that
 // the result equals (dx*dx + dy*dy) + dz*dz rounded after every operation.
-__device__ __attribute__((noinline)) double pair_r2_exact(double xi, double yi, double zi, double xj,
+__device__ __forceinline__ double pair_r2_exact(double xi, double yi, double zi, double xj,
                                                           double yj, double zj, double Lx, double Ly,
                                                           double Lz) {
 #pragma clang fp contract(off)
@@ -196,14 +196,36 @@ __device__ __attribute__((noinline)) double pair_r2_exact(double xi, double yi, 
   return s + szz;
 }
 
+__device__ __forceinline__ int bin_of(double r2, const double* t) {
+  int k = 0;
+#pragma unroll
+  for (int m = 0; m < kNumBins - 1; ++m) k += (r2 >= t[m]) ? 1 : 0;
+  return k;
+}
+
+// One thread per atom. Two passes over the 27-cell stencil: the first counts the
+// pairs per distance bin, the second writes each pair at its bin's offset, so each
+// atom's list is ordered by bin (stencil order inside a bin).
 __global__ void __launch_bounds__(kBlock)
 k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t* __restrict__ start,
-              const int32_t* __restrict__ cell_sorted, double cutR2, double cutA2, int capR, int capA,
+              const int32_t* __restrict__ cell_sorted, double rcR, double rcA, double skin, int capR, int capA,
               int32_t* __restrict__ nbrR, int32_t* __restrict__ cntR, int32_t* __restrict__ nbrA,
-              int32_t* __restrict__ cntA, int32_t* __restrict__ flags) {
+              int32_t* __restrict__ cntA, int32_t* __restrict__ bpR, int32_t* __restrict__ bpA,
+              int32_t* __restrict__ flags) {
   if (flags[FLAG_REBUILD] == 0) return;
   const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (p >= N) return;
+  // squared bin edges; the last edge is the list cutoff (rc + skin)^2
+  double tR[kNumBins], tA[kNumBins];
+#pragma unroll
+  for (int k = 0; k < kNumBins - 1; ++k) {
+    const double er = rcR + (double)bin_frac(k) * skin, ea = rcA + (double)bin_frac(k) * skin;
+    tR[k] = er * er;
+    tA[k] = ea * ea;
+  }
+  const double cutR = rcR + skin, cutA = rcA + skin;
+  tR[kNumBins - 1] = cutR * cutR;
+  tA[kNumBins - 1] = cutA * cutA;
   const double xi = x[p], yi = x[N + p], zi = x[2 * N + p];
   const int c = cell_sorted[p];
   const int cx = c % g.nc[0];
@@ -214,50 +236,85 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
     lo[d] = g.nc[d] >= 3 ? -1 : 0;
     nof[d] = g.nc[d] >= 3 ? 3 : g.nc[d];
   }
-  int nr = 0, na = 0;
-  for (int a = 0; a < nof[2]; ++a) {
-    const int zc = (cz + lo[2] + a + g.nc[2]) % g.nc[2];
-    for (int b = 0; b < nof[1]; ++b) {
-      const int yc = (cy + lo[1] + b + g.nc[1]) % g.nc[1];
-      for (int e = 0; e < nof[0]; ++e) {
-        const int xc = (cx + lo[0] + e + g.nc[0]) % g.nc[0];
-        const int cc = (zc * g.nc[1] + yc) * g.nc[0] + xc;
-        const int q0 = start[cc], q1 = start[cc + 1];
-        for (int q = q0; q < q1; ++q) {
-          if (q == p) continue;
-          const double r2 = pair_r2_exact(xi, yi, zi, x[q], x[N + q], x[2 * N + q], g.box[0],
-                                          g.box[1], g.box[2]);
-          if (r2 < cutR2) {
-            if (nr < capR) nbrR[(int64_t)nr * N + p] = q;
-            ++nr;
-            if (r2 < cutA2) {
-              if (na < capA) nbrA[(int64_t)na * N + p] = q;
-              ++na;
+  int cR[kNumBins], cA[kNumBins];
+#pragma unroll
+  for (int k = 0; k < kNumBins; ++k) {
+    cR[k] = 0;
+    cA[k] = 0;
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int a = 0; a < nof[2]; ++a) {
+      const int zc = (cz + lo[2] + a + g.nc[2]) % g.nc[2];
+      for (int b = 0; b < nof[1]; ++b) {
+        const int yc = (cy + lo[1] + b + g.nc[1]) % g.nc[1];
+        for (int e = 0; e < nof[0]; ++e) {
+          const int xc = (cx + lo[0] + e + g.nc[0]) % g.nc[0];
+          const int cc = (zc * g.nc[1] + yc) * g.nc[0] + xc;
+          const int q0 = start[cc], q1 = start[cc + 1];
+          for (int q = q0; q < q1; ++q) {
+            if (q == p) continue;
+            const double r2 = pair_r2_exact(xi, yi, zi, x[q], x[N + q], x[2 * N + q], g.box[0], g.box[1],
+                                            g.box[2]);
+            if (!(r2 < tR[kNumBins - 1])) continue;
+            const int br = bin_of(r2, tR);
+            if (pass == 0) {
+              cR[br] += 1;
+            } else {
+              const int pos = cR[br]++;
+              if (pos < capR) nbrR[(int64_t)pos * N + p] = q;
+            }
+            if (r2 < tA[kNumBins - 1]) {
+              const int ba = bin_of(r2, tA);
+              if (pass == 0) {
+                cA[ba] += 1;
+              } else {
+                const int pos = cA[ba]++;
+                if (pos < capA) nbrA[(int64_t)pos * N + p] = q;
+              }
             }
           }
         }
       }
     }
+    if (pass == 0) {
+      // counts -> start offsets of each bin; record cumulative breakpoints
+      int sr = 0, sa = 0;
+#pragma unroll
+      for (int k = 0; k < kNumBins; ++k) {
+        const int nr_k = cR[k], na_k = cA[k];
+        cR[k] = sr;
+        cA[k] = sa;
+        sr += nr_k;
+        sa += na_k;
+        bpR[(int64_t)k * N + p] = sr < capR ? sr : capR;
+        bpA[(int64_t)k * N + p] = sa < capA ? sa : capA;
+      }
+      cntR[p] = sr < capR ? sr : capR;
+      cntA[p] = sa < capA ? sa : capA;
+      if (sr > capR) atomicMax(&flags[FLAG_OVF_R], sr);
+      if (sa > capA) atomicMax(&flags[FLAG_OVF_A], sa);
+    }
   }
-  cntR[p] = nr < capR ? nr : capR;
-  cntA[p] = na < capA ? na : capA;
-  if (nr > capR) atomicMax(&flags[FLAG_OVF_R], nr);
-  if (na > capA) atomicMax(&flags[FLAG_OVF_A], na);
 }
 
+// After a build the positions equal the build positions: displacement 0, bin 0.
 __global__ void k_count_build(int32_t* flags) {
-  if (flags[FLAG_REBUILD] != 0 && threadIdx.x == 0) flags[FLAG_NBUILD] += 1;
+  if (flags[FLAG_REBUILD] != 0 && threadIdx.x == 0) {
+    flags[FLAG_NBUILD] += 1;
+    flags[FLAG_BIN] = 0;
+  }
 }
 
-// Lists in original ids, one row per original atom, ascending.
+// Lists in original ids, one row per original atom in [o_lo, o_hi), ascending.
 __global__ void k_export(int64_t N, const int32_t* __restrict__ perm, const int32_t* __restrict__ nbr,
-                         const int32_t* __restrict__ cnt, int cap, int32_t* __restrict__ rows,
-                         int32_t* __restrict__ row_cnt) {
+                         const int32_t* __restrict__ cnt, int cap, int64_t o_lo, int64_t o_hi,
+                         int32_t* __restrict__ rows, int32_t* __restrict__ row_cnt) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= N) return;
   const int64_t o = perm[p];
+  if (o < o_lo || o >= o_hi) return;
   const int n = cnt[p];
-  int32_t* row = rows + o * cap;
+  int32_t* row = rows + (o - o_lo) * cap;
   for (int k = 0; k < n; ++k) {
     const int32_t val = perm[nbr[(int64_t)k * N + p]];
     int j = k - 1;
@@ -267,7 +324,7 @@ __global__ void k_export(int64_t N, const int32_t* __restrict__ perm, const int3
     }
     row[j + 1] = val;
   }
-  row_cnt[o] = n;
+  row_cnt[o - o_lo] = n;
 }
 
 }  // namespace
@@ -290,13 +347,13 @@ hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st) {
 
 // Every kernel below returns at once when flags[FLAG_REBUILD] == 0, so the whole
 // rebuild can be enqueued each step and skipped on the device without a host sync.
-hipError_t launch_rebuild(int64_t N, const CellGrid& g, double cutR, double cutA, int capR, int capA,
-                          double* x, double* v, int32_t* type, int32_t* perm, double* x_alt,
+hipError_t launch_rebuild(int64_t N, const CellGrid& g, double rcR, double rcA, double skin, int capR,
+                          int capA, double* x, double* v, int32_t* type, int32_t* perm, double* x_alt,
                           double* v_alt, int32_t* type_alt, int32_t* perm_alt, double* x_build,
                           int32_t* cellid, int32_t* cell_sorted, int32_t* src, int32_t* key,
                           int32_t* cell_count, int32_t* cell_start, int32_t* cell_fill,
                           int32_t* scan_tmp, int32_t* nbrR, int32_t* cntR, int32_t* nbrA,
-                          int32_t* cntA, int32_t* flags, hipStream_t st) {
+                          int32_t* cntA, int32_t* bpR, int32_t* bpA, int32_t* flags, hipStream_t st) {
   const int nb = grid_blocks(N);
   const int ncell = g.ncell;
   hipError_t e;
@@ -318,17 +375,17 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, double cutR, double cutA
                      x_alt, v_alt, type_alt, perm_alt, x_build, cell_sorted, flags);
   hipLaunchKernelGGL(k_copy_back, dim3(nb), dim3(kBlock), 0, st, N, x_alt, v_alt, type_alt, perm_alt,
                      x, v, type, perm, flags);
-  const double cr2 = cutR * cutR, ca2 = cutA * cutA;
   hipLaunchKernelGGL(k_build_lists, dim3(nb), dim3(kBlock), 0, st, N, g, x, cell_start, cell_sorted,
-                     cr2, ca2, capR, capA, nbrR, cntR, nbrA, cntA, flags);
+                     rcR, rcA, skin, capR, capA, nbrR, cntR, nbrA, cntA, bpR, bpA, flags);
   hipLaunchKernelGGL(k_count_build, dim3(1), dim3(64), 0, st, flags);
   return hipGetLastError();
 }
 
 hipError_t launch_export(int64_t N, const int32_t* perm, const int32_t* nbr, const int32_t* cnt,
-                         int cap, int32_t* rows, int32_t* row_cnt, hipStream_t st) {
-  hipLaunchKernelGGL(k_export, dim3(grid_blocks(N)), dim3(kBlock), 0, st, N, perm, nbr, cnt, cap,
-                     rows, row_cnt);
+                         int cap, int64_t o_lo, int64_t o_hi, int32_t* rows, int32_t* row_cnt,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_export, dim3(grid_blocks(N)), dim3(kBlock), 0, st, N, perm, nbr, cnt, cap, o_lo,
+                     o_hi, rows, row_cnt);
   return hipGetLastError();
 }
 

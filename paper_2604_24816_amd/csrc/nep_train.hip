@@ -50,16 +50,18 @@ k_train_backward(ModelDev m, EvalBuffers b, const float* __restrict__ gF, double
     for (int k = 0; k < NA * NC; ++k) s[k] = 0.f;
     const int ti = MULTI ? b.type[i] : 0;
     const double xi = x[i], yi = x[N + i], zi = x[2 * N + i];
-    const int nr = b.nactR[i], na = b.nactA[i];
-    desc_accumulate<S, MULTI>(m, b, i, ti, xi, yi, zi, Lx, Ly, Lz, nr, na, q, s);
+    int nr = 0, na = 0;
+    desc_accumulate<S, MULTI>(m, b, i, ti, xi, yi, zi, Lx, Ly, Lz, q, s, nr, na);
+    const double rcR2 = m.rcR64 * m.rcR64, rcA2 = m.rcA64 * m.rcA64;
     desc_finish<S>(s, q);
     if (gF) {
       const float wi0 = gF[i], wi1 = gF[N + i], wi2 = gF[2 * N + i];
       // radial JVP: dq_n/dr_ij . w = g_n'(r) (u . w)
-      for (int p = 0; p < nr; ++p) {
-        const int32_t j = b.actR[(int64_t)p * N + i];
+      const int kR = list_bound(b.bpR, b.flags, N, i);
+      for (int p = 0; p < kR; ++p) {
+        const int32_t j = b.nbrR[(int64_t)p * N + i];
         float dx, dy, dz;
-        pair_vec(x, N, j, xi, yi, zi, Lx, Ly, Lz, dx, dy, dz);
+        if (!pair_inside(x, N, j, xi, yi, zi, Lx, Ly, Lz, rcR2, dx, dy, dz)) continue;
         const float r = sqrtf(dx * dx + dy * dy + dz * dz);
         const float rinv = 1.f / r;
         const int tj = MULTI ? b.type[j] : 0;
@@ -80,10 +82,11 @@ k_train_backward(ModelDev m, EvalBuffers b, const float* __restrict__ gF, double
       for (int n = 0; n < NA; ++n)
 #pragma unroll
         for (int lm = 0; lm < NC; ++lm) s[n * NC + lm] *= 2.f * kW[lm];
-      for (int p = 0; p < na; ++p) {
-        const int32_t j = b.actA[(int64_t)p * N + i];
+      const int kA = list_bound(b.bpA, b.flags, N, i);
+      for (int p = 0; p < kA; ++p) {
+        const int32_t j = b.nbrA[(int64_t)p * N + i];
         float dx, dy, dz;
-        pair_vec(x, N, j, xi, yi, zi, Lx, Ly, Lz, dx, dy, dz);
+        if (!pair_inside(x, N, j, xi, yi, zi, Lx, Ly, Lz, rcA2, dx, dy, dz)) continue;
         const float r = sqrtf(dx * dx + dy * dy + dz * dz);
         const float rinv = 1.f / r;
         const int tj = MULTI ? b.type[j] : 0;

@@ -58,7 +58,7 @@ def test_host_only_calls(lib):
     box = np.array([361.5, 361.5, 361.5])
     assert lib.nep_system_workspace_bytes(m.handle, None, ctypes.c_int64(4_000_000),
                                           box.ctypes.data_as(ctypes.c_void_p), 160, 96, ctypes.byref(ws)) == 0
-    assert 8e9 < ws.value < 2e10
+    assert 4e9 < ws.value < 2e10
     bad = np.array([1.0, np.nan])
     with pytest.raises(Exception):
         nep.NEPModel(hp, bad)
