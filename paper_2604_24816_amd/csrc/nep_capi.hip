@@ -71,14 +71,15 @@ struct Carver {
 
 CellGrid make_grid(const double box[3], double cut) {
   CellGrid g;
-  g.ncell = 1;
+  g.ncell = 8;
   for (int c = 0; c < 3; ++c) {
     int n = (int)std::floor(box[c] / cut);
     while (n > 1 && box[c] / n < cut * (1.0 + 1e-10)) --n;
     if (n < 1) n = 1;
     g.nc[c] = n;
+    g.nb[c] = (n + 1) / 2;
     g.box[c] = box[c];
-    g.ncell *= n;
+    g.ncell *= g.nb[c];
   }
   return g;
 }
@@ -249,6 +250,9 @@ EvalBuffers eval_buffers(nep_system* s, int slot) {
   b.bpA = s->bpA;
   b.nactR = s->nactR;
   b.nactA = s->nactA;
+  b.grid = s->grid;
+  b.cell_sorted = s->cell_sorted;
+  b.cell_start = s->cell_start;
   b.U = s->U;
   b.FpR = s->FpR;
   b.G = s->G;

@@ -41,12 +41,31 @@ __host__ __device__ constexpr float bin_frac(int k) {
   return k == 0 ? 0.f : (k == 1 ? 0.05f : (k == 2 ? 0.1f : (k == 3 ? 0.2f : (k == 4 ? 0.3f : (k == 5 ? 0.45f : (k == 6 ? 0.7f : 1.0f))))));
 }
 
-// Orthorhombic cell grid over the box.
+// Orthorhombic cell grid over the box. Cells are numbered brick by brick: bricks
+// of 2 x 2 x 2 cells in row-major brick order, cells inside a brick in row-major
+// order, so that consecutive cell ids (and the cell-sorted atoms of a 256-atom
+// tile) stay spatially compact. ncell counts brick slots (8 per brick); slots past
+// an odd grid edge hold no atoms.
 struct CellGrid {
   int nc[3];
+  int nb[3];
   int ncell;
   double box[3];
 };
+
+__host__ __device__ inline int cell_lin(const CellGrid& g, int cx, int cy, int cz) {
+  const int b = ((cz >> 1) * g.nb[1] + (cy >> 1)) * g.nb[0] + (cx >> 1);
+  return (b << 3) | ((cz & 1) << 2) | ((cy & 1) << 1) | (cx & 1);
+}
+
+// Cell coordinates of a cell id; false for brick slots outside the grid.
+__host__ __device__ inline bool cell_coords(const CellGrid& g, int lin, int& cx, int& cy, int& cz) {
+  const int b = lin >> 3;
+  cx = 2 * (b % g.nb[0]) + (lin & 1);
+  cy = 2 * ((b / g.nb[0]) % g.nb[1]) + ((lin >> 1) & 1);
+  cz = 2 * (b / (g.nb[0] * g.nb[1])) + ((lin >> 2) & 1);
+  return cx < g.nc[0] && cy < g.nc[1] && cz < g.nc[2];
+}
 
 // Device copy of one model (FP32 parameters, same packed order as the host FP64
 // vector) plus a bfloat16 copy of W0.
@@ -117,6 +136,9 @@ struct EvalBuffers {
   const int32_t* bpA;    // [kNumBins][N] bin breakpoints of the angular list
   int32_t* nactR;        // [N] pairs inside rc_radial at this evaluation
   int32_t* nactA;        // [N] pairs inside rc_angular
+  CellGrid grid;         // grid of the last list build
+  const int32_t* cell_sorted;  // [N] cell id of each (sorted) atom
+  const int32_t* cell_start;   // [ncell + 1] first atom of each cell
   float* U;              // [N]
   float* FpR;            // [nR][N] dU/dq for the radial block
   float* G;              // [nA * ncomp][N] dU/ds for the angular accumulators

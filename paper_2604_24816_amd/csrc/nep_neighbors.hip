@@ -42,7 +42,7 @@ __global__ void k_bin(int64_t N, CellGrid g, const double* __restrict__ x, int32
   const int cx = cell_coord(x[p], g.box[0], g.nc[0]);
   const int cy = cell_coord(x[N + p], g.box[1], g.nc[1]);
   const int cz = cell_coord(x[2 * N + p], g.box[2], g.nc[2]);
-  const int c = (cz * g.nc[1] + cy) * g.nc[0] + cx;
+  const int c = cell_lin(g, cx, cy, cz);
   cellid[p] = c;
   atomicAdd(&count[c], 1);
 }
@@ -227,10 +227,8 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
   tR[kNumBins - 1] = cutR * cutR;
   tA[kNumBins - 1] = cutA * cutA;
   const double xi = x[p], yi = x[N + p], zi = x[2 * N + p];
-  const int c = cell_sorted[p];
-  const int cx = c % g.nc[0];
-  const int cy = (c / g.nc[0]) % g.nc[1];
-  const int cz = c / (g.nc[0] * g.nc[1]);
+  int cx, cy, cz;
+  cell_coords(g, cell_sorted[p], cx, cy, cz);
   int lo[3], nof[3];
   for (int d = 0; d < 3; ++d) {
     lo[d] = g.nc[d] >= 3 ? -1 : 0;
@@ -249,7 +247,7 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
         const int yc = (cy + lo[1] + b + g.nc[1]) % g.nc[1];
         for (int e = 0; e < nof[0]; ++e) {
           const int xc = (cx + lo[0] + e + g.nc[0]) % g.nc[0];
-          const int cc = (zc * g.nc[1] + yc) * g.nc[0] + xc;
+          const int cc = cell_lin(g, xc, yc, zc);
           const int q0 = start[cc], q1 = start[cc + 1];
           for (int q = q0; q < q1; ++q) {
             if (q == p) continue;
