@@ -111,6 +111,8 @@ struct nep_system {
   int32_t *type, *type_alt, *perm, *perm_alt, *cellid, *cell_sorted, *src, *key;
   int32_t *cell_count, *cell_start, *cell_fill, *scan_tmp;
   int32_t *nbrR, *cntR, *nbrA, *cntA, *bpR, *bpA, *nactR, *nactA;
+  uint16_t *nbrAl, *selfl;
+  HaloTables ht;
   float *F[2], *U, *FpR, *G;
   float *gF, *vjp, *qs;
   double *partial, *gpart, *res, *staging;
@@ -158,6 +160,14 @@ int64_t layout(nep_system* s, char* base, int64_t N, int capR, int capA, int max
   S.cntR = c.take<int32_t>(N);
   S.nbrA = c.take<int32_t>((int64_t)capA * N);
   S.cntA = c.take<int32_t>(N);
+  S.nbrAl = c.take<uint16_t>((int64_t)capA * N);
+  S.selfl = c.take<uint16_t>(N);
+  {
+    const int64_t nt = grid_blocks(N);
+    S.ht.info = c.take<int32_t>(4 * nt);
+    S.ht.start = c.take<int32_t>(nt * kHaloCellsMax);
+    S.ht.off = c.take<int32_t>(nt * (kHaloCellsMax + 1));
+  }
   S.bpR = c.take<int32_t>((int64_t)kNumBins * N);
   S.bpA = c.take<int32_t>((int64_t)kNumBins * N);
   S.nactR = c.take<int32_t>(N);
@@ -250,9 +260,11 @@ EvalBuffers eval_buffers(nep_system* s, int slot) {
   b.bpA = s->bpA;
   b.nactR = s->nactR;
   b.nactA = s->nactA;
-  b.grid = s->grid;
-  b.cell_sorted = s->cell_sorted;
-  b.cell_start = s->cell_start;
+  b.nbrAl = s->nbrAl;
+  b.selfl = s->selfl;
+  b.hinfo = s->ht.info;
+  b.hstart = s->ht.start;
+  b.hoff = s->ht.off;
   b.U = s->U;
   b.FpR = s->FpR;
   b.G = s->G;
@@ -288,7 +300,7 @@ int rebuild(nep_system* s, double skin, int force) {
                         s->capA, s->x, s->v, s->type, s->perm, s->x_alt, s->v_alt, s->type_alt, s->perm_alt,
                         s->x_build, s->cellid, s->cell_sorted, s->src, s->key, s->cell_count, s->cell_start,
                         s->cell_fill, s->scan_tmp, s->nbrR, s->cntR, s->nbrA, s->cntA, s->bpR, s->bpA,
-                        s->flags, s->st));
+                        s->ht, s->nbrAl, s->selfl, s->flags, s->st));
   (void)force;
   return NEP_OK;
 }

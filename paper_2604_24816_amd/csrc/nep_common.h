@@ -67,6 +67,21 @@ __host__ __device__ inline bool cell_coords(const CellGrid& g, int lin, int& cx,
   return cx < g.nc[0] && cy < g.nc[1] && cz < g.nc[2];
 }
 
+// Force halo of a 256-atom tile (one workgroup of the force kernel): the non-empty
+// cells within one cell of a cell holding tile atoms, sorted by cell id, so their
+// atom ranges increase. Built once per list build; the angular list carries each
+// neighbour's index inside its tile's halo.
+constexpr int kTileCellsMax = 48;     // cells a tile may touch
+constexpr int kCandMax = 2048;        // >= 27 * kTileCellsMax, power of two
+constexpr int kHaloCellsMax = 512;    // cells per halo
+constexpr int kHaloMax = 4096;        // atoms per halo held in LDS
+constexpr uint16_t kNoLocal = 0xffff; // tile without an LDS halo
+struct HaloTables {
+  int32_t* info;   // [ntiles][4] = {ncells, natoms, ok, 0}
+  int32_t* start;  // [ntiles][kHaloCellsMax] first sorted atom of each halo cell
+  int32_t* off;    // [ntiles][kHaloCellsMax + 1] local offset of each halo cell
+};
+
 // Device copy of one model (FP32 parameters, same packed order as the host FP64
 // vector) plus a bfloat16 copy of W0.
 struct ModelDev {
@@ -118,7 +133,8 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, double rcR, double rcA, 
                           double* x_build, int32_t* cellid, int32_t* cell_sorted, int32_t* src,
                           int32_t* key, int32_t* cell_count, int32_t* cell_start, int32_t* cell_fill,
                           int32_t* scan_tmp, int32_t* nbrR, int32_t* cntR, int32_t* nbrA,
-                          int32_t* cntA, int32_t* bpR, int32_t* bpA, int32_t* flags, hipStream_t st);
+                          int32_t* cntA, int32_t* bpR, int32_t* bpA, HaloTables ht, uint16_t* nbrAl,
+                          uint16_t* selfl, int32_t* flags, hipStream_t st);
 // Rows of original ids [o_lo, o_hi), ascending, into rows[(o - o_lo) * cap + k].
 hipError_t launch_export(int64_t N, const int32_t* perm, const int32_t* nbr, const int32_t* cnt,
                          int cap, int64_t o_lo, int64_t o_hi, int32_t* rows, int32_t* row_cnt,
@@ -136,9 +152,11 @@ struct EvalBuffers {
   const int32_t* bpA;    // [kNumBins][N] bin breakpoints of the angular list
   int32_t* nactR;        // [N] pairs inside rc_radial at this evaluation
   int32_t* nactA;        // [N] pairs inside rc_angular
-  CellGrid grid;         // grid of the last list build
-  const int32_t* cell_sorted;  // [N] cell id of each (sorted) atom
-  const int32_t* cell_start;   // [ncell + 1] first atom of each cell
+  const uint16_t* nbrAl;  // [capA][N] halo-local index of each angular entry
+  const uint16_t* selfl;  // [N] halo-local index of the atom itself
+  const int32_t* hinfo;   // halo tables of the last list build (see HaloTables)
+  const int32_t* hstart;
+  const int32_t* hoff;
   float* U;              // [N]
   float* FpR;            // [nR][N] dU/dq for the radial block
   float* G;              // [nA * ncomp][N] dU/ds for the angular accumulators

@@ -244,138 +244,37 @@ __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers 
 
 // ------------------------------------------------------------------------ force halo in LDS
 // The angular force kernel scatters -dU_i/dr_ij into every neighbour j. A workgroup's
-// 256 cell-sorted atoms only reach atoms of the cells next to theirs (the halo), so the
-// scatter goes into an LDS copy of the halo's forces and one coalesced global atomic
-// per halo atom and component flushes it at the end (scattered global atomics resolve
-// at the memory side one cache line each; contiguous ones do not).
-constexpr int kTileCellsMax = 48;     // cells a tile may touch
-constexpr int kCandMax = 2048;        // >= 27 * kTileCellsMax, power of two
-constexpr int kHaloCellsMax = 512;
-constexpr int kHaloMax = 4096;        // halo atoms held in LDS
-
+// 256 cell-sorted atoms only reach atoms of the cells next to theirs (the tile's halo,
+// tabulated at list build), so the scatter goes into an LDS copy of the halo's forces
+// and one coalesced global atomic per halo atom and component flushes it at the end
+// (scattered global atomics resolve at the memory side one cache line each).
 struct HaloLds {
-  float F[3][kHaloMax];               // halo forces; the first kCandMax words hold the candidate cells first
-  int start[kHaloCellsMax];           // first sorted atom index of each halo cell (increasing)
-  int off[kHaloCellsMax + 1];         // local offset of each halo cell; off[ncells] = atoms
-  int scan[kBlock];
-  int ncells, natoms;
+  float F[3][kHaloMax];
+  int start[kHaloCellsMax];
+  int off[kHaloCellsMax + 1];
+  int ncells, natoms, ok;
 };
 
-// Exclusive prefix sum over the workgroup; returns this thread's prefix, total in *tot.
-__device__ __forceinline__ int block_scan(int v, int* scan, int* tot) {
-  __syncthreads();
-  scan[threadIdx.x] = v;
-  __syncthreads();
-  for (int off = 1; off < kBlock; off <<= 1) {
-    const int t = threadIdx.x >= (unsigned)off ? scan[threadIdx.x - off] : 0;
-    __syncthreads();
-    scan[threadIdx.x] += t;
-    __syncthreads();
-  }
-  const int incl = scan[threadIdx.x];
-  *tot = scan[kBlock - 1];
-  return incl - v;
-}
-
-// Builds the halo of tile [t0, t1): every non-empty cell within one cell (periodic) of a
-// cell holding tile atoms, sorted by cell id, with local offsets. Returns false when the
-// tile or its halo is larger than the LDS tables (the caller then scatters globally).
-// Every thread of the workgroup calls it; the result is uniform.
-__device__ bool build_halo(const EvalBuffers& b, int64_t t0, int64_t t1, HaloLds& h) {
-  const CellGrid& g = b.grid;
-  const int c_lo = b.cell_sorted[t0], c_hi = b.cell_sorted[t1 - 1];
-  const int ncr = c_hi - c_lo + 1;
-  if (ncr > kTileCellsMax) return false;
-  int n_sort = 64;
-  while (n_sort < 27 * ncr) n_sort <<= 1;
-  int* cand = reinterpret_cast<int*>(&h.F[0][0]);
-  for (int t = threadIdx.x; t < n_sort; t += kBlock) {
-    int v = 0x7fffffff;
-    if (t < 27 * ncr) {
-      const int c = c_lo + t / 27, o = t % 27;
-      int cx, cy, cz;
-      if (b.cell_start[c + 1] > b.cell_start[c] && cell_coords(g, c, cx, cy, cz)) {
-        const int nx = (cx + o % 3 - 1 + g.nc[0]) % g.nc[0];
-        const int ny = (cy + (o / 3) % 3 - 1 + g.nc[1]) % g.nc[1];
-        const int nz = (cz + o / 9 - 1 + g.nc[2]) % g.nc[2];
-        v = cell_lin(g, nx, ny, nz);
-      }
-    }
-    cand[t] = v;
-  }
-  __syncthreads();
-  // bitonic sort, ascending
-  for (int k = 2; k <= n_sort; k <<= 1)
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = threadIdx.x; t < n_sort; t += kBlock) {
-        const int u = t ^ j;
-        if (u > t) {
-          const int a = cand[t], c = cand[u];
-          if ((a > c) == ((t & k) == 0)) {
-            cand[t] = c;
-            cand[u] = a;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  // distinct non-empty cells, in order
-  const int per = (n_sort + kBlock - 1) / kBlock;
-  const int e0 = threadIdx.x * per;
-  int mine = 0;
-  for (int e = e0; e < e0 + per && e < n_sort; ++e) {
-    const int c = cand[e];
-    if (c != 0x7fffffff && (e == 0 || cand[e - 1] != c) && b.cell_start[c + 1] > b.cell_start[c]) ++mine;
-  }
-  int ncells = 0;
-  int pos = block_scan(mine, h.scan, &ncells);
-  if (ncells > kHaloCellsMax) return false;
-  for (int e = e0; e < e0 + per && e < n_sort; ++e) {
-    const int c = cand[e];
-    if (c != 0x7fffffff && (e == 0 || cand[e - 1] != c) && b.cell_start[c + 1] > b.cell_start[c]) {
-      h.start[pos] = b.cell_start[c];
-      h.off[pos] = b.cell_start[c + 1] - b.cell_start[c];
-      ++pos;
-    }
-  }
-  __syncthreads();
-  // counts -> offsets
-  const int per2 = (ncells + kBlock - 1) / kBlock;
-  const int k0 = threadIdx.x * per2;
-  int sum = 0;
-  for (int k = k0; k < k0 + per2 && k < ncells; ++k) sum += h.off[k];
-  int natoms = 0;
-  int run = block_scan(sum, h.scan, &natoms);
-  for (int k = k0; k < k0 + per2 && k < ncells; ++k) {
-    const int cnt = h.off[k];
-    h.off[k] = run;
-    run += cnt;
-  }
+// Loads the tile's halo table and clears the LDS forces; returns whether the tile
+// uses the LDS halo (uniform over the workgroup).
+__device__ bool load_halo(const EvalBuffers& b, int tile, HaloLds& h) {
   if (threadIdx.x == 0) {
-    h.off[ncells] = natoms;
-    h.ncells = ncells;
-    h.natoms = natoms;
+    h.ncells = b.hinfo[4 * tile + 0];
+    h.natoms = b.hinfo[4 * tile + 1];
+    h.ok = b.hinfo[4 * tile + 2];
   }
   __syncthreads();
-  if (natoms > kHaloMax) return false;
-  for (int t = threadIdx.x; t < natoms; t += kBlock) {
+  if (!h.ok) return false;
+  const int nc = h.ncells, na = h.natoms;
+  for (int k = threadIdx.x; k < nc; k += kBlock) h.start[k] = b.hstart[(int64_t)tile * kHaloCellsMax + k];
+  for (int k = threadIdx.x; k <= nc; k += kBlock) h.off[k] = b.hoff[(int64_t)tile * (kHaloCellsMax + 1) + k];
+  for (int t = threadIdx.x; t < na; t += kBlock) {
     h.F[0][t] = 0.f;
     h.F[1][t] = 0.f;
     h.F[2][t] = 0.f;
   }
   __syncthreads();
   return true;
-}
-
-// Local halo index of sorted atom j (j must lie in a halo cell).
-__device__ __forceinline__ int halo_local(const HaloLds& h, int j) {
-  int lo = 0, hi = h.ncells - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (h.start[mid] <= j) lo = mid;
-    else hi = mid - 1;
-  }
-  return h.off[lo] + (j - h.start[lo]);
 }
 
 // Adds the halo forces to F with one global atomic per halo atom and component.
@@ -406,9 +305,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t i = (int64_t)tile * kBlock + threadIdx.x;
   const bool valid = i < N;
-  const int64_t t0 = (int64_t)tile * kBlock;
-  const int64_t t1 = t0 + kBlock < N ? t0 + kBlock : N;
-  const bool lds = build_halo(b, t0, t1, halo);
+  const bool lds = load_halo(b, tile, halo);
   const double* __restrict__ x = b.x;
   const double Lx = b.box[0], Ly = b.box[1], Lz = b.box[2];
   const float rcR_inv = 1.f / m.rcR, rcA_inv = 1.f / m.rcA;
@@ -498,7 +395,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
       fy += f1;
       fz += f2;
       if (lds) {
-        const int lj = halo_local(halo, j);
+        const int lj = b.nbrAl[(int64_t)p * N + i];
         atomicAdd(&halo.F[0][lj], -f0);
         atomicAdd(&halo.F[1][lj], -f1);
         atomicAdd(&halo.F[2][lj], -f2);
@@ -515,7 +412,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
         for (int c = 0; c < 3; ++c) w[a * 3 + c] = fmaf(-d[a], f[c], w[a * 3 + c]);
     }
     if (lds) {
-      const int li = halo_local(halo, (int)i);
+      const int li = b.selfl[i];
       atomicAdd(&halo.F[0][li], fx);
       atomicAdd(&halo.F[1][li], fy);
       atomicAdd(&halo.F[2][li], fz);

@@ -196,6 +196,139 @@ __device__ __forceinline__ double pair_r2_exact(double xi, double yi, double zi,
   return s + szz;
 }
 
+// Exclusive prefix sum over the workgroup; returns this thread's prefix, total in *tot.
+__device__ __forceinline__ int block_scan(int v, int* scan, int* tot) {
+  __syncthreads();
+  scan[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const int t = threadIdx.x >= (unsigned)off ? scan[threadIdx.x - off] : 0;
+    __syncthreads();
+    scan[threadIdx.x] += t;
+    __syncthreads();
+  }
+  const int incl = scan[threadIdx.x];
+  *tot = scan[kBlock - 1];
+  return incl - v;
+}
+
+// One workgroup per 256-atom tile: the tile's force halo (every non-empty cell within
+// one cell, periodic, of a cell holding tile atoms), sorted by cell id, with local
+// offsets. ok = 0 when the tile or its halo exceeds the LDS tables of the force kernel.
+__global__ void __launch_bounds__(kBlock)
+k_halo_tables(int64_t N, CellGrid g, const int32_t* __restrict__ cell_sorted,
+              const int32_t* __restrict__ cell_start, HaloTables ht, const int32_t* __restrict__ flags) {
+  if (flags[FLAG_REBUILD] == 0) return;
+  __shared__ int cand[kCandMax];
+  __shared__ int scan[kBlock];
+  __shared__ int cnt[kHaloCellsMax];
+  const int tile = blockIdx.x;
+  const int64_t t0 = (int64_t)tile * kBlock;
+  const int64_t t1 = t0 + kBlock < N ? t0 + kBlock : N;
+  int32_t* info = ht.info + 4 * tile;
+  const int c_lo = cell_sorted[t0], c_hi = cell_sorted[t1 - 1];
+  const int ncr = c_hi - c_lo + 1;
+  if (ncr > kTileCellsMax) {
+    if (threadIdx.x == 0) {
+      info[0] = 0;
+      info[1] = 0;
+      info[2] = 0;
+      info[3] = 0;
+    }
+    return;
+  }
+  int n_sort = 64;
+  while (n_sort < 27 * ncr) n_sort <<= 1;
+  for (int t = threadIdx.x; t < n_sort; t += kBlock) {
+    int v = 0x7fffffff;
+    if (t < 27 * ncr) {
+      const int c = c_lo + t / 27, o = t % 27;
+      int cx, cy, cz;
+      if (cell_start[c + 1] > cell_start[c] && cell_coords(g, c, cx, cy, cz)) {
+        const int nx = (cx + o % 3 - 1 + g.nc[0]) % g.nc[0];
+        const int ny = (cy + (o / 3) % 3 - 1 + g.nc[1]) % g.nc[1];
+        const int nz = (cz + o / 9 - 1 + g.nc[2]) % g.nc[2];
+        v = cell_lin(g, nx, ny, nz);
+      }
+    }
+    cand[t] = v;
+  }
+  __syncthreads();
+  for (int k = 2; k <= n_sort; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < n_sort; t += kBlock) {
+        const int u = t ^ j;
+        if (u > t) {
+          const int a = cand[t], c = cand[u];
+          if ((a > c) == ((t & k) == 0)) {
+            cand[t] = c;
+            cand[u] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  const int per = (n_sort + kBlock - 1) / kBlock;
+  const int e0 = threadIdx.x * per;
+  int mine = 0;
+  for (int e = e0; e < e0 + per && e < n_sort; ++e) {
+    const int c = cand[e];
+    if (c != 0x7fffffff && (e == 0 || cand[e - 1] != c) && cell_start[c + 1] > cell_start[c]) ++mine;
+  }
+  int ncells = 0;
+  int pos = block_scan(mine, scan, &ncells);
+  if (ncells > kHaloCellsMax) {
+    if (threadIdx.x == 0) {
+      info[0] = 0;
+      info[1] = 0;
+      info[2] = 0;
+      info[3] = 0;
+    }
+    return;
+  }
+  int32_t* hs = ht.start + (int64_t)tile * kHaloCellsMax;
+  int32_t* ho = ht.off + (int64_t)tile * (kHaloCellsMax + 1);
+  for (int e = e0; e < e0 + per && e < n_sort; ++e) {
+    const int c = cand[e];
+    if (c != 0x7fffffff && (e == 0 || cand[e - 1] != c) && cell_start[c + 1] > cell_start[c]) {
+      hs[pos] = cell_start[c];
+      cnt[pos] = cell_start[c + 1] - cell_start[c];
+      ++pos;
+    }
+  }
+  __syncthreads();
+  const int per2 = (ncells + kBlock - 1) / kBlock;
+  const int k0 = threadIdx.x * per2;
+  int sum = 0;
+  for (int k = k0; k < k0 + per2 && k < ncells; ++k) sum += cnt[k];
+  int natoms = 0;
+  int run = block_scan(sum, scan, &natoms);
+  for (int k = k0; k < k0 + per2 && k < ncells; ++k) {
+    ho[k] = run;
+    run += cnt[k];
+  }
+  if (threadIdx.x == 0) {
+    ho[ncells] = natoms;
+    info[0] = ncells;
+    info[1] = natoms;
+    info[2] = natoms <= kHaloMax ? 1 : 0;
+    info[3] = 0;
+  }
+}
+
+// Halo-local index of sorted atom q in tile `tile` (q must lie in the halo).
+__device__ __forceinline__ int halo_index(const HaloTables& ht, int tile, int ncells, int q) {
+  const int32_t* hs = ht.start + (int64_t)tile * kHaloCellsMax;
+  const int32_t* ho = ht.off + (int64_t)tile * (kHaloCellsMax + 1);
+  int lo = 0, hi = ncells - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (hs[mid] <= q) lo = mid;
+    else hi = mid - 1;
+  }
+  return ho[lo] + (q - hs[lo]);
+}
+
 __device__ __forceinline__ int bin_of(double r2, const double* t) {
   int k = 0;
 #pragma unroll
@@ -210,11 +343,15 @@ __global__ void __launch_bounds__(kBlock)
 k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t* __restrict__ start,
               const int32_t* __restrict__ cell_sorted, double rcR, double rcA, double skin, int capR, int capA,
               int32_t* __restrict__ nbrR, int32_t* __restrict__ cntR, int32_t* __restrict__ nbrA,
-              int32_t* __restrict__ cntA, int32_t* __restrict__ bpR, int32_t* __restrict__ bpA,
-              int32_t* __restrict__ flags) {
+              int32_t* __restrict__ cntA, int32_t* __restrict__ bpR, int32_t* __restrict__ bpA, HaloTables ht,
+              uint16_t* __restrict__ nbrAl, uint16_t* __restrict__ selfl, int32_t* __restrict__ flags) {
   if (flags[FLAG_REBUILD] == 0) return;
   const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (p >= N) return;
+  const int tile = (int)(p / kBlock);
+  const bool hok = ht.info[4 * tile + 2] != 0;
+  const int hcells = ht.info[4 * tile + 0];
+  selfl[p] = hok ? (uint16_t)halo_index(ht, tile, hcells, (int)p) : kNoLocal;
   // squared bin edges; the last edge is the list cutoff (rc + skin)^2
   double tR[kNumBins], tA[kNumBins];
 #pragma unroll
@@ -249,6 +386,8 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
           const int xc = (cx + lo[0] + e + g.nc[0]) % g.nc[0];
           const int cc = cell_lin(g, xc, yc, zc);
           const int q0 = start[cc], q1 = start[cc + 1];
+          // halo-local index of the cell's first atom (cells are contiguous in the halo)
+          const int lbase = (pass == 1 && hok && q1 > q0) ? halo_index(ht, tile, hcells, q0) : 0;
           for (int q = q0; q < q1; ++q) {
             if (q == p) continue;
             const double r2 = pair_r2_exact(xi, yi, zi, x[q], x[N + q], x[2 * N + q], g.box[0], g.box[1],
@@ -267,7 +406,10 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
                 cA[ba] += 1;
               } else {
                 const int pos = cA[ba]++;
-                if (pos < capA) nbrA[(int64_t)pos * N + p] = q;
+                if (pos < capA) {
+                  nbrA[(int64_t)pos * N + p] = q;
+                  nbrAl[(int64_t)pos * N + p] = hok ? (uint16_t)(lbase + (q - q0)) : kNoLocal;
+                }
               }
             }
           }
@@ -351,7 +493,8 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, double rcR, double rcA, 
                           int32_t* cellid, int32_t* cell_sorted, int32_t* src, int32_t* key,
                           int32_t* cell_count, int32_t* cell_start, int32_t* cell_fill,
                           int32_t* scan_tmp, int32_t* nbrR, int32_t* cntR, int32_t* nbrA,
-                          int32_t* cntA, int32_t* bpR, int32_t* bpA, int32_t* flags, hipStream_t st) {
+                          int32_t* cntA, int32_t* bpR, int32_t* bpA, HaloTables ht, uint16_t* nbrAl,
+                          uint16_t* selfl, int32_t* flags, hipStream_t st) {
   const int nb = grid_blocks(N);
   const int ncell = g.ncell;
   hipError_t e;
@@ -373,8 +516,9 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, double rcR, double rcA, 
                      x_alt, v_alt, type_alt, perm_alt, x_build, cell_sorted, flags);
   hipLaunchKernelGGL(k_copy_back, dim3(nb), dim3(kBlock), 0, st, N, x_alt, v_alt, type_alt, perm_alt,
                      x, v, type, perm, flags);
+  hipLaunchKernelGGL(k_halo_tables, dim3(nb), dim3(kBlock), 0, st, N, g, cell_sorted, cell_start, ht, flags);
   hipLaunchKernelGGL(k_build_lists, dim3(nb), dim3(kBlock), 0, st, N, g, x, cell_start, cell_sorted,
-                     rcR, rcA, skin, capR, capA, nbrR, cntR, nbrA, cntA, bpR, bpA, flags);
+                     rcR, rcA, skin, capR, capA, nbrR, cntR, nbrA, cntA, bpR, bpA, ht, nbrAl, selfl, flags);
   hipLaunchKernelGGL(k_count_build, dim3(1), dim3(64), 0, st, flags);
   return hipGetLastError();
 }
