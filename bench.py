@@ -169,6 +169,19 @@ def run_forms(args):
     print(json.dumps(out))
 
 
+def copy_calibration(nbytes=1 << 30, reps=3):
+    """A plain copy of known size: reads nbytes and writes nbytes per launch."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read_per_launch": nbytes, "bytes_written_per_launch": nbytes,
+                                           "launches": reps}}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,11 +194,18 @@ def main():
     ap.add_argument("--forms", action="store_true",
                     help="time FP32, BF16 and surrogate MTS on the 200^3-cell (32M-atom) box instead")
     ap.add_argument("--epochs", type=int, default=10)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy three times (the reference kernel "
+                         "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               f"(the path shards by spatial decomposition, see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     if args.forms:
         if args.cells == 100:

@@ -110,12 +110,12 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 }
 
 // Minimum image of one FP64 component, as d = x_j - x_i; if (d > L/2) d -= L;
-// else if (d < -L/2) d += L.
+// else if (d < -L/2) d += L (written as selects, so no branch separates the
+// loads of a pair's three components).
 __device__ __forceinline__ double min_image(double d, double L) {
   const double half = 0.5 * L;
-  if (d > half) d -= L;
-  else if (d < -half) d += L;
-  return d;
+  const double lo = d + L, hi = d - L;
+  return d > half ? hi : (d < -half ? lo : d);
 }
 
 inline int grid_blocks(int64_t n, int block = kBlock) {
@@ -158,7 +158,7 @@ struct EvalBuffers {
   const int32_t* hstart;
   const int32_t* hoff;
   float* U;              // [N]
-  float* FpR;            // [nR][N] dU/dq for the radial block
+  float* FpR;            // [N][8] dU/dq for the radial block (nR <= 8 used, 32 B per atom)
   float* G;              // [nA * ncomp][N] dU/ds for the angular accumulators
   float* F;              // [3][N] forces (FP32 accumulation)
   double* partial;       // [nblocks][kPartialStride]

@@ -211,8 +211,14 @@ __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers 
 
   if (valid) {
     b.U[i] = U;
+    {
+      float t[8];
 #pragma unroll
-    for (int n = 0; n < NR; ++n) b.FpR[(int64_t)n * N + i] = fp[n];
+      for (int n = 0; n < 8; ++n) t[n] = n < NR ? fp[n] : 0.f;
+      float4* fr = reinterpret_cast<float4*>(b.FpR + 8 * i);
+      fr[0] = make_float4(t[0], t[1], t[2], t[3]);
+      fr[1] = make_float4(t[4], t[5], t[6], t[7]);
+    }
     // 4. dU/ds_nlm = dU/dq_nl * 2 W_lm s_nlm (+ four-body part for l = 2)
     float Gd[NA * NC];
 #pragma unroll
@@ -316,35 +322,44 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
   if (valid) {
     const double xi = x[i], yi = x[N + i], zi = x[2 * N + i];
     const int ti = MULTI ? b.type[i] : 0;
-    float fpi[NR];
-#pragma unroll
-    for (int n = 0; n < NR; ++n) fpi[n] = b.FpR[(int64_t)n * N + i];
+    float fpi[8];
+    {
+      const float4* fr = reinterpret_cast<const float4*>(b.FpR + 8 * i);
+      const float4 a = fr[0], c = fr[1];
+      fpi[0] = a.x; fpi[1] = a.y; fpi[2] = a.z; fpi[3] = a.w;
+      fpi[4] = c.x; fpi[5] = c.y; fpi[6] = c.z; fpi[7] = c.w;
+    }
+    const float* cR = m.cR;
+    const float* cA = m.cA;
     // radial: gather, F_i += (Fp_i . g'^{ij} + Fp_j . g'^{ji}) u
     const double rcR2 = m.rcR64 * m.rcR64, rcA2 = m.rcA64 * m.rcA64;
     const int kR = list_bound(b.bpR, b.flags, N, i);
-    for (int p = 0; p < kR; ++p) {
-      const int32_t j = b.nbrR[(int64_t)p * N + i];
+    for_each_entry(b.nbrR, x, N, i, kR, [&](int, int32_t j, double xj, double yj, double zj) {
       float dx, dy, dz;
-      if (!pair_inside(x, N, j, xi, yi, zi, Lx, Ly, Lz, rcR2, dx, dy, dz)) continue;
-      const float r = sqrtf(dx * dx + dy * dy + dz * dz);
-      const float rinv = 1.f / r;
-      const int tj = MULTI ? b.type[j] : 0;
+      if (!inside(xj, yj, zj, xi, yi, zi, Lx, Ly, Lz, rcR2, dx, dy, dz)) return;
+      const float4* fr = reinterpret_cast<const float4*>(b.FpR + 8 * (int64_t)j);
+      const float4 fa = fr[0], fb = fr[1];
+      const float fpj[8] = {fa.x, fa.y, fa.z, fa.w, fb.x, fb.y, fb.z, fb.w};
+      float r, rinv;
+      pair_r(dx, dy, dz, r, rinv);
       float g[NR], dg[NR];
-      radial_g_dg<NR, S::KR>(r, rcR_inv, m.cR + (ti * m.T + tj) * NR * S::KR, g, dg);
       float si = 0.f, sj = 0.f;
       if constexpr (MULTI) {
+        const int tj = b.type[j];
+        radial_g_dg<NR, S::KR>(r, rcR_inv, cR + (ti * m.T + tj) * NR * S::KR, g, dg);
         float g2[NR], dg2[NR];
-        radial_g_dg<NR, S::KR>(r, rcR_inv, m.cR + (tj * m.T + ti) * NR * S::KR, g2, dg2);
+        radial_g_dg<NR, S::KR>(r, rcR_inv, cR + (tj * m.T + ti) * NR * S::KR, g2, dg2);
 #pragma unroll
         for (int n = 0; n < NR; ++n) {
           si = fmaf(fpi[n], dg[n], si);
-          sj = fmaf(b.FpR[(int64_t)n * N + j], dg2[n], sj);
+          sj = fmaf(fpj[n], dg2[n], sj);
         }
       } else {
+        radial_g_dg<NR, S::KR>(r, rcR_inv, uniform_coeffs(cR), g, dg);
 #pragma unroll
         for (int n = 0; n < NR; ++n) {
           si = fmaf(fpi[n], dg[n], si);
-          sj = fmaf(b.FpR[(int64_t)n * N + j], dg[n], sj);
+          sj = fmaf(fpj[n], dg[n], sj);
         }
       }
       const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
@@ -359,23 +374,29 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
       for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int c = 0; c < 3; ++c) w[a * 3 + c] = fmaf(-d[a], f[c], w[a * 3 + c]);
-    }
+    });
     // angular + four-body: scatter
     float G[NA * NC];
 #pragma unroll
     for (int k = 0; k < NA * NC; ++k) G[k] = b.G[(int64_t)k * N + i];
     const int kA = list_bound(b.bpA, b.flags, N, i);
-    for (int p = 0; p < kA; ++p) {
-      const int32_t j = b.nbrA[(int64_t)p * N + i];
+    for_each_entry(b.nbrA, x, N, i, kA, [&](int p, int32_t j, double xj, double yj, double zj) {
       float dx, dy, dz;
-      if (!pair_inside(x, N, j, xi, yi, zi, Lx, Ly, Lz, rcA2, dx, dy, dz)) continue;
-      const float r = sqrtf(dx * dx + dy * dy + dz * dz);
-      const float rinv = 1.f / r;
-      const int tj = MULTI ? b.type[j] : 0;
+      if (!inside(xj, yj, zj, xi, yi, zi, Lx, Ly, Lz, rcA2, dx, dy, dz)) return;
+      const int lj = lds ? (int)b.nbrAl[(int64_t)p * N + i] : 0;
+      float r, rinv;
+      pair_r(dx, dy, dz, r, rinv);
       float g[NA], dg[NA];
-      radial_g_dg<NA, S::KA>(r, rcA_inv, m.cA + (ti * m.T + tj) * NA * S::KA, g, dg);
+      if constexpr (MULTI)
+        radial_g_dg<NA, S::KA>(r, rcA_inv, cA + (ti * m.T + b.type[j]) * NA * S::KA, g, dg);
+      else
+        radial_g_dg<NA, S::KA>(r, rcA_inv, uniform_coeffs(cA), g, dg);
       const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
-      float sc = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
+      // F_ij = sum_lm [ A_lm P_lm u + B_lm (grad P_lm - l P_lm u) / r ] with
+      // A_lm = sum_n G_nlm g'_n and B_lm = sum_n G_nlm g_n; the l P B terms are
+      // summed per l and scaled once.
+      float sA = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
+      float sB[4] = {0.f, 0.f, 0.f, 0.f};
       for_each_poly_grad<NC>(ux, uy, uz, [&](int lm, float P, float px, float py, float pz) {
         float A = 0.f, B = 0.f;
 #pragma unroll
@@ -383,11 +404,14 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
           A = fmaf(G[n * NC + lm], dg[n], A);
           B = fmaf(G[n * NC + lm], g[n], B);
         }
-        sc = fmaf(P, A - (float)comp_l(lm) * rinv * B, sc);
+        sA = fmaf(P, A, sA);
+        sB[comp_l(lm) - 1] = fmaf(P, B, sB[comp_l(lm) - 1]);
         vx = fmaf(B, px, vx);
         vy = fmaf(B, py, vy);
         vz = fmaf(B, pz, vz);
       });
+      const float lPB = fmaf(4.f, sB[3], fmaf(3.f, sB[2], fmaf(2.f, sB[1], sB[0])));
+      const float sc = fmaf(-rinv, lPB, sA);
       const float f0 = fmaf(ux, sc, vx * rinv);
       const float f1 = fmaf(uy, sc, vy * rinv);
       const float f2 = fmaf(uz, sc, vz * rinv);
@@ -395,7 +419,6 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
       fy += f1;
       fz += f2;
       if (lds) {
-        const int lj = b.nbrAl[(int64_t)p * N + i];
         atomicAdd(&halo.F[0][lj], -f0);
         atomicAdd(&halo.F[1][lj], -f1);
         atomicAdd(&halo.F[2][lj], -f2);
@@ -410,7 +433,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
       for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int c = 0; c < 3; ++c) w[a * 3 + c] = fmaf(-d[a], f[c], w[a * 3 + c]);
-    }
+    });
     if (lds) {
       const int li = b.selfl[i];
       atomicAdd(&halo.F[0][li], fx);

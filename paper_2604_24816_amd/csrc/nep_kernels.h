@@ -14,6 +14,12 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr float kPiF = 3.14159265358979323846f;
 
+// Read-only view of model coefficients in the constant address space: where the
+// index is the same for the whole wavefront (one species) the compiler loads the
+// block with scalar loads, keeping it out of vector registers.
+typedef const __attribute__((address_space(4))) float* cfloat_ptr;
+__device__ __forceinline__ cfloat_ptr uniform_coeffs(const float* p) { return (cfloat_ptr)p; }
+
 // Round-to-nearest-even conversion of an FP32 value to bfloat16 bits.
 __device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
   uint32_t u = __float_as_uint(f);
@@ -27,8 +33,8 @@ __device__ __forceinline__ __bf16 bits_to_bf16(uint16_t b) { return __builtin_bi
 // Chebyshev-based radial basis f_k(r) = (T_k(x) + 1) f_c(r) / 2 with
 // x = 2 (r/rc - 1)^2 - 1 and f_c = (1 + cos(pi r / rc)) / 2 (published NEP form).
 // Returns g_n = sum_k c_nk f_k.
-template <int N, int K>
-__device__ __forceinline__ void radial_g(float r, float rc_inv, const float* __restrict__ c, float* g) {
+template <int N, int K, class CP>
+__device__ __forceinline__ void radial_g(float r, float rc_inv, CP c, float* g) {
   float sn, cs;
   sincospif(r * rc_inv, &sn, &cs);
   const float fc = 0.5f * (1.f + cs);
@@ -55,9 +61,8 @@ __device__ __forceinline__ void radial_g(float r, float rc_inv, const float* __r
 }
 
 // g_n and dg_n/dr.
-template <int N, int K>
-__device__ __forceinline__ void radial_g_dg(float r, float rc_inv, const float* __restrict__ c, float* g,
-                                            float* dg) {
+template <int N, int K, class CP>
+__device__ __forceinline__ void radial_g_dg(float r, float rc_inv, CP c, float* g, float* dg) {
   float sn, cs;
   sincospif(r * rc_inv, &sn, &cs);
   const float fc = 0.5f * (1.f + cs);
@@ -125,6 +130,7 @@ struct Shape {
   static constexpr int NC = L3 * (L3 + 2);
   static constexpr int D = NR + NA * L3 + (FB ? NA : 0);
   static_assert(D <= 32 && H <= 32, "network tiles hold at most 32 descriptors and 32 hidden units");
+  static_assert(NR <= 8, "dU/dq of the radial block is stored in 8 floats per atom");
   static_assert(!FB || L3 >= 2, "the four-body term uses the l = 2 accumulators");
 };
 
@@ -133,6 +139,51 @@ using SurShape = Shape<5, 9, 5, 9, 2, false, 8>;
 
 constexpr int kLdsStride = 33;  // 32 columns + 1 pad word against bank conflicts
 
+
+// r and 1/r of an FP32 pair vector (hardware reciprocal square root, 1 ulp).
+__device__ __forceinline__ void pair_r(float dx, float dy, float dz, float& r, float& rinv) {
+  const float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+  rinv = __builtin_amdgcn_rsqf(r2);
+  r = r2 * rinv;
+}
+
+// Pair test for an entry whose position is already loaded: FP64 minimum-image
+// vector, kept when r^2 < cut2; rounded to FP32 after the subtraction.
+__device__ __forceinline__ bool inside(double xj, double yj, double zj, double xi, double yi, double zi,
+                                       double Lx, double Ly, double Lz, double cut2, float& dx, float& dy,
+                                       float& dz) {
+  const double ex = min_image(xj - xi, Lx);
+  const double ey = min_image(yj - yi, Ly);
+  const double ez = min_image(zj - zi, Lz);
+  if (!(ex * ex + ey * ey + ez * ez < cut2)) return false;
+  dx = (float)ex;
+  dy = (float)ey;
+  dz = (float)ez;
+  return true;
+}
+
+// Visits entries [0, k) of atom i's slot-major list, calling body(p, j, xj, yj, zj).
+// The index of entry p + 2 and the position of entry p + 1 are loaded before the
+// body of entry p runs, so their latency overlaps the pair arithmetic (the last
+// loads repeat entry k - 1: every address stays inside the list and the box).
+template <class Body>
+__device__ __forceinline__ void for_each_entry(const int32_t* __restrict__ nbr, const double* __restrict__ x,
+                                               int64_t N, int64_t i, int k, Body&& body) {
+  if (k <= 0) return;
+  int32_t j = nbr[i];
+  int32_t jn = nbr[(int64_t)(k > 1 ? 1 : 0) * N + i];
+  double xj = x[j], yj = x[N + j], zj = x[2 * N + j];
+  for (int p = 0; p < k; ++p) {
+    const int32_t jnn = nbr[(int64_t)(p + 2 < k ? p + 2 : k - 1) * N + i];
+    const double xn = x[jn], yn = x[N + jn], zn = x[2 * N + jn];
+    body(p, j, xj, yj, zj);
+    j = jn;
+    jn = jnn;
+    xj = xn;
+    yj = yn;
+    zj = zn;
+  }
+}
 
 // Pair test for one entry of a list with skin: FP64 minimum-image vector, kept when
 // r^2 < cut2 (the true cutoff); the vector is rounded to FP32 after the subtraction.
@@ -170,35 +221,40 @@ __device__ __forceinline__ void desc_accumulate(const ModelDev& m, const EvalBuf
   const double rcR2 = m.rcR64 * m.rcR64, rcA2 = m.rcA64 * m.rcA64;
   nr = 0;
   na = 0;
+  const float* cR = m.cR + (MULTI ? 0 : (ti * m.T) * NR * S::KR);
+  const float* cA = m.cA + (MULTI ? 0 : (ti * m.T) * NA * S::KA);
   const int kR = list_bound(b.bpR, b.flags, N, i);
-  for (int p = 0; p < kR; ++p) {
-    const int32_t j = b.nbrR[(int64_t)p * N + i];
+  for_each_entry(b.nbrR, x, N, i, kR, [&](int, int32_t j, double xj, double yj, double zj) {
     float dx, dy, dz;
-    if (!pair_inside(x, N, j, xi, yi, zi, Lx, Ly, Lz, rcR2, dx, dy, dz)) continue;
+    if (!inside(xj, yj, zj, xi, yi, zi, Lx, Ly, Lz, rcR2, dx, dy, dz)) return;
     ++nr;
-    const float r = sqrtf(dx * dx + dy * dy + dz * dz);
-    const int tj = MULTI ? b.type[j] : 0;
+    float r, rinv;
+    pair_r(dx, dy, dz, r, rinv);
     float g[NR];
-    radial_g<NR, S::KR>(r, rcR_inv, m.cR + (ti * m.T + tj) * NR * S::KR, g);
+    if constexpr (MULTI)
+      radial_g<NR, S::KR>(r, rcR_inv, m.cR + (ti * m.T + b.type[j]) * NR * S::KR, g);
+    else
+      radial_g<NR, S::KR>(r, rcR_inv, uniform_coeffs(cR), g);
 #pragma unroll
     for (int n = 0; n < NR; ++n) q[n] += g[n];
-  }
+  });
   const int kA = list_bound(b.bpA, b.flags, N, i);
-  for (int p = 0; p < kA; ++p) {
-    const int32_t j = b.nbrA[(int64_t)p * N + i];
+  for_each_entry(b.nbrA, x, N, i, kA, [&](int, int32_t j, double xj, double yj, double zj) {
     float dx, dy, dz;
-    if (!pair_inside(x, N, j, xi, yi, zi, Lx, Ly, Lz, rcA2, dx, dy, dz)) continue;
+    if (!inside(xj, yj, zj, xi, yi, zi, Lx, Ly, Lz, rcA2, dx, dy, dz)) return;
     ++na;
-    const float r = sqrtf(dx * dx + dy * dy + dz * dz);
-    const float rinv = 1.f / r;
-    const int tj = MULTI ? b.type[j] : 0;
+    float r, rinv;
+    pair_r(dx, dy, dz, r, rinv);
     float g[NA];
-    radial_g<NA, S::KA>(r, rcA_inv, m.cA + (ti * m.T + tj) * NA * S::KA, g);
+    if constexpr (MULTI)
+      radial_g<NA, S::KA>(r, rcA_inv, m.cA + (ti * m.T + b.type[j]) * NA * S::KA, g);
+    else
+      radial_g<NA, S::KA>(r, rcA_inv, uniform_coeffs(cA), g);
     for_each_poly<NC>(dx * rinv, dy * rinv, dz * rinv, [&](int lm, float P) {
 #pragma unroll
       for (int n = 0; n < NA; ++n) s[n * NC + lm] = fmaf(g[n], P, s[n * NC + lm]);
     });
-  }
+  });
 }
 
 // The 3x3 traceless matrix S = sum_j g (u u^T - I/3) of one channel from its

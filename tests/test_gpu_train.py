@@ -114,7 +114,7 @@ def test_position_gradient_is_minus_force():
     m = oracle.Model.from_hparams(hp, params)
     _, _, _, Fo = oracle.evaluate(m, at.x, at.types, at.box)
     assert np.abs(-x.grad.cpu().numpy() - Fo).max() < 1e-4
-    assert abs(float(E) - oracle.evaluate(m, at.x, at.types, at.box)[0]) / at.n < 1e-6
+    assert abs(float(E.detach()) - oracle.evaluate(m, at.x, at.types, at.box)[0]) / at.n < 1e-6
 
 
 def test_adam_update_matches_oracle():
