@@ -82,6 +82,19 @@ struct HaloTables {
   int32_t* off;    // [ntiles][kHaloCellsMax + 1] local offset of each halo cell
 };
 
+// Outputs of the list build.
+struct ListOut {
+  int32_t* nbrR;    // [capR][N] radial list, ordered by distance bin
+  int32_t* cntR;    // [N]
+  int32_t* nbrA;    // [capA][N] angular list, ordered by distance bin
+  int32_t* cntA;    // [N]
+  int32_t* bpR;     // [kNumBins][N] cumulative bin breakpoints
+  int32_t* bpA;     // [kNumBins][N]
+  uint16_t* nbrAl;  // [capA][N] halo-local index of each angular entry
+  uint16_t* selfl;  // [N] halo-local index of the atom itself
+};
+
+
 // Device copy of one model (FP32 parameters, same packed order as the host FP64
 // vector) plus a bfloat16 copy of W0.
 struct ModelDev {

@@ -180,22 +180,6 @@ __global__ void k_copy_back(int64_t N, const double* __restrict__ x2, const doub
   perm[p] = perm2[p];
 }
 
-// r^2 of the FP64 minimum-image pair vector, with no contraction into FMA so that
-// the result equals (dx*dx + dy*dy) + dz*dz rounded after every operation.
-__device__ __forceinline__ double pair_r2_exact(double xi, double yi, double zi, double xj,
-                                                          double yj, double zj, double Lx, double Ly,
-                                                          double Lz) {
-#pragma clang fp contract(off)
-  const double dx = min_image(xj - xi, Lx);
-  const double dy = min_image(yj - yi, Ly);
-  const double dz = min_image(zj - zi, Lz);
-  const double sxx = dx * dx;
-  const double syy = dy * dy;
-  const double szz = dz * dz;
-  const double s = sxx + syy;
-  return s + szz;
-}
-
 // Exclusive prefix sum over the workgroup; returns this thread's prefix, total in *tot.
 __device__ __forceinline__ int block_scan(int v, int* scan, int* tot) {
   __syncthreads();
@@ -336,22 +320,58 @@ __device__ __forceinline__ int bin_of(double r2, const double* t) {
   return k;
 }
 
+// Candidates of one stencil cell, four at a time (their positions are loaded
+// together before any is tested). The pair vector is the FP64 difference x_q - x_p
+// followed by the periodic shift of the stencil cell (-L, 0 or +L, the value the
+// minimum-image rule subtracts for every pair that can lie within the cutoff when
+// the dimension holds at least three cells), or by the minimum-image rule itself
+// in dimensions with fewer cells; r^2 = (dx*dx + dy*dy) + dz*dz without FMA.
+template <class Visit>
+__device__ __forceinline__ void scan_cell(const double* __restrict__ x, int64_t N, int q0, int q1, int64_t p,
+                                          double xi, double yi, double zi, double sx, double sy, double sz,
+                                          const CellGrid& g, double cut2, Visit&& visit) {
+#pragma clang fp contract(off)
+  const bool mx = g.nc[0] < 3, my = g.nc[1] < 3, mz = g.nc[2] < 3;
+  for (int q = q0; q < q1; q += 4) {
+    double px[4], py[4], pz[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int qq = q + u < q1 ? q + u : q1 - 1;
+      px[u] = x[qq];
+      py[u] = x[N + qq];
+      pz[u] = x[2 * N + qq];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      double dx = px[u] - xi, dy = py[u] - yi, dz = pz[u] - zi;
+      dx = mx ? min_image(dx, g.box[0]) : dx + sx;
+      dy = my ? min_image(dy, g.box[1]) : dy + sy;
+      dz = mz ? min_image(dz, g.box[2]) : dz + sz;
+      const double sxx = dx * dx;
+      const double syy = dy * dy;
+      const double szz = dz * dz;
+      const double sxy = sxx + syy;
+      const double r2 = sxy + szz;
+      if (q + u < q1 && q + u != p && r2 < cut2) visit(q + u, r2);
+    }
+  }
+}
+
 // One thread per atom. Two passes over the 27-cell stencil: the first counts the
 // pairs per distance bin, the second writes each pair at its bin's offset, so each
-// atom's list is ordered by bin (stencil order inside a bin).
+// atom's list is ordered by bin (stencil order inside a bin). Stencil cells whose
+// nearest point lies beyond the list cutoff (with a 1e-6 A margin) are skipped.
 __global__ void __launch_bounds__(kBlock)
 k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t* __restrict__ start,
               const int32_t* __restrict__ cell_sorted, double rcR, double rcA, double skin, int capR, int capA,
-              int32_t* __restrict__ nbrR, int32_t* __restrict__ cntR, int32_t* __restrict__ nbrA,
-              int32_t* __restrict__ cntA, int32_t* __restrict__ bpR, int32_t* __restrict__ bpA, HaloTables ht,
-              uint16_t* __restrict__ nbrAl, uint16_t* __restrict__ selfl, int32_t* __restrict__ flags) {
+              ListOut lo_, HaloTables ht, int32_t* __restrict__ flags) {
   if (flags[FLAG_REBUILD] == 0) return;
   const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (p >= N) return;
   const int tile = (int)(p / kBlock);
   const bool hok = ht.info[4 * tile + 2] != 0;
   const int hcells = ht.info[4 * tile + 0];
-  selfl[p] = hok ? (uint16_t)halo_index(ht, tile, hcells, (int)p) : kNoLocal;
+  lo_.selfl[p] = hok ? (uint16_t)halo_index(ht, tile, hcells, (int)p) : kNoLocal;
   // squared bin edges; the last edge is the list cutoff (rc + skin)^2
   double tR[kNumBins], tA[kNumBins];
 #pragma unroll
@@ -366,10 +386,16 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
   const double xi = x[p], yi = x[N + p], zi = x[2 * N + p];
   int cx, cy, cz;
   cell_coords(g, cell_sorted[p], cx, cy, cz);
+  const int cc3[3] = {cx, cy, cz};
+  const double pos3[3] = {xi, yi, zi};
   int lo[3], nof[3];
+  double dlo[3], dhi[3];  // distance from the atom to the lower / upper face of its cell
   for (int d = 0; d < 3; ++d) {
     lo[d] = g.nc[d] >= 3 ? -1 : 0;
     nof[d] = g.nc[d] >= 3 ? 3 : g.nc[d];
+    const double h = g.box[d] / g.nc[d];
+    dlo[d] = fmax(pos3[d] - cc3[d] * h - 1e-6, 0.0);
+    dhi[d] = fmax((cc3[d] + 1) * h - pos3[d] - 1e-6, 0.0);
   }
   int cR[kNumBins], cA[kNumBins];
 #pragma unroll
@@ -379,26 +405,33 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
   }
   for (int pass = 0; pass < 2; ++pass) {
     for (int a = 0; a < nof[2]; ++a) {
-      const int zc = (cz + lo[2] + a + g.nc[2]) % g.nc[2];
+      const int rz = cz + lo[2] + a;
+      const int zc = (rz + g.nc[2]) % g.nc[2];
+      const double sz = rz < 0 ? -g.box[2] : (rz >= g.nc[2] ? g.box[2] : 0.0);
+      const double gz = nof[2] < 3 ? 0.0 : (a == 0 ? dlo[2] : (a == 2 ? dhi[2] : 0.0));
       for (int b = 0; b < nof[1]; ++b) {
-        const int yc = (cy + lo[1] + b + g.nc[1]) % g.nc[1];
+        const int ry = cy + lo[1] + b;
+        const int yc = (ry + g.nc[1]) % g.nc[1];
+        const double sy = ry < 0 ? -g.box[1] : (ry >= g.nc[1] ? g.box[1] : 0.0);
+        const double gy = nof[1] < 3 ? 0.0 : (b == 0 ? dlo[1] : (b == 2 ? dhi[1] : 0.0));
         for (int e = 0; e < nof[0]; ++e) {
-          const int xc = (cx + lo[0] + e + g.nc[0]) % g.nc[0];
+          const int rx = cx + lo[0] + e;
+          const int xc = (rx + g.nc[0]) % g.nc[0];
+          const double sx = rx < 0 ? -g.box[0] : (rx >= g.nc[0] ? g.box[0] : 0.0);
+          const double gx = nof[0] < 3 ? 0.0 : (e == 0 ? dlo[0] : (e == 2 ? dhi[0] : 0.0));
+          if (gx * gx + gy * gy + gz * gz >= tR[kNumBins - 1]) continue;
           const int cc = cell_lin(g, xc, yc, zc);
           const int q0 = start[cc], q1 = start[cc + 1];
+          if (q1 <= q0) continue;
           // halo-local index of the cell's first atom (cells are contiguous in the halo)
-          const int lbase = (pass == 1 && hok && q1 > q0) ? halo_index(ht, tile, hcells, q0) : 0;
-          for (int q = q0; q < q1; ++q) {
-            if (q == p) continue;
-            const double r2 = pair_r2_exact(xi, yi, zi, x[q], x[N + q], x[2 * N + q], g.box[0], g.box[1],
-                                            g.box[2]);
-            if (!(r2 < tR[kNumBins - 1])) continue;
+          const int lbase = (pass == 1 && hok) ? halo_index(ht, tile, hcells, q0) : 0;
+          scan_cell(x, N, q0, q1, p, xi, yi, zi, sx, sy, sz, g, tR[kNumBins - 1], [&](int q, double r2) {
             const int br = bin_of(r2, tR);
             if (pass == 0) {
               cR[br] += 1;
             } else {
               const int pos = cR[br]++;
-              if (pos < capR) nbrR[(int64_t)pos * N + p] = q;
+              if (pos < capR) lo_.nbrR[(int64_t)pos * N + p] = q;
             }
             if (r2 < tA[kNumBins - 1]) {
               const int ba = bin_of(r2, tA);
@@ -407,12 +440,12 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
               } else {
                 const int pos = cA[ba]++;
                 if (pos < capA) {
-                  nbrA[(int64_t)pos * N + p] = q;
-                  nbrAl[(int64_t)pos * N + p] = hok ? (uint16_t)(lbase + (q - q0)) : kNoLocal;
+                  lo_.nbrA[(int64_t)pos * N + p] = q;
+                  lo_.nbrAl[(int64_t)pos * N + p] = hok ? (uint16_t)(lbase + (q - q0)) : kNoLocal;
                 }
               }
             }
-          }
+          });
         }
       }
     }
@@ -426,11 +459,11 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
         cA[k] = sa;
         sr += nr_k;
         sa += na_k;
-        bpR[(int64_t)k * N + p] = sr < capR ? sr : capR;
-        bpA[(int64_t)k * N + p] = sa < capA ? sa : capA;
+        lo_.bpR[(int64_t)k * N + p] = sr < capR ? sr : capR;
+        lo_.bpA[(int64_t)k * N + p] = sa < capA ? sa : capA;
       }
-      cntR[p] = sr < capR ? sr : capR;
-      cntA[p] = sa < capA ? sa : capA;
+      lo_.cntR[p] = sr < capR ? sr : capR;
+      lo_.cntA[p] = sa < capA ? sa : capA;
       if (sr > capR) atomicMax(&flags[FLAG_OVF_R], sr);
       if (sa > capA) atomicMax(&flags[FLAG_OVF_A], sa);
     }
@@ -517,8 +550,9 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, double rcR, double rcA, 
   hipLaunchKernelGGL(k_copy_back, dim3(nb), dim3(kBlock), 0, st, N, x_alt, v_alt, type_alt, perm_alt,
                      x, v, type, perm, flags);
   hipLaunchKernelGGL(k_halo_tables, dim3(nb), dim3(kBlock), 0, st, N, g, cell_sorted, cell_start, ht, flags);
+  const ListOut lout{nbrR, cntR, nbrA, cntA, bpR, bpA, nbrAl, selfl};
   hipLaunchKernelGGL(k_build_lists, dim3(nb), dim3(kBlock), 0, st, N, g, x, cell_start, cell_sorted,
-                     rcR, rcA, skin, capR, capA, nbrR, cntR, nbrA, cntA, bpR, bpA, ht, nbrAl, selfl, flags);
+                     rcR, rcA, skin, capR, capA, lout, ht, flags);
   hipLaunchKernelGGL(k_count_build, dim3(1), dim3(64), 0, st, flags);
   return hipGetLastError();
 }
