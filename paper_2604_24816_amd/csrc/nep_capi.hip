@@ -113,6 +113,7 @@ struct nep_system {
   int32_t *nbrR, *cntR, *nbrA, *cntA, *bpR, *bpA, *nactR, *nactA;
   uint16_t *nbrAl, *selfl;
   HaloTables ht;
+  ListScratch lsc;
   float *F[2], *U, *FpR, *G;
   float *gF, *vjp, *qs;
   double *partial, *gpart, *res, *staging;
@@ -162,6 +163,9 @@ int64_t layout(nep_system* s, char* base, int64_t N, int capR, int capA, int max
   S.cntA = c.take<int32_t>(N);
   S.nbrAl = c.take<uint16_t>((int64_t)capA * N);
   S.selfl = c.take<uint16_t>(N);
+  S.lsc.r = c.take<uint4>((int64_t)((capR + 15) / 16) * N * 4);
+  S.lsc.a = c.take<uint4>((int64_t)((capA + 15) / 16) * N * 4);
+  S.lsc.l = c.take<uint4>((int64_t)((capA + 15) / 16) * N * 2);
   {
     const int64_t nt = grid_blocks(N);
     S.ht.info = c.take<int32_t>(4 * nt);
@@ -300,7 +304,7 @@ int rebuild(nep_system* s, double skin, int force) {
                         s->capA, s->x, s->v, s->type, s->perm, s->x_alt, s->v_alt, s->type_alt, s->perm_alt,
                         s->x_build, s->cellid, s->cell_sorted, s->src, s->key, s->cell_count, s->cell_start,
                         s->cell_fill, s->scan_tmp, s->nbrR, s->cntR, s->nbrA, s->cntA, s->bpR, s->bpA,
-                        s->ht, s->nbrAl, s->selfl, s->flags, s->st));
+                        s->ht, s->nbrAl, s->selfl, s->lsc, s->flags, s->st));
   (void)force;
   return NEP_OK;
 }
@@ -433,7 +437,7 @@ static int max_cells(const double box[3], double rc) {
 
 int nep_system_workspace_bytes(const nep_model* full, const nep_model* sur, int64_t n_atoms, const double box[3],
                                int32_t cap_radial, int32_t cap_angular, int64_t* bytes) {
-  if (!bytes || !box || n_atoms < 1 || n_atoms > (int64_t)INT32_MAX || cap_radial < 1 || cap_angular < 1)
+  if (!bytes || !box || n_atoms < 1 || n_atoms >= kMaxAtoms || cap_radial < 1 || cap_angular < 1)
     return NEP_ERR_ARG;
   if (check_model_pair(full, sur)) return NEP_ERR_ARG;
   nep_system tmp;
@@ -446,7 +450,7 @@ int nep_system_workspace_bytes(const nep_model* full, const nep_model* sur, int6
 int nep_system_create(const nep_model* full, const nep_model* sur, int64_t n_atoms, const double box[3],
                       int32_t cap_radial, int32_t cap_angular, void* workspace, int64_t workspace_bytes,
                       void* hip_stream, nep_system** out) {
-  if (!out || !box || n_atoms < 1 || n_atoms > (int64_t)INT32_MAX || cap_radial < 1 || cap_angular < 1)
+  if (!out || !box || n_atoms < 1 || n_atoms >= kMaxAtoms || cap_radial < 1 || cap_angular < 1)
     return NEP_ERR_ARG;
   if (check_model_pair(full, sur)) return NEP_ERR_ARG;
   for (int c = 0; c < 3; ++c)

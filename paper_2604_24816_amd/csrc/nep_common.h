@@ -94,6 +94,16 @@ struct ListOut {
   uint16_t* selfl;  // [N] halo-local index of the atom itself
 };
 
+// Per-build scratch: each atom's candidates in stencil order, sixteen per segment
+// ([ceil(cap / 16)][N][16]): radial and angular entries as q | bin << 28 (64-byte
+// segments) and the 16-bit halo-local index of each angular entry (32-byte segments).
+struct ListScratch {
+  uint4* r;
+  uint4* a;
+  uint4* l;
+};
+constexpr int64_t kMaxAtoms = (int64_t)1 << 28;  // list entries keep the bin in bits 28-30
+
 
 // Device copy of one model (FP32 parameters, same packed order as the host FP64
 // vector) plus a bfloat16 copy of W0.
@@ -147,7 +157,7 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, double rcR, double rcA, 
                           int32_t* key, int32_t* cell_count, int32_t* cell_start, int32_t* cell_fill,
                           int32_t* scan_tmp, int32_t* nbrR, int32_t* cntR, int32_t* nbrA,
                           int32_t* cntA, int32_t* bpR, int32_t* bpA, HaloTables ht, uint16_t* nbrAl,
-                          uint16_t* selfl, int32_t* flags, hipStream_t st);
+                          uint16_t* selfl, ListScratch sc, int32_t* flags, hipStream_t st);
 // Rows of original ids [o_lo, o_hi), ascending, into rows[(o - o_lo) * cap + k].
 hipError_t launch_export(int64_t N, const int32_t* perm, const int32_t* nbr, const int32_t* cnt,
                          int cap, int64_t o_lo, int64_t o_hi, int32_t* rows, int32_t* row_cnt,

@@ -357,14 +357,37 @@ __device__ __forceinline__ void scan_cell(const double* __restrict__ x, int64_t 
   }
 }
 
-// One thread per atom. Two passes over the 27-cell stencil: the first counts the
-// pairs per distance bin, the second writes each pair at its bin's offset, so each
-// atom's list is ordered by bin (stencil order inside a bin). Stencil cells whose
-// nearest point lies beyond the list cutoff (with a 1e-6 A margin) are skipped.
+// Per-thread staging of one scratch column in LDS: entries are collected sixteen
+// at a time (stride 17 words, no bank conflicts) and written out as one 64-byte
+// segment at [k / 16][atom][16] (or 32 bytes of 16-bit values), so the global
+// stores are whole segments even though the threads flush at different times.
+constexpr int kStage = 16;
+constexpr int kStageStride = kStage + 1;
+
+__device__ __forceinline__ void stage_flush32(const uint32_t* st, uint4* col, int64_t N, int64_t p, int k) {
+  uint4* dst = col + ((int64_t)(k / kStage) * N + p) * (kStage / 4);
+#pragma unroll
+  for (int j = 0; j < kStage / 4; ++j)
+    dst[j] = make_uint4(st[4 * j], st[4 * j + 1], st[4 * j + 2], st[4 * j + 3]);
+}
+__device__ __forceinline__ void stage_flush16(const uint32_t* st, uint4* col, int64_t N, int64_t p, int k) {
+  uint4* dst = col + ((int64_t)(k / kStage) * N + p) * (kStage / 8);
+#pragma unroll
+  for (int j = 0; j < kStage / 8; ++j)
+    dst[j] = make_uint4((st[8 * j] & 0xffffu) | (st[8 * j + 1] << 16), (st[8 * j + 2] & 0xffffu) | (st[8 * j + 3] << 16),
+                        (st[8 * j + 4] & 0xffffu) | (st[8 * j + 5] << 16), (st[8 * j + 6] & 0xffffu) | (st[8 * j + 7] << 16));
+}
+
+// One thread per atom, one pass over the 27-cell stencil. Every candidate inside
+// the radial list cutoff is appended, in stencil order, to the atom's radial
+// scratch column as q | bin << 28, and also to the angular scratch columns (with
+// its halo-local index) when inside the angular list cutoff; per-bin counts give
+// the bin breakpoints. Stencil cells whose nearest point lies beyond the list
+// cutoff (with a 1e-6 A margin) are skipped. k_place_lists then orders the entries.
 __global__ void __launch_bounds__(kBlock)
 k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t* __restrict__ start,
               const int32_t* __restrict__ cell_sorted, double rcR, double rcA, double skin, int capR, int capA,
-              ListOut lo_, HaloTables ht, int32_t* __restrict__ flags) {
+              ListOut lo_, HaloTables ht, ListScratch sc, int32_t* __restrict__ flags) {
   if (flags[FLAG_REBUILD] == 0) return;
   const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (p >= N) return;
@@ -403,71 +426,176 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
     cR[k] = 0;
     cA[k] = 0;
   }
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int a = 0; a < nof[2]; ++a) {
-      const int rz = cz + lo[2] + a;
-      const int zc = (rz + g.nc[2]) % g.nc[2];
-      const double sz = rz < 0 ? -g.box[2] : (rz >= g.nc[2] ? g.box[2] : 0.0);
-      const double gz = nof[2] < 3 ? 0.0 : (a == 0 ? dlo[2] : (a == 2 ? dhi[2] : 0.0));
-      for (int b = 0; b < nof[1]; ++b) {
-        const int ry = cy + lo[1] + b;
-        const int yc = (ry + g.nc[1]) % g.nc[1];
-        const double sy = ry < 0 ? -g.box[1] : (ry >= g.nc[1] ? g.box[1] : 0.0);
-        const double gy = nof[1] < 3 ? 0.0 : (b == 0 ? dlo[1] : (b == 2 ? dhi[1] : 0.0));
-        for (int e = 0; e < nof[0]; ++e) {
-          const int rx = cx + lo[0] + e;
-          const int xc = (rx + g.nc[0]) % g.nc[0];
-          const double sx = rx < 0 ? -g.box[0] : (rx >= g.nc[0] ? g.box[0] : 0.0);
-          const double gx = nof[0] < 3 ? 0.0 : (e == 0 ? dlo[0] : (e == 2 ? dhi[0] : 0.0));
-          if (gx * gx + gy * gy + gz * gz >= tR[kNumBins - 1]) continue;
-          const int cc = cell_lin(g, xc, yc, zc);
-          const int q0 = start[cc], q1 = start[cc + 1];
-          if (q1 <= q0) continue;
-          // halo-local index of the cell's first atom (cells are contiguous in the halo)
-          const int lbase = (pass == 1 && hok) ? halo_index(ht, tile, hcells, q0) : 0;
-          scan_cell(x, N, q0, q1, p, xi, yi, zi, sx, sy, sz, g, tR[kNumBins - 1], [&](int q, double r2) {
-            const int br = bin_of(r2, tR);
-            if (pass == 0) {
-              cR[br] += 1;
-            } else {
-              const int pos = cR[br]++;
-              if (pos < capR) lo_.nbrR[(int64_t)pos * N + p] = q;
-            }
-            if (r2 < tA[kNumBins - 1]) {
-              const int ba = bin_of(r2, tA);
-              if (pass == 0) {
-                cA[ba] += 1;
-              } else {
-                const int pos = cA[ba]++;
-                if (pos < capA) {
-                  lo_.nbrA[(int64_t)pos * N + p] = q;
-                  lo_.nbrAl[(int64_t)pos * N + p] = hok ? (uint16_t)(lbase + (q - q0)) : kNoLocal;
-                }
+  int nr = 0, na = 0;
+  __shared__ uint32_t stage_r[kBlock * kStageStride], stage_a[kBlock * kStageStride],
+      stage_l[kBlock * kStageStride];
+  uint32_t* sr = stage_r + threadIdx.x * kStageStride;
+  uint32_t* sa = stage_a + threadIdx.x * kStageStride;
+  uint32_t* sl = stage_l + threadIdx.x * kStageStride;
+  for (int a = 0; a < nof[2]; ++a) {
+    const int rz = cz + lo[2] + a;
+    const int zc = (rz + g.nc[2]) % g.nc[2];
+    const double sz = rz < 0 ? -g.box[2] : (rz >= g.nc[2] ? g.box[2] : 0.0);
+    const double gz = nof[2] < 3 ? 0.0 : (a == 0 ? dlo[2] : (a == 2 ? dhi[2] : 0.0));
+    for (int b = 0; b < nof[1]; ++b) {
+      const int ry = cy + lo[1] + b;
+      const int yc = (ry + g.nc[1]) % g.nc[1];
+      const double sy = ry < 0 ? -g.box[1] : (ry >= g.nc[1] ? g.box[1] : 0.0);
+      const double gy = nof[1] < 3 ? 0.0 : (b == 0 ? dlo[1] : (b == 2 ? dhi[1] : 0.0));
+      for (int e = 0; e < nof[0]; ++e) {
+        const int rx = cx + lo[0] + e;
+        const int xc = (rx + g.nc[0]) % g.nc[0];
+        const double sx = rx < 0 ? -g.box[0] : (rx >= g.nc[0] ? g.box[0] : 0.0);
+        const double gx = nof[0] < 3 ? 0.0 : (e == 0 ? dlo[0] : (e == 2 ? dhi[0] : 0.0));
+        if (gx * gx + gy * gy + gz * gz >= tR[kNumBins - 1]) continue;
+        const int cc = cell_lin(g, xc, yc, zc);
+        const int q0 = start[cc], q1 = start[cc + 1];
+        if (q1 <= q0) continue;
+        // halo-local index of sorted atom q is loc0 + q (cells are contiguous in the halo)
+        const int loc0 = hok ? halo_index(ht, tile, hcells, q0) - q0 : 0;
+        scan_cell(x, N, q0, q1, p, xi, yi, zi, sx, sy, sz, g, tR[kNumBins - 1], [&](int q, double r2) {
+          const int br = bin_of(r2, tR);
+          cR[br] += 1;
+          if (nr < capR) {
+            sr[nr % kStage] = (uint32_t)q | ((uint32_t)br << 28);
+            if (nr % kStage == kStage - 1) stage_flush32(sr, sc.r, N, p, nr);
+          }
+          ++nr;
+          if (r2 < tA[kNumBins - 1]) {
+            const int ba = bin_of(r2, tA);
+            cA[ba] += 1;
+            if (na < capA) {
+              sa[na % kStage] = (uint32_t)q | ((uint32_t)ba << 28);
+              sl[na % kStage] = hok ? (uint32_t)(loc0 + q) : (uint32_t)kNoLocal;
+              if (na % kStage == kStage - 1) {
+                stage_flush32(sa, sc.a, N, p, na);
+                stage_flush16(sl, sc.l, N, p, na);
               }
             }
-          });
+            ++na;
+          }
+        });
+      }
+    }
+  }
+  // partial last words
+  if (nr < capR && nr % kStage != 0) stage_flush32(sr, sc.r, N, p, nr);
+  if (na < capA && na % kStage != 0) {
+    stage_flush32(sa, sc.a, N, p, na);
+    stage_flush16(sl, sc.l, N, p, na);
+  }
+  // cumulative breakpoints
+  int tr = 0, ta = 0;
+#pragma unroll
+  for (int k = 0; k < kNumBins; ++k) {
+    tr += cR[k];
+    ta += cA[k];
+    lo_.bpR[(int64_t)k * N + p] = tr < capR ? tr : capR;
+    lo_.bpA[(int64_t)k * N + p] = ta < capA ? ta : capA;
+  }
+  lo_.cntR[p] = nr < capR ? nr : capR;
+  lo_.cntA[p] = na < capA ? na : capA;
+  if (nr > capR) atomicMax(&flags[FLAG_OVF_R], nr);
+  if (na > capA) atomicMax(&flags[FLAG_OVF_A], na);
+}
+
+// One wavefront per 64 atoms: orders each atom's scratch entries by bin (stable
+// inside a bin) and writes the lists row by row, 64 consecutive atoms per store,
+// through an LDS tile of kPlaceRows rows; longer lists take further rounds.
+constexpr int kPlaceRows = 128;
+
+template <bool ANG>
+__device__ __forceinline__ void place_one(int64_t N, int64_t p, bool valid, int cap, int cnt,
+                                          const int32_t* __restrict__ bp, const uint4* __restrict__ col,
+                                          const uint4* __restrict__ lcol, int32_t* __restrict__ out,
+                                          uint16_t* __restrict__ lout, uint32_t* tile, uint16_t* ltile,
+                                          int rows_max) {
+  const int lane = threadIdx.x;
+  const int rows = ANG ? kPlaceRows / 2 : kPlaceRows;
+  for (int r0 = 0; r0 < rows_max; r0 += rows) {
+    if (valid) {
+      int off[kNumBins];
+      off[0] = 0;
+#pragma unroll
+      for (int k = 1; k < kNumBins; ++k) off[k] = bp[(int64_t)(k - 1) * N + p];
+      for (int g = 0; g < cnt; g += kStage) {
+        uint32_t v[kStage], h[kStage];
+        const uint4* src = col + ((int64_t)(g / kStage) * N + p) * (kStage / 4);
+#pragma unroll
+        for (int j = 0; j < kStage / 4; ++j) {
+          const uint4 w = src[j];
+          v[4 * j] = w.x;
+          v[4 * j + 1] = w.y;
+          v[4 * j + 2] = w.z;
+          v[4 * j + 3] = w.w;
+        }
+        if constexpr (ANG) {
+          const uint4* ls = lcol + ((int64_t)(g / kStage) * N + p) * (kStage / 8);
+#pragma unroll
+          for (int j = 0; j < kStage / 8; ++j) {
+            const uint4 w = ls[j];
+            const uint32_t t[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              h[8 * j + 2 * u] = t[u] & 0xffffu;
+              h[8 * j + 2 * u + 1] = t[u] >> 16;
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+          if (g + u < cnt) {
+            const int pos = off[v[u] >> 28]++ - r0;
+            if (pos >= 0 && pos < rows) {
+              tile[pos * 64 + lane] = v[u] & 0x0fffffffu;
+              if constexpr (ANG) ltile[pos * 64 + lane] = (uint16_t)h[u];
+            }
+          }
         }
       }
     }
-    if (pass == 0) {
-      // counts -> start offsets of each bin; record cumulative breakpoints
-      int sr = 0, sa = 0;
-#pragma unroll
-      for (int k = 0; k < kNumBins; ++k) {
-        const int nr_k = cR[k], na_k = cA[k];
-        cR[k] = sr;
-        cA[k] = sa;
-        sr += nr_k;
-        sa += na_k;
-        lo_.bpR[(int64_t)k * N + p] = sr < capR ? sr : capR;
-        lo_.bpA[(int64_t)k * N + p] = sa < capA ? sa : capA;
+    __syncthreads();
+    const int nrow = rows_max - r0 < rows ? rows_max - r0 : rows;
+    for (int r = 0; r < nrow; ++r) {
+      if (valid && r0 + r < cnt) {
+        out[(int64_t)(r0 + r) * N + p] = (int32_t)tile[r * 64 + lane];
+        if constexpr (ANG) lout[(int64_t)(r0 + r) * N + p] = ltile[r * 64 + lane];
       }
-      lo_.cntR[p] = sr < capR ? sr : capR;
-      lo_.cntA[p] = sa < capA ? sa : capA;
-      if (sr > capR) atomicMax(&flags[FLAG_OVF_R], sr);
-      if (sa > capA) atomicMax(&flags[FLAG_OVF_A], sa);
     }
+    __syncthreads();
   }
+}
+
+__global__ void __launch_bounds__(64)
+k_place_lists(int64_t N, ListOut lo_, ListScratch sc, const int32_t* __restrict__ flags) {
+  if (flags[FLAG_REBUILD] == 0) return;
+  __shared__ uint32_t tile[kPlaceRows * 64];
+  __shared__ int red[64];
+  const int64_t p = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const bool valid = p < N;
+  const int nr = valid ? lo_.cntR[p] : 0;
+  const int na = valid ? lo_.cntA[p] : 0;
+  // longest list of the wavefront (uniform loop bounds for the row writes)
+  red[threadIdx.x] = nr;
+  __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) {
+    if (threadIdx.x < (unsigned)o) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  const int rmax = red[0];
+  __syncthreads();
+  red[threadIdx.x] = na;
+  __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) {
+    if (threadIdx.x < (unsigned)o) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  const int amax = red[0];
+  __syncthreads();
+  place_one<false>(N, p, valid, 0, nr, lo_.bpR, sc.r, nullptr, lo_.nbrR, nullptr, tile, nullptr, rmax);
+  // angular: 64-row rounds, entries in the first half of the tile, local indices in the second
+  place_one<true>(N, p, valid, 0, na, lo_.bpA, sc.a, sc.l, lo_.nbrA, lo_.nbrAl, tile,
+                  reinterpret_cast<uint16_t*>(tile + (kPlaceRows / 2) * 64), amax);
 }
 
 // After a build the positions equal the build positions: displacement 0, bin 0.
@@ -527,7 +655,7 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, double rcR, double rcA, 
                           int32_t* cell_count, int32_t* cell_start, int32_t* cell_fill,
                           int32_t* scan_tmp, int32_t* nbrR, int32_t* cntR, int32_t* nbrA,
                           int32_t* cntA, int32_t* bpR, int32_t* bpA, HaloTables ht, uint16_t* nbrAl,
-                          uint16_t* selfl, int32_t* flags, hipStream_t st) {
+                          uint16_t* selfl, ListScratch sc, int32_t* flags, hipStream_t st) {
   const int nb = grid_blocks(N);
   const int ncell = g.ncell;
   hipError_t e;
@@ -552,7 +680,8 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, double rcR, double rcA, 
   hipLaunchKernelGGL(k_halo_tables, dim3(nb), dim3(kBlock), 0, st, N, g, cell_sorted, cell_start, ht, flags);
   const ListOut lout{nbrR, cntR, nbrA, cntA, bpR, bpA, nbrAl, selfl};
   hipLaunchKernelGGL(k_build_lists, dim3(nb), dim3(kBlock), 0, st, N, g, x, cell_start, cell_sorted,
-                     rcR, rcA, skin, capR, capA, lout, ht, flags);
+                     rcR, rcA, skin, capR, capA, lout, ht, sc, flags);
+  hipLaunchKernelGGL(k_place_lists, dim3(grid_blocks(N, 64)), dim3(64), 0, st, N, lout, sc, flags);
   hipLaunchKernelGGL(k_count_build, dim3(1), dim3(64), 0, st, flags);
   return hipGetLastError();
 }
