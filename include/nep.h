@@ -92,7 +92,7 @@ void nep_model_destroy(nep_model* m);
 
 /* Bytes of device workspace a system needs. surrogate may be NULL.
  * n_atoms: 1 .. 2^28 - 1 (list entries carry a 3-bit distance bin above the
- * 28-bit atom index while the lists are built).
+ * 28-bit atom index while the lists are built); cap_radial, cap_angular: 1 .. 4096.
  * cap_radial / cap_angular: per-atom capacities of the lists with skin
  * (radial cutoff + skin, angular cutoff + skin). */
 int nep_system_workspace_bytes(const nep_model* full, const nep_model* surrogate,

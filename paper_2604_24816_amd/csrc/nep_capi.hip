@@ -437,7 +437,8 @@ static int max_cells(const double box[3], double rc) {
 
 int nep_system_workspace_bytes(const nep_model* full, const nep_model* sur, int64_t n_atoms, const double box[3],
                                int32_t cap_radial, int32_t cap_angular, int64_t* bytes) {
-  if (!bytes || !box || n_atoms < 1 || n_atoms >= kMaxAtoms || cap_radial < 1 || cap_angular < 1)
+  if (!bytes || !box || n_atoms < 1 || n_atoms >= kMaxAtoms || cap_radial < 1 || cap_angular < 1 ||
+      cap_radial > kMaxCap || cap_angular > kMaxCap)
     return NEP_ERR_ARG;
   if (check_model_pair(full, sur)) return NEP_ERR_ARG;
   nep_system tmp;
@@ -450,7 +451,8 @@ int nep_system_workspace_bytes(const nep_model* full, const nep_model* sur, int6
 int nep_system_create(const nep_model* full, const nep_model* sur, int64_t n_atoms, const double box[3],
                       int32_t cap_radial, int32_t cap_angular, void* workspace, int64_t workspace_bytes,
                       void* hip_stream, nep_system** out) {
-  if (!out || !box || n_atoms < 1 || n_atoms >= kMaxAtoms || cap_radial < 1 || cap_angular < 1)
+  if (!out || !box || n_atoms < 1 || n_atoms >= kMaxAtoms || cap_radial < 1 || cap_angular < 1 ||
+      cap_radial > kMaxCap || cap_angular > kMaxCap)
     return NEP_ERR_ARG;
   if (check_model_pair(full, sur)) return NEP_ERR_ARG;
   for (int c = 0; c < 3; ++c)

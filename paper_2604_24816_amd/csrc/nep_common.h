@@ -103,6 +103,7 @@ struct ListScratch {
   uint4* l;
 };
 constexpr int64_t kMaxAtoms = (int64_t)1 << 28;  // list entries keep the bin in bits 28-30
+constexpr int kMaxCap = 4096;                     // per-atom list capacity (16-bit bin counters)
 
 
 // Device copy of one model (FP32 parameters, same packed order as the host FP64

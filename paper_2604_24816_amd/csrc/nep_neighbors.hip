@@ -357,6 +357,26 @@ __device__ __forceinline__ void scan_cell(const double* __restrict__ x, int64_t 
   }
 }
 
+// Eight 16-bit counters in two 64-bit registers (bins 0-3 and 4-7): a counter
+// update is a shift and two adds instead of a select chain over eight registers.
+struct BinCounts {
+  uint64_t lo = 0, hi = 0;
+  __device__ __forceinline__ void add(int b) {
+    const uint64_t inc = (uint64_t)1 << (16 * (b & 3));
+    lo += b < 4 ? inc : 0;
+    hi += b < 4 ? 0 : inc;
+  }
+  __device__ __forceinline__ int get(int b) const {
+    return (int)(((b < 4 ? lo : hi) >> (16 * (b & 3))) & 0xffffu);
+  }
+  // returns the counter, then increments it
+  __device__ __forceinline__ int take(int b) {
+    const int v = get(b);
+    add(b);
+    return v;
+  }
+};
+
 // Per-thread staging of one scratch column in LDS: entries are collected sixteen
 // at a time (stride 17 words, no bank conflicts) and written out as one 64-byte
 // segment at [k / 16][atom][16] (or 32 bytes of 16-bit values), so the global
@@ -420,12 +440,7 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
     dlo[d] = fmax(pos3[d] - cc3[d] * h - 1e-6, 0.0);
     dhi[d] = fmax((cc3[d] + 1) * h - pos3[d] - 1e-6, 0.0);
   }
-  int cR[kNumBins], cA[kNumBins];
-#pragma unroll
-  for (int k = 0; k < kNumBins; ++k) {
-    cR[k] = 0;
-    cA[k] = 0;
-  }
+  BinCounts cR, cA;
   int nr = 0, na = 0;
   __shared__ uint32_t stage_r[kBlock * kStageStride], stage_a[kBlock * kStageStride],
       stage_l[kBlock * kStageStride];
@@ -455,7 +470,7 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
         const int loc0 = hok ? halo_index(ht, tile, hcells, q0) - q0 : 0;
         scan_cell(x, N, q0, q1, p, xi, yi, zi, sx, sy, sz, g, tR[kNumBins - 1], [&](int q, double r2) {
           const int br = bin_of(r2, tR);
-          cR[br] += 1;
+          cR.add(br);
           if (nr < capR) {
             sr[nr % kStage] = (uint32_t)q | ((uint32_t)br << 28);
             if (nr % kStage == kStage - 1) stage_flush32(sr, sc.r, N, p, nr);
@@ -463,7 +478,7 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
           ++nr;
           if (r2 < tA[kNumBins - 1]) {
             const int ba = bin_of(r2, tA);
-            cA[ba] += 1;
+            cA.add(ba);
             if (na < capA) {
               sa[na % kStage] = (uint32_t)q | ((uint32_t)ba << 28);
               sl[na % kStage] = hok ? (uint32_t)(loc0 + q) : (uint32_t)kNoLocal;
@@ -488,8 +503,8 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
   int tr = 0, ta = 0;
 #pragma unroll
   for (int k = 0; k < kNumBins; ++k) {
-    tr += cR[k];
-    ta += cA[k];
+    tr += cR.get(k);
+    ta += cA.get(k);
     lo_.bpR[(int64_t)k * N + p] = tr < capR ? tr : capR;
     lo_.bpA[(int64_t)k * N + p] = ta < capA ? ta : capA;
   }
@@ -501,8 +516,10 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
 
 // One wavefront per 64 atoms: orders each atom's scratch entries by bin (stable
 // inside a bin) and writes the lists row by row, 64 consecutive atoms per store,
-// through an LDS tile of kPlaceRows rows; longer lists take further rounds.
-constexpr int kPlaceRows = 128;
+// through an LDS tile of kPlaceRows rows; longer lists take further rounds. The
+// angular round keeps its entries in rows 0..63 of the tile and the 16-bit local
+// indices right after them.
+constexpr int kPlaceRows = 126;  // radial rows per round; angular rounds take 63 (+1 spare row each)
 
 template <bool ANG>
 __device__ __forceinline__ void place_one(int64_t N, int64_t p, bool valid, int cap, int cnt,
@@ -511,13 +528,16 @@ __device__ __forceinline__ void place_one(int64_t N, int64_t p, bool valid, int 
                                           uint16_t* __restrict__ lout, uint32_t* tile, uint16_t* ltile,
                                           int rows_max) {
   const int lane = threadIdx.x;
-  const int rows = ANG ? kPlaceRows / 2 : kPlaceRows;
+  const int rows = ANG ? kPlaceRows / 2 : kPlaceRows;  // row `rows` of the tile is the spare row
   for (int r0 = 0; r0 < rows_max; r0 += rows) {
     if (valid) {
-      int off[kNumBins];
-      off[0] = 0;
+      BinCounts off;
 #pragma unroll
-      for (int k = 1; k < kNumBins; ++k) off[k] = bp[(int64_t)(k - 1) * N + p];
+      for (int k = 1; k < kNumBins; ++k) {
+        const int b0 = bp[(int64_t)(k - 1) * N + p];
+        if (k < 4) off.lo |= (uint64_t)b0 << (16 * k);
+        else off.hi |= (uint64_t)b0 << (16 * (k - 4));
+      }
       for (int g = 0; g < cnt; g += kStage) {
         uint32_t v[kStage], h[kStage];
         const uint4* src = col + ((int64_t)(g / kStage) * N + p) * (kStage / 4);
@@ -544,13 +564,12 @@ __device__ __forceinline__ void place_one(int64_t N, int64_t p, bool valid, int 
         }
 #pragma unroll
         for (int u = 0; u < kStage; ++u) {
-          if (g + u < cnt) {
-            const int pos = off[v[u] >> 28]++ - r0;
-            if (pos >= 0 && pos < rows) {
-              tile[pos * 64 + lane] = v[u] & 0x0fffffffu;
-              if constexpr (ANG) ltile[pos * 64 + lane] = (uint16_t)h[u];
-            }
-          }
+          const bool live = g + u < cnt;
+          const int pos = (live ? off.take((int)(v[u] >> 28)) : -1) - r0;
+          // entries outside this round go to the spare row `rows`
+          const int slot = (live && pos >= 0 && pos < rows ? pos : rows) * 64 + lane;
+          tile[slot] = v[u] & 0x0fffffffu;
+          if constexpr (ANG) ltile[slot] = (uint16_t)h[u];
         }
       }
     }
@@ -569,7 +588,7 @@ __device__ __forceinline__ void place_one(int64_t N, int64_t p, bool valid, int 
 __global__ void __launch_bounds__(64)
 k_place_lists(int64_t N, ListOut lo_, ListScratch sc, const int32_t* __restrict__ flags) {
   if (flags[FLAG_REBUILD] == 0) return;
-  __shared__ uint32_t tile[kPlaceRows * 64];
+  __shared__ uint32_t tile[(kPlaceRows + 2) * 64];
   __shared__ int red[64];
   const int64_t p = (int64_t)blockIdx.x * 64 + threadIdx.x;
   const bool valid = p < N;
@@ -595,7 +614,7 @@ k_place_lists(int64_t N, ListOut lo_, ListScratch sc, const int32_t* __restrict_
   place_one<false>(N, p, valid, 0, nr, lo_.bpR, sc.r, nullptr, lo_.nbrR, nullptr, tile, nullptr, rmax);
   // angular: 64-row rounds, entries in the first half of the tile, local indices in the second
   place_one<true>(N, p, valid, 0, na, lo_.bpA, sc.a, sc.l, lo_.nbrA, lo_.nbrAl, tile,
-                  reinterpret_cast<uint16_t*>(tile + (kPlaceRows / 2) * 64), amax);
+                  reinterpret_cast<uint16_t*>(tile + (kPlaceRows / 2 + 1) * 64), amax);
 }
 
 // After a build the positions equal the build positions: displacement 0, bin 0.
