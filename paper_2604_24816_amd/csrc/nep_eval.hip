@@ -342,10 +342,10 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
       const float fpj[8] = {fa.x, fa.y, fa.z, fa.w, fb.x, fb.y, fb.z, fb.w};
       float r, rinv;
       pair_r(dx, dy, dz, r, rinv);
-      float g[NR], dg[NR];
       float si = 0.f, sj = 0.f;
       if constexpr (MULTI) {
         const int tj = b.type[j];
+        float g[NR], dg[NR];
         radial_g_dg<NR, S::KR>(r, rcR_inv, cR + (ti * m.T + tj) * NR * S::KR, g, dg);
         float g2[NR], dg2[NR];
         radial_g_dg<NR, S::KR>(r, rcR_inv, cR + (tj * m.T + ti) * NR * S::KR, g2, dg2);
@@ -355,11 +355,17 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
           sj = fmaf(fpj[n], dg2[n], sj);
         }
       } else {
-        radial_g_dg<NR, S::KR>(r, rcR_inv, uniform_coeffs(cR), g, dg);
+        // one species: g'_n = sum_k c_nk e_k from the basis derivatives alone
+        float e[S::KR];
+        radial_basis_deriv<S::KR>(r, rcR_inv, e);
+        const cfloat_ptr c = uniform_coeffs(cR);
 #pragma unroll
         for (int n = 0; n < NR; ++n) {
-          si = fmaf(fpi[n], dg[n], si);
-          sj = fmaf(fpj[n], dg[n], sj);
+          float d = 0.f;
+#pragma unroll
+          for (int k = 0; k < S::KR; ++k) d = fmaf(c[n * S::KR + k], e[k], d);
+          si = fmaf(fpi[n], d, si);
+          sj = fmaf(fpj[n], d, sj);
         }
       }
       const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;

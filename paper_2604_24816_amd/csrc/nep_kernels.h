@@ -101,6 +101,56 @@ __device__ __forceinline__ void radial_g_dg(float r, float rc_inv, CP c, float* 
   }
 }
 
+// The radial basis itself, f_k = f_c (T_k + 1)/2 for k < K. For one species the
+// radial descriptors are linear in it, q_n = sum_k c_nk sum_j f_k(r_ij), so a center
+// accumulates the K basis sums and contracts with c once.
+template <int K>
+__device__ __forceinline__ void radial_basis(float r, float rc_inv, float* f) {
+  float sn, cs;
+  sincospif(r * rc_inv, &sn, &cs);
+  const float fc = 0.5f * (1.f + cs);
+  const float y = r * rc_inv - 1.f;
+  const float x = 2.f * y * y - 1.f;
+  const float hf = 0.5f * fc;
+  float Tm1 = 1.f, T = x;
+  f[0] = fc;
+  f[1] = fmaf(hf, x, hf);
+#pragma unroll
+  for (int k = 2; k < K; ++k) {
+    const float Tn = 2.f * x * T - Tm1;
+    Tm1 = T;
+    T = Tn;
+    f[k] = fmaf(hf, Tn, hf);
+  }
+}
+
+// e_k = d f_k / dr. For one species dU_i/dr_ij = sum_k w_ik e_k(r_ij) with
+// w_ik = sum_n (dU_i/dq_n) c_nk formed once per center.
+template <int K>
+__device__ __forceinline__ void radial_basis_deriv(float r, float rc_inv, float* e) {
+  float sn, cs;
+  sincospif(r * rc_inv, &sn, &cs);
+  const float fc = 0.5f * (1.f + cs);
+  const float dfc = -0.5f * kPiF * rc_inv * sn;
+  const float y = r * rc_inv - 1.f;
+  const float x = 2.f * y * y - 1.f;
+  const float hfd = 2.f * y * rc_inv * fc;  // (f_c / 2) dx/dr
+  const float hdf = 0.5f * dfc;
+  float Tm1 = 1.f, T = x, dTm1 = 0.f, dT = 1.f;
+  e[0] = dfc;
+  e[1] = fmaf(hdf, x + 1.f, hfd);
+#pragma unroll
+  for (int k = 2; k < K; ++k) {
+    const float Tn = 2.f * x * T - Tm1;
+    const float dTn = 2.f * T + 2.f * x * dT - dTm1;
+    Tm1 = T;
+    T = Tn;
+    dTm1 = dT;
+    dT = dTn;
+    e[k] = fmaf(hdf, Tn + 1.f, hfd * dTn);
+  }
+}
+
 // FP64 minimum-image pair vector, rounded to FP32 after the subtraction.
 __device__ __forceinline__ void pair_vec(const double* __restrict__ x, int64_t N, int64_t j, double xi,
                                          double yi, double zi, double Lx, double Ly, double Lz, float& dx,
@@ -224,20 +274,37 @@ __device__ __forceinline__ void desc_accumulate(const ModelDev& m, const EvalBuf
   const float* cR = m.cR + (MULTI ? 0 : (ti * m.T) * NR * S::KR);
   const float* cA = m.cA + (MULTI ? 0 : (ti * m.T) * NA * S::KA);
   const int kR = list_bound(b.bpR, b.flags, N, i);
+  float Qb[S::KR];  // basis sums (one species)
+#pragma unroll
+  for (int k = 0; k < S::KR; ++k) Qb[k] = 0.f;
   for_each_entry(b.nbrR, x, N, i, kR, [&](int, int32_t j, double xj, double yj, double zj) {
     float dx, dy, dz;
     if (!inside(xj, yj, zj, xi, yi, zi, Lx, Ly, Lz, rcR2, dx, dy, dz)) return;
     ++nr;
     float r, rinv;
     pair_r(dx, dy, dz, r, rinv);
-    float g[NR];
-    if constexpr (MULTI)
+    if constexpr (MULTI) {
+      float g[NR];
       radial_g<NR, S::KR>(r, rcR_inv, m.cR + (ti * m.T + b.type[j]) * NR * S::KR, g);
-    else
-      radial_g<NR, S::KR>(r, rcR_inv, uniform_coeffs(cR), g);
 #pragma unroll
-    for (int n = 0; n < NR; ++n) q[n] += g[n];
+      for (int n = 0; n < NR; ++n) q[n] += g[n];
+    } else {
+      float f[S::KR];
+      radial_basis<S::KR>(r, rcR_inv, f);
+#pragma unroll
+      for (int k = 0; k < S::KR; ++k) Qb[k] += f[k];
+    }
   });
+  if constexpr (!MULTI) {
+    const cfloat_ptr c = uniform_coeffs(cR);
+#pragma unroll
+    for (int n = 0; n < NR; ++n) {
+      float a = 0.f;
+#pragma unroll
+      for (int k = 0; k < S::KR; ++k) a = fmaf(c[n * S::KR + k], Qb[k], a);
+      q[n] += a;
+    }
+  }
   const int kA = list_bound(b.bpA, b.flags, N, i);
   for_each_entry(b.nbrA, x, N, i, kA, [&](int, int32_t j, double xj, double yj, double zj) {
     float dx, dy, dz;
