@@ -110,8 +110,9 @@ struct nep_system {
   double *x, *v, *x_alt, *v_alt, *x_build;
   int32_t *type, *type_alt, *perm, *perm_alt, *cellid, *cell_sorted, *src, *key;
   int32_t *cell_count, *cell_start, *cell_fill, *scan_tmp;
-  int32_t *nbrR, *cntR, *nbrA, *cntA, *bpR, *bpA, *nactR, *nactA;
-  uint16_t *nbrAl, *selfl;
+  int32_t *nbr, *cnt, *bp, *nactR, *nactA;
+  uint16_t *nbrl, *selfl;
+  BinEdges be;
   HaloTables ht;
   ListScratch lsc;
   float *F[2], *U, *FpR, *G;
@@ -157,23 +158,19 @@ int64_t layout(nep_system* s, char* base, int64_t N, int capR, int capA, int max
   S.cell_start = c.take<int32_t>(max_ncell + 1);
   S.cell_fill = c.take<int32_t>(max_ncell);
   S.scan_tmp = c.take<int32_t>(max_ncell / 1024 + 2);
-  S.nbrR = c.take<int32_t>((int64_t)capR * N);
-  S.cntR = c.take<int32_t>(N);
-  S.nbrA = c.take<int32_t>((int64_t)capA * N);
-  S.cntA = c.take<int32_t>(N);
-  S.nbrAl = c.take<uint16_t>((int64_t)capA * N);
+  S.nbr = c.take<int32_t>((int64_t)capR * N);
+  S.cnt = c.take<int32_t>(N);
+  S.nbrl = c.take<uint16_t>((int64_t)capR * N);
   S.selfl = c.take<uint16_t>(N);
-  S.lsc.r = c.take<uint4>((int64_t)((capR + 15) / 16) * N * 4);
-  S.lsc.a = c.take<uint4>((int64_t)((capA + 15) / 16) * N * 4);
-  S.lsc.l = c.take<uint4>((int64_t)((capA + 15) / 16) * N * 2);
+  S.lsc.q = c.take<uint4>((int64_t)((capR + 15) / 16) * N * 4);
+  S.lsc.l = c.take<uint4>((int64_t)((capR + 15) / 16) * N * 2);
   {
     const int64_t nt = grid_blocks(N);
     S.ht.info = c.take<int32_t>(4 * nt);
     S.ht.start = c.take<int32_t>(nt * kHaloCellsMax);
     S.ht.off = c.take<int32_t>(nt * (kHaloCellsMax + 1));
   }
-  S.bpR = c.take<int32_t>((int64_t)kNumBins * N);
-  S.bpA = c.take<int32_t>((int64_t)kNumBins * N);
+  S.bp = c.take<int32_t>((int64_t)kMaxBins * N);
   S.nactR = c.take<int32_t>(N);
   S.nactA = c.take<int32_t>(N);
   S.F[0] = c.take<float>(3 * N);
@@ -258,13 +255,11 @@ EvalBuffers eval_buffers(nep_system* s, int slot) {
   for (int c = 0; c < 3; ++c) b.box[c] = s->box[c];
   b.x = s->x;
   b.type = s->type;
-  b.nbrR = s->nbrR;
-  b.nbrA = s->nbrA;
-  b.bpR = s->bpR;
-  b.bpA = s->bpA;
+  b.nbr = s->nbr;
+  b.bp = s->bp;
   b.nactR = s->nactR;
   b.nactA = s->nactA;
-  b.nbrAl = s->nbrAl;
+  b.nbrl = s->nbrl;
   b.selfl = s->selfl;
   b.hinfo = s->ht.info;
   b.hstart = s->ht.start;
@@ -299,12 +294,33 @@ int reduce_ew(nep_system* s, int base) {
   return NEP_OK;
 }
 
+// Merged, sorted distance-bin edges of the list (see BinEdges).
+BinEdges make_bin_edges(double rcR, double rcA, double skin) {
+  std::vector<double> e;
+  for (int k = 0; k < kFracs; ++k) {
+    e.push_back(rcA + (double)bin_frac(k) * skin);
+    e.push_back(rcR + (double)bin_frac(k) * skin);
+  }
+  std::sort(e.begin(), e.end());
+  e.erase(std::unique(e.begin(), e.end()), e.end());
+  BinEdges be{};
+  be.nbins = (int)e.size();
+  for (int b = 0; b < be.nbins; ++b) be.e2[b] = e[b] * e[b];
+  for (int k = 0; k < kFracs; ++k) {
+    const double er = rcR + (double)bin_frac(k) * skin, ea = rcA + (double)bin_frac(k) * skin;
+    be.idxR[k] = (int)(std::find(e.begin(), e.end(), er) - e.begin());
+    be.idxA[k] = (int)(std::find(e.begin(), e.end(), ea) - e.begin());
+  }
+  return be;
+}
+
 int rebuild(nep_system* s, double skin, int force) {
-  HIPCHK(launch_rebuild(s->N, s->grid, s->model[0].hp.rc_radial, s->model[0].hp.rc_angular, skin, s->capR,
-                        s->capA, s->x, s->v, s->type, s->perm, s->x_alt, s->v_alt, s->type_alt, s->perm_alt,
-                        s->x_build, s->cellid, s->cell_sorted, s->src, s->key, s->cell_count, s->cell_start,
-                        s->cell_fill, s->scan_tmp, s->nbrR, s->cntR, s->nbrA, s->cntA, s->bpR, s->bpA,
-                        s->ht, s->nbrAl, s->selfl, s->lsc, s->flags, s->st));
+  s->be = make_bin_edges(s->model[0].hp.rc_radial, s->model[0].hp.rc_angular, skin);
+  const ListOut lists{s->nbr, s->cnt, s->bp, s->nbrl, s->selfl};
+  HIPCHK(launch_rebuild(s->N, s->grid, s->be, s->capR, s->capA, s->x, s->v, s->type, s->perm, s->x_alt,
+                        s->v_alt, s->type_alt, s->perm_alt, s->x_build, s->cellid, s->cell_sorted, s->src,
+                        s->key, s->cell_count, s->cell_start, s->cell_fill, s->scan_tmp, lists, s->ht, s->lsc,
+                        s->flags, s->st));
   (void)force;
   return NEP_OK;
 }
@@ -596,8 +612,9 @@ int nep_export_neighbors(nep_system* s, int32_t which, int64_t* offsets, int32_t
   std::vector<int32_t> all((size_t)N * cap);
   for (int64_t o0 = 0; o0 < N; o0 += chunk) {
     const int64_t o1 = std::min(N, o0 + chunk);
-    HIPCHK(launch_export(N, s->perm, which == 0 ? s->nbrR : s->nbrA, which == 0 ? s->cntR : s->cntA, cap, o0, o1,
-                         rows, rcnt, s->st));
+    // the angular list with skin is the prefix of bins up to rc_angular + skin
+    const int32_t* cnt_src = which == 0 ? s->cnt : s->bp + (int64_t)s->be.idxA[kFracs - 1] * N;
+    HIPCHK(launch_export(N, s->perm, s->nbr, cnt_src, cap, o0, o1, rows, rcnt, s->st));
     HIPCHK(hipMemcpyAsync(cnt.data() + o0, rcnt, (o1 - o0) * sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipMemcpyAsync(all.data() + o0 * cap, rows, (size_t)(o1 - o0) * cap * sizeof(int32_t),
                           hipMemcpyDeviceToHost, s->st));
@@ -676,7 +693,7 @@ int vv_step(nep_system* s, int slot, int prec, double dt, int rebuild_every, dou
   HIPCHK(launch_set_flag(s->flags, FLAG_REBUILD, scheduled, s->st));
   HIPCHK(launch_kick_drift(s->N, dt, s->grid, s->F[slot], s->type, s->mt, s->x, s->v, s->x_build,
                            0.25 * skin * skin, s->flags, s->partial, s->st));
-  HIPCHK(launch_select_bin(s->partial, s->nblocks, s->flags, skin, s->st));
+  HIPCHK(launch_select_bin(s->partial, s->nblocks, s->flags, skin, s->be, s->st));
   if (ev) HIPCHK(hipEventRecord(ev[1], s->st));
   int st = rebuild(s, skin, 0);
   if (st) return st;
@@ -920,7 +937,7 @@ int nep_pair_counts(nep_system* s, int64_t* counts3) {
   HIPCHK(launch_reduce_partials(s->partial, s->nblocks, P_ERR2, 1, s->res + 14, s->st));
   HIPCHK(launch_sum_i32(s->N, s->nactA, s->partial, P_ERR2, s->st));
   HIPCHK(launch_reduce_partials(s->partial, s->nblocks, P_ERR2, 1, s->res + 15, s->st));
-  HIPCHK(launch_sum_i32(s->N, s->cntR, s->partial, P_ERR2, s->st));
+  HIPCHK(launch_sum_i32(s->N, s->cnt, s->partial, P_ERR2, s->st));
   HIPCHK(launch_reduce_partials(s->partial, s->nblocks, P_ERR2, 1, s->res + 16, s->st));
   double r[3];
   HIPCHK(hipMemcpyAsync(r, s->res + 14, 3 * sizeof(double), hipMemcpyDeviceToHost, s->st));

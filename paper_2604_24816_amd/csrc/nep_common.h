@@ -25,21 +25,32 @@ enum {
   FLAG_NONFINITE = 3,  // NaN/Inf seen
   FLAG_REBUILD = 4,    // 1 = the current step rebuilds its lists
   FLAG_NBUILD = 5,     // number of list builds (device counter)
-  FLAG_SPARE = 6,
-  FLAG_BIN = 7,        // distance bin the evaluation kernels read up to (see kBinFrac)
+  FLAG_BIN_A = 6,      // last distance bin of the angular pairs an evaluation visits
+  FLAG_BIN_R = 7,      // last distance bin of the radial pairs an evaluation visits
   FLAG_COUNT = 8
 };
 
-// The lists with skin are stored partitioned into distance bins (by the distance
-// at build time): bin k holds pairs with rc + kBinFrac[k-1] skin <= r < rc + kBinFrac[k] skin
-// (bin 0: r < rc). Between rebuilds a pair distance changes by at most twice the
-// largest displacement d since the build, so an evaluation only needs the bins up
-// to the first k with kBinFrac[k] skin >= 2 d; every pair there is still tested
-// against the true cutoff. bp[k][i] = number of entries of atom i in bins 0..k.
-constexpr int kNumBins = 8;
+// Each atom has one neighbour list with skin (r < rc_radial + skin), ordered by the
+// distance at build time into bins. The bin edges are the angular edges
+// rc_angular + f_k skin and the radial edges rc_radial + f_k skin (f_k = bin_frac(k)),
+// merged, sorted and without duplicates; bin b holds the pairs with
+// E[b-1] <= r < E[b]. The angular candidates are therefore a prefix of the list.
+// Between rebuilds a distance changes by at most twice the largest displacement d
+// since the build, so an evaluation visits the radial pairs up to the edge
+// rc_radial + f_k skin and the angular pairs up to rc_angular + f_k skin for the
+// first k with f_k skin >= 2 d; every visited pair is still tested against the
+// true cutoff. bp[b][i] = number of entries of atom i in bins 0..b.
+constexpr int kFracs = 8;
 __host__ __device__ constexpr float bin_frac(int k) {
   return k == 0 ? 0.f : (k == 1 ? 0.05f : (k == 2 ? 0.1f : (k == 3 ? 0.2f : (k == 4 ? 0.3f : (k == 5 ? 0.45f : (k == 6 ? 0.7f : 1.0f))))));
 }
+constexpr int kMaxBins = 2 * kFracs;
+struct BinEdges {
+  double e2[kMaxBins];       // squared edges, ascending; e2[nbins - 1] = (rc_radial + skin)^2
+  int nbins;
+  int idxR[kFracs];          // bin whose upper edge is rc_radial + f_k skin
+  int idxA[kFracs];          // bin whose upper edge is rc_angular + f_k skin
+};
 
 // Orthorhombic cell grid over the box. Cells are numbered brick by brick: bricks
 // of 2 x 2 x 2 cells in row-major brick order, cells inside a brick in row-major
@@ -84,25 +95,21 @@ struct HaloTables {
 
 // Outputs of the list build.
 struct ListOut {
-  int32_t* nbrR;    // [capR][N] radial list, ordered by distance bin
-  int32_t* cntR;    // [N]
-  int32_t* nbrA;    // [capA][N] angular list, ordered by distance bin
-  int32_t* cntA;    // [N]
-  int32_t* bpR;     // [kNumBins][N] cumulative bin breakpoints
-  int32_t* bpA;     // [kNumBins][N]
-  uint16_t* nbrAl;  // [capA][N] halo-local index of each angular entry
+  int32_t* nbr;     // [capR][N] neighbour list with skin, ordered by distance bin
+  int32_t* cnt;     // [N]
+  int32_t* bp;      // [kMaxBins][N] cumulative bin breakpoints
+  uint16_t* nbrl;   // [capR][N] halo-local index of each entry
   uint16_t* selfl;  // [N] halo-local index of the atom itself
 };
 
 // Per-build scratch: each atom's candidates in stencil order, sixteen per segment
-// ([ceil(cap / 16)][N][16]): radial and angular entries as q | bin << 28 (64-byte
-// segments) and the 16-bit halo-local index of each angular entry (32-byte segments).
+// ([ceil(capR / 16)][N][16]): entries as q | bin << 28 (64-byte segments) and their
+// 16-bit halo-local indices (32-byte segments).
 struct ListScratch {
-  uint4* r;
-  uint4* a;
+  uint4* q;
   uint4* l;
 };
-constexpr int64_t kMaxAtoms = (int64_t)1 << 28;  // list entries keep the bin in bits 28-30
+constexpr int64_t kMaxAtoms = (int64_t)1 << 28;  // list entries keep the bin in bits 28-31
 constexpr int kMaxCap = 4096;                     // per-atom list capacity (16-bit bin counters)
 
 
@@ -151,14 +158,13 @@ inline int grid_blocks(int64_t n, int block = kBlock) {
 hipError_t launch_zero_i32(int32_t* p, int64_t n, hipStream_t st);
 hipError_t launch_zero_f32(float* p, int64_t n, hipStream_t st);
 hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st);
-hipError_t launch_rebuild(int64_t N, const CellGrid& g, double rcR, double rcA, double skin, int capR,
-                          int capA, double* x, double* v, int32_t* type, int32_t* perm,
-                          double* x_alt, double* v_alt, int32_t* type_alt, int32_t* perm_alt,
-                          double* x_build, int32_t* cellid, int32_t* cell_sorted, int32_t* src,
-                          int32_t* key, int32_t* cell_count, int32_t* cell_start, int32_t* cell_fill,
-                          int32_t* scan_tmp, int32_t* nbrR, int32_t* cntR, int32_t* nbrA,
-                          int32_t* cntA, int32_t* bpR, int32_t* bpA, HaloTables ht, uint16_t* nbrAl,
-                          uint16_t* selfl, ListScratch sc, int32_t* flags, hipStream_t st);
+hipError_t launch_rebuild(int64_t N, const CellGrid& g, const BinEdges& be, int capR, int capA,
+                          double* x, double* v, int32_t* type, int32_t* perm, double* x_alt,
+                          double* v_alt, int32_t* type_alt, int32_t* perm_alt, double* x_build,
+                          int32_t* cellid, int32_t* cell_sorted, int32_t* src, int32_t* key,
+                          int32_t* cell_count, int32_t* cell_start, int32_t* cell_fill,
+                          int32_t* scan_tmp, const ListOut& lists, HaloTables ht, ListScratch sc,
+                          int32_t* flags, hipStream_t st);
 // Rows of original ids [o_lo, o_hi), ascending, into rows[(o - o_lo) * cap + k].
 hipError_t launch_export(int64_t N, const int32_t* perm, const int32_t* nbr, const int32_t* cnt,
                          int cap, int64_t o_lo, int64_t o_hi, int32_t* rows, int32_t* row_cnt,
@@ -170,13 +176,11 @@ struct EvalBuffers {
   double box[3];
   const double* x;       // [3][N]
   const int32_t* type;   // [N]
-  const int32_t* nbrR;   // [capR][N] radial list with skin, in distance bins
-  const int32_t* nbrA;   // [capA][N] angular list with skin, in distance bins
-  const int32_t* bpR;    // [kNumBins][N] bin breakpoints of the radial list
-  const int32_t* bpA;    // [kNumBins][N] bin breakpoints of the angular list
+  const int32_t* nbr;    // [capR][N] neighbour list with skin, in distance bins
+  const int32_t* bp;     // [kMaxBins][N] bin breakpoints
   int32_t* nactR;        // [N] pairs inside rc_radial at this evaluation
   int32_t* nactA;        // [N] pairs inside rc_angular
-  const uint16_t* nbrAl;  // [capA][N] halo-local index of each angular entry
+  const uint16_t* nbrl;   // [capR][N] halo-local index of each entry
   const uint16_t* selfl;  // [N] halo-local index of the atom itself
   const int32_t* hinfo;   // halo tables of the last list build (see HaloTables)
   const int32_t* hstart;
@@ -207,9 +211,10 @@ hipError_t launch_max_partials(const double* partial, int nblocks, int slot, dou
 hipError_t launch_kick_drift(int64_t N, double dt, CellGrid g, const float* F, const int32_t* type,
                              MassTable mt, double* x, double* v, const double* x_build,
                              double half_skin2, int32_t* flags, double* partial, hipStream_t st);
-// FLAG_BIN from the per-workgroup displacement maxima the drift kernel left in partial.
+// FLAG_BIN_R / FLAG_BIN_A from the per-workgroup displacement maxima the drift
+// kernel left in partial.
 hipError_t launch_select_bin(const double* partial, int nblocks, int32_t* flags, double skin,
-                             hipStream_t st);
+                             const BinEdges& be, hipStream_t st);
 hipError_t launch_kick(int64_t N, double dt, const float* F, const int32_t* type, MassTable mt,
                        double* v, hipStream_t st);
 hipError_t launch_kick_diff(int64_t N, double dt, const float* Fa, const float* Fb,

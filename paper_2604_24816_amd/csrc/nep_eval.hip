@@ -331,20 +331,29 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
     }
     const float* cR = m.cR;
     const float* cA = m.cA;
-    // radial: gather, F_i += (Fp_i . g'^{ij} + Fp_j . g'^{ji}) u
+    float G[NA * NC];
+#pragma unroll
+    for (int k = 0; k < NA * NC; ++k) G[k] = b.G[(int64_t)k * N + i];
     const double rcR2 = m.rcR64 * m.rcR64, rcA2 = m.rcA64 * m.rcA64;
-    const int kR = list_bound(b.bpR, b.flags, N, i);
-    for_each_entry(b.nbrR, x, N, i, kR, [&](int, int32_t j, double xj, double yj, double zj) {
-      float dx, dy, dz;
-      if (!inside(xj, yj, zj, xi, yi, zi, Lx, Ly, Lz, rcR2, dx, dy, dz)) return;
+    const int kR = radial_bound(b, i), kA = angular_bound(b, i);
+    // One pass over the list. Radial pairs: gather, F_i += (Fp_i . g'^{ij} + Fp_j . g'^{ji}) u.
+    // Angular and four-body pairs (the angular prefix inside rc_angular): scatter
+    // dU_i/dr_ij into this atom and -dU_i/dr_ij into the neighbour.
+    for_each_entry(b.nbr, x, N, i, kR, [&](int p, int32_t j, double xj, double yj, double zj) {
+      double ex, ey, ez;
+      const double r2 = pair_r2_64(xj, yj, zj, xi, yi, zi, Lx, Ly, Lz, ex, ey, ez);
+      if (!(r2 < rcR2)) return;
+      const float dx = (float)ex, dy = (float)ey, dz = (float)ez;
+      const bool ang = p < kA && r2 < rcA2;
+      const int lj = (ang && lds) ? (int)b.nbrl[(int64_t)p * N + i] : 0;
       const float4* fr = reinterpret_cast<const float4*>(b.FpR + 8 * (int64_t)j);
       const float4 fa = fr[0], fb = fr[1];
       const float fpj[8] = {fa.x, fa.y, fa.z, fa.w, fb.x, fb.y, fb.z, fb.w};
       float r, rinv;
       pair_r(dx, dy, dz, r, rinv);
+      const int tj = MULTI ? b.type[j] : 0;
       float si = 0.f, sj = 0.f;
       if constexpr (MULTI) {
-        const int tj = b.type[j];
         float g[NR], dg[NR];
         radial_g_dg<NR, S::KR>(r, rcR_inv, cR + (ti * m.T + tj) * NR * S::KR, g, dg);
         float g2[NR], dg2[NR];
@@ -374,30 +383,20 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
       fy = fmaf(st, uy, fy);
       fz = fmaf(st, uz, fz);
       // virial of dU_i/dr_ij = si u
-      const float d[3] = {dx, dy, dz};
-      const float f[3] = {si * ux, si * uy, si * uz};
+      {
+        const float d[3] = {dx, dy, dz};
+        const float f[3] = {si * ux, si * uy, si * uz};
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) w[a * 3 + c] = fmaf(-d[a], f[c], w[a * 3 + c]);
-    });
-    // angular + four-body: scatter
-    float G[NA * NC];
-#pragma unroll
-    for (int k = 0; k < NA * NC; ++k) G[k] = b.G[(int64_t)k * N + i];
-    const int kA = list_bound(b.bpA, b.flags, N, i);
-    for_each_entry(b.nbrA, x, N, i, kA, [&](int p, int32_t j, double xj, double yj, double zj) {
-      float dx, dy, dz;
-      if (!inside(xj, yj, zj, xi, yi, zi, Lx, Ly, Lz, rcA2, dx, dy, dz)) return;
-      const int lj = lds ? (int)b.nbrAl[(int64_t)p * N + i] : 0;
-      float r, rinv;
-      pair_r(dx, dy, dz, r, rinv);
+          for (int c = 0; c < 3; ++c) w[a * 3 + c] = fmaf(-d[a], f[c], w[a * 3 + c]);
+      }
+      if (!ang) return;
       float g[NA], dg[NA];
       if constexpr (MULTI)
-        radial_g_dg<NA, S::KA>(r, rcA_inv, cA + (ti * m.T + b.type[j]) * NA * S::KA, g, dg);
+        radial_g_dg<NA, S::KA>(r, rcA_inv, cA + (ti * m.T + tj) * NA * S::KA, g, dg);
       else
         radial_g_dg<NA, S::KA>(r, rcA_inv, uniform_coeffs(cA), g, dg);
-      const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
       // F_ij = sum_lm [ A_lm P_lm u + B_lm (grad P_lm - l P_lm u) / r ] with
       // A_lm = sum_n G_nlm g'_n and B_lm = sum_n G_nlm g_n; the l P B terms are
       // summed per l and scaled once.

@@ -250,11 +250,24 @@ __device__ __forceinline__ bool pair_inside(const double* __restrict__ x, int64_
   return true;
 }
 
-// Number of list entries of atom i the current evaluation must visit: the entries
-// of the distance bins that pairs can have reached since the last build.
-__device__ __forceinline__ int list_bound(const int32_t* __restrict__ bp, const int32_t* __restrict__ flags,
-                                          int64_t N, int64_t i) {
-  return bp[(int64_t)flags[FLAG_BIN] * N + i];
+// Number of list entries of atom i the current evaluation must visit for radial
+// (resp. angular) pairs: the entries of the distance bins those pairs can have
+// reached since the last build. The angular bound never exceeds the radial one.
+__device__ __forceinline__ int radial_bound(const EvalBuffers& b, int64_t i) {
+  return b.bp[(int64_t)b.flags[FLAG_BIN_R] * b.N + i];
+}
+__device__ __forceinline__ int angular_bound(const EvalBuffers& b, int64_t i) {
+  return b.bp[(int64_t)b.flags[FLAG_BIN_A] * b.N + i];
+}
+
+// FP64 minimum-image vector of a pair whose position is loaded and its r^2.
+__device__ __forceinline__ double pair_r2_64(double xj, double yj, double zj, double xi, double yi, double zi,
+                                             double Lx, double Ly, double Lz, double& ex, double& ey,
+                                             double& ez) {
+  ex = min_image(xj - xi, Lx);
+  ey = min_image(yj - yi, Ly);
+  ez = min_image(zj - zi, Lz);
+  return ex * ex + ey * ey + ez * ez;
 }
 
 // Radial descriptors q[0..NR) and angular accumulators s[NA][NC] of center i over
@@ -273,19 +286,24 @@ __device__ __forceinline__ void desc_accumulate(const ModelDev& m, const EvalBuf
   na = 0;
   const float* cR = m.cR + (MULTI ? 0 : (ti * m.T) * NR * S::KR);
   const float* cA = m.cA + (MULTI ? 0 : (ti * m.T) * NA * S::KA);
-  const int kR = list_bound(b.bpR, b.flags, N, i);
+  const int kR = radial_bound(b, i), kA = angular_bound(b, i);
   float Qb[S::KR];  // basis sums (one species)
 #pragma unroll
   for (int k = 0; k < S::KR; ++k) Qb[k] = 0.f;
-  for_each_entry(b.nbrR, x, N, i, kR, [&](int, int32_t j, double xj, double yj, double zj) {
-    float dx, dy, dz;
-    if (!inside(xj, yj, zj, xi, yi, zi, Lx, Ly, Lz, rcR2, dx, dy, dz)) return;
+  // one pass over the list: radial terms for every pair inside rc_radial, angular
+  // terms for the pairs of the angular prefix inside rc_angular
+  for_each_entry(b.nbr, x, N, i, kR, [&](int p, int32_t j, double xj, double yj, double zj) {
+    double ex, ey, ez;
+    const double r2 = pair_r2_64(xj, yj, zj, xi, yi, zi, Lx, Ly, Lz, ex, ey, ez);
+    if (!(r2 < rcR2)) return;
+    const float dx = (float)ex, dy = (float)ey, dz = (float)ez;
     ++nr;
     float r, rinv;
     pair_r(dx, dy, dz, r, rinv);
+    const int tj = MULTI ? b.type[j] : 0;
     if constexpr (MULTI) {
       float g[NR];
-      radial_g<NR, S::KR>(r, rcR_inv, m.cR + (ti * m.T + b.type[j]) * NR * S::KR, g);
+      radial_g<NR, S::KR>(r, rcR_inv, m.cR + (ti * m.T + tj) * NR * S::KR, g);
 #pragma unroll
       for (int n = 0; n < NR; ++n) q[n] += g[n];
     } else {
@@ -293,6 +311,18 @@ __device__ __forceinline__ void desc_accumulate(const ModelDev& m, const EvalBuf
       radial_basis<S::KR>(r, rcR_inv, f);
 #pragma unroll
       for (int k = 0; k < S::KR; ++k) Qb[k] += f[k];
+    }
+    if (p < kA && r2 < rcA2) {
+      ++na;
+      float g[NA];
+      if constexpr (MULTI)
+        radial_g<NA, S::KA>(r, rcA_inv, m.cA + (ti * m.T + tj) * NA * S::KA, g);
+      else
+        radial_g<NA, S::KA>(r, rcA_inv, uniform_coeffs(cA), g);
+      for_each_poly<NC>(dx * rinv, dy * rinv, dz * rinv, [&](int lm, float P) {
+#pragma unroll
+        for (int n = 0; n < NA; ++n) s[n * NC + lm] = fmaf(g[n], P, s[n * NC + lm]);
+      });
     }
   });
   if constexpr (!MULTI) {
@@ -305,23 +335,6 @@ __device__ __forceinline__ void desc_accumulate(const ModelDev& m, const EvalBuf
       q[n] += a;
     }
   }
-  const int kA = list_bound(b.bpA, b.flags, N, i);
-  for_each_entry(b.nbrA, x, N, i, kA, [&](int, int32_t j, double xj, double yj, double zj) {
-    float dx, dy, dz;
-    if (!inside(xj, yj, zj, xi, yi, zi, Lx, Ly, Lz, rcA2, dx, dy, dz)) return;
-    ++na;
-    float r, rinv;
-    pair_r(dx, dy, dz, r, rinv);
-    float g[NA];
-    if constexpr (MULTI)
-      radial_g<NA, S::KA>(r, rcA_inv, m.cA + (ti * m.T + b.type[j]) * NA * S::KA, g);
-    else
-      radial_g<NA, S::KA>(r, rcA_inv, uniform_coeffs(cA), g);
-    for_each_poly<NC>(dx * rinv, dy * rinv, dz * rinv, [&](int lm, float P) {
-#pragma unroll
-      for (int n = 0; n < NA; ++n) s[n * NC + lm] = fmaf(g[n], P, s[n * NC + lm]);
-    });
-  });
 }
 
 // The 3x3 traceless matrix S = sum_j g (u u^T - I/3) of one channel from its

@@ -63,9 +63,11 @@ __global__ void k_kick_drift(int64_t N, double dt, CellGrid g, const float* __re
   if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * kPartialStride + P_MAXD2] = sh[0];
 }
 
-// FLAG_BIN = first bin k with bin_frac(k) * skin >= 2 * (largest displacement since the build);
-// a rebuild later in the same step resets it to 0.
-__global__ void k_select_bin(const double* __restrict__ partial, int nblocks, int32_t* flags, double skin) {
+// k = first bin fraction with bin_frac(k) * skin >= 2 * (largest displacement since the
+// build); the evaluation visits the bins up to the edges rc_radial + f_k skin and
+// rc_angular + f_k skin. A rebuild later in the same step resets them to k = 0.
+__global__ void k_select_bin(const double* __restrict__ partial, int nblocks, int32_t* flags, double skin,
+                             BinEdges be) {
   __shared__ double sh[kBlock];
   double m = 0.0;
   for (int b = threadIdx.x; b < nblocks; b += kBlock) m = fmax(m, partial[(int64_t)b * kPartialStride + P_MAXD2]);
@@ -77,10 +79,17 @@ __global__ void k_select_bin(const double* __restrict__ partial, int nblocks, in
   }
   if (threadIdx.x != 0) return;
   const double d = sqrt(sh[0]);
-  int k = kNumBins - 1;
-  for (int j = kNumBins - 1; j >= 0; --j)
+  int k = kFracs - 1;
+  for (int j = kFracs - 1; j >= 0; --j)
     if ((double)bin_frac(j) * skin >= 2.0 * d * (1.0 + 1e-12)) k = j;
-  flags[FLAG_BIN] = k;
+  int br = be.idxR[kFracs - 1], ba = be.idxA[kFracs - 1];
+  for (int j = 0; j < kFracs; ++j)
+    if (j == k) {
+      br = be.idxR[j];
+      ba = be.idxA[j];
+    }
+  flags[FLAG_BIN_R] = br;
+  flags[FLAG_BIN_A] = ba;
 }
 
 __global__ void k_kick(int64_t N, double dt, const float* __restrict__ F, const int32_t* __restrict__ type,
@@ -256,8 +265,9 @@ hipError_t launch_kick_drift(int64_t N, double dt, CellGrid g, const float* F, c
   return hipGetLastError();
 }
 
-hipError_t launch_select_bin(const double* partial, int nblocks, int32_t* flags, double skin, hipStream_t st) {
-  hipLaunchKernelGGL(k_select_bin, dim3(1), dim3(kBlock), 0, st, partial, nblocks, flags, skin);
+hipError_t launch_select_bin(const double* partial, int nblocks, int32_t* flags, double skin,
+                             const BinEdges& be, hipStream_t st) {
+  hipLaunchKernelGGL(k_select_bin, dim3(1), dim3(kBlock), 0, st, partial, nblocks, flags, skin, be);
   return hipGetLastError();
 }
 

@@ -313,10 +313,11 @@ __device__ __forceinline__ int halo_index(const HaloTables& ht, int tile, int nc
   return ho[lo] + (q - hs[lo]);
 }
 
-__device__ __forceinline__ int bin_of(double r2, const double* t) {
+// Distance bin of a pair inside the list cutoff: the number of interior edges <= r^2.
+__device__ __forceinline__ int bin_of(double r2, const BinEdges& be) {
   int k = 0;
 #pragma unroll
-  for (int m = 0; m < kNumBins - 1; ++m) k += (r2 >= t[m]) ? 1 : 0;
+  for (int m = 0; m < kMaxBins - 1; ++m) k += (m < be.nbins - 1 && r2 >= be.e2[m]) ? 1 : 0;
   return k;
 }
 
@@ -357,17 +358,23 @@ __device__ __forceinline__ void scan_cell(const double* __restrict__ x, int64_t 
   }
 }
 
-// Eight 16-bit counters in two 64-bit registers (bins 0-3 and 4-7): a counter
-// update is a shift and two adds instead of a select chain over eight registers.
+// Sixteen 16-bit counters in four 64-bit registers: a counter update is a shift
+// and a few selects and adds instead of a select chain over sixteen registers.
 struct BinCounts {
-  uint64_t lo = 0, hi = 0;
+  uint64_t w[4] = {0, 0, 0, 0};
   __device__ __forceinline__ void add(int b) {
     const uint64_t inc = (uint64_t)1 << (16 * (b & 3));
-    lo += b < 4 ? inc : 0;
-    hi += b < 4 ? 0 : inc;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] += (b >> 2) == k ? inc : 0;
   }
   __device__ __forceinline__ int get(int b) const {
-    return (int)(((b < 4 ? lo : hi) >> (16 * (b & 3))) & 0xffffu);
+    const uint64_t v = (b >> 2) == 0 ? w[0] : ((b >> 2) == 1 ? w[1] : ((b >> 2) == 2 ? w[2] : w[3]));
+    return (int)((v >> (16 * (b & 3))) & 0xffffu);
+  }
+  __device__ __forceinline__ void set(int b, int v) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if ((b >> 2) == k) w[k] |= (uint64_t)v << (16 * (b & 3));
   }
   // returns the counter, then increments it
   __device__ __forceinline__ int take(int b) {
@@ -398,16 +405,15 @@ __device__ __forceinline__ void stage_flush16(const uint32_t* st, uint4* col, in
                         (st[8 * j + 4] & 0xffffu) | (st[8 * j + 5] << 16), (st[8 * j + 6] & 0xffffu) | (st[8 * j + 7] << 16));
 }
 
-// One thread per atom, one pass over the 27-cell stencil. Every candidate inside
-// the radial list cutoff is appended, in stencil order, to the atom's radial
-// scratch column as q | bin << 28, and also to the angular scratch columns (with
-// its halo-local index) when inside the angular list cutoff; per-bin counts give
-// the bin breakpoints. Stencil cells whose nearest point lies beyond the list
-// cutoff (with a 1e-6 A margin) are skipped. k_place_lists then orders the entries.
+// One thread per atom, one pass over the 27-cell stencil. Every candidate inside the
+// list cutoff is appended, in stencil order, to the atom's scratch column as
+// q | bin << 28 together with its halo-local index; per-bin counts give the bin
+// breakpoints. Stencil cells whose nearest point lies beyond the list cutoff (with a
+// 1e-6 A margin) are skipped. k_place_lists then orders the entries by bin.
 __global__ void __launch_bounds__(kBlock)
 k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t* __restrict__ start,
-              const int32_t* __restrict__ cell_sorted, double rcR, double rcA, double skin, int capR, int capA,
-              ListOut lo_, HaloTables ht, ListScratch sc, int32_t* __restrict__ flags) {
+              const int32_t* __restrict__ cell_sorted, BinEdges be, int capR, int capA, ListOut lo_,
+              HaloTables ht, ListScratch sc, int32_t* __restrict__ flags) {
   if (flags[FLAG_REBUILD] == 0) return;
   const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (p >= N) return;
@@ -415,17 +421,7 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
   const bool hok = ht.info[4 * tile + 2] != 0;
   const int hcells = ht.info[4 * tile + 0];
   lo_.selfl[p] = hok ? (uint16_t)halo_index(ht, tile, hcells, (int)p) : kNoLocal;
-  // squared bin edges; the last edge is the list cutoff (rc + skin)^2
-  double tR[kNumBins], tA[kNumBins];
-#pragma unroll
-  for (int k = 0; k < kNumBins - 1; ++k) {
-    const double er = rcR + (double)bin_frac(k) * skin, ea = rcA + (double)bin_frac(k) * skin;
-    tR[k] = er * er;
-    tA[k] = ea * ea;
-  }
-  const double cutR = rcR + skin, cutA = rcA + skin;
-  tR[kNumBins - 1] = cutR * cutR;
-  tA[kNumBins - 1] = cutA * cutA;
+  const double cut2 = be.e2[be.nbins - 1];
   const double xi = x[p], yi = x[N + p], zi = x[2 * N + p];
   int cx, cy, cz;
   cell_coords(g, cell_sorted[p], cx, cy, cz);
@@ -440,12 +436,10 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
     dlo[d] = fmax(pos3[d] - cc3[d] * h - 1e-6, 0.0);
     dhi[d] = fmax((cc3[d] + 1) * h - pos3[d] - 1e-6, 0.0);
   }
-  BinCounts cR, cA;
-  int nr = 0, na = 0;
-  __shared__ uint32_t stage_r[kBlock * kStageStride], stage_a[kBlock * kStageStride],
-      stage_l[kBlock * kStageStride];
-  uint32_t* sr = stage_r + threadIdx.x * kStageStride;
-  uint32_t* sa = stage_a + threadIdx.x * kStageStride;
+  BinCounts cb;
+  int n = 0;
+  __shared__ uint32_t stage_q[kBlock * kStageStride], stage_l[kBlock * kStageStride];
+  uint32_t* sq = stage_q + threadIdx.x * kStageStride;
   uint32_t* sl = stage_l + threadIdx.x * kStageStride;
   for (int a = 0; a < nof[2]; ++a) {
     const int rz = cz + lo[2] + a;
@@ -462,85 +456,81 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
         const int xc = (rx + g.nc[0]) % g.nc[0];
         const double sx = rx < 0 ? -g.box[0] : (rx >= g.nc[0] ? g.box[0] : 0.0);
         const double gx = nof[0] < 3 ? 0.0 : (e == 0 ? dlo[0] : (e == 2 ? dhi[0] : 0.0));
-        if (gx * gx + gy * gy + gz * gz >= tR[kNumBins - 1]) continue;
+        if (gx * gx + gy * gy + gz * gz >= cut2) continue;
         const int cc = cell_lin(g, xc, yc, zc);
         const int q0 = start[cc], q1 = start[cc + 1];
         if (q1 <= q0) continue;
         // halo-local index of sorted atom q is loc0 + q (cells are contiguous in the halo)
         const int loc0 = hok ? halo_index(ht, tile, hcells, q0) - q0 : 0;
-        scan_cell(x, N, q0, q1, p, xi, yi, zi, sx, sy, sz, g, tR[kNumBins - 1], [&](int q, double r2) {
-          const int br = bin_of(r2, tR);
-          cR.add(br);
-          if (nr < capR) {
-            sr[nr % kStage] = (uint32_t)q | ((uint32_t)br << 28);
-            if (nr % kStage == kStage - 1) stage_flush32(sr, sc.r, N, p, nr);
-          }
-          ++nr;
-          if (r2 < tA[kNumBins - 1]) {
-            const int ba = bin_of(r2, tA);
-            cA.add(ba);
-            if (na < capA) {
-              sa[na % kStage] = (uint32_t)q | ((uint32_t)ba << 28);
-              sl[na % kStage] = hok ? (uint32_t)(loc0 + q) : (uint32_t)kNoLocal;
-              if (na % kStage == kStage - 1) {
-                stage_flush32(sa, sc.a, N, p, na);
-                stage_flush16(sl, sc.l, N, p, na);
-              }
+        scan_cell(x, N, q0, q1, p, xi, yi, zi, sx, sy, sz, g, cut2, [&](int q, double r2) {
+          const int bin = bin_of(r2, be);
+          cb.add(bin);
+          if (n < capR) {
+            sq[n % kStage] = (uint32_t)q | ((uint32_t)bin << 28);
+            sl[n % kStage] = hok ? (uint32_t)(loc0 + q) : (uint32_t)kNoLocal;
+            if (n % kStage == kStage - 1) {
+              stage_flush32(sq, sc.q, N, p, n);
+              stage_flush16(sl, sc.l, N, p, n);
             }
-            ++na;
           }
+          ++n;
         });
       }
     }
   }
-  // partial last words
-  if (nr < capR && nr % kStage != 0) stage_flush32(sr, sc.r, N, p, nr);
-  if (na < capA && na % kStage != 0) {
-    stage_flush32(sa, sc.a, N, p, na);
-    stage_flush16(sl, sc.l, N, p, na);
+  if (n < capR && n % kStage != 0) {
+    stage_flush32(sq, sc.q, N, p, n);
+    stage_flush16(sl, sc.l, N, p, n);
   }
-  // cumulative breakpoints
-  int tr = 0, ta = 0;
+  // cumulative breakpoints; angular candidates are the bins up to idxA[kFracs - 1]
+  int t = 0, na = 0;
 #pragma unroll
-  for (int k = 0; k < kNumBins; ++k) {
-    tr += cR.get(k);
-    ta += cA.get(k);
-    lo_.bpR[(int64_t)k * N + p] = tr < capR ? tr : capR;
-    lo_.bpA[(int64_t)k * N + p] = ta < capA ? ta : capA;
+  for (int k = 0; k < kMaxBins; ++k) {
+    if (k < be.nbins) {
+      t += cb.get(k);
+      if (k == be.idxA[kFracs - 1]) na = t;
+      lo_.bp[(int64_t)k * N + p] = t < capR ? t : capR;
+    }
   }
-  lo_.cntR[p] = nr < capR ? nr : capR;
-  lo_.cntA[p] = na < capA ? na : capA;
-  if (nr > capR) atomicMax(&flags[FLAG_OVF_R], nr);
+  lo_.cnt[p] = n < capR ? n : capR;
+  if (n > capR) atomicMax(&flags[FLAG_OVF_R], n);
   if (na > capA) atomicMax(&flags[FLAG_OVF_A], na);
 }
 
 // One wavefront per 64 atoms: orders each atom's scratch entries by bin (stable
-// inside a bin) and writes the lists row by row, 64 consecutive atoms per store,
-// through an LDS tile of kPlaceRows rows; longer lists take further rounds. The
-// angular round keeps its entries in rows 0..63 of the tile and the 16-bit local
-// indices right after them.
-constexpr int kPlaceRows = 126;  // radial rows per round; angular rounds take 63 (+1 spare row each)
+// inside a bin) and writes the list and its halo-local indices row by row, 64
+// consecutive atoms per store, through LDS tiles of kPlaceRows rows; longer lists
+// take further rounds. Entries outside the current round go to a spare row.
+constexpr int kPlaceRows = 127;
 
-template <bool ANG>
-__device__ __forceinline__ void place_one(int64_t N, int64_t p, bool valid, int cap, int cnt,
-                                          const int32_t* __restrict__ bp, const uint4* __restrict__ col,
-                                          const uint4* __restrict__ lcol, int32_t* __restrict__ out,
-                                          uint16_t* __restrict__ lout, uint32_t* tile, uint16_t* ltile,
-                                          int rows_max) {
+__global__ void __launch_bounds__(64)
+k_place_lists(int64_t N, int nbins, ListOut lo_, ListScratch sc, const int32_t* __restrict__ flags) {
+  if (flags[FLAG_REBUILD] == 0) return;
+  __shared__ uint32_t tile[(kPlaceRows + 1) * 64];
+  __shared__ uint16_t ltile[(kPlaceRows + 1) * 64];
+  __shared__ int red[64];
   const int lane = threadIdx.x;
-  const int rows = ANG ? kPlaceRows / 2 : kPlaceRows;  // row `rows` of the tile is the spare row
+  const int64_t p = (int64_t)blockIdx.x * 64 + lane;
+  const bool valid = p < N;
+  const int cnt = valid ? lo_.cnt[p] : 0;
+  // longest list of the wavefront (uniform loop bounds for the row writes)
+  red[lane] = cnt;
+  __syncthreads();
+  for (int o = 32; o > 0; o >>= 1) {
+    if (lane < o) red[lane] = max(red[lane], red[lane + o]);
+    __syncthreads();
+  }
+  const int rows_max = red[0];
+  constexpr int rows = kPlaceRows;  // row `rows` of the tiles is the spare row
   for (int r0 = 0; r0 < rows_max; r0 += rows) {
     if (valid) {
       BinCounts off;
 #pragma unroll
-      for (int k = 1; k < kNumBins; ++k) {
-        const int b0 = bp[(int64_t)(k - 1) * N + p];
-        if (k < 4) off.lo |= (uint64_t)b0 << (16 * k);
-        else off.hi |= (uint64_t)b0 << (16 * (k - 4));
-      }
+      for (int k = 1; k < kMaxBins; ++k)
+        if (k < nbins) off.set(k, lo_.bp[(int64_t)(k - 1) * N + p]);
       for (int g = 0; g < cnt; g += kStage) {
         uint32_t v[kStage], h[kStage];
-        const uint4* src = col + ((int64_t)(g / kStage) * N + p) * (kStage / 4);
+        const uint4* src = sc.q + ((int64_t)(g / kStage) * N + p) * (kStage / 4);
 #pragma unroll
         for (int j = 0; j < kStage / 4; ++j) {
           const uint4 w = src[j];
@@ -549,27 +539,24 @@ __device__ __forceinline__ void place_one(int64_t N, int64_t p, bool valid, int 
           v[4 * j + 2] = w.z;
           v[4 * j + 3] = w.w;
         }
-        if constexpr (ANG) {
-          const uint4* ls = lcol + ((int64_t)(g / kStage) * N + p) * (kStage / 8);
+        const uint4* ls = sc.l + ((int64_t)(g / kStage) * N + p) * (kStage / 8);
 #pragma unroll
-          for (int j = 0; j < kStage / 8; ++j) {
-            const uint4 w = ls[j];
-            const uint32_t t[4] = {w.x, w.y, w.z, w.w};
+        for (int j = 0; j < kStage / 8; ++j) {
+          const uint4 w = ls[j];
+          const uint32_t t[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              h[8 * j + 2 * u] = t[u] & 0xffffu;
-              h[8 * j + 2 * u + 1] = t[u] >> 16;
-            }
+          for (int u = 0; u < 4; ++u) {
+            h[8 * j + 2 * u] = t[u] & 0xffffu;
+            h[8 * j + 2 * u + 1] = t[u] >> 16;
           }
         }
 #pragma unroll
         for (int u = 0; u < kStage; ++u) {
           const bool live = g + u < cnt;
           const int pos = (live ? off.take((int)(v[u] >> 28)) : -1) - r0;
-          // entries outside this round go to the spare row `rows`
           const int slot = (live && pos >= 0 && pos < rows ? pos : rows) * 64 + lane;
           tile[slot] = v[u] & 0x0fffffffu;
-          if constexpr (ANG) ltile[slot] = (uint16_t)h[u];
+          ltile[slot] = (uint16_t)h[u];
         }
       }
     }
@@ -577,51 +564,20 @@ __device__ __forceinline__ void place_one(int64_t N, int64_t p, bool valid, int 
     const int nrow = rows_max - r0 < rows ? rows_max - r0 : rows;
     for (int r = 0; r < nrow; ++r) {
       if (valid && r0 + r < cnt) {
-        out[(int64_t)(r0 + r) * N + p] = (int32_t)tile[r * 64 + lane];
-        if constexpr (ANG) lout[(int64_t)(r0 + r) * N + p] = ltile[r * 64 + lane];
+        lo_.nbr[(int64_t)(r0 + r) * N + p] = (int32_t)tile[r * 64 + lane];
+        lo_.nbrl[(int64_t)(r0 + r) * N + p] = ltile[r * 64 + lane];
       }
     }
     __syncthreads();
   }
 }
 
-__global__ void __launch_bounds__(64)
-k_place_lists(int64_t N, ListOut lo_, ListScratch sc, const int32_t* __restrict__ flags) {
-  if (flags[FLAG_REBUILD] == 0) return;
-  __shared__ uint32_t tile[(kPlaceRows + 2) * 64];
-  __shared__ int red[64];
-  const int64_t p = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  const bool valid = p < N;
-  const int nr = valid ? lo_.cntR[p] : 0;
-  const int na = valid ? lo_.cntA[p] : 0;
-  // longest list of the wavefront (uniform loop bounds for the row writes)
-  red[threadIdx.x] = nr;
-  __syncthreads();
-  for (int o = 32; o > 0; o >>= 1) {
-    if (threadIdx.x < (unsigned)o) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + o]);
-    __syncthreads();
-  }
-  const int rmax = red[0];
-  __syncthreads();
-  red[threadIdx.x] = na;
-  __syncthreads();
-  for (int o = 32; o > 0; o >>= 1) {
-    if (threadIdx.x < (unsigned)o) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + o]);
-    __syncthreads();
-  }
-  const int amax = red[0];
-  __syncthreads();
-  place_one<false>(N, p, valid, 0, nr, lo_.bpR, sc.r, nullptr, lo_.nbrR, nullptr, tile, nullptr, rmax);
-  // angular: 64-row rounds, entries in the first half of the tile, local indices in the second
-  place_one<true>(N, p, valid, 0, na, lo_.bpA, sc.a, sc.l, lo_.nbrA, lo_.nbrAl, tile,
-                  reinterpret_cast<uint16_t*>(tile + (kPlaceRows / 2 + 1) * 64), amax);
-}
-
 // After a build the positions equal the build positions: displacement 0, bin 0.
-__global__ void k_count_build(int32_t* flags) {
+__global__ void k_count_build(int32_t* flags, int bin_r0, int bin_a0) {
   if (flags[FLAG_REBUILD] != 0 && threadIdx.x == 0) {
     flags[FLAG_NBUILD] += 1;
-    flags[FLAG_BIN] = 0;
+    flags[FLAG_BIN_R] = bin_r0;
+    flags[FLAG_BIN_A] = bin_a0;
   }
 }
 
@@ -633,7 +589,7 @@ __global__ void k_export(int64_t N, const int32_t* __restrict__ perm, const int3
   if (p >= N) return;
   const int64_t o = perm[p];
   if (o < o_lo || o >= o_hi) return;
-  const int n = cnt[p];
+  const int n = cnt[p] < cap ? cnt[p] : cap;
   int32_t* row = rows + (o - o_lo) * cap;
   for (int k = 0; k < n; ++k) {
     const int32_t val = perm[nbr[(int64_t)k * N + p]];
@@ -667,14 +623,13 @@ hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st) {
 
 // Every kernel below returns at once when flags[FLAG_REBUILD] == 0, so the whole
 // rebuild can be enqueued each step and skipped on the device without a host sync.
-hipError_t launch_rebuild(int64_t N, const CellGrid& g, double rcR, double rcA, double skin, int capR,
-                          int capA, double* x, double* v, int32_t* type, int32_t* perm, double* x_alt,
+hipError_t launch_rebuild(int64_t N, const CellGrid& g, const BinEdges& be, int capR, int capA,
+                          double* x, double* v, int32_t* type, int32_t* perm, double* x_alt,
                           double* v_alt, int32_t* type_alt, int32_t* perm_alt, double* x_build,
                           int32_t* cellid, int32_t* cell_sorted, int32_t* src, int32_t* key,
                           int32_t* cell_count, int32_t* cell_start, int32_t* cell_fill,
-                          int32_t* scan_tmp, int32_t* nbrR, int32_t* cntR, int32_t* nbrA,
-                          int32_t* cntA, int32_t* bpR, int32_t* bpA, HaloTables ht, uint16_t* nbrAl,
-                          uint16_t* selfl, ListScratch sc, int32_t* flags, hipStream_t st) {
+                          int32_t* scan_tmp, const ListOut& lout, HaloTables ht, ListScratch sc,
+                          int32_t* flags, hipStream_t st) {
   const int nb = grid_blocks(N);
   const int ncell = g.ncell;
   hipError_t e;
@@ -697,11 +652,10 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, double rcR, double rcA, 
   hipLaunchKernelGGL(k_copy_back, dim3(nb), dim3(kBlock), 0, st, N, x_alt, v_alt, type_alt, perm_alt,
                      x, v, type, perm, flags);
   hipLaunchKernelGGL(k_halo_tables, dim3(nb), dim3(kBlock), 0, st, N, g, cell_sorted, cell_start, ht, flags);
-  const ListOut lout{nbrR, cntR, nbrA, cntA, bpR, bpA, nbrAl, selfl};
-  hipLaunchKernelGGL(k_build_lists, dim3(nb), dim3(kBlock), 0, st, N, g, x, cell_start, cell_sorted,
-                     rcR, rcA, skin, capR, capA, lout, ht, sc, flags);
-  hipLaunchKernelGGL(k_place_lists, dim3(grid_blocks(N, 64)), dim3(64), 0, st, N, lout, sc, flags);
-  hipLaunchKernelGGL(k_count_build, dim3(1), dim3(64), 0, st, flags);
+  hipLaunchKernelGGL(k_build_lists, dim3(nb), dim3(kBlock), 0, st, N, g, x, cell_start, cell_sorted, be,
+                     capR, capA, lout, ht, sc, flags);
+  hipLaunchKernelGGL(k_place_lists, dim3(grid_blocks(N, 64)), dim3(64), 0, st, N, be.nbins, lout, sc, flags);
+  hipLaunchKernelGGL(k_count_build, dim3(1), dim3(64), 0, st, flags, be.idxR[0], be.idxA[0]);
   return hipGetLastError();
 }
 

@@ -57,9 +57,9 @@ k_train_backward(ModelDev m, EvalBuffers b, const float* __restrict__ gF, double
     if (gF) {
       const float wi0 = gF[i], wi1 = gF[N + i], wi2 = gF[2 * N + i];
       // radial JVP: dq_n/dr_ij . w = g_n'(r) (u . w)
-      const int kR = list_bound(b.bpR, b.flags, N, i);
+      const int kR = radial_bound(b, i);
       for (int p = 0; p < kR; ++p) {
-        const int32_t j = b.nbrR[(int64_t)p * N + i];
+        const int32_t j = b.nbr[(int64_t)p * N + i];
         float dx, dy, dz;
         if (!pair_inside(x, N, j, xi, yi, zi, Lx, Ly, Lz, rcR2, dx, dy, dz)) continue;
         const float r = sqrtf(dx * dx + dy * dy + dz * dz);
@@ -82,9 +82,9 @@ k_train_backward(ModelDev m, EvalBuffers b, const float* __restrict__ gF, double
       for (int n = 0; n < NA; ++n)
 #pragma unroll
         for (int lm = 0; lm < NC; ++lm) s[n * NC + lm] *= 2.f * kW[lm];
-      const int kA = list_bound(b.bpA, b.flags, N, i);
+      const int kA = angular_bound(b, i);
       for (int p = 0; p < kA; ++p) {
-        const int32_t j = b.nbrA[(int64_t)p * N + i];
+        const int32_t j = b.nbr[(int64_t)p * N + i];
         float dx, dy, dz;
         if (!pair_inside(x, N, j, xi, yi, zi, Lx, Ly, Lz, rcA2, dx, dy, dz)) continue;
         const float r = sqrtf(dx * dx + dy * dy + dz * dz);
