@@ -93,6 +93,21 @@ struct HaloTables {
   int32_t* off;    // [ntiles][kHaloCellsMax + 1] local offset of each halo cell
 };
 
+// Per-atom neighbour record: 64 bytes ([N][4] 16-byte words) holding what a
+// neighbour's pair terms read, so a gather touches one half cache line.
+// word 0 = (x, y) FP64; word 1 = (z FP64, w0, w1); word 2 = (w2 .. w5);
+// word 3 = (w6, w7, w8, 0). The w are written by the descriptor kernel: for one
+// species w_k = sum_n (dU/dq_n) c_nk (k < 9), with several species w_n = dU/dq_n.
+__device__ __forceinline__ void rec_put_pos(uint4* rec, int64_t i, double x, double y, double z) {
+  const uint64_t bx = __builtin_bit_cast(uint64_t, x), by = __builtin_bit_cast(uint64_t, y),
+                 bz = __builtin_bit_cast(uint64_t, z);
+  rec[4 * i] = make_uint4((uint32_t)bx, (uint32_t)(bx >> 32), (uint32_t)by, (uint32_t)(by >> 32));
+  reinterpret_cast<uint2*>(rec + 4 * i + 1)[0] = make_uint2((uint32_t)bz, (uint32_t)(bz >> 32));
+}
+__device__ __forceinline__ double rec_f64(uint32_t lo, uint32_t hi) {
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // Outputs of the list build.
 struct ListOut {
   int32_t* nbr;     // [capR][N] neighbour list with skin, ordered by distance bin
@@ -163,8 +178,8 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, const BinEdges& be, int 
                           double* v_alt, int32_t* type_alt, int32_t* perm_alt, double* x_build,
                           int32_t* cellid, int32_t* cell_sorted, int32_t* src, int32_t* key,
                           int32_t* cell_count, int32_t* cell_start, int32_t* cell_fill,
-                          int32_t* scan_tmp, const ListOut& lists, HaloTables ht, ListScratch sc,
-                          int32_t* flags, hipStream_t st);
+                          int32_t* scan_tmp, uint4* rec, const ListOut& lists, HaloTables ht,
+                          ListScratch sc, int32_t* flags, hipStream_t st);
 // Rows of original ids [o_lo, o_hi), ascending, into rows[(o - o_lo) * cap + k].
 hipError_t launch_export(int64_t N, const int32_t* perm, const int32_t* nbr, const int32_t* cnt,
                          int cap, int64_t o_lo, int64_t o_hi, int32_t* rows, int32_t* row_cnt,
@@ -186,7 +201,7 @@ struct EvalBuffers {
   const int32_t* hstart;
   const int32_t* hoff;
   float* U;              // [N]
-  float* FpR;            // [N][8] dU/dq for the radial block (nR <= 8 used, 32 B per atom)
+  uint4* rec;            // [N][4] neighbour records (positions read, w written)
   float* G;              // [nA * ncomp][N] dU/ds for the angular accumulators
   float* F;              // [3][N] forces (FP32 accumulation)
   double* partial;       // [nblocks][kPartialStride]
@@ -209,7 +224,7 @@ hipError_t launch_reduce_partials(const double* partial, int nblocks, int first,
 hipError_t launch_max_partials(const double* partial, int nblocks, int slot, double* out,
                                hipStream_t st);
 hipError_t launch_kick_drift(int64_t N, double dt, CellGrid g, const float* F, const int32_t* type,
-                             MassTable mt, double* x, double* v, const double* x_build,
+                             MassTable mt, double* x, double* v, uint4* rec, const double* x_build,
                              double half_skin2, int32_t* flags, double* partial, hipStream_t st);
 // FLAG_BIN_R / FLAG_BIN_A from the per-workgroup displacement maxima the drift
 // kernel left in partial.
@@ -227,7 +242,7 @@ hipError_t launch_set_flag(int32_t* flags, int idx, int value, hipStream_t st);
 hipError_t launch_sum_i32(int64_t N, const int32_t* a, double* partial, int slot, hipStream_t st);
 hipError_t launch_state_in(int64_t N, const double* x_aos, const double* v_aos,
                            const int32_t* type_in, int n_types, CellGrid g, double* x, double* v,
-                           int32_t* type, int32_t* perm, int32_t* flags, hipStream_t st);
+                           int32_t* type, int32_t* perm, uint4* rec, int32_t* flags, hipStream_t st);
 hipError_t launch_state_out(int64_t N, const int32_t* perm, const double* soa, double* aos,
                             hipStream_t st);
 hipError_t launch_forces_out(int64_t N, const int32_t* perm, const float* F, double* aos,

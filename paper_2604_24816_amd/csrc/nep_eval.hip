@@ -182,7 +182,6 @@ __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers 
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t i = (int64_t)tile * kBlock + threadIdx.x;
   const bool valid = i < N;
-  const double* __restrict__ x = b.x;
   const double Lx = b.box[0], Ly = b.box[1], Lz = b.box[2];
 
   float q[D];
@@ -194,7 +193,8 @@ __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers 
   const int ti = valid ? (MULTI ? b.type[i] : 0) : 0;
 
   if (valid) {
-    const double xi = x[i], yi = x[N + i], zi = x[2 * N + i];
+    const uint4 w0 = b.rec[4 * i], w1 = b.rec[4 * i + 1];
+    const double xi = rec_f64(w0.x, w0.y), yi = rec_f64(w0.z, w0.w), zi = rec_f64(w1.x, w1.y);
     int nr = 0, na = 0;
     desc_accumulate<S, MULTI>(m, b, i, ti, xi, yi, zi, Lx, Ly, Lz, q, s, nr, na);
     b.nactR[i] = nr;
@@ -212,12 +212,28 @@ __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers 
   if (valid) {
     b.U[i] = U;
     {
-      float t[8];
+      // neighbour record words 1.zw, 2, 3: w_k = sum_n (dU/dq_n) c_nk for one species
+      // (the radial force of a pair then needs only the basis derivatives), dU/dq_n otherwise
+      float t[12];
+      if constexpr (MULTI) {
 #pragma unroll
-      for (int n = 0; n < 8; ++n) t[n] = n < NR ? fp[n] : 0.f;
-      float4* fr = reinterpret_cast<float4*>(b.FpR + 8 * i);
-      fr[0] = make_float4(t[0], t[1], t[2], t[3]);
-      fr[1] = make_float4(t[4], t[5], t[6], t[7]);
+        for (int k = 0; k < 12; ++k) t[k] = k < NR ? fp[k] : 0.f;
+      } else {
+        const cfloat_ptr c = uniform_coeffs(m.cR);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+          float a = 0.f;
+          if (k < S::KR) {
+#pragma unroll
+            for (int n = 0; n < NR; ++n) a = fmaf(fp[n], c[n * S::KR + k], a);
+          }
+          t[k] = a;
+        }
+      }
+      uint4* r = b.rec + 4 * i;
+      reinterpret_cast<float2*>(r + 1)[1] = make_float2(t[0], t[1]);
+      reinterpret_cast<float4*>(r + 2)[0] = make_float4(t[2], t[3], t[4], t[5]);
+      reinterpret_cast<float4*>(r + 3)[0] = make_float4(t[6], t[7], t[8], t[9]);
     }
     // 4. dU/ds_nlm = dU/dq_nl * 2 W_lm s_nlm (+ four-body part for l = 2)
     float Gd[NA * NC];
@@ -312,7 +328,6 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
   const int64_t i = (int64_t)tile * kBlock + threadIdx.x;
   const bool valid = i < N;
   const bool lds = load_halo(b, tile, halo);
-  const double* __restrict__ x = b.x;
   const double Lx = b.box[0], Ly = b.box[1], Lz = b.box[2];
   const float rcR_inv = 1.f / m.rcR, rcA_inv = 1.f / m.rcA;
   float fx = 0.f, fy = 0.f, fz = 0.f;
@@ -320,15 +335,15 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
 #pragma unroll
   for (int k = 0; k < 9; ++k) w[k] = 0.f;
   if (valid) {
-    const double xi = x[i], yi = x[N + i], zi = x[2 * N + i];
+    const uint4* ri = b.rec + 4 * i;
+    const uint4 r0 = ri[0], r1 = ri[1], r2w = ri[2], r3 = ri[3];
+    const double xi = rec_f64(r0.x, r0.y), yi = rec_f64(r0.z, r0.w), zi = rec_f64(r1.x, r1.y);
     const int ti = MULTI ? b.type[i] : 0;
-    float fpi[8];
-    {
-      const float4* fr = reinterpret_cast<const float4*>(b.FpR + 8 * i);
-      const float4 a = fr[0], c = fr[1];
-      fpi[0] = a.x; fpi[1] = a.y; fpi[2] = a.z; fpi[3] = a.w;
-      fpi[4] = c.x; fpi[5] = c.y; fpi[6] = c.z; fpi[7] = c.w;
-    }
+    // own radial coefficients (w_k for one species, dU/dq_n for several)
+    const float wi[10] = {__uint_as_float(r1.z), __uint_as_float(r1.w), __uint_as_float(r2w.x),
+                          __uint_as_float(r2w.y), __uint_as_float(r2w.z), __uint_as_float(r2w.w),
+                          __uint_as_float(r3.x), __uint_as_float(r3.y), __uint_as_float(r3.z),
+                          __uint_as_float(r3.w)};
     const float* cR = m.cR;
     const float* cA = m.cA;
     float G[NA * NC];
@@ -336,19 +351,22 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
     for (int k = 0; k < NA * NC; ++k) G[k] = b.G[(int64_t)k * N + i];
     const double rcR2 = m.rcR64 * m.rcR64, rcA2 = m.rcA64 * m.rcA64;
     const int kR = radial_bound(b, i), kA = angular_bound(b, i);
-    // One pass over the list. Radial pairs: gather, F_i += (Fp_i . g'^{ij} + Fp_j . g'^{ji}) u.
+    // One pass over the list. Radial pairs: gather, F_i += (dU_i/dr_ij + dU_j/dr_ji) along u,
+    // with the neighbour's radial coefficients read from its record.
     // Angular and four-body pairs (the angular prefix inside rc_angular): scatter
     // dU_i/dr_ij into this atom and -dU_i/dr_ij into the neighbour.
-    for_each_entry(b.nbr, x, N, i, kR, [&](int p, int32_t j, double xj, double yj, double zj) {
+    for_each_rec<4>(b.nbr, b.rec, N, i, kR, [&](int p, int32_t j, const uint4* rw) {
       double ex, ey, ez;
-      const double r2 = pair_r2_64(xj, yj, zj, xi, yi, zi, Lx, Ly, Lz, ex, ey, ez);
+      const double r2 = pair_r2_64(rec_f64(rw[0].x, rw[0].y), rec_f64(rw[0].z, rw[0].w),
+                                   rec_f64(rw[1].x, rw[1].y), xi, yi, zi, Lx, Ly, Lz, ex, ey, ez);
       if (!(r2 < rcR2)) return;
       const float dx = (float)ex, dy = (float)ey, dz = (float)ez;
       const bool ang = p < kA && r2 < rcA2;
       const int lj = (ang && lds) ? (int)b.nbrl[(int64_t)p * N + i] : 0;
-      const float4* fr = reinterpret_cast<const float4*>(b.FpR + 8 * (int64_t)j);
-      const float4 fa = fr[0], fb = fr[1];
-      const float fpj[8] = {fa.x, fa.y, fa.z, fa.w, fb.x, fb.y, fb.z, fb.w};
+      const float wj[10] = {__uint_as_float(rw[1].z), __uint_as_float(rw[1].w), __uint_as_float(rw[2].x),
+                            __uint_as_float(rw[2].y), __uint_as_float(rw[2].z), __uint_as_float(rw[2].w),
+                            __uint_as_float(rw[3].x), __uint_as_float(rw[3].y), __uint_as_float(rw[3].z),
+                            __uint_as_float(rw[3].w)};
       float r, rinv;
       pair_r(dx, dy, dz, r, rinv);
       const int tj = MULTI ? b.type[j] : 0;
@@ -360,21 +378,17 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
         radial_g_dg<NR, S::KR>(r, rcR_inv, cR + (tj * m.T + ti) * NR * S::KR, g2, dg2);
 #pragma unroll
         for (int n = 0; n < NR; ++n) {
-          si = fmaf(fpi[n], dg[n], si);
-          sj = fmaf(fpj[n], dg2[n], sj);
+          si = fmaf(wi[n], dg[n], si);
+          sj = fmaf(wj[n], dg2[n], sj);
         }
       } else {
-        // one species: g'_n = sum_k c_nk e_k from the basis derivatives alone
+        // one species: dU/dr along u = sum_k w_k e_k with the basis derivatives e_k
         float e[S::KR];
         radial_basis_deriv<S::KR>(r, rcR_inv, e);
-        const cfloat_ptr c = uniform_coeffs(cR);
 #pragma unroll
-        for (int n = 0; n < NR; ++n) {
-          float d = 0.f;
-#pragma unroll
-          for (int k = 0; k < S::KR; ++k) d = fmaf(c[n * S::KR + k], e[k], d);
-          si = fmaf(fpi[n], d, si);
-          sj = fmaf(fpj[n], d, sj);
+        for (int k = 0; k < S::KR; ++k) {
+          si = fmaf(wi[k], e[k], si);
+          sj = fmaf(wj[k], e[k], sj);
         }
       }
       const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;

@@ -180,7 +180,7 @@ struct Shape {
   static constexpr int NC = L3 * (L3 + 2);
   static constexpr int D = NR + NA * L3 + (FB ? NA : 0);
   static_assert(D <= 32 && H <= 32, "network tiles hold at most 32 descriptors and 32 hidden units");
-  static_assert(NR <= 8, "dU/dq of the radial block is stored in 8 floats per atom");
+  static_assert(NR <= 10 && KR <= 10, "the neighbour record holds 10 radial coefficients");
   static_assert(!FB || L3 >= 2, "the four-body term uses the l = 2 accumulators");
 };
 
@@ -212,26 +212,30 @@ __device__ __forceinline__ bool inside(double xj, double yj, double zj, double x
   return true;
 }
 
-// Visits entries [0, k) of atom i's slot-major list, calling body(p, j, xj, yj, zj).
-// The index of entry p + 2 and the position of entry p + 1 are loaded before the
-// body of entry p runs, so their latency overlaps the pair arithmetic (the last
-// loads repeat entry k - 1: every address stays inside the list and the box).
-template <class Body>
-__device__ __forceinline__ void for_each_entry(const int32_t* __restrict__ nbr, const double* __restrict__ x,
-                                               int64_t N, int64_t i, int k, Body&& body) {
+// Visits entries [0, k) of atom i's slot-major list, calling body(p, j, w) with the
+// first W 16-byte words of neighbour j's record. The index of entry p + 2 and the
+// record words of entry p + 1 are loaded before the body of entry p runs, so their
+// latency overlaps the pair arithmetic (the last loads repeat entry k - 1: every
+// address stays inside the list and the records).
+template <int W, class Body>
+__device__ __forceinline__ void for_each_rec(const int32_t* __restrict__ nbr, const uint4* __restrict__ rec,
+                                             int64_t N, int64_t i, int k, Body&& body) {
   if (k <= 0) return;
   int32_t j = nbr[i];
   int32_t jn = nbr[(int64_t)(k > 1 ? 1 : 0) * N + i];
-  double xj = x[j], yj = x[N + j], zj = x[2 * N + j];
+  uint4 cur[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) cur[w] = rec[4 * (int64_t)j + w];
   for (int p = 0; p < k; ++p) {
     const int32_t jnn = nbr[(int64_t)(p + 2 < k ? p + 2 : k - 1) * N + i];
-    const double xn = x[jn], yn = x[N + jn], zn = x[2 * N + jn];
-    body(p, j, xj, yj, zj);
+    uint4 nxt[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) nxt[w] = rec[4 * (int64_t)jn + w];
+    body(p, j, cur);
     j = jn;
     jn = jnn;
-    xj = xn;
-    yj = yn;
-    zj = zn;
+#pragma unroll
+    for (int w = 0; w < W; ++w) cur[w] = nxt[w];
   }
 }
 
@@ -279,7 +283,6 @@ __device__ __forceinline__ void desc_accumulate(const ModelDev& m, const EvalBuf
                                                 double Lz, float* q, float* s, int& nr, int& na) {
   constexpr int NR = S::NR, NA = S::NA, NC = S::NC;
   const int64_t N = b.N;
-  const double* __restrict__ x = b.x;
   const float rcR_inv = 1.f / m.rcR, rcA_inv = 1.f / m.rcA;
   const double rcR2 = m.rcR64 * m.rcR64, rcA2 = m.rcA64 * m.rcA64;
   nr = 0;
@@ -292,9 +295,10 @@ __device__ __forceinline__ void desc_accumulate(const ModelDev& m, const EvalBuf
   for (int k = 0; k < S::KR; ++k) Qb[k] = 0.f;
   // one pass over the list: radial terms for every pair inside rc_radial, angular
   // terms for the pairs of the angular prefix inside rc_angular
-  for_each_entry(b.nbr, x, N, i, kR, [&](int p, int32_t j, double xj, double yj, double zj) {
+  for_each_rec<2>(b.nbr, b.rec, N, i, kR, [&](int p, int32_t j, const uint4* w) {
     double ex, ey, ez;
-    const double r2 = pair_r2_64(xj, yj, zj, xi, yi, zi, Lx, Ly, Lz, ex, ey, ez);
+    const double r2 = pair_r2_64(rec_f64(w[0].x, w[0].y), rec_f64(w[0].z, w[0].w), rec_f64(w[1].x, w[1].y),
+                                 xi, yi, zi, Lx, Ly, Lz, ex, ey, ez);
     if (!(r2 < rcR2)) return;
     const float dx = (float)ex, dy = (float)ey, dz = (float)ez;
     ++nr;

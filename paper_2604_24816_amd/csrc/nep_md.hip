@@ -34,21 +34,25 @@ __device__ __forceinline__ double wrap_coord(double xv, double L) {
 // v += dt/2 F/(m xi); x += dt v; wrap; flag a rebuild when |x - x_build| > skin/2.
 __global__ void k_kick_drift(int64_t N, double dt, CellGrid g, const float* __restrict__ F,
                              const int32_t* __restrict__ type, MassTable mt, double* __restrict__ x,
-                             double* __restrict__ v, const double* __restrict__ xb, double half_skin2,
+                             double* __restrict__ v, uint4* __restrict__ rec, const double* __restrict__ xb,
+                             double half_skin2,
                              int32_t* __restrict__ flags, double* __restrict__ partial) {
   __shared__ double sh[kBlock];
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double d2 = 0.0;
   if (p < N) {
   const double inv = mt.inv_mxi[type[p]];
+  double xn[3];
   for (int c = 0; c < 3; ++c) {
     double vv = v[c * N + p] + 0.5 * dt * (double)F[c * N + p] * inv;
     double xx = wrap_coord(x[c * N + p] + dt * vv, g.box[c]);
     v[c * N + p] = vv;
     x[c * N + p] = xx;
+    xn[c] = xx;
     const double d = min_image(xx - xb[c * N + p], g.box[c]);
     d2 += d * d;
   }
+  rec_put_pos(rec, p, xn[0], xn[1], xn[2]);
   if (!(d2 <= half_skin2)) flags[FLAG_REBUILD] = 1;  // also catches NaN
   if (!(d2 == d2)) d2 = 1e300;
   }
@@ -184,9 +188,10 @@ __global__ void k_set_flag(int32_t* flags, int idx, int value) {
 __global__ void k_state_in(int64_t N, const double* __restrict__ xa, const double* __restrict__ va,
                            const int32_t* __restrict__ tin, int n_types, CellGrid g, double* __restrict__ x,
                            double* __restrict__ v, int32_t* __restrict__ type, int32_t* __restrict__ perm,
-                           int32_t* __restrict__ flags) {
+                           uint4* __restrict__ rec, int32_t* __restrict__ flags) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= N) return;
+  double xn[3];
   for (int c = 0; c < 3; ++c) {
     double xv = xa[3 * p + c];
     if (!isfinite(xv)) flags[FLAG_NONFINITE] = 1;
@@ -195,10 +200,12 @@ __global__ void k_state_in(int64_t N, const double* __restrict__ xa, const doubl
       if (xv >= g.box[c]) xv -= g.box[c];
     }
     x[c * N + p] = xv;
+    xn[c] = xv;
     const double vv = va ? va[3 * p + c] : 0.0;
     if (!isfinite(vv)) flags[FLAG_NONFINITE] = 1;
     v[c * N + p] = vv;
   }
+  rec_put_pos(rec, p, xn[0], xn[1], xn[2]);
   const int t = tin[p];
   if (t < 0 || t >= n_types) flags[FLAG_TYPE] = 1;
   type[p] = (t < 0 || t >= n_types) ? 0 : t;
@@ -258,10 +265,10 @@ hipError_t launch_max_partials(const double* partial, int nblocks, int slot, dou
 }
 
 hipError_t launch_kick_drift(int64_t N, double dt, CellGrid g, const float* F, const int32_t* type,
-                             MassTable mt, double* x, double* v, const double* x_build, double half_skin2,
-                             int32_t* flags, double* partial, hipStream_t st) {
+                             MassTable mt, double* x, double* v, uint4* rec, const double* x_build,
+                             double half_skin2, int32_t* flags, double* partial, hipStream_t st) {
   hipLaunchKernelGGL(k_kick_drift, dim3(grid_blocks(N)), dim3(kBlock), 0, st, N, dt, g, F, type, mt, x, v,
-                     x_build, half_skin2, flags, partial);
+                     rec, x_build, half_skin2, flags, partial);
   return hipGetLastError();
 }
 
@@ -307,9 +314,9 @@ hipError_t launch_set_flag(int32_t* flags, int idx, int value, hipStream_t st) {
 
 hipError_t launch_state_in(int64_t N, const double* x_aos, const double* v_aos, const int32_t* type_in,
                            int n_types, CellGrid g, double* x, double* v, int32_t* type, int32_t* perm,
-                           int32_t* flags, hipStream_t st) {
+                           uint4* rec, int32_t* flags, hipStream_t st) {
   hipLaunchKernelGGL(k_state_in, dim3(grid_blocks(N)), dim3(kBlock), 0, st, N, x_aos, v_aos, type_in,
-                     n_types, g, x, v, type, perm, flags);
+                     n_types, g, x, v, type, perm, rec, flags);
   return hipGetLastError();
 }
 

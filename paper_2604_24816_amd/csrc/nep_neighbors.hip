@@ -168,14 +168,18 @@ __global__ void k_permute(int64_t N, const int32_t* __restrict__ src, const int3
 __global__ void k_copy_back(int64_t N, const double* __restrict__ x2, const double* __restrict__ v2,
                             const int32_t* __restrict__ type2, const int32_t* __restrict__ perm2,
                             double* __restrict__ x, double* __restrict__ v, int32_t* __restrict__ type,
-                            int32_t* __restrict__ perm, const int32_t* __restrict__ flags) {
+                            int32_t* __restrict__ perm, uint4* __restrict__ rec,
+                            const int32_t* __restrict__ flags) {
   if (flags[FLAG_REBUILD] == 0) return;
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= N) return;
+  double xn[3];
   for (int c = 0; c < 3; ++c) {
-    x[c * N + p] = x2[c * N + p];
+    xn[c] = x2[c * N + p];
+    x[c * N + p] = xn[c];
     v[c * N + p] = v2[c * N + p];
   }
+  rec_put_pos(rec, p, xn[0], xn[1], xn[2]);
   type[p] = type2[p];
   perm[p] = perm2[p];
 }
@@ -328,7 +332,7 @@ __device__ __forceinline__ int bin_of(double r2, const BinEdges& be) {
 // the dimension holds at least three cells), or by the minimum-image rule itself
 // in dimensions with fewer cells; r^2 = (dx*dx + dy*dy) + dz*dz without FMA.
 template <class Visit>
-__device__ __forceinline__ void scan_cell(const double* __restrict__ x, int64_t N, int q0, int q1, int64_t p,
+__device__ __forceinline__ void scan_cell(const uint4* __restrict__ rec, int64_t N, int q0, int q1, int64_t p,
                                           double xi, double yi, double zi, double sx, double sy, double sz,
                                           const CellGrid& g, double cut2, Visit&& visit) {
 #pragma clang fp contract(off)
@@ -337,10 +341,11 @@ __device__ __forceinline__ void scan_cell(const double* __restrict__ x, int64_t 
     double px[4], py[4], pz[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int qq = q + u < q1 ? q + u : q1 - 1;
-      px[u] = x[qq];
-      py[u] = x[N + qq];
-      pz[u] = x[2 * N + qq];
+      const int64_t qq = q + u < q1 ? q + u : q1 - 1;
+      const uint4 w0 = rec[4 * qq], w1 = rec[4 * qq + 1];
+      px[u] = rec_f64(w0.x, w0.y);
+      py[u] = rec_f64(w0.z, w0.w);
+      pz[u] = rec_f64(w1.x, w1.y);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -411,7 +416,7 @@ __device__ __forceinline__ void stage_flush16(const uint32_t* st, uint4* col, in
 // breakpoints. Stencil cells whose nearest point lies beyond the list cutoff (with a
 // 1e-6 A margin) are skipped. k_place_lists then orders the entries by bin.
 __global__ void __launch_bounds__(kBlock)
-k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t* __restrict__ start,
+k_build_lists(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_t* __restrict__ start,
               const int32_t* __restrict__ cell_sorted, BinEdges be, int capR, int capA, ListOut lo_,
               HaloTables ht, ListScratch sc, int32_t* __restrict__ flags) {
   if (flags[FLAG_REBUILD] == 0) return;
@@ -422,7 +427,8 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
   const int hcells = ht.info[4 * tile + 0];
   lo_.selfl[p] = hok ? (uint16_t)halo_index(ht, tile, hcells, (int)p) : kNoLocal;
   const double cut2 = be.e2[be.nbins - 1];
-  const double xi = x[p], yi = x[N + p], zi = x[2 * N + p];
+  const uint4 r0w = rec[4 * p], r1w = rec[4 * p + 1];
+  const double xi = rec_f64(r0w.x, r0w.y), yi = rec_f64(r0w.z, r0w.w), zi = rec_f64(r1w.x, r1w.y);
   int cx, cy, cz;
   cell_coords(g, cell_sorted[p], cx, cy, cz);
   const int cc3[3] = {cx, cy, cz};
@@ -462,7 +468,7 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
         if (q1 <= q0) continue;
         // halo-local index of sorted atom q is loc0 + q (cells are contiguous in the halo)
         const int loc0 = hok ? halo_index(ht, tile, hcells, q0) - q0 : 0;
-        scan_cell(x, N, q0, q1, p, xi, yi, zi, sx, sy, sz, g, cut2, [&](int q, double r2) {
+        scan_cell(rec, N, q0, q1, p, xi, yi, zi, sx, sy, sz, g, cut2, [&](int q, double r2) {
           const int bin = bin_of(r2, be);
           cb.add(bin);
           if (n < capR) {
@@ -628,8 +634,8 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, const BinEdges& be, int 
                           double* v_alt, int32_t* type_alt, int32_t* perm_alt, double* x_build,
                           int32_t* cellid, int32_t* cell_sorted, int32_t* src, int32_t* key,
                           int32_t* cell_count, int32_t* cell_start, int32_t* cell_fill,
-                          int32_t* scan_tmp, const ListOut& lout, HaloTables ht, ListScratch sc,
-                          int32_t* flags, hipStream_t st) {
+                          int32_t* scan_tmp, uint4* rec, const ListOut& lout, HaloTables ht,
+                          ListScratch sc, int32_t* flags, hipStream_t st) {
   const int nb = grid_blocks(N);
   const int ncell = g.ncell;
   hipError_t e;
@@ -650,9 +656,9 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, const BinEdges& be, int 
   hipLaunchKernelGGL(k_permute, dim3(nb), dim3(kBlock), 0, st, N, src, cellid, x, v, type, perm,
                      x_alt, v_alt, type_alt, perm_alt, x_build, cell_sorted, flags);
   hipLaunchKernelGGL(k_copy_back, dim3(nb), dim3(kBlock), 0, st, N, x_alt, v_alt, type_alt, perm_alt,
-                     x, v, type, perm, flags);
+                     x, v, type, perm, rec, flags);
   hipLaunchKernelGGL(k_halo_tables, dim3(nb), dim3(kBlock), 0, st, N, g, cell_sorted, cell_start, ht, flags);
-  hipLaunchKernelGGL(k_build_lists, dim3(nb), dim3(kBlock), 0, st, N, g, x, cell_start, cell_sorted, be,
+  hipLaunchKernelGGL(k_build_lists, dim3(nb), dim3(kBlock), 0, st, N, g, rec, cell_start, cell_sorted, be,
                      capR, capA, lout, ht, sc, flags);
   hipLaunchKernelGGL(k_place_lists, dim3(grid_blocks(N, 64)), dim3(64), 0, st, N, be.nbins, lout, sc, flags);
   hipLaunchKernelGGL(k_count_build, dim3(1), dim3(64), 0, st, flags, be.idxR[0], be.idxA[0]);
