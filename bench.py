@@ -184,6 +184,10 @@ def run_forms(args):
     t_frames = time.perf_counter() - t
     n_frames = int(fr.x.shape[0])
     res = SG.train_surrogate(fr, shp, sur0, epochs=args.epochs, batch=8, lr=1e-2)
+    # the same surrogate with 5 / 4 A cutoffs (fewer pairs per inner step)
+    shp_s = I.SURROGATE_SHORT_HPARAMS
+    sur0_s = I.surrogate_from_teacher(hp, params, shp_s, 1)
+    res_s = SG.train_surrogate(fr, shp_s, sur0_s, epochs=args.epochs, batch=8, lr=1e-2)
     del fr
     torch.cuda.empty_cache()
     at = I.workload_32m(args.cells)
@@ -194,15 +198,20 @@ def run_forms(args):
                                     sur=(shp, res.params))
     forms["mts_untrained"] = run_form("mts", hp, params, at, args.steps, 4 * max(1, args.warmup // 4),
                                       sur=(shp, sur0))
+    forms["mts_short_trained"] = run_form("mts", hp, params, at, args.steps, 4 * max(1, args.warmup // 4),
+                                          sur=(shp_s, res_s.params))
+    forms["mts_short_untrained"] = run_form("mts", hp, params, at, args.steps, 4 * max(1, args.warmup // 4),
+                                            sur=(shp_s, sur0_s))
     out = {"metric": "atom-steps/s per GPU (s/step/atom): plain FP32 NEP vs BF16/MTS surrogate",
            "value": forms["mts_trained"]["atom_steps_per_s"], "unit": "atom-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "data": "synthetic (seeded FCC box, random-weight NEP)",
            "config": {"workload": f"fcc_cu_{args.cells}^3_cells_{at.n}_atoms_forms", "n_atoms": at.n},
-           "training": {"frames": n_frames, "frame_generation_s": t_frames,
-                        "epochs": args.epochs, "seconds": res.seconds, "loss_history": res.history,
-                        "val_force_rmse_init": res.val_force_rmse_init, "val_force_rmse": res.val_force_rmse,
-                        "val_energy_mae_init": res.val_energy_mae_init, "val_energy_mae": res.val_energy_mae},
+           "training": {"frames": n_frames, "frame_generation_s": t_frames, "epochs": args.epochs,
+                        **{name: {"seconds": r.seconds, "loss_history": r.history,
+                                  "val_force_rmse_init": r.val_force_rmse_init, "val_force_rmse": r.val_force_rmse,
+                                  "val_energy_mae_init": r.val_energy_mae_init, "val_energy_mae": r.val_energy_mae}
+                           for name, r in (("teacher_cutoffs", res), ("short_cutoffs", res_s))}},
            "forms": forms}
     print(json.dumps(out))
 

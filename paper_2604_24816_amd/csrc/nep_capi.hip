@@ -271,6 +271,8 @@ EvalBuffers eval_buffers(nep_system* s, int slot) {
   b.F = s->F[slot];
   b.partial = s->partial;
   b.flags = s->flags;
+  b.flag_r = slot == 0 ? FLAG_BIN_R : FLAG_BIN_R1;
+  b.flag_a = slot == 0 ? FLAG_BIN_A : FLAG_BIN_A1;
   return b;
 }
 
@@ -295,28 +297,33 @@ int reduce_ew(nep_system* s, int base) {
   return NEP_OK;
 }
 
-// Merged, sorted distance-bin edges of the list (see BinEdges).
-BinEdges make_bin_edges(double rcR, double rcA, double skin) {
+// Merged, sorted distance-bin edges of the list (see BinEdges): the full model's
+// radial and angular edges; each model's bounds are the first edges at or beyond
+// its own cutoffs plus f_k skin.
+BinEdges make_bin_edges(const nep_hparams* hp0, const nep_hparams* hp1, double skin) {
   std::vector<double> e;
   for (int k = 0; k < kFracs; ++k) {
-    e.push_back(rcA + (double)bin_frac(k) * skin);
-    e.push_back(rcR + (double)bin_frac(k) * skin);
+    e.push_back(hp0->rc_angular + (double)bin_frac(k) * skin);
+    e.push_back(hp0->rc_radial + (double)bin_frac(k) * skin);
   }
   std::sort(e.begin(), e.end());
   e.erase(std::unique(e.begin(), e.end()), e.end());
   BinEdges be{};
   be.nbins = (int)e.size();
   for (int b = 0; b < be.nbins; ++b) be.e2[b] = e[b] * e[b];
-  for (int k = 0; k < kFracs; ++k) {
-    const double er = rcR + (double)bin_frac(k) * skin, ea = rcA + (double)bin_frac(k) * skin;
-    be.idxR[k] = (int)(std::find(e.begin(), e.end(), er) - e.begin());
-    be.idxA[k] = (int)(std::find(e.begin(), e.end(), ea) - e.begin());
-  }
+  const nep_hparams* hp[2] = {hp0, hp1 ? hp1 : hp0};
+  for (int m = 0; m < 2; ++m)
+    for (int k = 0; k < kFracs; ++k) {
+      const double er = hp[m]->rc_radial + (double)bin_frac(k) * skin;
+      const double ea = hp[m]->rc_angular + (double)bin_frac(k) * skin;
+      be.idxR[m][k] = std::min(be.nbins - 1, (int)(std::lower_bound(e.begin(), e.end(), er) - e.begin()));
+      be.idxA[m][k] = std::min(be.nbins - 1, (int)(std::lower_bound(e.begin(), e.end(), ea) - e.begin()));
+    }
   return be;
 }
 
 int rebuild(nep_system* s, double skin, int force) {
-  s->be = make_bin_edges(s->model[0].hp.rc_radial, s->model[0].hp.rc_angular, skin);
+  s->be = make_bin_edges(&s->model[0].hp, s->has_model[1] ? &s->model[1].hp : nullptr, skin);
   const ListOut lists{s->nbr, s->cnt, s->bp, s->nbrl, s->selfl};
   HIPCHK(launch_rebuild(s->N, s->grid, s->be, s->capR, s->capA, s->x, s->v, s->type, s->perm, s->x_alt,
                         s->v_alt, s->type_alt, s->perm_alt, s->x_build, s->cellid, s->cell_sorted, s->src,
@@ -614,7 +621,7 @@ int nep_export_neighbors(nep_system* s, int32_t which, int64_t* offsets, int32_t
   for (int64_t o0 = 0; o0 < N; o0 += chunk) {
     const int64_t o1 = std::min(N, o0 + chunk);
     // the angular list with skin is the prefix of bins up to rc_angular + skin
-    const int32_t* cnt_src = which == 0 ? s->cnt : s->bp + (int64_t)s->be.idxA[kFracs - 1] * N;
+    const int32_t* cnt_src = which == 0 ? s->cnt : s->bp + (int64_t)s->be.idxA[0][kFracs - 1] * N;
     HIPCHK(launch_export(N, s->perm, s->nbr, cnt_src, cap, o0, o1, rows, rcnt, s->st));
     HIPCHK(hipMemcpyAsync(cnt.data() + o0, rcnt, (o1 - o0) * sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
     HIPCHK(hipMemcpyAsync(all.data() + o0 * cap, rows, (size_t)(o1 - o0) * cap * sizeof(int32_t),

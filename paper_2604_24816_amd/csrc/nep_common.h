@@ -25,9 +25,11 @@ enum {
   FLAG_NONFINITE = 3,  // NaN/Inf seen
   FLAG_REBUILD = 4,    // 1 = the current step rebuilds its lists
   FLAG_NBUILD = 5,     // number of list builds (device counter)
-  FLAG_BIN_A = 6,      // last distance bin of the angular pairs an evaluation visits
-  FLAG_BIN_R = 7,      // last distance bin of the radial pairs an evaluation visits
-  FLAG_COUNT = 8
+  FLAG_BIN_A = 6,      // last distance bin of the angular pairs an evaluation of model 0 visits
+  FLAG_BIN_R = 7,      // last distance bin of the radial pairs an evaluation of model 0 visits
+  FLAG_BIN_A1 = 8,     // the same for model 1 (the surrogate, whose cutoffs may be shorter)
+  FLAG_BIN_R1 = 9,
+  FLAG_COUNT = 10
 };
 
 // Each atom has one neighbour list with skin (r < rc_radial + skin), ordered by the
@@ -39,7 +41,9 @@ enum {
 // since the build, so an evaluation visits the radial pairs up to the edge
 // rc_radial + f_k skin and the angular pairs up to rc_angular + f_k skin for the
 // first k with f_k skin >= 2 d; every visited pair is still tested against the
-// true cutoff. bp[b][i] = number of entries of atom i in bins 0..b.
+// true cutoff. The edges come from the full model's cutoffs; a surrogate with
+// shorter cutoffs visits the bins up to the first edge beyond its own.
+// bp[b][i] = number of entries of atom i in bins 0..b.
 constexpr int kFracs = 8;
 __host__ __device__ constexpr float bin_frac(int k) {
   return k == 0 ? 0.f : (k == 1 ? 0.05f : (k == 2 ? 0.1f : (k == 3 ? 0.2f : (k == 4 ? 0.3f : (k == 5 ? 0.45f : (k == 6 ? 0.7f : 1.0f))))));
@@ -48,8 +52,8 @@ constexpr int kMaxBins = 2 * kFracs;
 struct BinEdges {
   double e2[kMaxBins];       // squared edges, ascending; e2[nbins - 1] = (rc_radial + skin)^2
   int nbins;
-  int idxR[kFracs];          // bin whose upper edge is rc_radial + f_k skin
-  int idxA[kFracs];          // bin whose upper edge is rc_angular + f_k skin
+  int idxR[2][kFracs];       // per model: first bin whose upper edge is >= rc_radial + f_k skin
+  int idxA[2][kFracs];       // per model: the same for rc_angular + f_k skin
 };
 
 // Orthorhombic cell grid over the box. Cells are numbered brick by brick: bricks
@@ -206,6 +210,7 @@ struct EvalBuffers {
   float* F;              // [3][N] forces (FP32 accumulation)
   double* partial;       // [nblocks][kPartialStride]
   int32_t* flags;
+  int flag_r, flag_a;    // flag words holding this model's last radial / angular bin
 };
 bool eval_supported(const ModelDev& m);
 // ev (nullable): three events recorded before the descriptor kernel, between the

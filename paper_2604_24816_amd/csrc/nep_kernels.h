@@ -258,10 +258,10 @@ __device__ __forceinline__ bool pair_inside(const double* __restrict__ x, int64_
 // (resp. angular) pairs: the entries of the distance bins those pairs can have
 // reached since the last build. The angular bound never exceeds the radial one.
 __device__ __forceinline__ int radial_bound(const EvalBuffers& b, int64_t i) {
-  return b.bp[(int64_t)b.flags[FLAG_BIN_R] * b.N + i];
+  return b.bp[(int64_t)b.flags[b.flag_r] * b.N + i];
 }
 __device__ __forceinline__ int angular_bound(const EvalBuffers& b, int64_t i) {
-  return b.bp[(int64_t)b.flags[FLAG_BIN_A] * b.N + i];
+  return b.bp[(int64_t)b.flags[b.flag_a] * b.N + i];
 }
 
 // FP64 minimum-image vector of a pair whose position is loaded and its r^2.

@@ -86,14 +86,18 @@ __global__ void k_select_bin(const double* __restrict__ partial, int nblocks, in
   int k = kFracs - 1;
   for (int j = kFracs - 1; j >= 0; --j)
     if ((double)bin_frac(j) * skin >= 2.0 * d * (1.0 + 1e-12)) k = j;
-  int br = be.idxR[kFracs - 1], ba = be.idxA[kFracs - 1];
+  int br0 = 0, ba0 = 0, br1 = 0, ba1 = 0;
   for (int j = 0; j < kFracs; ++j)
     if (j == k) {
-      br = be.idxR[j];
-      ba = be.idxA[j];
+      br0 = be.idxR[0][j];
+      ba0 = be.idxA[0][j];
+      br1 = be.idxR[1][j];
+      ba1 = be.idxA[1][j];
     }
-  flags[FLAG_BIN_R] = br;
-  flags[FLAG_BIN_A] = ba;
+  flags[FLAG_BIN_R] = br0;
+  flags[FLAG_BIN_A] = ba0;
+  flags[FLAG_BIN_R1] = br1;
+  flags[FLAG_BIN_A1] = ba1;
 }
 
 __global__ void k_kick(int64_t N, double dt, const float* __restrict__ F, const int32_t* __restrict__ type,

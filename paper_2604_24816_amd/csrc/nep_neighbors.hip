@@ -494,7 +494,7 @@ k_build_lists(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_
   for (int k = 0; k < kMaxBins; ++k) {
     if (k < be.nbins) {
       t += cb.get(k);
-      if (k == be.idxA[kFracs - 1]) na = t;
+      if (k == be.idxA[0][kFracs - 1]) na = t;
       lo_.bp[(int64_t)k * N + p] = t < capR ? t : capR;
     }
   }
@@ -579,11 +579,13 @@ k_place_lists(int64_t N, int nbins, ListOut lo_, ListScratch sc, const int32_t* 
 }
 
 // After a build the positions equal the build positions: displacement 0, bin 0.
-__global__ void k_count_build(int32_t* flags, int bin_r0, int bin_a0) {
+__global__ void k_count_build(int32_t* flags, int bin_r0, int bin_a0, int bin_r1, int bin_a1) {
   if (flags[FLAG_REBUILD] != 0 && threadIdx.x == 0) {
     flags[FLAG_NBUILD] += 1;
     flags[FLAG_BIN_R] = bin_r0;
     flags[FLAG_BIN_A] = bin_a0;
+    flags[FLAG_BIN_R1] = bin_r1;
+    flags[FLAG_BIN_A1] = bin_a1;
   }
 }
 
@@ -661,7 +663,8 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, const BinEdges& be, int 
   hipLaunchKernelGGL(k_build_lists, dim3(nb), dim3(kBlock), 0, st, N, g, rec, cell_start, cell_sorted, be,
                      capR, capA, lout, ht, sc, flags);
   hipLaunchKernelGGL(k_place_lists, dim3(grid_blocks(N, 64)), dim3(64), 0, st, N, be.nbins, lout, sc, flags);
-  hipLaunchKernelGGL(k_count_build, dim3(1), dim3(64), 0, st, flags, be.idxR[0], be.idxA[0]);
+  hipLaunchKernelGGL(k_count_build, dim3(1), dim3(64), 0, st, flags, be.idxR[0][0], be.idxA[0][0], be.idxR[1][0],
+                     be.idxA[1][0]);
   return hipGetLastError();
 }
 

@@ -184,6 +184,8 @@ class HParams:
 
 FULL_HPARAMS = HParams()
 SURROGATE_HPARAMS = HParams(l_max_3b=2, l_max_4b=0, n_hidden=8)
+# The same surrogate with 5 / 4 A cutoffs: fewer pairs, so a cheaper inner step.
+SURROGATE_SHORT_HPARAMS = HParams(rc_radial=5.0, rc_angular=4.0, l_max_3b=2, l_max_4b=0, n_hidden=8)
 
 # Descriptor scaler of the synthetic models, one constant per descriptor block
 # (radial, angular l = 1..4, four-body). The constants were chosen once so that
@@ -228,8 +230,9 @@ def surrogate_from_teacher(teacher_hp: HParams, teacher: np.ndarray, sur_hp: HPa
                            seed: int, std: float = 0.1) -> np.ndarray:
     """Surrogate initial parameters: expansion coefficients copied from the teacher, network drawn.
 
-    The surrogate keeps the teacher's cutoffs, channel counts and basis sizes, so its
-    coefficient blocks are identical; its scaler keeps the teacher's radial and l <= l_max
+    The surrogate keeps the teacher's channel counts and basis sizes, so its coefficient
+    blocks have the teacher's shape and values (with shorter cutoffs they expand the
+    basis over the shorter range); its scaler keeps the teacher's radial and l <= l_max
     entries; the network is drawn N(0, std) from ``seed``.
     """
     assert (sur_hp.n_types, sur_hp.n_max_radial, sur_hp.n_max_angular, sur_hp.basis_radial,

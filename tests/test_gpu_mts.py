@@ -19,10 +19,14 @@ def models():
     return hp, teacher, shp, sur
 
 
-def test_mts_blocks_match_oracle_rrespa(models):
+@pytest.mark.parametrize("cutoffs", ["teacher", "short"])
+def test_mts_blocks_match_oracle_rrespa(models, cutoffs):
     hp, teacher, shp, sur = models
+    if cutoffs == "short":
+        shp = I.SURROGATE_SHORT_HPARAMS
+        sur = I.surrogate_from_teacher(hp, teacher, shp, 1)
     at = I.workload_small()
-    say("case: MTS k=4, 3 blocks, 4000 atoms, untrained surrogate, no fallback")
+    say(f"case: MTS k=4, 3 blocks, 4000 atoms, untrained surrogate ({cutoffs} cutoffs), no fallback")
     s = make_system(at, hp, teacher, shp, sur)
     th = s.step(12, dt=1.0, rebuild_every=10, skin=1.0, mts_k=4, fallback_rms=1e9, fallback_max=1e9,
                 thermo_every=4)

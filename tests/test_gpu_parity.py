@@ -99,13 +99,16 @@ def test_two_species_alloy_with_vacancies():
     assert ok, msg
 
 
-def test_surrogate_shape(full):
+@pytest.mark.parametrize("cutoffs", ["teacher", "short"])
+def test_surrogate_shape(full, cutoffs):
+    """The surrogate in slot 1 of a system built around the full model; with 5 / 4 A
+    cutoffs it visits only the bins of the shared list up to its own cutoffs."""
     hp, params, m = full
-    shp = I.SURROGATE_HPARAMS
+    shp = I.SURROGATE_HPARAMS if cutoffs == "teacher" else I.SURROGATE_SHORT_HPARAMS
     sp = I.surrogate_from_teacher(hp, params, shp, 1)
     ms = oracle.Model.from_hparams(shp, sp)
     at = I.fcc_box(5, 0.12, 9)
-    say("case: surrogate (hidden 8, l_max 2, no four-body), fp32")
+    say(f"case: surrogate (hidden 8, l_max 2, no four-body, {cutoffs} cutoffs), fp32")
     s = make_system(at, hp, params, shp, sp)
     E, W, F, U = s.compute(slot=1, per_atom=True)
     Eo, Wo, Uo, Fo = oracle.evaluate(ms, at.x, at.types, at.box)
