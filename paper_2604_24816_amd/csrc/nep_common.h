@@ -44,9 +44,9 @@ enum {
 // true cutoff. The edges come from the full model's cutoffs; a surrogate with
 // shorter cutoffs visits the bins up to the first edge beyond its own.
 // bp[b][i] = number of entries of atom i in bins 0..b.
-constexpr int kFracs = 8;
+constexpr int kFracs = 5;
 __host__ __device__ constexpr float bin_frac(int k) {
-  return k == 0 ? 0.f : (k == 1 ? 0.05f : (k == 2 ? 0.1f : (k == 3 ? 0.2f : (k == 4 ? 0.3f : (k == 5 ? 0.45f : (k == 6 ? 0.7f : 1.0f))))));
+  return k == 0 ? 0.f : (k == 1 ? 0.05f : (k == 2 ? 0.15f : (k == 3 ? 0.35f : 1.0f)));
 }
 constexpr int kMaxBins = 2 * kFracs;
 struct BinEdges {

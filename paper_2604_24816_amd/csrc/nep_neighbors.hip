@@ -363,29 +363,21 @@ __device__ __forceinline__ void scan_cell(const uint4* __restrict__ rec, int64_t
   }
 }
 
-// Sixteen 16-bit counters in four 64-bit registers: a counter update is a shift
-// and a few selects and adds instead of a select chain over sixteen registers.
+// kMaxBins 16-bit counters packed in 64-bit registers: a counter update is a shift
+// and a few selects and adds instead of a select chain over kMaxBins registers.
 struct BinCounts {
-  uint64_t w[4] = {0, 0, 0, 0};
+  static constexpr int kWords = (kMaxBins + 3) / 4;
+  uint64_t w[kWords] = {};
   __device__ __forceinline__ void add(int b) {
     const uint64_t inc = (uint64_t)1 << (16 * (b & 3));
 #pragma unroll
-    for (int k = 0; k < 4; ++k) w[k] += (b >> 2) == k ? inc : 0;
+    for (int k = 0; k < kWords; ++k) w[k] += (b >> 2) == k ? inc : 0;
   }
   __device__ __forceinline__ int get(int b) const {
-    const uint64_t v = (b >> 2) == 0 ? w[0] : ((b >> 2) == 1 ? w[1] : ((b >> 2) == 2 ? w[2] : w[3]));
-    return (int)((v >> (16 * (b & 3))) & 0xffffu);
-  }
-  __device__ __forceinline__ void set(int b, int v) {
+    uint64_t v = w[0];
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if ((b >> 2) == k) w[k] |= (uint64_t)v << (16 * (b & 3));
-  }
-  // returns the counter, then increments it
-  __device__ __forceinline__ int take(int b) {
-    const int v = get(b);
-    add(b);
-    return v;
+    for (int k = 1; k < kWords; ++k) v = (b >> 2) == k ? w[k] : v;
+    return (int)((v >> (16 * (b & 3))) & 0xffffu);
   }
 };
 
@@ -528,12 +520,12 @@ k_place_lists(int64_t N, int nbins, ListOut lo_, ListScratch sc, const int32_t* 
   }
   const int rows_max = red[0];
   constexpr int rows = kPlaceRows;  // row `rows` of the tiles is the spare row
+  __shared__ uint16_t off[kMaxBins * 64];  // next position of each bin, per lane
   for (int r0 = 0; r0 < rows_max; r0 += rows) {
     if (valid) {
-      BinCounts off;
 #pragma unroll
-      for (int k = 1; k < kMaxBins; ++k)
-        if (k < nbins) off.set(k, lo_.bp[(int64_t)(k - 1) * N + p]);
+      for (int k = 0; k < kMaxBins; ++k)
+        off[k * 64 + lane] = (uint16_t)(k == 0 || k >= nbins ? 0 : lo_.bp[(int64_t)(k - 1) * N + p]);
       for (int g = 0; g < cnt; g += kStage) {
         uint32_t v[kStage], h[kStage];
         const uint4* src = sc.q + ((int64_t)(g / kStage) * N + p) * (kStage / 4);
@@ -559,7 +551,13 @@ k_place_lists(int64_t N, int nbins, ListOut lo_, ListScratch sc, const int32_t* 
 #pragma unroll
         for (int u = 0; u < kStage; ++u) {
           const bool live = g + u < cnt;
-          const int pos = (live ? off.take((int)(v[u] >> 28)) : -1) - r0;
+          const int oi = (int)(v[u] >> 28) * 64 + lane;
+          int pos = -1;
+          if (live) {
+            pos = off[oi];
+            off[oi] = (uint16_t)(pos + 1);
+          }
+          pos -= r0;
           const int slot = (live && pos >= 0 && pos < rows ? pos : rows) * 64 + lane;
           tile[slot] = v[u] & 0x0fffffffu;
           ltile[slot] = (uint16_t)h[u];
