@@ -495,22 +495,31 @@ k_build_lists(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_
   if (na > capA) atomicMax(&flags[FLAG_OVF_A], na);
 }
 
-// One wavefront per 64 atoms: orders each atom's scratch entries by bin (stable
-// inside a bin) and writes the list and its halo-local indices row by row, 64
-// consecutive atoms per store, through LDS tiles of kPlaceRows rows; longer lists
-// take further rounds. Entries outside the current round go to a spare row.
+// One wavefront per 32 atoms, two lanes per atom: orders each atom's scratch entries
+// by bin (stable inside a bin) and writes the list and its halo-local indices row by
+// row, 32 consecutive atoms (128 bytes) per store, through LDS tiles of kPlaceRows
+// rows; longer lists take further rounds. Lane h = 0 places the first segments of the
+// column, lane h = 1 the rest after counting the bins of the first part. Entries
+// outside the current round go to a spare row.
 constexpr int kPlaceRows = 127;
+constexpr int kPlaceAtoms = 32;
 
 __global__ void __launch_bounds__(64)
 k_place_lists(int64_t N, int nbins, ListOut lo_, ListScratch sc, const int32_t* __restrict__ flags) {
   if (flags[FLAG_REBUILD] == 0) return;
-  __shared__ uint32_t tile[(kPlaceRows + 1) * 64];
-  __shared__ uint16_t ltile[(kPlaceRows + 1) * 64];
+  __shared__ uint32_t tile[(kPlaceRows + 1) * kPlaceAtoms];
+  __shared__ uint16_t ltile[(kPlaceRows + 1) * kPlaceAtoms];
+  __shared__ uint16_t off[kMaxBins * 64];  // next position of each bin, per lane
   __shared__ int red[64];
   const int lane = threadIdx.x;
-  const int64_t p = (int64_t)blockIdx.x * 64 + lane;
+  const int a = lane & (kPlaceAtoms - 1);  // atom of the wavefront
+  const int h = lane / kPlaceAtoms;        // which part of its column
+  const int64_t p = (int64_t)blockIdx.x * kPlaceAtoms + a;
   const bool valid = p < N;
   const int cnt = valid ? lo_.cnt[p] : 0;
+  // the first part: half the column rounded up to whole 16-entry segments
+  const int split = ((cnt + 1) / 2 + kStage - 1) / kStage * kStage;
+  const int g_lo = h == 0 ? 0 : split, g_hi = h == 0 ? (split < cnt ? split : cnt) : cnt;
   // longest list of the wavefront (uniform loop bounds for the row writes)
   red[lane] = cnt;
   __syncthreads();
@@ -520,14 +529,29 @@ k_place_lists(int64_t N, int nbins, ListOut lo_, ListScratch sc, const int32_t* 
   }
   const int rows_max = red[0];
   constexpr int rows = kPlaceRows;  // row `rows` of the tiles is the spare row
-  __shared__ uint16_t off[kMaxBins * 64];  // next position of each bin, per lane
   for (int r0 = 0; r0 < rows_max; r0 += rows) {
     if (valid) {
 #pragma unroll
       for (int k = 0; k < kMaxBins; ++k)
         off[k * 64 + lane] = (uint16_t)(k == 0 || k >= nbins ? 0 : lo_.bp[(int64_t)(k - 1) * N + p]);
-      for (int g = 0; g < cnt; g += kStage) {
-        uint32_t v[kStage], h[kStage];
+      if (h == 1) {
+        // the second part starts after the first part's entries of each bin
+        for (int g = 0; g < g_lo; g += kStage) {
+          const uint4* src = sc.q + ((int64_t)(g / kStage) * N + p) * (kStage / 4);
+#pragma unroll
+          for (int j = 0; j < kStage / 4; ++j) {
+            const uint4 w = src[j];
+            const uint32_t t[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int oi = (int)(t[u] >> 28) * 64 + lane;
+              off[oi] = (uint16_t)(off[oi] + 1);
+            }
+          }
+        }
+      }
+      for (int g = g_lo; g < g_hi; g += kStage) {
+        uint32_t v[kStage], hl[kStage];
         const uint4* src = sc.q + ((int64_t)(g / kStage) * N + p) * (kStage / 4);
 #pragma unroll
         for (int j = 0; j < kStage / 4; ++j) {
@@ -544,13 +568,13 @@ k_place_lists(int64_t N, int nbins, ListOut lo_, ListScratch sc, const int32_t* 
           const uint32_t t[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            h[8 * j + 2 * u] = t[u] & 0xffffu;
-            h[8 * j + 2 * u + 1] = t[u] >> 16;
+            hl[8 * j + 2 * u] = t[u] & 0xffffu;
+            hl[8 * j + 2 * u + 1] = t[u] >> 16;
           }
         }
 #pragma unroll
         for (int u = 0; u < kStage; ++u) {
-          const bool live = g + u < cnt;
+          const bool live = g + u < g_hi;
           const int oi = (int)(v[u] >> 28) * 64 + lane;
           int pos = -1;
           if (live) {
@@ -558,18 +582,19 @@ k_place_lists(int64_t N, int nbins, ListOut lo_, ListScratch sc, const int32_t* 
             off[oi] = (uint16_t)(pos + 1);
           }
           pos -= r0;
-          const int slot = (live && pos >= 0 && pos < rows ? pos : rows) * 64 + lane;
+          const int slot = (live && pos >= 0 && pos < rows ? pos : rows) * kPlaceAtoms + a;
           tile[slot] = v[u] & 0x0fffffffu;
-          ltile[slot] = (uint16_t)h[u];
+          ltile[slot] = (uint16_t)hl[u];
         }
       }
     }
     __syncthreads();
+    // rows r0 + 2t + h: the two halves of the wavefront write alternate rows
     const int nrow = rows_max - r0 < rows ? rows_max - r0 : rows;
-    for (int r = 0; r < nrow; ++r) {
+    for (int r = h; r < nrow; r += 2) {
       if (valid && r0 + r < cnt) {
-        lo_.nbr[(int64_t)(r0 + r) * N + p] = (int32_t)tile[r * 64 + lane];
-        lo_.nbrl[(int64_t)(r0 + r) * N + p] = ltile[r * 64 + lane];
+        lo_.nbr[(int64_t)(r0 + r) * N + p] = (int32_t)tile[r * kPlaceAtoms + a];
+        lo_.nbrl[(int64_t)(r0 + r) * N + p] = ltile[r * kPlaceAtoms + a];
       }
     }
     __syncthreads();
@@ -660,7 +685,8 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, const BinEdges& be, int 
   hipLaunchKernelGGL(k_halo_tables, dim3(nb), dim3(kBlock), 0, st, N, g, cell_sorted, cell_start, ht, flags);
   hipLaunchKernelGGL(k_build_lists, dim3(nb), dim3(kBlock), 0, st, N, g, rec, cell_start, cell_sorted, be,
                      capR, capA, lout, ht, sc, flags);
-  hipLaunchKernelGGL(k_place_lists, dim3(grid_blocks(N, 64)), dim3(64), 0, st, N, be.nbins, lout, sc, flags);
+  hipLaunchKernelGGL(k_place_lists, dim3(grid_blocks(N, kPlaceAtoms)), dim3(64), 0, st, N, be.nbins, lout, sc,
+                     flags);
   hipLaunchKernelGGL(k_count_build, dim3(1), dim3(64), 0, st, flags, be.idxR[0][0], be.idxA[0][0], be.idxR[1][0],
                      be.idxA[1][0]);
   return hipGetLastError();
