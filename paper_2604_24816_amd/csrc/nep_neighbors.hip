@@ -463,6 +463,17 @@ k_build_lists(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_
         scan_cell(rec, N, q0, q1, p, xi, yi, zi, sx, sy, sz, g, cut2, [&](int q, double r2) {
           const int bin = bin_of(r2, be);
           cb.add(bin);
+          if ((n + 1) % kPartLen == 0 && (n + 1) / kPartLen < kPlaceParts && n < capR) {
+            // per-bin counts of the first n + 1 entries: where part (n + 1) / 32 of the
+            // placement starts
+            uint4* c = sc.cum + ((int64_t)((n + 1) / kPartLen - 1) * N + p) * 2;
+            static_assert(BinCounts::kWords <= 4, "bin counters fit two 16-byte words");
+            uint64_t w4[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int k = 0; k < BinCounts::kWords; ++k) w4[k] = cb.w[k];
+            c[0] = make_uint4((uint32_t)w4[0], (uint32_t)(w4[0] >> 32), (uint32_t)w4[1], (uint32_t)(w4[1] >> 32));
+            c[1] = make_uint4((uint32_t)w4[2], (uint32_t)(w4[2] >> 32), (uint32_t)w4[3], (uint32_t)(w4[3] >> 32));
+          }
           if (n < capR) {
             sq[n % kStage] = (uint32_t)q | ((uint32_t)bin << 28);
             sl[n % kStage] = hok ? (uint32_t)(loc0 + q) : (uint32_t)kNoLocal;
@@ -495,14 +506,15 @@ k_build_lists(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_
   if (na > capA) atomicMax(&flags[FLAG_OVF_A], na);
 }
 
-// One wavefront per 32 atoms, two lanes per atom: orders each atom's scratch entries
-// by bin (stable inside a bin) and writes the list and its halo-local indices row by
-// row, 32 consecutive atoms (128 bytes) per store, through LDS tiles of kPlaceRows
-// rows; longer lists take further rounds. Lane h = 0 places the first segments of the
-// column, lane h = 1 the rest after counting the bins of the first part. Entries
+// One wavefront per 16 atoms, four lanes per atom: orders each atom's scratch
+// entries by bin (stable inside a bin) and writes the list and its halo-local
+// indices row by row, 16 consecutive atoms (64 bytes) per store, through LDS tiles of
+// kPlaceRows rows; longer lists take further rounds. Lane h places entries
+// [32 h, 32 (h + 1)) (the last lane the rest), starting each bin after the entries
+// of earlier parts (their per-bin counts were saved by the list build). Entries
 // outside the current round go to a spare row.
 constexpr int kPlaceRows = 127;
-constexpr int kPlaceAtoms = 32;
+constexpr int kPlaceAtoms = 64 / kPlaceParts;
 
 __global__ void __launch_bounds__(64)
 k_place_lists(int64_t N, int nbins, ListOut lo_, ListScratch sc, const int32_t* __restrict__ flags) {
@@ -512,14 +524,14 @@ k_place_lists(int64_t N, int nbins, ListOut lo_, ListScratch sc, const int32_t* 
   __shared__ uint16_t off[kMaxBins * 64];  // next position of each bin, per lane
   __shared__ int red[64];
   const int lane = threadIdx.x;
-  const int a = lane & (kPlaceAtoms - 1);  // atom of the wavefront
-  const int h = lane / kPlaceAtoms;        // which part of its column
+  const int a = lane % kPlaceAtoms;  // atom of the wavefront
+  const int h = lane / kPlaceAtoms;  // which part of its column
   const int64_t p = (int64_t)blockIdx.x * kPlaceAtoms + a;
   const bool valid = p < N;
   const int cnt = valid ? lo_.cnt[p] : 0;
-  // the first part: half the column rounded up to whole 16-entry segments
-  const int split = ((cnt + 1) / 2 + kStage - 1) / kStage * kStage;
-  const int g_lo = h == 0 ? 0 : split, g_hi = h == 0 ? (split < cnt ? split : cnt) : cnt;
+  const int g_lo = h * kPartLen;
+  const int g_hi = h == kPlaceParts - 1 ? cnt : (g_lo + kPartLen < cnt ? g_lo + kPartLen : cnt);
+  const bool work = valid && g_lo < cnt;
   // longest list of the wavefront (uniform loop bounds for the row writes)
   red[lane] = cnt;
   __syncthreads();
@@ -528,27 +540,24 @@ k_place_lists(int64_t N, int nbins, ListOut lo_, ListScratch sc, const int32_t* 
     __syncthreads();
   }
   const int rows_max = red[0];
+  // per-bin counts of the entries before this part
+  uint64_t before[4] = {0, 0, 0, 0};
+  if (work && h > 0) {
+    const uint4* c = sc.cum + ((int64_t)(h - 1) * N + p) * 2;
+    const uint4 c0 = c[0], c1 = c[1];
+    before[0] = ((uint64_t)c0.y << 32) | c0.x;
+    before[1] = ((uint64_t)c0.w << 32) | c0.z;
+    before[2] = ((uint64_t)c1.y << 32) | c1.x;
+    before[3] = ((uint64_t)c1.w << 32) | c1.z;
+  }
   constexpr int rows = kPlaceRows;  // row `rows` of the tiles is the spare row
   for (int r0 = 0; r0 < rows_max; r0 += rows) {
-    if (valid) {
+    if (work) {
 #pragma unroll
-      for (int k = 0; k < kMaxBins; ++k)
-        off[k * 64 + lane] = (uint16_t)(k == 0 || k >= nbins ? 0 : lo_.bp[(int64_t)(k - 1) * N + p]);
-      if (h == 1) {
-        // the second part starts after the first part's entries of each bin
-        for (int g = 0; g < g_lo; g += kStage) {
-          const uint4* src = sc.q + ((int64_t)(g / kStage) * N + p) * (kStage / 4);
-#pragma unroll
-          for (int j = 0; j < kStage / 4; ++j) {
-            const uint4 w = src[j];
-            const uint32_t t[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const int oi = (int)(t[u] >> 28) * 64 + lane;
-              off[oi] = (uint16_t)(off[oi] + 1);
-            }
-          }
-        }
+      for (int k = 0; k < kMaxBins; ++k) {
+        const int start = k == 0 || k >= nbins ? 0 : lo_.bp[(int64_t)(k - 1) * N + p];
+        const int prior = (int)((before[k >> 2] >> (16 * (k & 3))) & 0xffffu);
+        off[k * 64 + lane] = (uint16_t)(start + prior);
       }
       for (int g = g_lo; g < g_hi; g += kStage) {
         uint32_t v[kStage], hl[kStage];
@@ -589,9 +598,9 @@ k_place_lists(int64_t N, int nbins, ListOut lo_, ListScratch sc, const int32_t* 
       }
     }
     __syncthreads();
-    // rows r0 + 2t + h: the two halves of the wavefront write alternate rows
+    // the kPlaceParts lane groups write interleaved rows
     const int nrow = rows_max - r0 < rows ? rows_max - r0 : rows;
-    for (int r = h; r < nrow; r += 2) {
+    for (int r = h; r < nrow; r += kPlaceParts) {
       if (valid && r0 + r < cnt) {
         lo_.nbr[(int64_t)(r0 + r) * N + p] = (int32_t)tile[r * kPlaceAtoms + a];
         lo_.nbrl[(int64_t)(r0 + r) * N + p] = ltile[r * kPlaceAtoms + a];
