@@ -244,6 +244,19 @@ def weight_grad(model: Model, x, types, box, gE, gF=None):
     return grad
 
 
+def param_grad(model: Model, x, types, box, gE, gF=None):
+    """d(gE*E + sum gF.F)/d(every packed parameter): [cR | cA | sigma | W0 | b0 | w1 | b1]."""
+    x = _f64(x)
+    types = np.ascontiguousarray(types, np.int32)
+    box = _f64(box)
+    grad = np.zeros(model.params.size)
+    gFa = None if gF is None else _f64(gF)
+    st = _load().orc_param_grad(*model._args(), ctypes.c_int64(x.shape[0]), _p(x), _p(types),
+                                _p(box), ctypes.c_double(gE), _p(gFa), _p(grad))
+    _check(st, "param_grad")
+    return grad
+
+
 def adam(theta, g, m1, m2, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     """One Adam step in place on FP64 arrays."""
     for a in (theta, g, m1, m2):

@@ -306,9 +306,23 @@ struct CenterTerms {
   std::vector<double> J;    // [npairs][D][3] dq_nu / d r_ij
 };
 
+// Intermediate per-pair tables of one center, kept on request for the
+// coefficient gradients: basis values f_k, df_k/dr at both cutoffs, the angular
+// radial functions g_n and g_n', the angular pair indices, the Legendre tables
+// over angular pairs and the four-body matrices S_n.
+struct CenterTables {
+  std::vector<double> fR, dfR;   // [npairs][kR]
+  std::vector<double> fA, dfA;   // [npairs][kA] (zero beyond the angular cutoff)
+  std::vector<double> gA, dgA;   // [npairs][nA]
+  std::vector<int> ang;          // pair index of each angular neighbour
+  std::vector<double> cosjk, Pjk, dPjk;  // [na][na], [na][na][L3+1] x 2
+  std::vector<double> S;         // [nA][3][3]
+};
+
 // jac_for: -2 = no Jacobian, -1 = every pair, >= 0 = only the pair with that neighbour id.
 void center_terms(const Model& m, const CellGrid* g, int64_t n, const double* x, const int32_t* type,
-                  const double* box, int64_t i, int precision_bf16, int64_t jac_for, CenterTerms& ct) {
+                  const double* box, int64_t i, int precision_bf16, int64_t jac_for, CenterTerms& ct,
+                  CenterTables* tab = nullptr) {
   const int D = m.D, H = m.H, nR = m.nR, nA = m.nA, kR = m.kR, kA = m.kA, L3 = m.L3;
   std::vector<int32_t> nb;
   neighbors_of(g, n, x, box, m.rcR, i, nb);
@@ -327,10 +341,21 @@ void center_terms(const Model& m, const CellGrid* g, int64_t n, const double* x,
   std::vector<double> gR(np * nR), dgR(np * nR), gA(np * nA, 0.0), dgA(np * nA, 0.0);
   std::vector<char> isA(np, 0);
   std::vector<double> f(std::max(kR, kA)), df(std::max(kR, kA));
+  if (tab) {
+    tab->fR.assign((size_t)np * kR, 0.0);
+    tab->dfR.assign((size_t)np * kR, 0.0);
+    tab->fA.assign((size_t)np * kA, 0.0);
+    tab->dfA.assign((size_t)np * kA, 0.0);
+  }
   for (int p = 0; p < np; ++p) {
     const int tj = type[ct.pairs[p].j];
     const double r = ct.pairs[p].r;
     radial_basis(r, m.rcR, kR, f.data(), df.data());
+    if (tab)
+      for (int k = 0; k < kR; ++k) {
+        tab->fR[(size_t)p * kR + k] = f[k];
+        tab->dfR[(size_t)p * kR + k] = df[k];
+      }
     const double* c = m.cR + ((int64_t)ti * m.T + tj) * nR * kR;
     for (int a = 0; a < nR; ++a) {
       double s = 0, ds = 0;
@@ -341,6 +366,11 @@ void center_terms(const Model& m, const CellGrid* g, int64_t n, const double* x,
     if (r < m.rcA) {
       isA[p] = 1;
       radial_basis(r, m.rcA, kA, f.data(), df.data());
+      if (tab)
+        for (int k = 0; k < kA; ++k) {
+          tab->fA[(size_t)p * kA + k] = f[k];
+          tab->dfA[(size_t)p * kA + k] = df[k];
+        }
       const double* ca = m.cA + ((int64_t)ti * m.T + tj) * nA * kA;
       for (int a = 0; a < nA; ++a) {
         double s = 0, ds = 0;
@@ -407,6 +437,15 @@ void center_terms(const Model& m, const CellGrid* g, int64_t n, const double* x,
         for (int k = 0; k < 3; ++k) tr += S2[r * 3 + k] * Sm[k * 3 + r];
       ct.q[nR + L3 * nA + nn] = tr;
     }
+  }
+  if (tab) {
+    tab->gA = gA;
+    tab->dgA = dgA;
+    tab->ang = ang;
+    tab->cosjk = cosjk;
+    tab->Pjk = Pjk;
+    tab->dPjk = dPjk;
+    tab->S = S;
   }
   // Network: U = sum_mu w1 tanh(sum_nu W0 qs - b0) - b1, qs = q * sigma.
   std::vector<double> qs(D), Wr(H * D);
@@ -989,6 +1028,209 @@ int orc_weight_grad(const int32_t* ip, const double* dp, const double* params, i
   for (int64_t k = 0; k < G; ++k) {
     double s = 0;
     for (int t = 0; t < nt; ++t) s += part[(size_t)t * G + k];
+    grad[k] = s;
+  }
+  return OK;
+}
+
+// Gradient of L = gE * E + sum_i gF_i . F_i with respect to every packed
+// parameter, in the packed order [cR | cA | sigma | W0 | b0 | w1 | b1]: the
+// trainable expansion coefficients c^{t_i t_j}_{nk} of the radial functions
+// (Section III.B), the descriptor scaler and the network.
+// Each center contributes L_a = gE U_a - Fp_a . v_a, with v_a the descriptor JVP
+// along gF as in orc_weight_grad. Its derivative with respect to the descriptor
+// is rho_a = gE Fp_a - (d^2 U_a / dq^2) v_a = sigma * (W0^T alpha), and with
+// respect to v_a it is -Fp_a = -sigma * (W0^T beta), where alpha = gE w1 d +
+// 2 z w1 t d and beta = w1 d. The descriptor and its JVP depend on c only through
+// the per-pair radial values g_n(r_aj) = sum_k c_nk f_k(r_aj) and their radial
+// derivatives g'_n(r_aj) = sum_k c_nk f'_k(r_aj), so
+//   dL/dc^{t_a t}_{nk} = sum over neighbours j of type t of
+//                        f_k(r_aj) dL_a/dg_n(r_aj) + f'_k(r_aj) dL_a/dg'_n(r_aj),
+// and the partial derivatives with respect to g_n and g'_n are taken term by term
+// from the radial sum, the Legendre double sum of q_nl and the four-body trace.
+int orc_param_grad(const int32_t* ip, const double* dp, const double* params, int64_t n_params,
+                   int64_t n, const double* x, const int32_t* type, const double* box,
+                   double gE, const double* gF, double* grad) {
+  Model m;
+  int st = parse_model(ip, dp, params, n_params, m);
+  if (st) return st;
+  if (!grad) return ERR_ARG;
+  if (!box_ok(box, m.rcR)) return ERR_BOX;
+  const int D = m.D, H = m.H, T = m.T, nR = m.nR, nA = m.nA, kR = m.kR, kA = m.kA, L3 = m.L3;
+  const int64_t G = n_params;
+  const int64_t oA = (int64_t)T * T * nR * kR;       // start of cA
+  const int64_t oS = oA + (int64_t)T * T * nA * kA;  // start of sigma
+  const int64_t oN = m.off_nn;                         // start of W0
+  CellGrid g;
+  const bool use_grid = n > 256;
+  if (use_grid) g.build(n, x, box, m.rcR);
+  const int nt = nthreads();
+  std::vector<double> part((size_t)nt * G, 0.0);
+#pragma omp parallel
+  {
+#ifdef _OPENMP
+    const int tid = omp_get_thread_num();
+#else
+    const int tid = 0;
+#endif
+    double* gacc = &part[(size_t)tid * G];
+    CenterTerms ct;
+    CenterTables tb;
+    std::vector<double> qs(D), v(D), vs(D), z(H), t(H), dd(H), al(H), be(H), rho(D), phi(D);
+    std::vector<double> w, uw;
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t a = 0; a < n; ++a) {
+      center_terms(m, use_grid ? &g : nullptr, n, x, type, box, a, 0, gF != nullptr ? -1 : -2, ct, &tb);
+      const int np = (int)ct.pairs.size();
+      const int ti = type[a];
+      // w_p = gF_j - gF_a per pair, u_p . w_p, and the JVP v = sum_p J_p w_p
+      w.assign((size_t)np * 3, 0.0);
+      uw.assign(np, 0.0);
+      for (int k = 0; k < D; ++k) v[k] = 0.0;
+      if (gF) {
+        for (int p = 0; p < np; ++p) {
+          const int64_t j = ct.pairs[p].j;
+          for (int c = 0; c < 3; ++c) w[3 * p + c] = gF[3 * j + c] - gF[3 * a + c];
+          uw[p] = ct.pairs[p].u[0] * w[3 * p] + ct.pairs[p].u[1] * w[3 * p + 1] + ct.pairs[p].u[2] * w[3 * p + 2];
+          for (int k = 0; k < D; ++k)
+            for (int c = 0; c < 3; ++c) v[k] += ct.J[((size_t)p * D + k) * 3 + c] * w[3 * p + c];
+        }
+      }
+      // network terms
+      for (int k = 0; k < D; ++k) {
+        qs[k] = ct.q[k] * m.sigma[k];
+        vs[k] = v[k] * m.sigma[k];
+      }
+      for (int mu = 0; mu < H; ++mu) {
+        double s = 0;
+        for (int k = 0; k < D; ++k) s += m.W0[mu * D + k] * vs[k];
+        z[mu] = s;
+        t[mu] = std::tanh(ct.h[mu]);
+        dd[mu] = 1.0 - t[mu] * t[mu];
+        be[mu] = m.w1[mu] * dd[mu];
+        al[mu] = gE * be[mu] + 2.0 * z[mu] * m.w1[mu] * t[mu] * dd[mu];
+      }
+      for (int k = 0; k < D; ++k) {
+        double sa = 0, sb = 0;
+        for (int mu = 0; mu < H; ++mu) {
+          sa += m.W0[mu * D + k] * al[mu];
+          sb += m.W0[mu * D + k] * be[mu];
+        }
+        rho[k] = m.sigma[k] * sa;
+        phi[k] = m.sigma[k] * sb;
+        // scaler: dL/dsigma_k = q_k (W0^T alpha)_k - v_k (W0^T beta)_k
+        gacc[oS + k] += ct.q[k] * sa - v[k] * sb;
+      }
+      // network parameters
+      for (int mu = 0; mu < H; ++mu) {
+        const double zwtd = 2.0 * z[mu] * m.w1[mu] * t[mu] * dd[mu];
+        for (int k = 0; k < D; ++k) gacc[oN + mu * D + k] += gE * be[mu] * qs[k] - (be[mu] * vs[k] - zwtd * qs[k]);
+        gacc[oN + (int64_t)H * D + mu] += -gE * be[mu] - zwtd;
+        gacc[oN + (int64_t)H * D + H + mu] += gE * t[mu] - z[mu] * dd[mu];
+      }
+      gacc[oN + (int64_t)H * D + 2 * H] += -gE;
+      // radial coefficients: q_n = sum_j g_n, v_n = sum_j g'_n (u . w)
+      for (int p = 0; p < np; ++p) {
+        const int tj = type[ct.pairs[p].j];
+        double* gc = gacc + ((int64_t)ti * T + tj) * nR * kR;
+        for (int nn = 0; nn < nR; ++nn)
+          for (int k = 0; k < kR; ++k)
+            gc[nn * kR + k] += rho[nn] * tb.fR[(size_t)p * kR + k] - phi[nn] * tb.dfR[(size_t)p * kR + k] * uw[p];
+      }
+      // angular coefficients
+      const int na = (int)tb.ang.size();
+      auto Pt = [&](int aa, int bb, int l) { return tb.Pjk[((size_t)aa * na + bb) * (L3 + 1) + l]; };
+      auto dPt = [&](int aa, int bb, int l) { return tb.dPjk[((size_t)aa * na + bb) * (L3 + 1) + l]; };
+      for (int aa = 0; aa < na; ++aa) {
+        const int p = tb.ang[aa];
+        const int tj = type[ct.pairs[p].j];
+        const double* ua = ct.pairs[p].u;
+        const double ra = ct.pairs[p].r;
+        double* gc = gacc + oA + ((int64_t)ti * T + tj) * nA * kA;
+        for (int nn = 0; nn < nA; ++nn) {
+          double Gg = 0.0, Gp = 0.0;  // dL_a/dg_n(r_a), dL_a/dg'_n(r_a)
+          for (int l = 1; l <= L3; ++l) {
+            double dq = 0.0, dv = 0.0;
+            for (int bb = 0; bb < na; ++bb) {
+              const int pb = tb.ang[bb];
+              const double gb = tb.gA[(size_t)pb * nA + nn], dgb = tb.dgA[(size_t)pb * nA + nn];
+              const double* ub = ct.pairs[pb].u;
+              const double* wb = &w[3 * pb];
+              const double* wa = &w[3 * p];
+              const double c = tb.cosjk[(size_t)aa * na + bb];
+              // q_nl = sum_{j,k} g_j g_k P_l(c_jk)
+              dq += 2.0 * gb * Pt(aa, bb, l);
+              // v_nl = 2 sum_{j,k} g_k [g'_j P_l(c_jk) (u_j.w_j) + g_j P_l'(c_jk) (u_k - c_jk u_j).w_j / r_j]
+              // with g_a in the role of g_k ...
+              const double ua_wb = ua[0] * wb[0] + ua[1] * wb[1] + ua[2] * wb[2];
+              dv += 2.0 * (dgb * Pt(bb, aa, l) * uw[pb] + gb * dPt(bb, aa, l) * (ua_wb - c * uw[pb]) / ct.pairs[pb].r);
+              // ... and in the role of g_j
+              const double ub_wa = ub[0] * wa[0] + ub[1] * wa[1] + ub[2] * wa[2];
+              dv += 2.0 * gb * dPt(aa, bb, l) * (ub_wa - c * uw[p]) / ra;
+            }
+            const int k = nR + (l - 1) * nA + nn;
+            Gg += rho[k] * dq - phi[k] * dv;
+            Gp += -phi[k] * dq * uw[p];  // dv_nl/dg'_a = (dq_nl/dg_a) (u_a.w_a)
+          }
+          if (m.L4 == 2) {
+            // q4 = tr(S^3), S = sum_j g_j M_j, M_j = u_j u_j^T - I/3;
+            // v4 = 3 tr(S^2 Sd), Sd = sum_j [g'_j (u_j.w_j) M_j + g_j N_j],
+            // N_j = sum_c w_jc dM_j/d(r_j)_c = [(w - (u.w) u) u^T + u (w - (u.w) u)^T] / r_j
+            auto Mof = [](const double* u, double* M) {
+              for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) M[r * 3 + c] = u[r] * u[c] - (r == c ? 1.0 / 3.0 : 0.0);
+            };
+            auto Nof = [](const double* u, const double* wv, double uwv, double r, double* N) {
+              double e[3];
+              for (int c = 0; c < 3; ++c) e[c] = wv[c] - uwv * u[c];
+              for (int r0 = 0; r0 < 3; ++r0)
+                for (int c = 0; c < 3; ++c) N[r0 * 3 + c] = (e[r0] * u[c] + u[r0] * e[c]) / r;
+            };
+            auto mul = [](const double* A, const double* B, double* C) {
+              for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) {
+                  double s = 0;
+                  for (int k = 0; k < 3; ++k) s += A[r * 3 + k] * B[k * 3 + c];
+                  C[r * 3 + c] = s;
+                }
+            };
+            auto tr = [](const double* A, const double* B) {
+              double s = 0;
+              for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) s += A[r * 3 + c] * B[c * 3 + r];
+              return s;
+            };
+            const double* Sm = &tb.S[nn * 9];
+            double S2[9], Sd[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, Ma[9], Na[9], M[9], N[9];
+            mul(Sm, Sm, S2);
+            for (int bb = 0; bb < na; ++bb) {
+              const int pb = tb.ang[bb];
+              Mof(ct.pairs[pb].u, M);
+              Nof(ct.pairs[pb].u, &w[3 * pb], uw[pb], ct.pairs[pb].r, N);
+              const double gb = tb.gA[(size_t)pb * nA + nn], dgb = tb.dgA[(size_t)pb * nA + nn];
+              for (int e = 0; e < 9; ++e) Sd[e] += dgb * uw[pb] * M[e] + gb * N[e];
+            }
+            Mof(ua, Ma);
+            Nof(ua, &w[3 * p], uw[p], ra, Na);
+            double MS[9], SM[9];
+            mul(Ma, Sm, MS);
+            mul(Sm, Ma, SM);
+            for (int e = 0; e < 9; ++e) MS[e] += SM[e];
+            const double dq4 = 3.0 * tr(S2, Ma);
+            const double dv4 = 3.0 * tr(MS, Sd) + 3.0 * tr(S2, Na);
+            const int k = nR + L3 * nA + nn;
+            Gg += rho[k] * dq4 - phi[k] * dv4;
+            Gp += -phi[k] * dq4 * uw[p];
+          }
+          for (int k = 0; k < kA; ++k)
+            gc[nn * kA + k] += Gg * tb.fA[(size_t)p * kA + k] + Gp * tb.dfA[(size_t)p * kA + k];
+        }
+      }
+    }
+  }
+  for (int64_t k = 0; k < G; ++k) {
+    double s = 0;
+    for (int tt = 0; tt < nt; ++tt) s += part[(size_t)tt * G + k];
     grad[k] = s;
   }
   return OK;

@@ -461,6 +461,58 @@ def test_weight_gradient_fd(full_hp):
         assert abs(fd - grad[k]) < 2e-6 * max(1.0, abs(grad[k])), (k, fd, grad[k])
 
 
+@pytest.mark.parametrize("kind", ["full", "two_species", "surrogate"])
+def test_param_gradient_fd(kind):
+    """Gradient with respect to the expansion coefficients c (radial and angular, every
+    species pair), the scaler and the network, against central differences of the
+    oracle's own E and F; its network block equals weight_grad."""
+    if kind == "two_species":
+        hp = I.HParams(n_types=2)
+        p = I.random_model(hp, 8)
+        at = I.alloy_box(4, 1, 30, 2, 0.17, 3)
+    elif kind == "surrogate":
+        thp = I.FULL_HPARAMS
+        hp = I.SURROGATE_HPARAMS
+        p = I.surrogate_from_teacher(thp, I.random_model(thp, 0), hp, 3)
+        at = I.fcc_box(4, 0.17, 23)
+    else:
+        hp = I.FULL_HPARAMS
+        p = I.random_model(hp, 6)
+        at = I.fcc_box(4, 0.17, 23)
+    m = oracle.Model.from_hparams(hp, p)
+    rng = np.random.default_rng(2)
+    gF = rng.normal(size=(at.n, 3))
+    gE = 0.7
+    grad = oracle.param_grad(m, at.x, at.types, at.box, gE, gF)
+    o = hp.offsets()
+    off = o["W0"][0]
+    ref = oracle.weight_grad(m, at.x, at.types, at.box, gE, gF)
+    assert np.abs(grad[off:] - ref).max() < 1e-12 * np.abs(ref).max()
+    grad0 = oracle.param_grad(m, at.x, at.types, at.box, gE, None)
+
+    def loss(pp, with_f=True):
+        E, _, _, F = oracle.evaluate(oracle.Model.from_hparams(hp, pp), at.x, at.types, at.box)
+        return gE * E + (np.sum(gF * F) if with_f else 0.0)
+    # entries from every block of cR and cA (each species pair) and the scaler
+    idx = []
+    for name in ("cR", "cA"):
+        a, b = o[name]
+        blk = (b - a) // hp.n_types ** 2
+        for t in range(hp.n_types ** 2):
+            idx += list(a + t * blk + rng.choice(blk, 3, replace=False))
+    idx += list(o["sigma"][0] + rng.choice(hp.n_desc, 3, replace=False))
+    for k in idx:
+        for with_f, g in ((True, grad), (False, grad0)):
+            h = 1e-6
+            pp = p.copy()
+            pp[k] += h
+            lp = loss(pp, with_f)
+            pp[k] -= 2 * h
+            lm = loss(pp, with_f)
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - g[k]) < 1e-6 * max(1.0, abs(g[k])), (kind, k, with_f, fd, g[k])
+
+
 def test_bf16_rounding_closed_forms():
     import torch
     assert oracle.round_bf16(1.0) == 1.0
