@@ -184,6 +184,21 @@ int nep_train_forward(nep_system* s, int32_t slot, const float* theta, double* e
 int nep_train_backward(nep_system* s, int32_t slot, const float* theta, double gE,
                        const float* gF, float* grad, int32_t accumulate);
 
+/* The same with respect to every parameter of the model (Section III.B names
+ * the expansion coefficients c of the radial functions trainable): params and
+ * grad are device FP32 vectors of n_params values in the packed order of
+ * nep_model_create, [cR | cA | sigma | W0 | b0 | w1 | b1]. The forward call
+ * evaluates the model with all parameters taken from params; the backward call
+ * writes (or, with accumulate = 1, adds) dL/dparams, including dL/dc and the
+ * gradient with respect to the descriptor scaler sigma (a caller that keeps
+ * sigma fixed ignores that block). The gradient kernels use the system's
+ * partial-sum buffer, so calls on one system must not overlap. The same
+ * ordering rules as nep_train_backward apply. Does not synchronise. */
+int nep_train_forward_params(nep_system* s, int32_t slot, const float* params, double* energy,
+                             float* forces);
+int nep_train_backward_params(nep_system* s, int32_t slot, const float* params, double gE,
+                              const float* gF, float* grad, int32_t accumulate);
+
 /* One Adam step on device FP32 arrays theta, grad, m1, m2 of length n
  * (t = 1-based step count), on the system's stream. */
 int nep_adam_update(nep_system* s, float* theta, const float* grad, float* m1, float* m2,

@@ -899,6 +899,45 @@ int nep_train_backward(nep_system* s, int32_t slot, const float* theta, double g
   return NEP_OK;
 }
 
+int nep_train_forward_params(nep_system* s, int32_t slot, const float* params, double* energy, float* forces) {
+  if (!s || !params || !energy || slot < 0 || slot > 1 || !s->has_model[slot]) return fail(s, NEP_ERR_ARG, "bad argument");
+  if (!s->have_list) return fail(s, NEP_ERR_STALE_LIST, "build the neighbour lists first");
+  HIPCHK(launch_train_forward_params(s->mdev[slot], params, eval_buffers(s, slot), s->st));
+  s->force_valid[slot] = false;
+  int st;
+  if ((st = reduce_ew(s, 0))) return st;
+  if (forces) HIPCHK(launch_scatter_vec_f32(s->N, s->perm, s->F[slot], forces, s->st));
+  double r;
+  HIPCHK(hipMemcpyAsync(&r, s->res, sizeof(double), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  *energy = r;
+  if (!std::isfinite(r)) return fail(s, NEP_ERR_NONFINITE, "non-finite energy");
+  return NEP_OK;
+}
+
+int nep_train_backward_params(nep_system* s, int32_t slot, const float* params, double gE, const float* gF,
+                              float* grad, int32_t accumulate) {
+  if (!s || !params || !grad || slot < 0 || slot > 1 || !s->has_model[slot]) return fail(s, NEP_ERR_ARG, "bad argument");
+  if (!s->have_list) return fail(s, NEP_ERR_STALE_LIST, "build the neighbour lists first");
+  TrainBuffers t;
+  t.e = eval_buffers(s, slot);
+  t.theta = params;
+  t.gE = gE;
+  t.gF = nullptr;
+  if (gF) {
+    HIPCHK(launch_gather_vec_f32(s->N, s->perm, gF, s->gF, s->st));
+    t.gF = s->gF;
+  }
+  t.vjp = nullptr;
+  t.qs = nullptr;
+  t.gpart = s->gpart;
+  t.grad = grad;
+  t.accumulate = accumulate ? 1 : 0;
+  HIPCHK(launch_train_backward_params(s->mdev[slot], t, s->st));
+  s->force_valid[slot] = false;
+  return NEP_OK;
+}
+
 int nep_adam_update(nep_system* s, float* theta, const float* grad, float* m1, float* m2, int64_t n, int64_t t,
                     double lr, double beta1, double beta2, double eps) {
   if (!s || !theta || !grad || !m1 || !m2 || n < 1 || t < 1) return fail(s, NEP_ERR_ARG, "bad argument");

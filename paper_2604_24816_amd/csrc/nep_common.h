@@ -277,6 +277,11 @@ struct TrainBuffers {
 hipError_t launch_train_forward(const ModelDev& m, const float* theta, const EvalBuffers& b,
                                 hipStream_t st);
 hipError_t launch_train_backward(const ModelDev& m, const TrainBuffers& t, hipStream_t st);
+// The same with every parameter taken from a packed FP32 vector
+// [cR | cA | sigma | W0 | b0 | w1 | b1] (t.theta) and the gradient written in that order.
+hipError_t launch_train_forward_params(const ModelDev& m, const float* params, const EvalBuffers& b,
+                                       hipStream_t st);
+hipError_t launch_train_backward_params(const ModelDev& m, const TrainBuffers& t, hipStream_t st);
 int train_partial_blocks(int64_t N);
 int train_grad_stride();
 hipError_t launch_adam(float* theta, const float* g, float* m1, float* m2, int64_t n, int64_t t,

@@ -379,21 +379,41 @@ __device__ __forceinline__ void desc_finish(const float* s, float* q) {
   }
 }
 
-// d tr(S^3) / d s for the l = 2 accumulators (xy, yz, 3z^2 - r^2, xz, x^2 - y^2)
-// of one channel: 3 S^2 contracted with dS/ds.
+// 3 Q contracted with dS/ds for the l = 2 accumulators (xy, yz, 3z^2 - r^2, xz,
+// x^2 - y^2) of one channel, for a symmetric 3x3 matrix Q.
+__device__ __forceinline__ void fourbody_contract(const Sym3& Q, float* d5) {
+  d5[0] = 6.f * Q.xy;
+  d5[1] = 6.f * Q.yz;
+  d5[2] = Q.zz - 0.5f * (Q.xx + Q.yy);
+  d5[3] = 6.f * Q.xz;
+  d5[4] = 1.5f * (Q.xx - Q.yy);
+}
+
+// d tr(S^3) / d s: the contraction above with Q = S^2.
 __device__ __forceinline__ void fourbody_ds(const float* sl, float* d5) {
   const Sym3 a = s_matrix(sl);
-  const float Qxx = a.xx * a.xx + a.xy * a.xy + a.xz * a.xz;
-  const float Qyy = a.xy * a.xy + a.yy * a.yy + a.yz * a.yz;
-  const float Qzz = a.xz * a.xz + a.yz * a.yz + a.zz * a.zz;
-  const float Qxy = a.xx * a.xy + a.xy * a.yy + a.xz * a.yz;
-  const float Qyz = a.xy * a.xz + a.yy * a.yz + a.yz * a.zz;
-  const float Qxz = a.xx * a.xz + a.xy * a.yz + a.xz * a.zz;
-  d5[0] = 6.f * Qxy;
-  d5[1] = 6.f * Qyz;
-  d5[2] = Qzz - 0.5f * (Qxx + Qyy);
-  d5[3] = 6.f * Qxz;
-  d5[4] = 1.5f * (Qxx - Qyy);
+  Sym3 Q;
+  Q.xx = a.xx * a.xx + a.xy * a.xy + a.xz * a.xz;
+  Q.yy = a.xy * a.xy + a.yy * a.yy + a.yz * a.yz;
+  Q.zz = a.xz * a.xz + a.yz * a.yz + a.zz * a.zz;
+  Q.xy = a.xx * a.xy + a.xy * a.yy + a.xz * a.yz;
+  Q.yz = a.xy * a.xz + a.yy * a.yz + a.yz * a.zz;
+  Q.xz = a.xx * a.xz + a.xy * a.yz + a.xz * a.zz;
+  fourbody_contract(Q, d5);
+}
+
+// Derivative of fourbody_ds along the accumulator direction sdl (the Hessian of
+// tr(S^3) times sdl): S^2 is replaced by S Sd + Sd S.
+__device__ __forceinline__ void fourbody_ds_dir(const float* sl, const float* sdl, float* d5) {
+  const Sym3 a = s_matrix(sl), b = s_matrix(sdl);
+  Sym3 Q;
+  Q.xx = 2.f * (a.xx * b.xx + a.xy * b.xy + a.xz * b.xz);
+  Q.yy = 2.f * (a.xy * b.xy + a.yy * b.yy + a.yz * b.yz);
+  Q.zz = 2.f * (a.xz * b.xz + a.yz * b.yz + a.zz * b.zz);
+  Q.xy = a.xx * b.xy + a.xy * b.yy + a.xz * b.yz + b.xx * a.xy + b.xy * a.yy + b.xz * a.yz;
+  Q.yz = a.xy * b.xz + a.yy * b.yz + a.yz * b.zz + b.xy * a.xz + b.yy * a.yz + b.yz * a.zz;
+  Q.xz = a.xx * b.xz + a.xy * b.yz + a.xz * b.zz + b.xx * a.xz + b.xy * a.yz + b.xz * a.zz;
+  fourbody_contract(Q, d5);
 }
 
 template <class S>

@@ -1,5 +1,6 @@
 // Differentiation of L = gE * E + sum_i gF_i . F_i with respect to the network
-// parameters theta = (W0, b0, w1, b1), and the Adam update.
+// parameters theta = (W0, b0, w1, b1), with respect to the expansion coefficients
+// and the scaler, and the Adam update.
 //
 // With F = -dE/dx, sum_i gF_i . F_i = -sum_a dU_a/dq_a . v_a where
 // v_a = sum_j dq_a/dr_aj . (gF_j - gF_a) is the descriptor JVP along gF.
@@ -208,6 +209,302 @@ k_train_backward(ModelDev m, EvalBuffers b, const float* __restrict__ gF, double
   }
 }
 
+// Sum of v over the wavefront, added by its first lane to an LDS word.
+__device__ __forceinline__ void wave_add_lds(float v, float* dst) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0) atomicAdd(dst, v);
+}
+
+// Adds v for centers of species ti into dst[ti * stride] (one species: dst).
+template <bool MULTI>
+__device__ __forceinline__ void wave_add_by_type(float v, int ti, int T, float* dst, int stride) {
+  if constexpr (MULTI) {
+    for (int t = 0; t < T; ++t) wave_add_lds(ti == t ? v : 0.f, dst + t * stride);
+  } else {
+    wave_add_lds(v, dst);
+  }
+}
+
+// Gradient of L = gE * E + sum_i gF_i . F_i with respect to the expansion
+// coefficients c of the radial functions (Section III.B) and the descriptor
+// scaler sigma. Each center contributes L_i = gE U_i - Fp_i . v_i (v_i: the
+// descriptor JVP along gF). With alpha and beta as in k_train_backward,
+// rho = sigma * (W0^T alpha) is dL_i/dq and -Fp = -sigma * (W0^T beta) is dL_i/dv.
+//  * radial: q_n and v_n are linear in c through the basis sums over the neighbours
+//    j of each species t, F_k = sum f_k(r_ij) and E_k = sum f'_k(r_ij) (u.w), so
+//    dL/dc^{t_i t}_{nk} += rho_n F_k - Fp_n E_k;
+//  * angular: with s_nlm, its JVP sd_nlm and the weights W_lm of q_nl,
+//      A_nlm = 2 W_lm Fp_nl s_nlm,  C_nlm = 2 W_lm (rho_nl s_nlm - Fp_nl sd_nlm)
+//    (plus, for the four-body term, Fp4 dq4/ds in A and rho4 dq4/ds - Fp4 (d^2q4/ds^2) sd
+//    in C), and each pair adds f_k (X_n - Z_n) - f'_k (u.w) Y_n to dL/dc_nk, with
+//    X_n = sum_lm C_nlm P_lm, Y_n = sum_lm A_nlm P_lm and
+//    Z_n = sum_lm A_nlm (grad P_lm . w - l P_lm (u.w)) / r;
+//  * scaler: dL/dsigma_k += q_k (W0^T alpha)_k - v_k (W0^T beta)_k.
+// Sums over the workgroup run in FP32 (wavefront shuffles, then LDS atomics); each
+// workgroup writes its sums as FP64 in the packed order [cR | cA | sigma].
+template <class S, bool MULTI>
+__global__ void __launch_bounds__(kBlock, 1)
+k_train_cgrad(ModelDev m, EvalBuffers b, const float* __restrict__ gF, double gE, double* __restrict__ gpart) {
+  constexpr int NR = S::NR, NA = S::NA, NC = S::NC, D = S::D, H = S::H, KR = S::KR, KA = S::KA;
+  constexpr int TT = MULTI ? kMaxTypes : 1;
+  static_assert(kMaxTypes * kMaxTypes * (NR * KR + NA * KA) + D <= kGradStride, "partial row too short");
+  __shared__ float red[kMaxTypes * kMaxTypes * (NR * KR + NA * KA) + D];
+  const int T = MULTI ? m.T : 1;
+  const int oA = T * T * NR * KR, oS = oA + T * T * NA * KA;
+  const int nred = oS + D;
+  for (int e = threadIdx.x; e < nred; e += kBlock) red[e] = 0.f;
+  __syncthreads();
+  const int64_t N = b.N;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int64_t i = (int64_t)tile * kBlock + threadIdx.x;
+  const bool valid = i < N;
+  const double* __restrict__ x = b.x;
+  const double Lx = b.box[0], Ly = b.box[1], Lz = b.box[2];
+  const float rcR_inv = 1.f / m.rcR, rcA_inv = 1.f / m.rcA;
+  const double rcR2 = m.rcR64 * m.rcR64, rcA2 = m.rcA64 * m.rcA64;
+
+  float q[D], v[D], s[NA * NC], sd[NA * NC], Fk[TT][KR], Ek[TT][KR];
+#pragma unroll
+  for (int k = 0; k < D; ++k) q[k] = v[k] = 0.f;
+#pragma unroll
+  for (int k = 0; k < NA * NC; ++k) s[k] = sd[k] = 0.f;
+#pragma unroll
+  for (int t = 0; t < TT; ++t)
+#pragma unroll
+    for (int k = 0; k < KR; ++k) Fk[t][k] = Ek[t][k] = 0.f;
+  int ti = 0;
+  double xi = 0, yi = 0, zi = 0;
+  float wi0 = 0.f, wi1 = 0.f, wi2 = 0.f;
+  if (valid) {
+    ti = MULTI ? b.type[i] : 0;
+    xi = x[i];
+    yi = x[N + i];
+    zi = x[2 * N + i];
+    int nr = 0, na = 0;
+    desc_accumulate<S, MULTI>(m, b, i, ti, xi, yi, zi, Lx, Ly, Lz, q, s, nr, na);
+    desc_finish<S>(s, q);
+    if (gF) {
+      wi0 = gF[i];
+      wi1 = gF[N + i];
+      wi2 = gF[2 * N + i];
+    }
+    // radial basis sums per neighbour species
+    const int kR = radial_bound(b, i);
+    for (int p = 0; p < kR; ++p) {
+      const int32_t j = b.nbr[(int64_t)p * N + i];
+      float dx, dy, dz;
+      if (!pair_inside(x, N, j, xi, yi, zi, Lx, Ly, Lz, rcR2, dx, dy, dz)) continue;
+      const float r = sqrtf(dx * dx + dy * dy + dz * dz);
+      const float rinv = 1.f / r;
+      const int tj = MULTI ? b.type[j] : 0;
+      float f[KR], e[KR];
+      radial_basis<KR>(r, rcR_inv, f);
+      float uw = 0.f;
+      if (gF) {
+        radial_basis_deriv<KR>(r, rcR_inv, e);
+        uw = ((gF[j] - wi0) * dx + (gF[N + j] - wi1) * dy + (gF[2 * N + j] - wi2) * dz) * rinv;
+      } else {
+#pragma unroll
+        for (int k = 0; k < KR; ++k) e[k] = 0.f;
+      }
+#pragma unroll
+      for (int t = 0; t < TT; ++t) {
+        const bool on = !MULTI || tj == t;
+#pragma unroll
+        for (int k = 0; k < KR; ++k) {
+          Fk[t][k] += on ? f[k] : 0.f;
+          Ek[t][k] = fmaf(on ? e[k] : 0.f, uw, Ek[t][k]);
+        }
+      }
+    }
+    if (gF) {
+      // radial JVP v_n = sum_t sum_k c^{t_i t}_{nk} E_k
+#pragma unroll
+      for (int t = 0; t < TT; ++t) {
+        if (t >= T) break;
+        const float* c = m.cR + (ti * T + t) * NR * KR;
+#pragma unroll
+        for (int n = 0; n < NR; ++n)
+#pragma unroll
+          for (int k = 0; k < KR; ++k) v[n] = fmaf(c[n * KR + k], Ek[t][k], v[n]);
+      }
+      // angular JVP sd_nlm = sum_j [g_n' (u.w) P_lm + g_n (grad P_lm . w - l P_lm (u.w)) / r]
+      const int kA = angular_bound(b, i);
+      for (int p = 0; p < kA; ++p) {
+        const int32_t j = b.nbr[(int64_t)p * N + i];
+        float dx, dy, dz;
+        if (!pair_inside(x, N, j, xi, yi, zi, Lx, Ly, Lz, rcA2, dx, dy, dz)) continue;
+        const float r = sqrtf(dx * dx + dy * dy + dz * dz);
+        const float rinv = 1.f / r;
+        const int tj = MULTI ? b.type[j] : 0;
+        float g[NA], dg[NA];
+        radial_g_dg<NA, KA>(r, rcA_inv, m.cA + (ti * m.T + tj) * NA * KA, g, dg);
+        const float w0 = gF[j] - wi0, w1 = gF[N + j] - wi1, w2 = gF[2 * N + j] - wi2;
+        const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
+        const float uw = ux * w0 + uy * w1 + uz * w2;
+        for_each_poly_grad<NC>(ux, uy, uz, [&](int lm, float P, float px, float py, float pz) {
+          const float a = uw * P;
+          const float bb = (px * w0 + py * w1 + pz * w2 - (float)comp_l(lm) * P * uw) * rinv;
+#pragma unroll
+          for (int n = 0; n < NA; ++n) sd[n * NC + lm] = fmaf(dg[n], a, fmaf(g[n], bb, sd[n * NC + lm]));
+        });
+      }
+#pragma unroll
+      for (int n = 0; n < NA; ++n)
+#pragma unroll
+        for (int lm = 0; lm < NC; ++lm) {
+          const int k = NR + (comp_l(lm) - 1) * NA + n;
+          v[k] = fmaf(2.f * kW[lm] * s[n * NC + lm], sd[n * NC + lm], v[k]);
+        }
+      if constexpr (S::FB) {
+#pragma unroll
+        for (int n = 0; n < NA; ++n) {
+          float d4[5];
+          fourbody_ds(s + n * NC, d4);
+#pragma unroll
+          for (int c = 0; c < 5; ++c) v[NR + S::L3 * NA + n] = fmaf(d4[c], sd[n * NC + 3 + c], v[NR + S::L3 * NA + n]);
+        }
+      }
+    }
+  }
+  // network: rho = sigma W0^T alpha, Fp = sigma W0^T beta
+  float al[H], be[H];
+  const float gEf = (float)gE;
+#pragma unroll
+  for (int mu = 0; mu < H; ++mu) {
+    float h = -m.b0[mu], z = 0.f;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      h = fmaf(m.W0[mu * D + k], q[k] * m.sigma[k], h);
+      z = fmaf(m.W0[mu * D + k], v[k] * m.sigma[k], z);
+    }
+    const float t = tanhf(h);
+    const float d = 1.f - t * t;
+    be[mu] = m.w1[mu] * d;
+    al[mu] = fmaf(gEf, be[mu], 2.f * z * m.w1[mu] * t * d);
+  }
+  float rho[D], fp[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    float sa = 0.f, sb = 0.f;
+#pragma unroll
+    for (int mu = 0; mu < H; ++mu) {
+      sa = fmaf(m.W0[mu * D + k], al[mu], sa);
+      sb = fmaf(m.W0[mu * D + k], be[mu], sb);
+    }
+    rho[k] = m.sigma[k] * sa;
+    fp[k] = m.sigma[k] * sb;
+    wave_add_lds(valid ? q[k] * sa - v[k] * sb : 0.f, red + oS + k);
+  }
+  // radial coefficients
+#pragma unroll
+  for (int t = 0; t < TT; ++t) {
+    if (t >= T) break;
+#pragma unroll
+    for (int n = 0; n < NR; ++n)
+#pragma unroll
+      for (int k = 0; k < KR; ++k)
+        wave_add_by_type<MULTI>(valid ? rho[n] * Fk[t][k] - fp[n] * Ek[t][k] : 0.f, ti, T,
+                                red + (t * NR + n) * KR + k, T * NR * KR);
+  }
+  // angular coefficients A (in place of s) and C (in place of sd)
+  if constexpr (S::FB) {
+#pragma unroll
+    for (int n = 0; n < NA; ++n) {
+      float d4[5], h4[5];
+      fourbody_ds(s + n * NC, d4);
+      fourbody_ds_dir(s + n * NC, sd + n * NC, h4);
+      const int k4 = NR + S::L3 * NA + n;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        const int lm = 3 + c;
+        const int k = NR + NA + n;  // l = 2
+        const float a = 2.f * kW[lm] * fp[k] * s[n * NC + lm] + fp[k4] * d4[c];
+        const float cc = 2.f * kW[lm] * (rho[k] * s[n * NC + lm] - fp[k] * sd[n * NC + lm]) + rho[k4] * d4[c] -
+                         fp[k4] * h4[c];
+        s[n * NC + lm] = a;
+        sd[n * NC + lm] = cc;
+      }
+    }
+  }
+#pragma unroll
+  for (int n = 0; n < NA; ++n)
+#pragma unroll
+    for (int lm = 0; lm < NC; ++lm) {
+      if (S::FB && comp_l(lm) == 2) continue;
+      const int k = NR + (comp_l(lm) - 1) * NA + n;
+      const float a = 2.f * kW[lm] * fp[k] * s[n * NC + lm];
+      const float cc = 2.f * kW[lm] * (rho[k] * s[n * NC + lm] - fp[k] * sd[n * NC + lm]);
+      s[n * NC + lm] = a;
+      sd[n * NC + lm] = cc;
+    }
+  for (int t = 0; t < TT; ++t) {
+    if (t >= T) break;
+    float acc[NA * KA];
+#pragma unroll
+    for (int k = 0; k < NA * KA; ++k) acc[k] = 0.f;
+    if (valid) {
+      const int kA = angular_bound(b, i);
+      for (int p = 0; p < kA; ++p) {
+        const int32_t j = b.nbr[(int64_t)p * N + i];
+        float dx, dy, dz;
+        if (!pair_inside(x, N, j, xi, yi, zi, Lx, Ly, Lz, rcA2, dx, dy, dz)) continue;
+        if (MULTI && b.type[j] != t) continue;
+        const float r = sqrtf(dx * dx + dy * dy + dz * dz);
+        const float rinv = 1.f / r;
+        const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
+        float w0 = 0.f, w1 = 0.f, w2 = 0.f;
+        if (gF) {
+          w0 = gF[j] - wi0;
+          w1 = gF[N + j] - wi1;
+          w2 = gF[2 * N + j] - wi2;
+        }
+        const float uw = ux * w0 + uy * w1 + uz * w2;
+        float X[NA], Y[NA], Z[NA];
+#pragma unroll
+        for (int n = 0; n < NA; ++n) X[n] = Y[n] = Z[n] = 0.f;
+        for_each_poly_grad<NC>(ux, uy, uz, [&](int lm, float P, float px, float py, float pz) {
+          const float bb = (px * w0 + py * w1 + pz * w2 - (float)comp_l(lm) * P * uw) * rinv;
+#pragma unroll
+          for (int n = 0; n < NA; ++n) {
+            X[n] = fmaf(sd[n * NC + lm], P, X[n]);
+            Y[n] = fmaf(s[n * NC + lm], P, Y[n]);
+            Z[n] = fmaf(s[n * NC + lm], bb, Z[n]);
+          }
+        });
+        float f[KA], e[KA];
+        radial_basis<KA>(r, rcA_inv, f);
+        radial_basis_deriv<KA>(r, rcA_inv, e);
+#pragma unroll
+        for (int n = 0; n < NA; ++n) {
+          const float xz = X[n] - Z[n], yu = Y[n] * uw;
+#pragma unroll
+          for (int k = 0; k < KA; ++k) acc[n * KA + k] = fmaf(f[k], xz, fmaf(-e[k], yu, acc[n * KA + k]));
+        }
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < NA; ++n)
+#pragma unroll
+      for (int k = 0; k < KA; ++k)
+        wave_add_by_type<MULTI>(valid ? acc[n * KA + k] : 0.f, ti, T, red + oA + (t * NA + n) * KA + k,
+                                T * NA * KA);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nred; e += kBlock) gpart[(int64_t)tile * kGradStride + e] = (double)red[e];
+}
+
+// grad[e] for e < n (the [cR | cA | sigma] block) = sum over workgroups (FP64).
+__global__ void k_cgrad_reduce(const double* __restrict__ gpart, int nblocks, int n, float* __restrict__ grad,
+                               int accumulate) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  double sum = 0.0;
+  for (int blk = 0; blk < nblocks; ++blk) sum += gpart[(int64_t)blk * kGradStride + e];
+  grad[e] = accumulate ? (float)((double)grad[e] + sum) : (float)sum;
+}
+
 // grad[theta] = sum over workgroups (FP64), in theta's packed order.
 __global__ void k_grad_reduce(const double* __restrict__ gpart, int nblocks, int H, int D, double gE, int64_t N,
                               float* __restrict__ grad, int accumulate) {
@@ -256,6 +553,33 @@ hipError_t launch_backward_shape(const ModelDev& m, const TrainBuffers& t, hipSt
   return hipGetLastError();
 }
 
+template <class S>
+hipError_t launch_cgrad_shape(const ModelDev& m, const TrainBuffers& t, hipStream_t st) {
+  const int nb = grid_blocks(t.e.N);
+  if (m.T > 1)
+    hipLaunchKernelGGL((k_train_cgrad<S, true>), dim3(nb), dim3(kBlock), 0, st, m, t.e, t.gF, t.gE, t.gpart);
+  else
+    hipLaunchKernelGGL((k_train_cgrad<S, false>), dim3(nb), dim3(kBlock), 0, st, m, t.e, t.gF, t.gE, t.gpart);
+  const int n = m.T * m.T * (m.nR * m.kR + m.nA * m.kA) + m.D;
+  hipLaunchKernelGGL(k_cgrad_reduce, dim3(grid_blocks(n)), dim3(kBlock), 0, st, t.gpart, nb, n, t.grad,
+                     t.accumulate);
+  return hipGetLastError();
+}
+
+// The model with every parameter read from a packed FP32 vector
+// [cR | cA | sigma | W0 | b0 | w1 | b1].
+ModelDev with_params(const ModelDev& m, const float* p) {
+  ModelDev mp = m;
+  mp.cR = p;
+  mp.cA = mp.cR + m.T * m.T * m.nR * m.kR;
+  mp.sigma = mp.cA + m.T * m.T * m.nA * m.kA;
+  mp.W0 = mp.sigma + m.D;
+  mp.b0 = mp.W0 + m.H * m.D;
+  mp.w1 = mp.b0 + m.H;
+  mp.b1 = mp.w1 + m.H;
+  return mp;
+}
+
 ModelDev with_theta(const ModelDev& m, const float* theta) {
   ModelDev mt = m;
   const int G = m.H * m.D;
@@ -282,6 +606,31 @@ int train_grad_stride() { return kGradStride; }
 
 hipError_t launch_train_forward(const ModelDev& m, const float* theta, const EvalBuffers& b, hipStream_t st) {
   return launch_eval(with_theta(m, theta), 0, b, st);
+}
+
+int param_block_offset(const ModelDev& m) {
+  return m.T * m.T * (m.nR * m.kR + m.nA * m.kA) + m.D;
+}
+
+hipError_t launch_train_forward_params(const ModelDev& m, const float* params, const EvalBuffers& b,
+                                       hipStream_t st) {
+  return launch_eval(with_params(m, params), 0, b, st);
+}
+
+hipError_t launch_train_backward_params(const ModelDev& m, const TrainBuffers& t, hipStream_t st) {
+  const ModelDev mp = with_params(m, t.theta);
+  TrainBuffers tn = t;
+  tn.grad = t.grad + param_block_offset(m);
+  hipError_t e;
+  if (is_shape<FullShape>(mp)) {
+    if ((e = launch_backward_shape<FullShape>(mp, tn, st)) != hipSuccess) return e;
+    return launch_cgrad_shape<FullShape>(mp, t, st);
+  }
+  if (is_shape<SurShape>(mp)) {
+    if ((e = launch_backward_shape<SurShape>(mp, tn, st)) != hipSuccess) return e;
+    return launch_cgrad_shape<SurShape>(mp, t, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_train_backward(const ModelDev& m, const TrainBuffers& t, hipStream_t st) {

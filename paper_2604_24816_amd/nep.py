@@ -27,7 +27,8 @@ EXPORTED = [
     "nep_param_count", "nep_model_create", "nep_model_destroy", "nep_system_workspace_bytes",
     "nep_system_create", "nep_system_destroy", "nep_system_set_params", "nep_set_state",
     "nep_build_neighbors", "nep_export_neighbors", "nep_compute_energy_forces_virial", "nep_step",
-    "nep_get_state", "nep_get_stats", "nep_train_forward", "nep_train_backward", "nep_adam_update",
+    "nep_get_state", "nep_get_stats", "nep_train_forward", "nep_train_backward", "nep_train_forward_params",
+    "nep_train_backward_params", "nep_adam_update",
     "nep_surrogate_error", "nep_status_string", "nep_last_error", "nep_profile", "nep_profile_read",
     "nep_pair_counts",
 ]
@@ -74,6 +75,8 @@ def load_library(path: str = LIB_PATH):
         "nep_get_stats": [vp, vp],
         "nep_train_forward": [vp, i32, vp, vp, vp],
         "nep_train_backward": [vp, i32, vp, f64, vp, vp, i32],
+        "nep_train_forward_params": [vp, i32, vp, vp, vp],
+        "nep_train_backward_params": [vp, i32, vp, f64, vp, vp, i32],
         "nep_adam_update": [vp, vp, vp, vp, vp, i64, i64, f64, f64, f64, f64],
         "nep_surrogate_error": [vp, i32, vp],
         "nep_profile": [vp, i32],
@@ -292,23 +295,44 @@ class NEPSystem:
     # ------------------------------------------------------------------ training
     def train_forward(self, slot: int, theta: torch.Tensor):
         """(E float, F torch [N][3] float32) with network parameters theta (device FP32)."""
-        self.generation += 1
-        theta = theta.detach().to(self.device, torch.float32).contiguous()
-        F = torch.empty((self.n, 3), dtype=torch.float32, device=self.device)
-        E = ctypes.c_double()
-        self._check(self.lib.nep_train_forward(self.handle, slot, _t_ptr(theta), ctypes.byref(E), _t_ptr(F)))
-        return E.value, F
+        return self._train_forward(self.lib.nep_train_forward, slot, theta, False)
 
     def train_backward(self, slot: int, theta: torch.Tensor, gE: float, gF: Optional[torch.Tensor],
                        out: Optional[torch.Tensor] = None):
         """dL/dtheta for L = gE*E + sum gF.F (FP32, device); adds into ``out`` when given."""
-        theta = theta.detach().to(self.device, torch.float32).contiguous()
+        return self._train_backward(self.lib.nep_train_backward, slot, theta, gE, gF, out, False)
+
+    def train_forward_params(self, slot: int, params: torch.Tensor):
+        """As train_forward with every parameter (packed [cR | cA | sigma | W0 | b0 | w1 | b1])."""
+        return self._train_forward(self.lib.nep_train_forward_params, slot, params, True)
+
+    def train_backward_params(self, slot: int, params: torch.Tensor, gE: float, gF: Optional[torch.Tensor],
+                              out: Optional[torch.Tensor] = None):
+        """dL/dparams in the packed order, including the expansion coefficients and the scaler."""
+        return self._train_backward(self.lib.nep_train_backward_params, slot, params, gE, gF, out, True)
+
+    def _expect(self, slot, theta, all_params):
+        hp = (self.full if slot == 0 else self.surrogate).hp
+        n = hp.n_params() if all_params else hp.n_hidden * hp.n_desc + 2 * hp.n_hidden + 1
+        if theta.numel() != n:
+            raise ValueError(f"parameter vector has {theta.numel()} values, the model in slot {slot} takes {n}")
+        return theta.detach().to(self.device, torch.float32).contiguous()
+
+    def _train_forward(self, fn, slot, theta, all_params):
+        self.generation += 1
+        theta = self._expect(slot, theta, all_params)
+        F = torch.empty((self.n, 3), dtype=torch.float32, device=self.device)
+        E = ctypes.c_double()
+        self._check(fn(self.handle, slot, _t_ptr(theta), ctypes.byref(E), _t_ptr(F)))
+        return E.value, F
+
+    def _train_backward(self, fn, slot, theta, gE, gF, out, all_params):
+        theta = self._expect(slot, theta, all_params)
         acc = out is not None
         grad = out if acc else torch.empty_like(theta)
         gFc = None if gF is None else gF.detach().to(self.device, torch.float32).contiguous()
-        self._check(self.lib.nep_train_backward(self.handle, slot, _t_ptr(theta), float(gE),
-                                                _t_ptr(gFc) if gFc is not None else None, _t_ptr(grad),
-                                                1 if acc else 0))
+        self._check(fn(self.handle, slot, _t_ptr(theta), float(gE), _t_ptr(gFc) if gFc is not None else None,
+                       _t_ptr(grad), 1 if acc else 0))
         return grad
 
     def adam(self, theta: torch.Tensor, grad: torch.Tensor, m1: torch.Tensor, m2: torch.Tensor, t: int,

@@ -2,11 +2,13 @@
 library's own forward/backward kernels and Adam, and the multiple-time-step driver.
 
 The surrogate has 8 hidden units, n_max 4, l_max 2 and no four-body term; its
-descriptor coefficients are copied from the full model and frozen, so only the
-network (8 x 15 + 8 + 8 + 1 = 137 parameters) is trained, on energy and force MSE
-against the full model's labels. Every arithmetic step of training runs in the
-library's kernels (descriptors, network, forces, weight gradients, Adam); torch only
-holds the arrays and forms the loss residuals.
+descriptor coefficients start as a copy of the full model's. By default they stay
+frozen and only the network (8 x 15 + 8 + 8 + 1 = 137 parameters) is trained, on
+energy and force MSE against the full model's labels; with ``train_coeffs`` the 90
+radial and angular expansion coefficients are trained as well, as the paper's
+description of c as trainable allows. Every arithmetic step of training runs in the
+library's kernels (descriptors, network, forces, parameter gradients, Adam); torch
+only holds the arrays and forms the loss residuals.
 """
 from __future__ import annotations
 
@@ -81,14 +83,17 @@ def _with_network(hp: I.HParams, params: np.ndarray, theta: np.ndarray) -> np.nd
     return p
 
 
-def evaluate_frames(system: NEPSystem, frames: Frames, idx, theta: torch.Tensor, skin: float = 1.0):
-    """(force RMSE eV/A, energy MAE eV/atom) of model theta (slot 0) against the labels."""
+def evaluate_frames(system: NEPSystem, frames: Frames, idx, theta: torch.Tensor, skin: float = 1.0,
+                    all_params: bool = False):
+    """(force RMSE eV/A, energy MAE eV/atom) of model theta (slot 0) against the labels;
+    theta holds the network block, or every parameter when ``all_params``."""
     se, ae, cnt = 0.0, 0.0, 0
     n = frames.x.shape[1]
+    fwd = system.train_forward_params if all_params else system.train_forward
     for f in idx:
         system.set_state(frames.x[f], frames.types, frames.masses)
         system.build_neighbors(skin)
-        E, F = system.train_forward(0, theta)
+        E, F = fwd(0, theta)
         d = (F - frames.F[f]).double()
         se += float((d * d).sum())
         ae += abs(E - frames.E[f]) / n
@@ -99,8 +104,12 @@ def evaluate_frames(system: NEPSystem, frames: Frames, idx, theta: torch.Tensor,
 def train_surrogate(frames: Frames, sur_hp: I.HParams, sur_params: np.ndarray, epochs: int = 10,
                     batch: int = 8, lr: float = 1e-3, lam_e: float = 1.0, lam_f: float = 1.0,
                     val_fraction: float = 0.1, seed: int = 0, skin: float = 1.0,
-                    cap_radial: int = 256, cap_angular: int = 160, log=None) -> TrainResult:
-    """Adam on energy + force MSE, mini-batches of `batch` frames, on the GPU."""
+                    cap_radial: int = 256, cap_angular: int = 160, train_coeffs: bool = False,
+                    log=None) -> TrainResult:
+    """Adam on energy + force MSE, mini-batches of `batch` frames, on the GPU.
+
+    The network block is trained; with ``train_coeffs`` the radial and angular expansion
+    coefficients c are trained too (the descriptor scaler stays fixed)."""
     t0 = time.perf_counter()
     nf, n = frames.x.shape[0], frames.x.shape[1]
     rng = np.random.default_rng(seed)
@@ -108,11 +117,18 @@ def train_surrogate(frames: Frames, sur_hp: I.HParams, sur_params: np.ndarray, e
     nval = max(1, int(round(val_fraction * nf)))
     val, tr = order[:nval], order[nval:]
     s = NEPSystem(NEPModel(sur_hp, sur_params), n, frames.box, cap_radial=cap_radial, cap_angular=cap_angular)
-    theta = torch.tensor(network_params(sur_hp, sur_params), dtype=torch.float32, device=s.device)
+    if train_coeffs:
+        theta = torch.tensor(sur_params, dtype=torch.float32, device=s.device)
+        fwd, bwd = s.train_forward_params, s.train_backward_params
+        frozen = slice(*sur_hp.offsets()["sigma"])
+    else:
+        theta = torch.tensor(network_params(sur_hp, sur_params), dtype=torch.float32, device=s.device)
+        fwd, bwd = s.train_forward, s.train_backward
+        frozen = None
     m1 = torch.zeros_like(theta)
     m2 = torch.zeros_like(theta)
     grad = torch.zeros_like(theta)
-    rmse0, mae0 = evaluate_frames(s, frames, val, theta, skin)
+    rmse0, mae0 = evaluate_frames(s, frames, val, theta, skin, train_coeffs)
     history, step = [], 0
     for ep in range(epochs):
         perm = rng.permutation(tr)
@@ -122,20 +138,26 @@ def train_surrogate(frames: Frames, sur_hp: I.HParams, sur_params: np.ndarray, e
             for f in perm[b0:b0 + batch]:
                 s.set_state(frames.x[f], frames.types, frames.masses)
                 s.build_neighbors(skin)
-                E, F = s.train_forward(0, theta)
+                E, F = fwd(0, theta)
                 de = (E - frames.E[f]) / n
                 dF = F - frames.F[f]
                 tot += lam_e * de * de + lam_f * float((dF.double() ** 2).sum()) / (3 * n)
                 gE = 2.0 * lam_e * de / n / batch
                 gF = (2.0 * lam_f / (3 * n * batch)) * dF
-                s.train_backward(0, theta, gE, gF, out=grad)
+                bwd(0, theta, gE, gF, out=grad)
+            if frozen is not None:
+                grad[frozen] = 0.0   # Adam then leaves these entries unchanged
             step += 1
             s.adam(theta, grad, m1, m2, step, lr=lr)
         history.append(tot / max(1, (len(perm) // batch) * batch))
         if log:
             log(f"epoch {ep}: loss {history[-1]:.4e}")
-    rmse, mae = evaluate_frames(s, frames, val, theta, skin)
-    params = _with_network(sur_hp, sur_params, theta.double().cpu().numpy())
+    rmse, mae = evaluate_frames(s, frames, val, theta, skin, train_coeffs)
+    if train_coeffs:
+        params = theta.double().cpu().numpy()
+        params[frozen] = sur_params[frozen]
+    else:
+        params = _with_network(sur_hp, sur_params, theta.double().cpu().numpy())
     s.close()
     return TrainResult(params, history, rmse0, rmse, mae0, mae, time.perf_counter() - t0)
 

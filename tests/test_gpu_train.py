@@ -69,6 +69,48 @@ def test_weight_gradient_matches_oracle(kind):
     assert np.allclose(acc.cpu().numpy(), 2 * g0, rtol=1e-6, atol=1e-6)
 
 
+@pytest.mark.parametrize("kind", ["full", "two_species", "surrogate"])
+def test_param_gradient_matches_oracle(kind):
+    """Gradient with respect to every parameter (expansion coefficients per species pair,
+    scaler, network) against the oracle's, block by block; the forward with the packed
+    vector equals the network-only forward."""
+    if kind == "surrogate":
+        thp = I.FULL_HPARAMS
+        hp = I.SURROGATE_HPARAMS
+        params = I.surrogate_from_teacher(thp, I.random_model(thp, 0), hp, 3)
+    elif kind == "two_species":
+        hp = I.HParams(n_types=2)
+        params = I.random_model(hp, 8)
+    else:
+        hp = I.FULL_HPARAMS
+        params = I.random_model(hp, 6)
+    at = I.alloy_box(6, 1, 30, 2, 0.17, 3) if kind == "two_species" else I.fcc_box(6, 0.17, 40)
+    say(f"case: gradient of every parameter, {kind}, N={at.n}")
+    s = make_system(at, hp, params)
+    pt = torch.tensor(params, dtype=torch.float32, device="cuda")
+    E1, F1 = s.train_forward_params(0, pt)
+    E0, F0 = s.train_forward(0, _nn(hp, params))
+    # same FP32 values; the forces may differ in rounding where LDS atomics reorder sums
+    assert abs(E1 - E0) <= 1e-9 * abs(E0) and float((F1 - F0).abs().max()) < 1e-5
+    rng = np.random.default_rng(5)
+    gF = rng.normal(size=(at.n, 3))
+    gE = 0.7
+    m = oracle.Model.from_hparams(hp, params)
+    o = hp.offsets()
+    for with_f in (True, False):
+        gFt = torch.tensor(gF, dtype=torch.float32, device="cuda") if with_f else None
+        g = s.train_backward_params(0, pt, gE, gFt).cpu().numpy()
+        ref = oracle.param_grad(m, at.x, at.types, at.box, gE, gF if with_f else None)
+        for name in ("cR", "cA", "sigma"):
+            a, b = o[name]
+            _compare(g[a:b], ref[a:b], f"{name} ({'energy+force' if with_f else 'energy'})")
+        a = o["W0"][0]
+        _compare(g[a:], ref[a:], f"network ({'energy+force' if with_f else 'energy'})")
+    acc = torch.tensor(g, device="cuda")
+    s.train_backward_params(0, pt, gE, None, out=acc)
+    assert np.allclose(acc.cpu().numpy(), 2 * g, rtol=1e-6, atol=1e-6)
+
+
 def test_autograd_function_energy_force_loss_16_frames():
     """Loss of energy + force MSE over 16 thermally disordered 32,000-atom frames."""
     from paper_2604_24816_amd import autograd as AG
