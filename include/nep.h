@@ -159,6 +159,13 @@ int nep_step(nep_system* s, int64_t n_steps, double dt_fs, int32_t rebuild_every
              int32_t mts_k, double fallback_rms, double fallback_max, int32_t precision,
              double* thermo, int32_t thermo_every, int64_t max_rows, int64_t* rows_written);
 
+/* How nep_step's MTS judge reads fallback_rms and fallback_max: relative = 0
+ * (the default) takes them in eV/A; relative = 1 takes them as multiples of
+ * the per-component rms of the full model's forces at the end of the block
+ * being judged, so the test follows the force scale as the system heats or
+ * disorders. It changes only the fallback decision. */
+int nep_set_judge(nep_system* s, int32_t relative);
+
 /* Positions and velocities [N][3] in original order, and the step counter. */
 int nep_get_state(nep_system* s, double* x, double* v, int64_t* step, int32_t on_device);
 

@@ -105,6 +105,7 @@ struct nep_system {
   int force_prec[2] = {0, 0};
   int64_t step = 0;
   int64_t n_mts_blocks = 0, n_fallback_blocks = 0, n_steps_total = 0;
+  int judge_relative = 0;  // nep_set_judge
   std::string err;
   // device buffers (inside the caller's workspace)
   double *x, *v, *x_alt, *v_alt, *x_build;
@@ -724,15 +725,19 @@ int vv_step(nep_system* s, int slot, int prec, double dt, int rebuild_every, dou
   return NEP_OK;
 }
 
-int force_error(nep_system* s, double* rms, double* mx) {
+// Surrogate force error against the full model: rms per component and max
+// |F_full - F_surrogate| over atoms; frms (nullable) = rms per component of F_full.
+int force_error(nep_system* s, double* rms, double* mx, double* frms = nullptr) {
   HIPCHK(launch_force_error(s->N, s->F[0], s->F[1], s->partial, s->st));
   HIPCHK(launch_reduce_partials(s->partial, s->nblocks, P_ERR2, 1, s->res + 12, s->st));
   HIPCHK(launch_max_partials(s->partial, s->nblocks, P_ERRMAX, s->res + 13, s->st));
-  double r[2];
-  HIPCHK(hipMemcpyAsync(r, s->res + 12, 2 * sizeof(double), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(launch_reduce_partials(s->partial, s->nblocks, P_F2, 1, s->res + 14, s->st));
+  double r[3];
+  HIPCHK(hipMemcpyAsync(r, s->res + 12, 3 * sizeof(double), hipMemcpyDeviceToHost, s->st));
   HIPCHK(hipStreamSynchronize(s->st));
   *rms = std::sqrt(r[0] / (3.0 * s->N));
   *mx = r[1];
+  if (frms) *frms = std::sqrt(r[2] / (3.0 * s->N));
   return NEP_OK;
 }
 
@@ -780,18 +785,23 @@ int nep_step(nep_system* s, int64_t n_steps, double dt_fs, int32_t rebuild_every
     const double big = mts_k * dt_fs;
     const int64_t nblk = n_steps / mts_k;
     int fallback = 0, clean = 0;
+    // thresholds: absolute (eV/A), or multiples of the block's own rms full-model force
+    auto over = [&](double rms, double mx, double frms) {
+      const double scale = s->judge_relative ? frms : 1.0;
+      return rms > fallback_rms * scale || mx > fallback_max * scale;
+    };
     for (int64_t b = 0; b < nblk; ++b) {
-      double rms = 0, mx = 0;
+      double rms = 0, mx = 0, frms = 0;
       if (!fallback) {
         HIPCHK(launch_kick_diff(s->N, 0.5 * big, s->F[0], s->F[1], s->type, s->mt, s->v, s->st));
         for (int k = 0; k < mts_k; ++k)
           if ((st = vv_step(s, 1, precision, dt_fs, rebuild_every, skin))) return st;
         if ((st = do_eval(s, 0, precision))) return st;
         if ((st = reduce_ew(s, 0))) return st;
-        if ((st = force_error(s, &rms, &mx))) return st;
+        if ((st = force_error(s, &rms, &mx, &frms))) return st;
         HIPCHK(launch_kick_diff(s->N, 0.5 * big, s->F[0], s->F[1], s->type, s->mt, s->v, s->st));
         s->n_mts_blocks++;
-        if (rms > fallback_rms || mx > fallback_max) {
+        if (over(rms, mx, frms)) {
           fallback = 1;
           clean = 0;
         }
@@ -800,9 +810,9 @@ int nep_step(nep_system* s, int64_t n_steps, double dt_fs, int32_t rebuild_every
           if ((st = vv_step(s, 0, precision, dt_fs, rebuild_every, skin))) return st;
         if ((st = reduce_ew(s, 0))) return st;
         if ((st = do_eval(s, 1, precision))) return st;  // shadow surrogate evaluation
-        if ((st = force_error(s, &rms, &mx))) return st;
+        if ((st = force_error(s, &rms, &mx, &frms))) return st;
         s->n_fallback_blocks++;
-        if (rms <= fallback_rms && mx <= fallback_max) {
+        if (!over(rms, mx, frms)) {
           if (++clean >= 10) fallback = 0;
         } else {
           clean = 0;
@@ -817,6 +827,12 @@ int nep_step(nep_system* s, int64_t n_steps, double dt_fs, int32_t rebuild_every
   if (rows_written) *rows_written = rows;
   if ((st = check_flags(s))) return st;
   HIPCHK(hipStreamSynchronize(s->st));
+  return NEP_OK;
+}
+
+int nep_set_judge(nep_system* s, int32_t relative) {
+  if (!s || relative < 0 || relative > 1) return fail(s, NEP_ERR_ARG, "bad argument");
+  s->judge_relative = relative;
   return NEP_OK;
 }
 

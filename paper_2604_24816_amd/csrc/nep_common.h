@@ -15,7 +15,7 @@ constexpr int kNumXcd = 8;           // MI355X: 8 accelerator complex dies, one 
 constexpr int kPartialStride = 16;   // doubles per workgroup in reduction partials
 
 // Energy/virial partial slots.
-enum { P_ENERGY = 0, P_VIR = 1 /* 9 values */, P_KE = 10, P_ERR2 = 11, P_ERRMAX = 12, P_MAXD2 = 13 };
+enum { P_ENERGY = 0, P_VIR = 1 /* 9 values */, P_KE = 10, P_ERR2 = 11, P_ERRMAX = 12, P_MAXD2 = 13, P_F2 = 14 };
 
 // Device flag words (int32).
 enum {

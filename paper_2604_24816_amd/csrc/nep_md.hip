@@ -146,14 +146,17 @@ __global__ void k_force_error(int64_t N, const float* __restrict__ Fa, const flo
                               double* __restrict__ partial) {
   __shared__ double sh[kBlock];
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double e2 = 0.0;
+  double e2 = 0.0, f2 = 0.0;
   if (p < N) {
     for (int c = 0; c < 3; ++c) {
-      const double d = (double)Fa[c * N + p] - (double)Fb[c * N + p];
+      const double a = (double)Fa[c * N + p];
+      const double d = a - (double)Fb[c * N + p];
       e2 += d * d;
+      f2 += a * a;
     }
   }
   block_partial(e2, sh, partial + (int64_t)blockIdx.x * kPartialStride + P_ERR2);
+  block_partial(f2, sh, partial + (int64_t)blockIdx.x * kPartialStride + P_F2);
   // maximum |e| over the block
   __syncthreads();
   sh[threadIdx.x] = sqrt(e2);

@@ -27,8 +27,8 @@ EXPORTED = [
     "nep_param_count", "nep_model_create", "nep_model_destroy", "nep_system_workspace_bytes",
     "nep_system_create", "nep_system_destroy", "nep_system_set_params", "nep_set_state",
     "nep_build_neighbors", "nep_export_neighbors", "nep_compute_energy_forces_virial", "nep_step",
-    "nep_get_state", "nep_get_stats", "nep_train_forward", "nep_train_backward", "nep_train_forward_params",
-    "nep_train_backward_params", "nep_adam_update",
+    "nep_set_judge", "nep_get_state", "nep_get_stats", "nep_train_forward", "nep_train_backward",
+    "nep_train_forward_params", "nep_train_backward_params", "nep_adam_update",
     "nep_surrogate_error", "nep_status_string", "nep_last_error", "nep_profile", "nep_profile_read",
     "nep_pair_counts",
 ]
@@ -72,6 +72,7 @@ def load_library(path: str = LIB_PATH):
         "nep_compute_energy_forces_virial": [vp, i32, i32, vp, vp, vp, vp, i32],
         "nep_step": [vp, i64, f64, i32, f64, i32, f64, f64, i32, vp, i32, i64, vp],
         "nep_get_state": [vp, vp, vp, vp, i32],
+        "nep_set_judge": [vp, i32],
         "nep_get_stats": [vp, vp],
         "nep_train_forward": [vp, i32, vp, vp, vp],
         "nep_train_backward": [vp, i32, vp, f64, vp, vp, i32],
@@ -253,9 +254,13 @@ class NEPSystem:
 
     def step(self, n_steps: int, dt: float = 1.0, rebuild_every: int = 10, skin: float = 1.0,
              mts_k: int = 0, fallback_rms: float = 0.05, fallback_max: float = 1.0, precision="fp32",
-             thermo_every: int = 0, max_rows: int = 4096):
-        """Advance n_steps; returns thermo rows [k][8] (step, PE, KE, T, P, err_rms, err_max, fallback)."""
+             thermo_every: int = 0, max_rows: int = 4096, relative_judge: bool = False):
+        """Advance n_steps; returns thermo rows [k][8] (step, PE, KE, T, P, err_rms, err_max, fallback).
+
+        With ``relative_judge`` the MTS fallback thresholds are multiples of each block's rms
+        full-model force instead of eV/A."""
         self.generation += 1
+        self._check(self.lib.nep_set_judge(self.handle, 1 if relative_judge else 0))
         rows = ctypes.c_int64()
         th = np.zeros((max_rows, 8)) if thermo_every > 0 else None
         self._check(self.lib.nep_step(self.handle, int(n_steps), float(dt), int(rebuild_every), float(skin),

@@ -13,6 +13,7 @@ only holds the arrays and forms the loss residuals.
 from __future__ import annotations
 
 import dataclasses
+import math
 import time
 from typing import List, Optional
 
@@ -105,11 +106,12 @@ def train_surrogate(frames: Frames, sur_hp: I.HParams, sur_params: np.ndarray, e
                     batch: int = 8, lr: float = 1e-3, lam_e: float = 1.0, lam_f: float = 1.0,
                     val_fraction: float = 0.1, seed: int = 0, skin: float = 1.0,
                     cap_radial: int = 256, cap_angular: int = 160, train_coeffs: bool = False,
-                    log=None) -> TrainResult:
+                    lr_end: Optional[float] = None, log=None) -> TrainResult:
     """Adam on energy + force MSE, mini-batches of `batch` frames, on the GPU.
 
     The network block is trained; with ``train_coeffs`` the radial and angular expansion
-    coefficients c are trained too (the descriptor scaler stays fixed)."""
+    coefficients c are trained too (the descriptor scaler stays fixed). With ``lr_end`` the
+    step size follows a cosine from ``lr`` down to ``lr_end`` over all steps."""
     t0 = time.perf_counter()
     nf, n = frames.x.shape[0], frames.x.shape[1]
     rng = np.random.default_rng(seed)
@@ -130,6 +132,7 @@ def train_surrogate(frames: Frames, sur_hp: I.HParams, sur_params: np.ndarray, e
     grad = torch.zeros_like(theta)
     rmse0, mae0 = evaluate_frames(s, frames, val, theta, skin, train_coeffs)
     history, step = [], 0
+    total = epochs * max(1, len(tr) // batch)
     for ep in range(epochs):
         perm = rng.permutation(tr)
         tot = 0.0
@@ -147,8 +150,9 @@ def train_surrogate(frames: Frames, sur_hp: I.HParams, sur_params: np.ndarray, e
                 bwd(0, theta, gE, gF, out=grad)
             if frozen is not None:
                 grad[frozen] = 0.0   # Adam then leaves these entries unchanged
+            lr_t = lr if lr_end is None else lr_end + 0.5 * (lr - lr_end) * (1.0 + math.cos(math.pi * step / total))
             step += 1
-            s.adam(theta, grad, m1, m2, step, lr=lr)
+            s.adam(theta, grad, m1, m2, step, lr=lr_t)
         history.append(tot / max(1, (len(perm) // batch) * batch))
         if log:
             log(f"epoch {ep}: loss {history[-1]:.4e}")

@@ -70,6 +70,23 @@ def test_mts_fallback_engages(models):
     assert np.abs(min_image_diff(x, xo, at.box)).max() < 1e-6
 
 
+def test_relative_judge_follows_the_full_force_scale(models):
+    """With a zero-force surrogate the block's rms error equals the rms full-model force
+    exactly, so a relative threshold just below 1 falls back at the first block and one
+    just above 1 never does."""
+    hp, teacher, shp, sur = models
+    zero = sur.copy()
+    zero[shp.offsets()["W0"][0]:] = 0.0
+    at = I.workload_small()
+    for frac, mts, fb in ((0.999, 1, 2), (1.001, 3, 0)):
+        say(f"case: relative judge {frac} x rms(F_full), zero-force surrogate")
+        s = make_system(at, hp, teacher, shp, zero)
+        th = s.step(12, mts_k=4, fallback_rms=frac, fallback_max=1e9, thermo_every=4, relative_judge=True)
+        st = s.stats()
+        assert st["mts_blocks"] == mts and st["fallback_blocks"] == fb, (frac, st)
+        assert th[0, 7] == (1 if fb else 0)
+
+
 def test_surrogate_training_and_gain(models):
     """Trained surrogate against the untrained one: lower force error against the full model,
     and an MTS run whose judge accepts the trained surrogate but falls back for the untrained."""
@@ -94,3 +111,23 @@ def test_surrogate_training_and_gain(models):
         say(f"  {name}: mean block rms error {runs[name][1]:.4e} eV/A, stats {runs[name][0]}")
     assert runs["trained"][1] < runs["untrained"][1]
     assert runs["trained"][0]["fallback_blocks"] < runs["untrained"][0]["fallback_blocks"]
+
+
+def test_coefficient_training_beats_network_only(models):
+    """Training the expansion coefficients as well as the network lowers the 5 / 4 A
+    surrogate's held-out force error against the full model, at equal epochs."""
+    from paper_2604_24816_amd import surrogate as SG
+    hp, teacher, _, _ = models
+    shp = I.SURROGATE_SHORT_HPARAMS
+    sur0 = I.surrogate_from_teacher(hp, teacher, shp, 1)
+    say("case: 5/4 A surrogate, network-only against coefficient training (40 x 10 frames, 6 epochs)")
+    fr = SG.generate_frames(hp, teacher, n_traj=40, cells=10, steps=100, every=10)
+    nn = SG.train_surrogate(fr, shp, sur0, epochs=6, batch=8, lr=1e-2)
+    co = SG.train_surrogate(fr, shp, sur0, epochs=6, batch=8, lr=1e-2, train_coeffs=True)
+    say(f"  held-out force RMSE: start {nn.val_force_rmse_init:.4e}, network only {nn.val_force_rmse:.4e}, "
+        f"with coefficients {co.val_force_rmse:.4e} eV/A")
+    assert co.val_force_rmse < 0.85 * nn.val_force_rmse
+    o = shp.offsets()
+    a, b = o["sigma"]
+    assert np.array_equal(co.params[a:b], sur0[a:b])              # the scaler stays fixed
+    assert np.abs(co.params[:a] - sur0[:a]).max() > 1e-3          # the coefficients moved
