@@ -12,6 +12,8 @@
 //     (Section III.B), with Chebyshev first-kind radial bases (Section III.B)
 //     and separate radial / angular cutoffs (Fig. 1);
 //   * the four-body term with l_max = 2 (Section VI.A);
+//   * optionally, the ZBL screened-Coulomb repulsion added to the Cu and HfO2
+//     models (Section VI.A), half of each pair's energy per atom;
 //   * forces F = -dU/dx and the virial;
 //   * velocity-Verlet integration with the step, temperature and neighbour
 //     settings of Section VI.A;
@@ -47,6 +49,8 @@ enum { OK = 0, ERR_ARG = -1, ERR_BOX = -2, ERR_CAP = -3 };
 struct Model {
   int T = 0, nR = 0, kR = 0, nA = 0, kA = 0, L3 = 0, L4 = 0, H = 0, D = 0;
   double rcR = 0, rcA = 0;
+  double zi = 0, zo = 0;        // ZBL switching radii (zo = 0: no ZBL term)
+  double Z[2] = {0, 0};         // atomic number of each species (ZBL)
   const double* cR = nullptr;   // [T][T][nR][kR]
   const double* cA = nullptr;   // [T][T][nA][kA]
   const double* sigma = nullptr;  // [D]
@@ -59,7 +63,7 @@ struct Model {
 };
 
 // ip = {n_types, n_max_R, n_max_A, basis_R, basis_A, l_max_3b, l_max_4b, n_hidden}
-// dp = {rc_radial, rc_angular}
+// dp = {rc_radial, rc_angular, zbl_inner, zbl_outer, Z_0, Z_1}
 int parse_model(const int32_t* ip, const double* dp, const double* p, int64_t n_params, Model& m) {
   if (!ip || !dp || !p) return ERR_ARG;
   m.T = ip[0];
@@ -75,6 +79,15 @@ int parse_model(const int32_t* ip, const double* dp, const double* p, int64_t n_
   if (m.T < 1 || m.nR < 1 || m.nA < 1 || m.kR < 2 || m.kA < 2 || m.L3 < 1 || m.L3 > 8 ||
       !(m.L4 == 0 || m.L4 == 2) || m.H < 1 || !(m.rcR > 0) || !(m.rcA > 0) || m.rcA > m.rcR)
     return ERR_ARG;
+  m.zi = dp[2];
+  m.zo = dp[3];
+  m.Z[0] = dp[4];
+  m.Z[1] = dp[5];
+  if (m.zo != 0.0) {
+    if (!(m.zo > 0 && m.zi >= 0 && m.zi < m.zo && m.zo <= m.rcR) || m.T > 2) return ERR_ARG;
+    for (int t = 0; t < m.T; ++t)
+      if (!(m.Z[t] > 0)) return ERR_ARG;
+  }
   m.D = m.nR + m.nA * m.L3 + (m.L4 == 2 ? m.nA : 0);
   int64_t off = 0;
   m.cR = p + off; off += (int64_t)m.T * m.T * m.nR * m.kR;
@@ -277,6 +290,41 @@ void real_sph_harm(int l, const double* u, double* Y) {
   }
 }
 
+// ZBL universal screened Coulomb repulsion between species ti and tj at distance r
+// (Ziegler, Biersack and Littmark; Section VI.A adds it to the Cu and HfO2 models
+// with an outer cutoff):
+//   phi(r) = k_e Z_i Z_j / r * sum_m c_m exp(-d_m r / a),  a = 0.8854 a_0 / (Z_i^0.23 + Z_j^0.23),
+// with k_e = e^2 / (4 pi eps_0) and a_0 the Bohr radius, multiplied by a switch that
+// is 1 below zi, (1 + cos(pi (r - zi) / (zo - zi))) / 2 between zi and zo and 0 beyond.
+// Returns the switched energy e and its derivative de = d e / d r.
+void zbl_pair(const Model& m, int ti, int tj, double r, double& e, double& de) {
+  e = 0.0;
+  de = 0.0;
+  if (!(m.zo > 0.0) || !(r < m.zo)) return;
+  const double ke = 14.399645478;   // eV A
+  const double a0 = 0.529177210903;  // A
+  const double c[4] = {0.18175, 0.50986, 0.28022, 0.02817};
+  const double d[4] = {3.19980, 0.94229, 0.40290, 0.20162};
+  const double zz = m.Z[ti] * m.Z[tj];
+  const double a = 0.8854 * a0 / (std::pow(m.Z[ti], 0.23) + std::pow(m.Z[tj], 0.23));
+  double S = 0.0, dS = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    const double t = c[k] * std::exp(-d[k] * r / a);
+    S += t;
+    dS += -d[k] / a * t;
+  }
+  const double phi = ke * zz / r * S;
+  const double dphi = ke * zz * (dS / r - S / (r * r));
+  double sw = 1.0, dsw = 0.0;
+  if (r >= m.zi) {
+    const double w = kPi / (m.zo - m.zi);
+    sw = 0.5 * (1.0 + std::cos(w * (r - m.zi)));
+    dsw = -0.5 * w * std::sin(w * (r - m.zi));
+  }
+  e = phi * sw;
+  de = dphi * sw + phi * dsw;
+}
+
 // Round to bfloat16 (8 significant bits) with round-to-nearest-even, from FP64.
 double round_bf16(double v) {
   if (v == 0.0 || !std::isfinite(v)) return v;
@@ -304,6 +352,7 @@ struct CenterTerms {
   std::vector<double> Fp;   // [D] dU/dq (unscaled descriptor)
   std::vector<PairGeom> pairs;  // radial neighbours (r < rcR), ascending id
   std::vector<double> J;    // [npairs][D][3] dq_nu / d r_ij
+  std::vector<double> zd;   // [npairs] d(half the ZBL pair energy)/dr (zero without ZBL)
 };
 
 // Intermediate per-pair tables of one center, kept on request for the
@@ -337,6 +386,15 @@ void center_terms(const Model& m, const CellGrid* g, int64_t n, const double* x,
   }
   const int np = (int)ct.pairs.size();
   const int ti = type[i];
+  // ZBL: half of each pair's repulsion belongs to U_i.
+  double Uz = 0.0;
+  ct.zd.assign(np, 0.0);
+  for (int p = 0; p < np; ++p) {
+    double e, de;
+    zbl_pair(m, ti, type[ct.pairs[p].j], ct.pairs[p].r, e, de);
+    Uz += 0.5 * e;
+    ct.zd[p] = 0.5 * de;
+  }
   // Radial functions g_n and derivatives for both cutoffs.
   std::vector<double> gR(np * nR), dgR(np * nR), gA(np * nA, 0.0), dgA(np * nA, 0.0);
   std::vector<char> isA(np, 0);
@@ -468,7 +526,7 @@ void center_terms(const Model& m, const CellGrid* g, int64_t n, const double* x,
     a1[mu] = m.w1[mu] * (1.0 - t * t);
     if (precision_bf16) a1[mu] = round_bf16(a1[mu]);
   }
-  ct.U = U - m.b1;
+  ct.U = U - m.b1 + Uz;
   ct.Fp.assign(D, 0.0);
   for (int v = 0; v < D; ++v) {
     double s = 0;
@@ -534,11 +592,12 @@ void center_terms(const Model& m, const CellGrid* g, int64_t n, const double* x,
   }
 }
 
-// dU_i / d r_ij = sum_nu Fp_nu dq_nu/dr_ij for pair p of center ct.
+// dU_i / d r_ij = sum_nu Fp_nu dq_nu/dr_ij (+ the ZBL half pair term along u) for pair p of center ct.
 void pair_force(const CenterTerms& ct, int D, int p, double* out) {
   out[0] = out[1] = out[2] = 0.0;
   for (int v = 0; v < D; ++v)
     for (int c = 0; c < 3; ++c) out[c] += ct.Fp[v] * ct.J[((size_t)p * D + v) * 3 + c];
+  for (int c = 0; c < 3; ++c) out[c] += ct.zd[p] * ct.pairs[p].u[c];
 }
 
 int find_pair(const CenterTerms& ct, int32_t j) {

@@ -15,7 +15,7 @@ workloads (radial 6 A, angular 5 A).
 from __future__ import annotations
 
 import dataclasses
-from typing import Optional
+from typing import Optional, Tuple
 
 import numpy as np
 
@@ -148,6 +148,15 @@ class HParams:
     l_max_3b: int = 4
     l_max_4b: int = 2
     n_hidden: int = 30
+    # ZBL repulsion (Section VI.A): outer switching radius (0 = none), inner radius
+    # (None = half the outer one) and the atomic number of each species
+    zbl_outer: float = 0.0
+    zbl_inner_radius: Optional[float] = None
+    zbl_z: Tuple[float, ...] = (29.0, 29.0)
+
+    @property
+    def zbl_inner(self) -> float:
+        return 0.5 * self.zbl_outer if self.zbl_inner_radius is None else self.zbl_inner_radius
 
     @property
     def n_desc(self) -> int:
@@ -161,7 +170,9 @@ class HParams:
                          self.l_max_4b, self.n_hidden], dtype=np.int32)
 
     def real_array(self) -> np.ndarray:
-        return np.array([self.rc_radial, self.rc_angular], dtype=np.float64)
+        z = list(self.zbl_z) + [0.0] * (2 - len(self.zbl_z))
+        return np.array([self.rc_radial, self.rc_angular, self.zbl_inner, self.zbl_outer, z[0], z[1]],
+                        dtype=np.float64)
 
     def sizes(self) -> dict:
         t = self.n_types

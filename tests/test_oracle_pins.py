@@ -304,6 +304,90 @@ def test_forces_equal_minus_energy_gradient(full_hp, block):
         assert abs(fd - F[k, c]) < 1e-7 * max(1.0, scale), (block, k, c, fd, F[k, c])
 
 
+# ----------------------------------------------------------------------------- ZBL repulsion
+
+KE_COULOMB = 14.3996454784   # e^2 / (4 pi eps0) in eV A (CODATA)
+
+
+def _zbl_models(z=(29.0, 29.0), n_types=1, outer=2.0):
+    hp0 = I.HParams(n_types=n_types)
+    hpz = I.HParams(n_types=n_types, zbl_outer=outer, zbl_z=z)
+    p = I.random_model(hp0, 0)
+    return hp0, hpz, oracle.Model.from_hparams(hp0, p), oracle.Model.from_hparams(hpz, p)
+
+
+def _dimer_dE(m0, mz, r, types=(0, 0)):
+    x = np.array([[10.0, 10.0, 10.0], [10.0 + r, 10.0, 10.0]])
+    t = np.array(types, np.int32)
+    box = np.array([30.0, 30.0, 30.0])
+    return oracle.evaluate(mz, x, t, box)[0] - oracle.evaluate(m0, x, t, box)[0]
+
+
+def test_zbl_dimer_limits_and_switch():
+    """The ZBL term of a dimer (energy with it minus without): as r -> 0 it tends to the
+    bare Coulomb repulsion k_e Z_i Z_j / r (the screening weights sum to one); below the
+    inner radius r E / (k_e Z_i Z_j) is the screening function, inside (0, 1) and
+    decreasing; it is zero from the outer radius on, and value and slope are continuous
+    at both radii (inner radius = half the outer one)."""
+    _, _, m0, mz = _zbl_models()
+    zz = KE_COULOMB * 29.0 * 29.0
+    for r in (1e-6, 1e-7):
+        assert abs(_dimer_dE(m0, mz, r) * r / zz - 1.0) < 20.0 * r
+    scr = [_dimer_dE(m0, mz, r) * r / zz for r in (0.2, 0.5, 0.9)]
+    assert 1.0 > scr[0] > scr[1] > scr[2] > 0.0
+    assert _dimer_dE(m0, mz, 2.0) == 0.0 and _dimer_dE(m0, mz, 2.7) == 0.0
+    h = 1e-6
+    for r0 in (1.0, 2.0):
+        lo, hi = _dimer_dE(m0, mz, r0 - h), _dimer_dE(m0, mz, r0 + h)
+        slo = (_dimer_dE(m0, mz, r0 - h) - _dimer_dE(m0, mz, r0 - 2 * h)) / h
+        shi = (_dimer_dE(m0, mz, r0 + 2 * h) - _dimer_dE(m0, mz, r0 + h)) / h
+        # no jump: the change across r0 is what the one-sided slopes give over 2h
+        assert abs((hi - lo) - h * (slo + shi)) < 1e-3 * h * max(1.0, abs(slo)), (r0, lo, hi)
+        assert abs(slo - shi) < 1e-3 * max(1.0, abs(slo)), (r0, slo, shi)
+    assert abs(_dimer_dE(m0, mz, 2.0 - 1e-4)) < 1e-6
+
+
+def test_zbl_two_species_symmetry():
+    """Cu-Au pairs: the limit k_e Z_Cu Z_Au / r, and the pair term does not depend on
+    which atom is the center."""
+    _, _, m0, mz = _zbl_models(z=(29.0, 79.0), n_types=2)
+    zz = KE_COULOMB * 29.0 * 79.0
+    assert abs(_dimer_dE(m0, mz, 1e-7, (0, 1)) * 1e-7 / zz - 1.0) < 1e-5
+    for r in (0.4, 1.3):
+        assert abs(_dimer_dE(m0, mz, r, (0, 1)) - _dimer_dE(m0, mz, r, (1, 0))) < 1e-9 * abs(
+            _dimer_dE(m0, mz, r, (0, 1)))
+
+
+def test_zbl_forces_and_virial_fd():
+    """With close pairs (FCC compressed to a nearest-neighbour distance of 2.05 A, many
+    pairs inside 2 A), forces are minus the energy gradient, they sum to zero, and the
+    virial is minus the strain derivative of the energy."""
+    _, _, _, mz = _zbl_models()
+    at = I.fcc_box(5, 0.1, 31)
+    x, box = at.x * 0.8, at.box * 0.8
+    cnt, _ = oracle.neighbors(x, box, 2.0)
+    assert cnt.sum() > 200
+    E, W, U, F = oracle.evaluate(mz, x, at.types, box)
+    assert np.abs(F.sum(0)).max() < 1e-9 * np.abs(F).max()
+    rng = np.random.default_rng(4)
+    h = 1e-6
+    for _ in range(8):
+        k, c = int(rng.integers(at.n)), int(rng.integers(3))
+        xp, xm = x.copy(), x.copy()
+        xp[k, c] += h
+        xm[k, c] -= h
+        fd = -(oracle.evaluate(mz, xp, at.types, box)[0] - oracle.evaluate(mz, xm, at.types, box)[0]) / (2 * h)
+        assert abs(fd - F[k, c]) < 1e-6 * max(1.0, np.abs(F).max()), (k, c, fd, F[k, c])
+    for a in range(3):
+        e = 1e-7
+        sc = np.ones(3)
+        sc[a] = 1 + e
+        Ep = oracle.evaluate(mz, x * sc, at.types, box * sc)[0]
+        sc[a] = 1 - e
+        Em = oracle.evaluate(mz, x * sc, at.types, box * sc)[0]
+        assert abs(-(Ep - Em) / (2 * e) - W[a, a]) < 1e-6 * np.abs(W).max()
+
+
 def test_net_force_zero_and_invariances(full_model):
     at = I.fcc_box(4, 0.2, 8)
     E, W, U, F = oracle.evaluate(full_model, at.x, at.types, at.box)
