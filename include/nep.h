@@ -73,6 +73,14 @@ typedef struct nep_hparams {
   int32_t l_max_3b, l_max_4b;
   int32_t n_hidden;
   double rc_radial, rc_angular;  /* rc_angular <= rc_radial */
+  /* ZBL screened-Coulomb repulsion (Section VI.A adds it to the Cu and HfO2
+   * models with an outer cutoff): zbl_rc_outer = 0 leaves it out; otherwise
+   * 0 <= zbl_rc_inner < zbl_rc_outer <= rc_radial, and each pair closer than
+   * zbl_rc_outer adds the universal ZBL energy of atomic numbers zbl_z[t_i],
+   * zbl_z[t_j] (> 0), switched off by a cosine between the two radii, half to
+   * each atom's energy. It has no trainable parameters. */
+  double zbl_rc_inner, zbl_rc_outer;
+  double zbl_z[2];
 } nep_hparams;
 
 /* Packed FP64 parameter vector, in this order:

@@ -42,7 +42,10 @@ bool hp_valid(const nep_hparams* hp) {
   return hp->n_types >= 1 && hp->n_types <= kMaxTypes && hp->n_max_radial >= 0 && hp->n_max_angular >= 0 &&
          hp->basis_radial >= 1 && hp->basis_angular >= 1 && hp->l_max_3b >= 1 && hp->l_max_3b <= 4 &&
          (hp->l_max_4b == 0 || hp->l_max_4b == 2) && hp->n_hidden >= 1 && hp->rc_radial > 0 &&
-         hp->rc_angular > 0 && hp->rc_angular <= hp->rc_radial && std::isfinite(hp->rc_radial);
+         hp->rc_angular > 0 && hp->rc_angular <= hp->rc_radial && std::isfinite(hp->rc_radial) &&
+         (hp->zbl_rc_outer == 0.0 ||
+          (hp->zbl_rc_outer > 0 && hp->zbl_rc_inner >= 0 && hp->zbl_rc_inner < hp->zbl_rc_outer &&
+           hp->zbl_rc_outer <= hp->rc_radial && hp->zbl_z[0] > 0 && (hp->n_types < 2 || hp->zbl_z[1] > 0)));
 }
 
 // Round an FP64 value to bfloat16 bits, nearest-even, directly from FP64.
@@ -248,6 +251,20 @@ int upload_model(nep_system* s, int slot) {
   d.w1 = d.b0 + H;
   d.b1 = d.w1 + H;
   d.W0bf = s->mbf[slot];
+  // ZBL constants per species pair: k_e Z_i Z_j (k_e = e^2 / 4 pi eps0 in eV A) and
+  // 1 / a with the universal screening length a = 0.8854 a_0 / (Z_i^0.23 + Z_j^0.23)
+  const double zo = m.hp.zbl_rc_outer;
+  d.zbl_o2 = zo > 0 ? zo * zo : 0.0;
+  d.zbl_ri = m.hp.zbl_rc_inner;
+  d.zbl_ro = zo;
+  for (int k = 0; k < kMaxTypes * kMaxTypes; ++k) d.zbl_kzz[k] = d.zbl_ainv[k] = 0.0;
+  if (zo > 0)
+    for (int a = 0; a < T; ++a)
+      for (int c = 0; c < T; ++c) {
+        const double za = m.hp.zbl_z[a], zc = m.hp.zbl_z[c];
+        d.zbl_kzz[a * T + c] = 14.399645478 * za * zc;
+        d.zbl_ainv[a * T + c] = (std::pow(za, 0.23) + std::pow(zc, 0.23)) / (0.8854 * 0.529177210903);
+      }
   s->force_valid[slot] = false;
   return NEP_OK;
 }

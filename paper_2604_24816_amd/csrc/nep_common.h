@@ -149,6 +149,12 @@ struct ModelDev {
   const float* w1;
   const float* b1;
   const uint16_t* W0bf;  // [H][D] bfloat16 bits, rounded from the FP64 parameters
+  // ZBL repulsion: pairs with r^2 < zbl_o2 (0: no ZBL term), switched between
+  // zbl_ri and zbl_ro; per species pair (t_i * T + t_j) k_e Z_i Z_j and 1 / a_ij
+  double zbl_o2;
+  double zbl_ri, zbl_ro;
+  double zbl_kzz[kMaxTypes * kMaxTypes];
+  double zbl_ainv[kMaxTypes * kMaxTypes];
 };
 
 // XCD-aware mapping of a workgroup id to a contiguous tile index: workgroups

@@ -264,6 +264,45 @@ __device__ __forceinline__ int angular_bound(const EvalBuffers& b, int64_t i) {
   return b.bp[(int64_t)b.flags[b.flag_a] * b.N + i];
 }
 
+// ZBL universal screened Coulomb repulsion of one pair at distance r (the published
+// Ziegler-Biersack-Littmark form, added to the Cu and HfO2 models in Section VI.A):
+// phi = k_e Z_i Z_j / r * sum_m c_m exp(-d_m r / a) times a switch that is 1 below
+// zbl_ri and (1 + cos(pi (r - zbl_ri) / (zbl_ro - zbl_ri))) / 2 up to zbl_ro.
+// Returns the switched energy e and de = d e / d r, in FP64: only the rare pairs
+// inside the ZBL radius get here, and the repulsion is steep enough there that an
+// FP32 distance would cost several FP32 roundings of the atom's energy.
+template <bool MULTI>
+__device__ __forceinline__ void zbl_pair(const ModelDev& m, int tp, double r, double& e, double& de) {
+  double kzz = m.zbl_kzz[0], ainv = m.zbl_ainv[0];
+  if constexpr (MULTI) {
+#pragma unroll
+    for (int k = 1; k < kMaxTypes * kMaxTypes; ++k) {
+      kzz = tp == k ? m.zbl_kzz[k] : kzz;
+      ainv = tp == k ? m.zbl_ainv[k] : ainv;
+    }
+  }
+  constexpr double c[4] = {0.18175, 0.50986, 0.28022, 0.02817};
+  constexpr double d[4] = {3.19980, 0.94229, 0.40290, 0.20162};
+  double S = 0.0, dS = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double t = c[k] * exp(-d[k] * ainv * r);
+    S += t;
+    dS -= d[k] * ainv * t;
+  }
+  const double rinv = 1.0 / r;
+  const double phi = kzz * rinv * S;
+  const double dphi = kzz * rinv * (dS - S * rinv);
+  double sw = 1.0, dsw = 0.0;
+  if (r >= m.zbl_ri) {
+    const double w = 3.14159265358979323846 / (m.zbl_ro - m.zbl_ri);
+    sw = 0.5 * (1.0 + cos(w * (r - m.zbl_ri)));
+    dsw = -0.5 * w * sin(w * (r - m.zbl_ri));
+  }
+  e = phi * sw;
+  de = dphi * sw + phi * dsw;
+}
+
 // FP64 minimum-image vector of a pair whose position is loaded and its r^2.
 __device__ __forceinline__ double pair_r2_64(double xj, double yj, double zj, double xi, double yi, double zi,
                                              double Lx, double Ly, double Lz, double& ex, double& ey,
@@ -274,13 +313,50 @@ __device__ __forceinline__ double pair_r2_64(double xj, double yj, double zj, do
   return ex * ex + ey * ey + ez * ez;
 }
 
+// ZBL terms of center i over its list (the pairs with r^2 < zbl_o2): half of each
+// pair's energy into uz, and, when f is given, the force on i (the whole pair
+// derivative, both atoms' halves, along u) into f[3] and the virial of dU_i/dr_ij
+// into w[9]. Called only for centers that have such pairs, after the main loop.
+template <bool MULTI>
+__device__ __forceinline__ void zbl_center(const ModelDev& m, const EvalBuffers& b, int64_t i, int ti, double xi,
+                                        double yi, double zi, float* uz, float* f, float* w) {
+  const int64_t N = b.N;
+  const double Lx = b.box[0], Ly = b.box[1], Lz = b.box[2];
+  const int kR = radial_bound(b, i);
+  for (int p = 0; p < kR; ++p) {
+    const int32_t j = b.nbr[(int64_t)p * N + i];
+    const uint4 w0 = b.rec[4 * (int64_t)j], w1 = b.rec[4 * (int64_t)j + 1];
+    const double ex = min_image(rec_f64(w0.x, w0.y) - xi, Lx);
+    const double ey = min_image(rec_f64(w0.z, w0.w) - yi, Ly);
+    const double ez = min_image(rec_f64(w1.x, w1.y) - zi, Lz);
+    const double r2 = ex * ex + ey * ey + ez * ez;
+    if (!(r2 < m.zbl_o2)) continue;
+    const double r = sqrt(r2);
+    const int tj = MULTI ? b.type[j] : 0;
+    double e, de;
+    zbl_pair<MULTI>(m, ti * m.T + tj, r, e, de);
+    if (uz) *uz += (float)(0.5 * e);
+    if (f) {
+      const double d[3] = {ex, ey, ez};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double fa = de * d[a] / r;  // both halves of the pair derivative along u
+        f[a] += (float)fa;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) w[a * 3 + c] += (float)(-d[a] * 0.5 * de * d[c] / r);
+      }
+    }
+  }
+}
+
 // Radial descriptors q[0..NR) and angular accumulators s[NA][NC] of center i over
 // the pairs inside the true cutoffs, all channels in one pass over the neighbours
-// (geometry computed once per pair and reused for every n). Returns the pair counts.
+// (geometry computed once per pair and reused for every n). Returns the pair counts
+// and the number of pairs inside the ZBL radius (nclose).
 template <class S, bool MULTI>
 __device__ __forceinline__ void desc_accumulate(const ModelDev& m, const EvalBuffers& b, int64_t i, int ti,
                                                 double xi, double yi, double zi, double Lx, double Ly,
-                                                double Lz, float* q, float* s, int& nr, int& na) {
+                                                double Lz, float* q, float* s, int& nclose, int& nr, int& na) {
   constexpr int NR = S::NR, NA = S::NA, NC = S::NC;
   const int64_t N = b.N;
   const float rcR_inv = 1.f / m.rcR, rcA_inv = 1.f / m.rcA;
@@ -305,6 +381,7 @@ __device__ __forceinline__ void desc_accumulate(const ModelDev& m, const EvalBuf
     float r, rinv;
     pair_r(dx, dy, dz, r, rinv);
     const int tj = MULTI ? b.type[j] : 0;
+    nclose += r2 < m.zbl_o2 ? 1 : 0;
     if constexpr (MULTI) {
       float g[NR];
       radial_g<NR, S::KR>(r, rcR_inv, m.cR + (ti * m.T + tj) * NR * S::KR, g);

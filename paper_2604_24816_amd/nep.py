@@ -45,7 +45,9 @@ class _HParams(ctypes.Structure):
                 ("n_max_angular", ctypes.c_int32), ("basis_radial", ctypes.c_int32),
                 ("basis_angular", ctypes.c_int32), ("l_max_3b", ctypes.c_int32),
                 ("l_max_4b", ctypes.c_int32), ("n_hidden", ctypes.c_int32),
-                ("rc_radial", ctypes.c_double), ("rc_angular", ctypes.c_double)]
+                ("rc_radial", ctypes.c_double), ("rc_angular", ctypes.c_double),
+                ("zbl_rc_inner", ctypes.c_double), ("zbl_rc_outer", ctypes.c_double),
+                ("zbl_z", ctypes.c_double * 2)]
 
 
 _lib = None
@@ -101,8 +103,10 @@ def load_library(path: str = LIB_PATH):
 
 
 def _hp_struct(hp: inputs.HParams) -> _HParams:
+    z = list(hp.zbl_z) + [0.0] * (2 - len(hp.zbl_z))
     return _HParams(hp.n_types, hp.n_max_radial, hp.n_max_angular, hp.basis_radial, hp.basis_angular,
-                    hp.l_max_3b, hp.l_max_4b, hp.n_hidden, hp.rc_radial, hp.rc_angular)
+                    hp.l_max_3b, hp.l_max_4b, hp.n_hidden, hp.rc_radial, hp.rc_angular,
+                    hp.zbl_inner, hp.zbl_outer, (ctypes.c_double * 2)(z[0], z[1]))
 
 
 def _np_ptr(a: np.ndarray):
