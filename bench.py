@@ -14,6 +14,7 @@ kernel (the force kernel, timed with HIP events on the library's stream over
 the timed region) and the FP64 CPU oracle timed on this host's cores.
 """
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -260,6 +261,8 @@ def main():
     ap.add_argument("--forms", action="store_true",
                     help="time FP32, BF16 and surrogate MTS on the 200^3-cell (32M-atom) box instead")
     ap.add_argument("--epochs", type=int, default=40, help="surrogate training epochs (forms only)")
+    ap.add_argument("--zbl", type=float, default=0.0,
+                    help="add the ZBL repulsion with this outer radius in A (the paper's Cu model uses 2.0)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the reference kernel "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -284,6 +287,8 @@ def main():
     from paper_2604_24816_amd import nep
 
     hp = I.FULL_HPARAMS
+    if args.zbl > 0:
+        hp = dataclasses.replace(hp, zbl_outer=args.zbl)
     params = I.random_model(hp, 0)
     at = I.workload_4m(args.cells)
     s = nep.NEPSystem(nep.NEPModel(hp, params), at.n, at.box)
@@ -324,7 +329,8 @@ def main():
         "dtype": "fp32" if args.precision == "fp32" else "fp32+bf16-mfma",
         "data": "synthetic (seeded FCC box, random-weight NEP)",
         "config": {"workload": f"fcc_cu_{args.cells}x{args.cells}x{args.cells}_cells_{n}_atoms_nve",
-                   "n_atoms": n, "model": "NEP rc 6/5 A, n_max 4, basis 8, l_max 4 + 4-body, 30 hidden",
+                   "n_atoms": n, "model": "NEP rc 6/5 A, n_max 4, basis 8, l_max 4 + 4-body, 30 hidden"
+                   + (f", ZBL outer {args.zbl} A" if args.zbl > 0 else ""),
                    "precision": args.precision, "dt_fs": 1.0, "rebuild_every": 10, "skin_A": 1.0,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "kernel": "k_force", "achieved": achieved,

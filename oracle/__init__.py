@@ -215,6 +215,24 @@ def velocity_verlet(model: Model, x, v, types, masses, box, dt, n_steps):
     return x, v, thermo
 
 
+def nvt(model: Model, x, v, types, masses, box, dt, n_steps, T0, tau, eta, ve):
+    """NVT (Nose-Hoover chain) steps; returns (x, v, eta, ve, thermo[n_steps+1][5] =
+    PE, KE, T, P, conserved energy). eta, ve: chain state of length M (copied)."""
+    x = _f64(x).copy()
+    v = _f64(v).copy()
+    eta = _f64(eta).copy()
+    ve = _f64(ve).copy()
+    types = np.ascontiguousarray(types, np.int32)
+    masses = _f64(masses)
+    box = _f64(box)
+    thermo = np.zeros((n_steps + 1, 5))
+    st = _load().orc_nvt(*model._args(), ctypes.c_int64(x.shape[0]), _p(x), _p(v), _p(types), _p(masses),
+                         _p(box), ctypes.c_double(dt), ctypes.c_int64(n_steps), ctypes.c_double(T0),
+                         ctypes.c_double(tau), ctypes.c_int32(eta.size), _p(eta), _p(ve), _p(thermo))
+    _check(st, "nvt")
+    return x, v, eta, ve, thermo
+
+
 def mts(full: Model, sur: Model, x, v, types, masses, box, dt, k, n_blocks):
     """r-RESPA blocks; returns (x, v, err[n_blocks][2] = rms, max of |F_full - F_s|)."""
     x = _f64(x).copy()

@@ -16,7 +16,8 @@
 //     models (Section VI.A), half of each pair's energy per atom;
 //   * forces F = -dU/dx and the virial;
 //   * velocity-Verlet integration with the step, temperature and neighbour
-//     settings of Section VI.A;
+//     settings of Section VI.A, and its NVT form with a Nose-Hoover chain (the
+//     application run of Section VII uses the NVT ensemble);
 //   * gradients of energy and force losses with respect to the network weights.
 //
 // Where the paper names a piece without printing its formula, this file takes
@@ -946,6 +947,125 @@ int orc_velocity_verlet(const int32_t* ip, const double* dp, const double* param
       for (int c = 0; c < 3; ++c) v[3 * i + c] += 0.5 * dt * F[3 * i + c] * inv;
     }
     thermo_row(s);
+  }
+  return OK;
+}
+
+// Nose-Hoover chain (NVT) state and its half step, in the explicit reversible
+// Trotter form of Martyna, Tuckerman, Tobias and Klein (Mol. Phys. 87, 1117, 1996).
+// The chain has M thermostats with positions eta_k and velocities ve_k (1/fs) and
+// masses Q_1 = Nf kT0 tau^2, Q_k = kT0 tau^2 (k >= 2), Nf = 3N - 3; the forces on it are
+//   G_1 = (2 KE - Nf kT0) / Q_1,  G_k = (Q_{k-1} ve_{k-1}^2 - kT0) / Q_k.
+// One half step of length h = dt/2 moves the outermost velocity by G h/2, sweeps the
+// chain inwards (each ve_k damped by exp(-ve_{k+1} h/4) before and after its kick
+// G_k h/2), scales the particle velocities by exp(-ve_1 h), advances eta_k by ve_k h,
+// then sweeps outwards in the mirror order with freshly computed forces.
+struct Chain {
+  int M = 0;
+  double kT = 0, Nf = 0;
+  std::vector<double> Q, eta, ve;
+  double G(int k, double ke) const {
+    if (k == 0) return (2.0 * ke - Nf * kT) / Q[0];
+    return (Q[k - 1] * ve[k - 1] * ve[k - 1] - kT) / Q[k];
+  }
+  // Returns the velocity scale factor; ke is updated to the scaled kinetic energy.
+  double half_step(double h, double& ke) {
+    const int L = M - 1;
+    ve[L] += G(L, ke) * h / 2;
+    for (int k = L - 1; k >= 0; --k) {
+      const double d = std::exp(-ve[k + 1] * h / 4);
+      ve[k] *= d;
+      ve[k] += G(k, ke) * h / 2;
+      ve[k] *= d;
+    }
+    const double sc = std::exp(-ve[0] * h);
+    ke *= sc * sc;
+    for (int k = 0; k < M; ++k) eta[k] += ve[k] * h;
+    for (int k = 0; k < L; ++k) {
+      const double d = std::exp(-ve[k + 1] * h / 4);
+      ve[k] *= d;
+      ve[k] += G(k, ke) * h / 2;
+      ve[k] *= d;
+    }
+    ve[L] += G(L, ke) * h / 2;
+    return sc;
+  }
+  // The chain's share of the conserved energy.
+  double energy() const {
+    double e = Nf * kT * eta[0];
+    for (int k = 0; k < M; ++k) e += 0.5 * Q[k] * ve[k] * ve[k];
+    for (int k = 1; k < M; ++k) e += kT * eta[k];
+    return e;
+  }
+};
+
+// NVT velocity Verlet: a chain half step, half kick, drift, forces, half kick, a chain
+// half step. eta and ve (length M) are the chain state, updated in place.
+// thermo[s][5] = {PE, KE, T, P, conserved energy} for s = 0..n_steps.
+int orc_nvt(const int32_t* ip, const double* dp, const double* params, int64_t n_params, int64_t n, double* x,
+            double* v, const int32_t* type, const double* masses, const double* box, double dt, int64_t n_steps,
+            double T0, double tau, int32_t M, double* eta, double* ve, double* thermo) {
+  Model m;
+  int st = parse_model(ip, dp, params, n_params, m);
+  if (st) return st;
+  if (M < 1 || !(T0 > 0) || !(tau > 0) || !eta || !ve || n < 2) return ERR_ARG;
+  Chain ch;
+  ch.M = M;
+  ch.kT = kBoltzmann * T0;
+  ch.Nf = 3.0 * n - 3.0;
+  ch.Q.assign(M, ch.kT * tau * tau);
+  ch.Q[0] *= ch.Nf;
+  ch.eta.assign(eta, eta + M);
+  ch.ve.assign(ve, ve + M);
+  std::vector<double> F(3 * n);
+  double E = 0, W[9];
+  st = evaluate_all(m, n, x, type, box, 0, nullptr, F.data(), &E, W);
+  if (st) return st;
+  const double V = box[0] * box[1] * box[2];
+  auto kinetic = [&]() {
+    double ke = 0;
+    for (int64_t i = 0; i < n; ++i)
+      for (int c = 0; c < 3; ++c) ke += 0.5 * masses[type[i]] * kXi * v[3 * i + c] * v[3 * i + c];
+    return ke;
+  };
+  auto row = [&](int64_t s) {
+    if (!thermo) return;
+    const double ke = kinetic();
+    thermo[5 * s + 0] = E;
+    thermo[5 * s + 1] = ke;
+    thermo[5 * s + 2] = 2.0 * ke / (ch.Nf * kBoltzmann);
+    thermo[5 * s + 3] = (2.0 * ke + (W[0] + W[4] + W[8])) / (3.0 * V);
+    thermo[5 * s + 4] = E + ke + ch.energy();
+  };
+  auto thermostat = [&]() {
+    double ke = kinetic();
+    const double sc = ch.half_step(0.5 * dt, ke);
+    for (int64_t k = 0; k < 3 * n; ++k) v[k] *= sc;
+  };
+  row(0);
+  for (int64_t s = 1; s <= n_steps; ++s) {
+    thermostat();
+    for (int64_t i = 0; i < n; ++i) {
+      const double inv = 1.0 / (masses[type[i]] * kXi);
+      for (int c = 0; c < 3; ++c) {
+        v[3 * i + c] += 0.5 * dt * F[3 * i + c] * inv;
+        x[3 * i + c] += dt * v[3 * i + c];
+        if (x[3 * i + c] < 0.0) x[3 * i + c] += box[c];
+        else if (x[3 * i + c] >= box[c]) x[3 * i + c] -= box[c];
+      }
+    }
+    st = evaluate_all(m, n, x, type, box, 0, nullptr, F.data(), &E, W);
+    if (st) return st;
+    for (int64_t i = 0; i < n; ++i) {
+      const double inv = 1.0 / (masses[type[i]] * kXi);
+      for (int c = 0; c < 3; ++c) v[3 * i + c] += 0.5 * dt * F[3 * i + c] * inv;
+    }
+    thermostat();
+    row(s);
+  }
+  for (int k = 0; k < M; ++k) {
+    eta[k] = ch.eta[k];
+    ve[k] = ch.ve[k];
   }
   return OK;
 }

@@ -597,6 +597,81 @@ def test_param_gradient_fd(kind):
             assert abs(fd - g[k]) < 1e-6 * max(1.0, abs(g[k])), (kind, k, with_f, fd, g[k])
 
 
+# ----------------------------------------------------------------------------- NVT (Nose-Hoover chain)
+
+def _zero_force_model(hp):
+    p = I.random_model(hp, 0)
+    p[hp.offsets()["W0"][0]:] = 0.0    # constant network output: no forces
+    return oracle.Model.from_hparams(hp, p)
+
+
+@pytest.mark.parametrize("M", [1, 3])
+def test_nvt_chain_follows_its_equations_of_motion(full_hp, M):
+    """With zero forces the particles only feel the chain, and the state (KE, chain
+    velocities and positions) obeys dKE/dt = -2 v_1 KE, dv_k/dt = G_k - v_k v_{k+1}
+    (no damping term for the last), deta_k/dt = v_k. The integrator must converge to
+    an independent high-accuracy solution of these equations at second order in dt."""
+    from scipy.integrate import solve_ivp
+    m0 = _zero_force_model(full_hp)
+    at = I.fcc_box(3, 0.1, 3)
+    at = I.Atoms(x=at.x * 1.5, types=at.types, box=at.box * 1.5, masses=at.masses)
+    at.v = I.maxwell_boltzmann(at, 600.0, 4)
+    n, T0, tau, kB = at.n, 300.0, 20.0, 8.617333262e-5
+    Nf, kT = 3 * n - 3, kB * T0
+    Q = np.full(M, kT * tau * tau)
+    Q[0] *= Nf
+    ke0 = 0.5 * np.sum(at.masses[at.types][:, None] * at.v ** 2) * 103.642697
+
+    def rhs(t, y):
+        ke, ve = y[0], y[1:1 + M]
+        G = np.empty(M)
+        G[0] = (2 * ke - Nf * kT) / Q[0]
+        G[1:] = (Q[:-1] * ve[:-1] ** 2 - kT) / Q[1:]
+        dve = G.copy()
+        dve[:-1] -= ve[:-1] * ve[1:]
+        return np.concatenate([[-2 * ve[0] * ke], dve, ve])
+    ref = solve_ivp(rhs, (0, 100.0), np.concatenate([[ke0], np.zeros(2 * M)]), method="DOP853",
+                    rtol=1e-12, atol=1e-14).y[:, -1]
+    errs = []
+    for dt in (0.25, 0.125):
+        _, _, eta, ve, th = oracle.nvt(m0, at.x, at.v, at.types, at.masses, at.box, dt, int(100 / dt), T0, tau,
+                                       np.zeros(M), np.zeros(M))
+        errs.append(max(abs(th[-1, 1] - ref[0]) / ref[0],
+                        np.abs(ve - ref[1:1 + M]).max() / np.abs(ref[1:1 + M]).max(),
+                        np.abs(eta - ref[1 + M:]).max() / np.abs(ref[1 + M:]).max()))
+    assert errs[1] < 2e-5, errs
+    assert 3.8 < errs[0] / errs[1] < 4.2, errs
+
+
+def test_nvt_with_a_stiff_chain_mass_is_nve(full_model):
+    """tau -> infinity decouples the chain: the steps are velocity Verlet's."""
+    at = I.fcc_box(4, 0.1, 7)
+    at.v = I.maxwell_boltzmann(at, 600.0, 8)
+    x1, v1, _ = oracle.velocity_verlet(full_model, at.x, at.v, at.types, at.masses, at.box, 1.0, 6)
+    x2, v2, _, _, _ = oracle.nvt(full_model, at.x, at.v, at.types, at.masses, at.box, 1.0, 6, 300.0, 1e9,
+                                 np.zeros(3), np.zeros(3))
+    assert np.abs(x1 - x2).max() < 1e-10 and np.abs(v1 - v2).max() < 1e-12
+
+
+def test_nvt_time_reversible_and_conserving(full_model):
+    """Reversing particle and chain velocities retraces the trajectory, and the extended
+    energy (PE + KE + chain energy) drifts as dt^2."""
+    at = I.fcc_box(4, 0.1, 7)
+    at.v = I.maxwell_boltzmann(at, 600.0, 8)
+    x, v, eta, ve, _ = oracle.nvt(full_model, at.x, at.v, at.types, at.masses, at.box, 1.0, 12, 300.0, 10.0,
+                                  np.zeros(3), np.zeros(3))
+    xb, vb, _, _, _ = oracle.nvt(full_model, x, -v, at.types, at.masses, at.box, 1.0, 12, 300.0, 10.0, eta, -ve)
+    d = xb - at.x
+    d -= at.box * np.round(d / at.box)
+    assert np.abs(d).max() < 1e-9 and np.abs(vb + at.v).max() < 1e-11
+    drift = []
+    for dt in (1.0, 0.5):
+        th = oracle.nvt(full_model, at.x, at.v, at.types, at.masses, at.box, dt, int(40 / dt), 300.0, 20.0,
+                        np.zeros(3), np.zeros(3))[4]
+        drift.append(np.abs(th[:, 4] - th[0, 4]).max())
+    assert 3.0 < drift[0] / drift[1] < 5.0, drift
+
+
 def test_bf16_rounding_closed_forms():
     import torch
     assert oracle.round_bf16(1.0) == 1.0
