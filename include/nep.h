@@ -167,6 +167,23 @@ int nep_step(nep_system* s, int64_t n_steps, double dt_fs, int32_t rebuild_every
              int32_t mts_k, double fallback_rms, double fallback_max, int32_t precision,
              double* thermo, int32_t thermo_every, int64_t max_rows, int64_t* rows_written);
 
+/* NVT. With chain_length >= 1, nep_step (mts_k = 0) integrates velocity Verlet
+ * with a Nose-Hoover chain of that many thermostats (at most 16) at the target
+ * temperature (K) with period tau_fs (fs): chain masses Q_1 = Nf kT tau^2 and
+ * Q_k = kT tau^2, Nf = 3N - 3, and a chain half step (the explicit reversible
+ * Trotter form of Martyna, Tuckerman, Tobias and Klein, 1996) before the first
+ * and after the second half kick of every step. The application run of Section
+ * VII uses the NVT ensemble without naming its thermostat. chain_length = 0
+ * returns to NVE. Every call resets the chain state to zero. nep_step refuses
+ * mts_k > 0 while a thermostat is set. Synchronises. */
+int nep_set_thermostat(nep_system* s, double temperature, double tau_fs, int32_t chain_length);
+
+/* The chain state (host arrays of chain_length values, nullable) and its share
+ * of the conserved energy, Nf kT eta_1 + kT sum_{k>=2} eta_k + sum_k Q_k v_k^2 / 2
+ * (eV, nullable); PE + KE + that share is conserved by the NVT dynamics.
+ * Synchronises. */
+int nep_get_thermostat(nep_system* s, double* eta, double* v_eta, double* chain_energy);
+
 /* How nep_step's MTS judge reads fallback_rms and fallback_max: relative = 0
  * (the default) takes them in eV/A; relative = 1 takes them as multiples of
  * the per-component rms of the full model's forces at the end of the block

@@ -109,6 +109,10 @@ struct nep_system {
   int64_t step = 0;
   int64_t n_mts_blocks = 0, n_fallback_blocks = 0, n_steps_total = 0;
   int judge_relative = 0;  // nep_set_judge
+  // NVT (nep_set_thermostat): Nose-Hoover chain length (0 = NVE), target and period
+  int nvt_M = 0;
+  double nvt_T = 0, nvt_tau = 0;
+  double* nhc = nullptr;  // device chain state {eta[kMaxChain], v_eta[kMaxChain], scale}
   std::string err;
   // device buffers (inside the caller's workspace)
   double *x, *v, *x_alt, *v_alt, *x_build;
@@ -191,6 +195,7 @@ int64_t layout(nep_system* s, char* base, int64_t N, int capR, int capA, int max
   S.res = c.take<double>(kResults);
   S.staging = c.take<double>(3 * N);
   S.flags = c.take<int32_t>(FLAG_COUNT);
+  S.nhc = c.take<double>(kNhcDoubles);
   for (int k = 0; k < 2; ++k) {
     S.mparams[k] = c.take<float>(np[k] > 0 ? np[k] : 1);
     S.mbf[k] = c.take<uint16_t>(HD[k] > 0 ? HD[k] : 1);
@@ -742,6 +747,15 @@ int vv_step(nep_system* s, int slot, int prec, double dt, int rebuild_every, dou
   return NEP_OK;
 }
 
+// One Nose-Hoover chain half step (dt/2) on the current velocities.
+int nhc_half(nep_system* s, double dt) {
+  HIPCHK(launch_kinetic(s->N, s->v, s->type, s->mt, s->partial, s->st));
+  HIPCHK(launch_reduce_partials(s->partial, s->nblocks, P_KE, 1, s->res + 18, s->st));
+  HIPCHK(launch_nhc_half(s->N, s->res + 18, s->nhc, s->nvt_M, kBoltzmann * s->nvt_T, s->nvt_tau, 0.5 * dt, s->v,
+                         s->st));
+  return NEP_OK;
+}
+
 // Surrogate force error against the full model: rms per component and max
 // |F_full - F_surrogate| over atoms; frms (nullable) = rms per component of F_full.
 int force_error(nep_system* s, double* rms, double* mx, double* frms = nullptr) {
@@ -769,6 +783,7 @@ int nep_step(nep_system* s, int64_t n_steps, double dt_fs, int32_t rebuild_every
   if (!s->have_state) return fail(s, NEP_ERR_ARG, "no state set");
   if (mts_k > 0 && (!s->has_model[1] || n_steps % mts_k != 0))
     return fail(s, NEP_ERR_ARG, "MTS needs a surrogate model and n_steps divisible by mts_k");
+  if (mts_k > 0 && s->nvt_M > 0) return fail(s, NEP_ERR_ARG, "the thermostat runs with plain velocity Verlet only");
   if (thermo && (thermo_every < 1 || max_rows < 1)) return fail(s, NEP_ERR_ARG, "thermo_every and max_rows must be >= 1");
   if (rows_written) *rows_written = 0;
   int st;
@@ -783,7 +798,9 @@ int nep_step(nep_system* s, int64_t n_steps, double dt_fs, int32_t rebuild_every
     if (!s->force_valid[0] || s->force_prec[0] != precision)
       if ((st = do_eval(s, 0, precision))) return st;
     for (int64_t k = 0; k < n_steps; ++k) {
+      if (s->nvt_M > 0 && (st = nhc_half(s, dt_fs))) return st;
       if ((st = vv_step(s, 0, precision, dt_fs, rebuild_every, skin))) return st;
+      if (s->nvt_M > 0 && (st = nhc_half(s, dt_fs))) return st;
       if (want_row(k == n_steps - 1)) {
         if ((st = reduce_ew(s, 0))) return st;
         if ((st = thermo_row(s, thermo + 8 * rows, 0.0, 0.0, 0))) return st;
@@ -844,6 +861,44 @@ int nep_step(nep_system* s, int64_t n_steps, double dt_fs, int32_t rebuild_every
   if (rows_written) *rows_written = rows;
   if ((st = check_flags(s))) return st;
   HIPCHK(hipStreamSynchronize(s->st));
+  return NEP_OK;
+}
+
+int nep_set_thermostat(nep_system* s, double temperature, double tau_fs, int32_t chain_length) {
+  if (!s || chain_length < 0 || chain_length > kMaxChain) return fail(s, NEP_ERR_ARG, "bad argument");
+  if (chain_length > 0 && !(temperature > 0 && tau_fs > 0 && std::isfinite(temperature) && std::isfinite(tau_fs)))
+    return fail(s, NEP_ERR_ARG, "temperature and tau must be positive");
+  if (s->N < 2) return fail(s, NEP_ERR_ARG, "a thermostat needs at least two atoms");
+  s->nvt_M = chain_length;
+  s->nvt_T = temperature;
+  s->nvt_tau = tau_fs;
+  double zero[kNhcDoubles] = {0};
+  zero[2 * kMaxChain] = 1.0;
+  HIPCHK(hipMemcpyAsync(s->nhc, zero, sizeof(zero), hipMemcpyHostToDevice, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  return NEP_OK;
+}
+
+int nep_get_thermostat(nep_system* s, double* eta, double* v_eta, double* chain_energy) {
+  if (!s) return NEP_ERR_ARG;
+  double h[kNhcDoubles];
+  HIPCHK(hipMemcpyAsync(h, s->nhc, sizeof(h), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  const int M = s->nvt_M;
+  for (int k = 0; k < M; ++k) {
+    if (eta) eta[k] = h[k];
+    if (v_eta) v_eta[k] = h[kMaxChain + k];
+  }
+  if (chain_energy) {
+    // Nf kT eta_1 + kT sum_{k>=2} eta_k + sum_k Q_k v_k^2 / 2
+    const double kT = kBoltzmann * s->nvt_T, Nf = 3.0 * s->N - 3.0, t2 = s->nvt_tau * s->nvt_tau;
+    double e = 0.0;
+    for (int k = 0; k < M; ++k) {
+      const double Q = (k == 0 ? Nf : 1.0) * kT * t2;
+      e += (k == 0 ? Nf * kT : kT) * h[k] + 0.5 * Q * h[kMaxChain + k] * h[kMaxChain + k];
+    }
+    *chain_energy = e;
+  }
   return NEP_OK;
 }
 

@@ -248,6 +248,13 @@ hipError_t launch_kick(int64_t N, double dt, const float* F, const int32_t* type
                        double* v, hipStream_t st);
 hipError_t launch_kick_diff(int64_t N, double dt, const float* Fa, const float* Fb,
                             const int32_t* type, MassTable mt, double* v, hipStream_t st);
+// Nose-Hoover chain: at most kMaxChain thermostats; the device state holds
+// {eta[kMaxChain], v_eta[kMaxChain], velocity scale}.
+constexpr int kMaxChain = 16;
+constexpr int kNhcDoubles = 2 * kMaxChain + 1;
+// One chain half step of length h from the kinetic energy *ke, then v *= the scale.
+hipError_t launch_nhc_half(int64_t N, const double* ke, double* nhc, int M, double kT, double tau, double h,
+                           double* v, hipStream_t st);
 hipError_t launch_kinetic(int64_t N, const double* v, const int32_t* type, MassTable mt,
                           double* partial, hipStream_t st);
 hipError_t launch_force_error(int64_t N, const float* Fa, const float* Fb, double* partial,

@@ -168,6 +168,47 @@ __global__ void k_force_error(int64_t N, const float* __restrict__ Fa, const flo
   if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * kPartialStride + P_ERRMAX] = sh[0];
 }
 
+// One half step (h = dt/2) of a Nose-Hoover chain in the explicit reversible
+// Trotter form of Martyna, Tuckerman, Tobias and Klein (1996), FP64, one thread.
+// nhc = {eta[kMaxChain], v_eta[kMaxChain], scale}; ke = the current kinetic energy.
+// Chain masses Q_1 = Nf kT tau^2, Q_k = kT tau^2; forces G_1 = (2 KE - Nf kT)/Q_1,
+// G_k = (Q_{k-1} v_{k-1}^2 - kT)/Q_k. The outermost velocity takes a quarter-step kick,
+// the chain is swept inwards (each v_k damped by exp(-v_{k+1} h/4) around its kick),
+// the particle velocities are to be scaled by exp(-v_1 h), the positions advance by
+// v_k h, and the chain is swept outwards again with the forces recomputed.
+__global__ void k_nhc_half(const double* __restrict__ ke_in, double* __restrict__ nhc, int M, double kT,
+                           double Nf, double tau2, double h) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double* eta = nhc;
+  double* ve = nhc + kMaxChain;
+  double ke = *ke_in;
+  const double Q1 = Nf * kT * tau2, Qk = kT * tau2;
+  auto force = [&](int k) {
+    return k == 0 ? (2.0 * ke - Nf * kT) / Q1 : ((k == 1 ? Q1 : Qk) * ve[k - 1] * ve[k - 1] - kT) / Qk;
+  };
+  const int L = M - 1;
+  ve[L] += 0.5 * h * force(L);
+  for (int k = L - 1; k >= 0; --k) {
+    const double d = exp(-0.25 * h * ve[k + 1]);
+    ve[k] = (ve[k] * d + 0.5 * h * force(k)) * d;
+  }
+  const double sc = exp(-h * ve[0]);
+  ke *= sc * sc;
+  for (int k = 0; k < M; ++k) eta[k] += h * ve[k];
+  for (int k = 0; k < L; ++k) {
+    const double d = exp(-0.25 * h * ve[k + 1]);
+    ve[k] = (ve[k] * d + 0.5 * h * force(k)) * d;
+  }
+  ve[L] += 0.5 * h * force(L);
+  nhc[2 * kMaxChain] = sc;
+}
+
+// v *= scale (the chain's velocity scaling), all 3N components.
+__global__ void k_scale_v(int64_t n3, const double* __restrict__ scale, double* __restrict__ v) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n3) v[k] *= *scale;
+}
+
 __global__ void k_max_partials(const double* __restrict__ partial, int nblocks, int slot,
                                double* __restrict__ out) {
   __shared__ double sh[kBlock];
@@ -282,6 +323,13 @@ hipError_t launch_kick_drift(int64_t N, double dt, CellGrid g, const float* F, c
 hipError_t launch_select_bin(const double* partial, int nblocks, int32_t* flags, double skin,
                              const BinEdges& be, hipStream_t st) {
   hipLaunchKernelGGL(k_select_bin, dim3(1), dim3(kBlock), 0, st, partial, nblocks, flags, skin, be);
+  return hipGetLastError();
+}
+
+hipError_t launch_nhc_half(int64_t N, const double* ke, double* nhc, int M, double kT, double tau, double h,
+                           double* v, hipStream_t st) {
+  hipLaunchKernelGGL(k_nhc_half, dim3(1), dim3(64), 0, st, ke, nhc, M, kT, 3.0 * (double)N - 3.0, tau * tau, h);
+  hipLaunchKernelGGL(k_scale_v, dim3(grid_blocks(3 * N)), dim3(kBlock), 0, st, 3 * N, nhc + 2 * kMaxChain, v);
   return hipGetLastError();
 }
 

@@ -27,8 +27,9 @@ EXPORTED = [
     "nep_param_count", "nep_model_create", "nep_model_destroy", "nep_system_workspace_bytes",
     "nep_system_create", "nep_system_destroy", "nep_system_set_params", "nep_set_state",
     "nep_build_neighbors", "nep_export_neighbors", "nep_compute_energy_forces_virial", "nep_step",
-    "nep_set_judge", "nep_get_state", "nep_get_stats", "nep_train_forward", "nep_train_backward",
-    "nep_train_forward_params", "nep_train_backward_params", "nep_adam_update",
+    "nep_set_judge", "nep_set_thermostat", "nep_get_thermostat", "nep_get_state", "nep_get_stats",
+    "nep_train_forward", "nep_train_backward", "nep_train_forward_params", "nep_train_backward_params",
+    "nep_adam_update",
     "nep_surrogate_error", "nep_status_string", "nep_last_error", "nep_profile", "nep_profile_read",
     "nep_pair_counts",
 ]
@@ -75,6 +76,8 @@ def load_library(path: str = LIB_PATH):
         "nep_step": [vp, i64, f64, i32, f64, i32, f64, f64, i32, vp, i32, i64, vp],
         "nep_get_state": [vp, vp, vp, vp, i32],
         "nep_set_judge": [vp, i32],
+        "nep_set_thermostat": [vp, f64, f64, i32],
+        "nep_get_thermostat": [vp, vp, vp, vp],
         "nep_get_stats": [vp, vp],
         "nep_train_forward": [vp, i32, vp, vp, vp],
         "nep_train_backward": [vp, i32, vp, f64, vp, vp, i32],
@@ -272,6 +275,18 @@ class NEPSystem:
                                       _np_ptr(th) if th is not None else None, int(max(thermo_every, 1)),
                                       int(max_rows), ctypes.byref(rows)))
         return th[: rows.value].copy() if th is not None else None
+
+    def set_thermostat(self, temperature: float, tau: float = 100.0, chain: int = 3):
+        """NVT with a Nose-Hoover chain (chain = 0: back to NVE); resets the chain state."""
+        self._check(self.lib.nep_set_thermostat(self.handle, float(temperature), float(tau), int(chain)))
+        self._chain = int(chain)
+
+    def get_thermostat(self):
+        """(eta, v_eta, chain energy in eV) of the Nose-Hoover chain."""
+        m = getattr(self, "_chain", 0)
+        eta, ve, e = np.zeros(max(m, 1)), np.zeros(max(m, 1)), ctypes.c_double()
+        self._check(self.lib.nep_get_thermostat(self.handle, _np_ptr(eta), _np_ptr(ve), ctypes.byref(e)))
+        return eta[:m], ve[:m], e.value
 
     def stats(self) -> dict:
         s = np.zeros(4, np.int64)
