@@ -261,6 +261,8 @@ def main():
     ap.add_argument("--forms", action="store_true",
                     help="time FP32, BF16 and surrogate MTS on the 200^3-cell (32M-atom) box instead")
     ap.add_argument("--epochs", type=int, default=40, help="surrogate training epochs (forms only)")
+    ap.add_argument("--nvt", type=float, default=0.0,
+                    help="run NVT at this temperature (K) with a Nose-Hoover chain of 3, tau 100 fs")
     ap.add_argument("--zbl", type=float, default=0.0,
                     help="add the ZBL repulsion with this outer radius in A (the paper's Cu model uses 2.0)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -294,6 +296,8 @@ def main():
     s = nep.NEPSystem(nep.NEPModel(hp, params), at.n, at.box)
     s.set_state(at.x, at.types, at.masses, at.v)
     s.build_neighbors(1.0)
+    if args.nvt > 0:
+        s.set_thermostat(args.nvt, tau=100.0, chain=3)
     s.step(args.warmup, dt=1.0, rebuild_every=10, skin=1.0, precision=args.precision)
     # timed region
     s.profile(True)
@@ -328,7 +332,8 @@ def main():
         "vs_baseline": None,
         "dtype": "fp32" if args.precision == "fp32" else "fp32+bf16-mfma",
         "data": "synthetic (seeded FCC box, random-weight NEP)",
-        "config": {"workload": f"fcc_cu_{args.cells}x{args.cells}x{args.cells}_cells_{n}_atoms_nve",
+        "config": {"workload": f"fcc_cu_{args.cells}x{args.cells}x{args.cells}_cells_{n}_atoms_"
+                               + (f"nvt_{args.nvt:g}K" if args.nvt > 0 else "nve"),
                    "n_atoms": n, "model": "NEP rc 6/5 A, n_max 4, basis 8, l_max 4 + 4-body, 30 hidden"
                    + (f", ZBL outer {args.zbl} A" if args.zbl > 0 else ""),
                    "precision": args.precision, "dt_fs": 1.0, "rebuild_every": 10, "skin_A": 1.0,

@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers 
 #pragma unroll
   for (int k = 0; k < NA * NC; ++k) s[k] = 0.f;
   const int ti = valid ? (MULTI ? b.type[i] : 0) : 0;
-  int nclose = 0;  // pairs inside the ZBL radius
+  ZblSeenFor<MULTI> zs;  // pairs inside the ZBL radius
   double xi = 0.0, yi = 0.0, zi = 0.0;
 
   if (valid) {
@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers 
     yi = rec_f64(w0.z, w0.w);
     zi = rec_f64(w1.x, w1.y);
     int nr = 0, na = 0;
-    desc_accumulate<S, MULTI>(m, b, i, ti, xi, yi, zi, Lx, Ly, Lz, q, s, nclose, nr, na);
+    desc_accumulate<S, MULTI>(m, b, i, ti, xi, yi, zi, Lx, Ly, Lz, q, s, zs, nr, na);
     b.nactR[i] = nr;
     b.nactA[i] = na;
     desc_finish<S>(s, q);
@@ -263,7 +263,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers 
     b.F[N + i] = 0.f;
     b.F[2 * N + i] = 0.f;
     // ZBL energy (half of each close pair), after the descriptors are no longer live
-    if (nclose) zbl_center<MULTI>(m, b, i, ti, xi, yi, zi, &U, nullptr, nullptr);
+    if (zs.n) zbl_center<MULTI>(m, b, i, ti, xi, yi, zi, zs, &U, nullptr, nullptr);
     b.U[i] = U;
   }
   const double e = block_sum(valid ? (double)U : 0.0, red);
@@ -357,7 +357,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
     for (int k = 0; k < NA * NC; ++k) G[k] = b.G[(int64_t)k * N + i];
     const double rcR2 = m.rcR64 * m.rcR64, rcA2 = m.rcA64 * m.rcA64;
     const int kR = radial_bound(b, i), kA = angular_bound(b, i);
-    int nclose = 0;  // pairs inside the ZBL radius
+    ZblSeenFor<MULTI> zs;  // pairs inside the ZBL radius
     // One pass over the list. Radial pairs: gather, F_i += (dU_i/dr_ij + dU_j/dr_ji) along u,
     // with the neighbour's radial coefficients read from its record.
     // Angular and four-body pairs (the angular prefix inside rc_angular): scatter
@@ -398,7 +398,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
           sj = fmaf(wj[k], e[k], sj);
         }
       }
-      nclose += r2 < m.zbl_o2 ? 1 : 0;
+      if (r2 < m.zbl_o2) zs.add(p);
       const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
       const float st = (si + sj);
       fx = fmaf(st, ux, fx);
@@ -461,9 +461,9 @@ __global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) 
 #pragma unroll
         for (int c = 0; c < 3; ++c) w[a * 3 + c] = fmaf(-d[a], f[c], w[a * 3 + c]);
     });
-    if (nclose) {
+    if (zs.n) {
       float f[3] = {fx, fy, fz};
-      zbl_center<MULTI>(m, b, i, ti, xi, yi, zi, nullptr, f, w);
+      zbl_center<MULTI>(m, b, i, ti, xi, yi, zi, zs, nullptr, f, w);
       fx = f[0];
       fy = f[1];
       fz = f[2];

@@ -313,17 +313,39 @@ __device__ __forceinline__ double pair_r2_64(double xj, double yj, double zj, do
   return ex * ex + ey * ey + ez * ez;
 }
 
-// ZBL terms of center i over its list (the pairs with r^2 < zbl_o2): half of each
-// pair's energy into uz, and, when f is given, the force on i (the whole pair
-// derivative, both atoms' halves, along u) into f[3] and the virial of dU_i/dr_ij
-// into w[9]. Called only for centers that have such pairs, after the main loop.
+// Close pairs (inside the outer ZBL radius) seen by a main loop: their count and
+// the list positions of the first CAP of them, 16 bits each (CAP = 0: count only,
+// for kernels with no registers to spare).
+template <int CAP>
+struct ZblSeen {
+  static_assert(CAP >= 0 && CAP <= 4, "four 16-bit slots");
+  int n = 0;
+  uint64_t slots = 0;
+  __device__ __forceinline__ void add(int p) {
+    if constexpr (CAP > 0) {
+      if (n < CAP) slots |= (uint64_t)p << (16 * n);
+    }
+    ++n;
+  }
+};
 template <bool MULTI>
+using ZblSeenFor = ZblSeen<MULTI ? 0 : 4>;
+
+// ZBL terms of center i (the pairs with r^2 < zbl_o2): half of each pair's energy
+// into uz, and, when f is given, the force on i (the whole pair derivative, both
+// atoms' halves, along u) into f[3] and the virial of dU_i/dr_ij into w[9]. Called
+// only for centers that have such pairs, after the main loop: it visits the
+// recorded list positions, or the whole radial list when there were more.
+template <bool MULTI, int CAP>
 __device__ __forceinline__ void zbl_center(const ModelDev& m, const EvalBuffers& b, int64_t i, int ti, double xi,
-                                        double yi, double zi, float* uz, float* f, float* w) {
+                                        double yi, double zi, const ZblSeen<CAP>& seen, float* uz, float* f,
+                                        float* w) {
   const int64_t N = b.N;
   const double Lx = b.box[0], Ly = b.box[1], Lz = b.box[2];
-  const int kR = radial_bound(b, i);
-  for (int p = 0; p < kR; ++p) {
+  const bool all = seen.n > CAP;
+  const int kR = all ? radial_bound(b, i) : seen.n;
+  for (int q = 0; q < kR; ++q) {
+    const int p = all ? q : (int)((seen.slots >> (16 * q)) & 0xffffu);
     const int32_t j = b.nbr[(int64_t)p * N + i];
     const uint4 w0 = b.rec[4 * (int64_t)j], w1 = b.rec[4 * (int64_t)j + 1];
     const double ex = min_image(rec_f64(w0.x, w0.y) - xi, Lx);
@@ -352,11 +374,12 @@ __device__ __forceinline__ void zbl_center(const ModelDev& m, const EvalBuffers&
 // Radial descriptors q[0..NR) and angular accumulators s[NA][NC] of center i over
 // the pairs inside the true cutoffs, all channels in one pass over the neighbours
 // (geometry computed once per pair and reused for every n). Returns the pair counts
-// and the number of pairs inside the ZBL radius (nclose).
+// and the pairs inside the ZBL radius (zs).
 template <class S, bool MULTI>
 __device__ __forceinline__ void desc_accumulate(const ModelDev& m, const EvalBuffers& b, int64_t i, int ti,
                                                 double xi, double yi, double zi, double Lx, double Ly,
-                                                double Lz, float* q, float* s, int& nclose, int& nr, int& na) {
+                                                double Lz, float* q, float* s, ZblSeenFor<MULTI>& zs, int& nr,
+                                                int& na) {
   constexpr int NR = S::NR, NA = S::NA, NC = S::NC;
   const int64_t N = b.N;
   const float rcR_inv = 1.f / m.rcR, rcA_inv = 1.f / m.rcA;
@@ -381,7 +404,7 @@ __device__ __forceinline__ void desc_accumulate(const ModelDev& m, const EvalBuf
     float r, rinv;
     pair_r(dx, dy, dz, r, rinv);
     const int tj = MULTI ? b.type[j] : 0;
-    nclose += r2 < m.zbl_o2 ? 1 : 0;
+    if (r2 < m.zbl_o2) zs.add(p);
     if constexpr (MULTI) {
       float g[NR];
       radial_g<NR, S::KR>(r, rcR_inv, m.cR + (ti * m.T + tj) * NR * S::KR, g);

@@ -52,8 +52,8 @@ k_train_backward(ModelDev m, EvalBuffers b, const float* __restrict__ gF, double
     const int ti = MULTI ? b.type[i] : 0;
     const double xi = x[i], yi = x[N + i], zi = x[2 * N + i];
     int nr = 0, na = 0;
-    int nclose = 0;  // the ZBL terms do not depend on the parameters
-    desc_accumulate<S, MULTI>(m, b, i, ti, xi, yi, zi, Lx, Ly, Lz, q, s, nclose, nr, na);
+    ZblSeenFor<MULTI> zs;  // the ZBL terms do not depend on the parameters
+    desc_accumulate<S, MULTI>(m, b, i, ti, xi, yi, zi, Lx, Ly, Lz, q, s, zs, nr, na);
     const double rcR2 = m.rcR64 * m.rcR64, rcA2 = m.rcA64 * m.rcA64;
     desc_finish<S>(s, q);
     if (gF) {
@@ -283,8 +283,8 @@ k_train_cgrad(ModelDev m, EvalBuffers b, const float* __restrict__ gF, double gE
     yi = x[N + i];
     zi = x[2 * N + i];
     int nr = 0, na = 0;
-    int nclose = 0;  // the ZBL terms do not depend on the parameters
-    desc_accumulate<S, MULTI>(m, b, i, ti, xi, yi, zi, Lx, Ly, Lz, q, s, nclose, nr, na);
+    ZblSeenFor<MULTI> zs;  // the ZBL terms do not depend on the parameters
+    desc_accumulate<S, MULTI>(m, b, i, ti, xi, yi, zi, Lx, Ly, Lz, q, s, zs, nr, na);
     desc_finish<S>(s, q);
     if (gF) {
       wi0 = gF[i];
