@@ -62,3 +62,20 @@ def test_host_only_calls(lib):
     bad = np.array([1.0, np.nan])
     with pytest.raises(Exception):
         nep.NEPModel(hp, bad)
+
+
+@pytest.mark.parametrize("zbl,ok", [((2.0, None, (29.0,)), True), ((2.4, 2.05, (29.0,)), True),
+                                    ((7.0, None, (29.0,)), False),    # outer radius beyond rc_radial
+                                    ((2.0, 2.0, (29.0,)), False),     # inner radius not below the outer
+                                    ((2.0, None, (0.0,)), False)])    # no atomic number
+def test_zbl_hparams_validated_on_the_host(lib, zbl, ok):
+    from paper_2604_24816_amd import inputs as I
+    from paper_2604_24816_amd import nep
+    outer, inner, z = zbl
+    hp = I.HParams(zbl_outer=outer, zbl_inner_radius=inner, zbl_z=z)
+    hs = nep._hp_struct(hp)
+    n, d = ctypes.c_int64(), ctypes.c_int32()
+    st = lib.nep_param_count(ctypes.byref(hs), ctypes.byref(n), ctypes.byref(d))
+    assert (st == 0) == ok
+    if ok:
+        assert n.value == I.HParams().n_params()   # ZBL adds no parameters
