@@ -57,7 +57,10 @@ enum nep_status {
 
 enum nep_precision {
   NEP_FP32 = 0,  /* descriptors, forces FP32; network FP32 MFMA, FP32 accumulate   */
-  NEP_BF16 = 1   /* as FP32, but the network's matrix operands are bfloat16        */
+  NEP_BF16 = 1,  /* as FP32, but the network's matrix operands are bfloat16        */
+  NEP_FP64 = 2   /* every operation FP64 from FP64 parameters, for checks (finite
+                    differences, reference comparisons): much slower; accepted by
+                    nep_compute_energy_forces_virial only                        */
 };
 
 /* Model hyperparameters (Section VI.A: n_max 4, basis size 8, three-body

@@ -130,6 +130,8 @@ struct nep_system {
   int32_t* flags;
   float* mparams[2];
   uint16_t* mbf[2];
+  double* mparams64[2];
+  Model64 m64[2];
   int nblocks = 1;
   // kernel timing with events (off unless nep_profile enables it)
   bool prof = false;
@@ -199,6 +201,7 @@ int64_t layout(nep_system* s, char* base, int64_t N, int capR, int capA, int max
   for (int k = 0; k < 2; ++k) {
     S.mparams[k] = c.take<float>(np[k] > 0 ? np[k] : 1);
     S.mbf[k] = c.take<uint16_t>(HD[k] > 0 ? HD[k] : 1);
+    S.mparams64[k] = c.take<double>(np[k] > 0 ? np[k] : 1);
   }
   S.vjp = nullptr;
   S.qs = nullptr;
@@ -232,6 +235,8 @@ int upload_model(nep_system* s, int slot) {
   for (int k = 0; k < H * D; ++k) bf[k] = f64_to_bf16_bits(m.params[offW0 + k]);
   HIPCHK(hipMemcpyAsync(s->mparams[slot], f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, s->st));
   HIPCHK(hipMemcpyAsync(s->mbf[slot], bf.data(), bf.size() * sizeof(uint16_t), hipMemcpyHostToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(s->mparams64[slot], m.params.data(), m.params.size() * sizeof(double),
+                        hipMemcpyHostToDevice, s->st));
   HIPCHK(hipStreamSynchronize(s->st));  // host vectors go out of scope
   ModelDev& d = s->mdev[slot];
   d.T = T;
@@ -256,6 +261,17 @@ int upload_model(nep_system* s, int slot) {
   d.w1 = d.b0 + H;
   d.b1 = d.w1 + H;
   d.W0bf = s->mbf[slot];
+  {
+    Model64& q = s->m64[slot];
+    const double* p64 = s->mparams64[slot];
+    q.cR = p64;
+    q.cA = q.cR + (int64_t)T * T * nR * kR;
+    q.sigma = q.cA + (int64_t)T * T * nA * kA;
+    q.W0 = q.sigma + D;
+    q.b0 = q.W0 + (int64_t)H * D;
+    q.w1 = q.b0 + H;
+    q.b1 = m.params[offW0 + (int64_t)H * D + 2 * H];
+  }
   // ZBL constants per species pair: k_e Z_i Z_j (k_e = e^2 / 4 pi eps0 in eV A) and
   // 1 / a with the universal screening length a = 0.8854 a_0 / (Z_i^0.23 + Z_j^0.23)
   const double zo = m.hp.zbl_rc_outer;
@@ -663,21 +679,32 @@ int nep_export_neighbors(nep_system* s, int32_t which, int64_t* offsets, int32_t
 int nep_compute_energy_forces_virial(nep_system* s, int32_t slot, int32_t precision, double* energy,
                                      double* virial9, double* forces, double* per_atom_energy,
                                      int32_t on_device) {
-  if (!s || !energy || !virial9 || slot < 0 || slot > 1 || !s->has_model[slot] || precision < 0 || precision > 1)
+  if (!s || !energy || !virial9 || slot < 0 || slot > 1 || !s->has_model[slot] || precision < 0 || precision > 2)
     return fail(s, NEP_ERR_ARG, "bad argument");
   if (!s->have_list) return fail(s, NEP_ERR_STALE_LIST, "build the neighbour lists first");
-  int st = do_eval(s, slot, precision);
-  if (st) return st;
-  if ((st = reduce_ew(s, 0))) return st;
   const int64_t N = s->N;
+  int st;
+  // FP64: per-atom energies and dU/dq in the dU/ds buffer (1 + D <= 60 doubles per
+  // atom), forces in the sort scratch x_alt; the FP32 forces of the slot are stale after
+  double* U64 = reinterpret_cast<double*>(s->G);
+  double* F64 = s->x_alt;
+  if (precision == NEP_FP64) {
+    HIPCHK(launch_eval64(s->mdev[slot], s->m64[slot], eval_buffers(s, slot), U64, U64 + N, F64, s->st));
+    s->force_valid[slot] = false;
+  } else if ((st = do_eval(s, slot, precision))) {
+    return st;
+  }
+  if ((st = reduce_ew(s, 0))) return st;
   if (forces) {
     double* dst = on_device ? forces : s->staging;
-    HIPCHK(launch_forces_out(N, s->perm, s->F[slot], dst, s->st));
+    if (precision == NEP_FP64) HIPCHK(launch_state_out(N, s->perm, F64, dst, s->st));
+    else HIPCHK(launch_forces_out(N, s->perm, s->F[slot], dst, s->st));
     if (!on_device) HIPCHK(hipMemcpyAsync(forces, s->staging, 3 * N * sizeof(double), hipMemcpyDeviceToHost, s->st));
   }
   if (per_atom_energy) {
     double* dst = on_device ? per_atom_energy : s->staging;
-    HIPCHK(launch_scalar_out(N, s->perm, s->U, dst, s->st));
+    if (precision == NEP_FP64) HIPCHK(launch_scalar_out64(N, s->perm, U64, dst, s->st));
+    else HIPCHK(launch_scalar_out(N, s->perm, s->U, dst, s->st));
     if (!on_device)
       HIPCHK(hipMemcpyAsync(per_atom_energy, s->staging, N * sizeof(double), hipMemcpyDeviceToHost, s->st));
   }

@@ -248,6 +248,23 @@ hipError_t launch_kick(int64_t N, double dt, const float* F, const int32_t* type
                        double* v, hipStream_t st);
 hipError_t launch_kick_diff(int64_t N, double dt, const float* Fa, const float* Fb,
                             const int32_t* type, MassTable mt, double* v, hipStream_t st);
+// FP64 parameters of one model (the packed FP64 vector on the device), for the
+// FP64 evaluation (nep_eval64.hip).
+struct Model64 {
+  const double* cR;
+  const double* cA;
+  const double* sigma;
+  const double* W0;
+  const double* b0;
+  const double* w1;
+  double b1;
+};
+// Energy partials, forces F64 [3][N] (sorted order) and virial partials in FP64;
+// U64 [N] and Fp64 [D][N] are its per-atom energies and dU/dq.
+hipError_t launch_eval64(const ModelDev& m, const Model64& p, const EvalBuffers& b, double* U64, double* Fp64,
+                         double* F64, hipStream_t st);
+hipError_t launch_scalar_out64(int64_t N, const int32_t* perm, const double* u, double* out, hipStream_t st);
+
 // Nose-Hoover chain: at most kMaxChain thermostats; the device state holds
 // {eta[kMaxChain], v_eta[kMaxChain], velocity scale}.
 constexpr int kMaxChain = 16;

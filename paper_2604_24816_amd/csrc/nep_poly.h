@@ -27,40 +27,40 @@ __host__ __device__ constexpr int comp_l(int lm) {
 }
 
 // Calls f(lm, P) for every component lm < NC (NC = 3, 8, 15 or 24).
-template <int NC, typename Fn>
-__device__ __forceinline__ void for_each_poly(float x, float y, float z, Fn&& f) {
+template <int NC, typename R, typename Fn>
+__device__ __forceinline__ void for_each_poly(R x, R y, R z, Fn&& f) {
   f(0, y);
   f(1, z);
   f(2, x);
   if constexpr (NC > 3) {
-    const float x2 = x * x, y2 = y * y, z2 = z * z;
+    const R x2 = x * x, y2 = y * y, z2 = z * z;
     f(3, x * y);
     f(4, y * z);
-    f(5, 2.f * z2 - x2 - y2);
+    f(5, R(2) * z2 - x2 - y2);
     f(6, x * z);
     f(7, x2 - y2);
     if constexpr (NC > 8) {
-      const float t = 4.f * z2 - x2 - y2;
-      f(8, y * (3.f * x2 - y2));
+      const R t = R(4) * z2 - x2 - y2;
+      f(8, y * (R(3) * x2 - y2));
       f(9, x * y * z);
       f(10, y * t);
-      f(11, z * (2.f * z2 - 3.f * x2 - 3.f * y2));
+      f(11, z * (R(2) * z2 - R(3) * x2 - R(3) * y2));
       f(12, x * t);
       f(13, z * (x2 - y2));
-      f(14, x * (x2 - 3.f * y2));
+      f(14, x * (x2 - R(3) * y2));
       if constexpr (NC > 15) {
-        const float rho2 = x2 + y2;
-        const float a = 6.f * z2 - rho2;
-        const float b = 4.f * z2 - 3.f * rho2;
+        const R rho2 = x2 + y2;
+        const R a = R(6) * z2 - rho2;
+        const R b = R(4) * z2 - R(3) * rho2;
         f(15, x * y * (x2 - y2));
-        f(16, y * z * (3.f * x2 - y2));
+        f(16, y * z * (R(3) * x2 - y2));
         f(17, x * y * a);
         f(18, y * z * b);
-        f(19, 8.f * z2 * z2 - 24.f * z2 * rho2 + 3.f * rho2 * rho2);
+        f(19, R(8) * z2 * z2 - R(24) * z2 * rho2 + R(3) * rho2 * rho2);
         f(20, x * z * b);
         f(21, (x2 - y2) * a);
-        f(22, x * z * (x2 - 3.f * y2));
-        f(23, x2 * x2 - 6.f * x2 * y2 + y2 * y2);
+        f(22, x * z * (x2 - R(3) * y2));
+        f(23, x2 * x2 - R(6) * x2 * y2 + y2 * y2);
       }
     }
   }
@@ -68,43 +68,43 @@ __device__ __forceinline__ void for_each_poly(float x, float y, float z, Fn&& f)
 
 // Calls f(lm, P, dP/dx, dP/dy, dP/dz) with the gradient of the homogeneous
 // polynomial evaluated at u.
-template <int NC, typename Fn>
-__device__ __forceinline__ void for_each_poly_grad(float x, float y, float z, Fn&& f) {
-  f(0, y, 0.f, 1.f, 0.f);
-  f(1, z, 0.f, 0.f, 1.f);
-  f(2, x, 1.f, 0.f, 0.f);
+template <int NC, typename R, typename Fn>
+__device__ __forceinline__ void for_each_poly_grad(R x, R y, R z, Fn&& f) {
+  f(0, y, R(0), R(1), R(0));
+  f(1, z, R(0), R(0), R(1));
+  f(2, x, R(1), R(0), R(0));
   if constexpr (NC > 3) {
-    const float x2 = x * x, y2 = y * y, z2 = z * z;
-    f(3, x * y, y, x, 0.f);
-    f(4, y * z, 0.f, z, y);
-    f(5, 2.f * z2 - x2 - y2, -2.f * x, -2.f * y, 4.f * z);
-    f(6, x * z, z, 0.f, x);
-    f(7, x2 - y2, 2.f * x, -2.f * y, 0.f);
+    const R x2 = x * x, y2 = y * y, z2 = z * z;
+    f(3, x * y, y, x, R(0));
+    f(4, y * z, R(0), z, y);
+    f(5, R(2) * z2 - x2 - y2, -R(2) * x, -R(2) * y, R(4) * z);
+    f(6, x * z, z, R(0), x);
+    f(7, x2 - y2, R(2) * x, -R(2) * y, R(0));
     if constexpr (NC > 8) {
-      const float xy = x * y, xz = x * z, yz = y * z;
-      const float t = 4.f * z2 - x2 - y2;
-      f(8, y * (3.f * x2 - y2), 6.f * xy, 3.f * (x2 - y2), 0.f);
+      const R xy = x * y, xz = x * z, yz = y * z;
+      const R t = R(4) * z2 - x2 - y2;
+      f(8, y * (R(3) * x2 - y2), R(6) * xy, R(3) * (x2 - y2), R(0));
       f(9, xy * z, yz, xz, xy);
-      f(10, y * t, -2.f * xy, 4.f * z2 - x2 - 3.f * y2, 8.f * yz);
-      f(11, z * (2.f * z2 - 3.f * x2 - 3.f * y2), -6.f * xz, -6.f * yz, 6.f * z2 - 3.f * x2 - 3.f * y2);
-      f(12, x * t, 4.f * z2 - 3.f * x2 - y2, -2.f * xy, 8.f * xz);
-      f(13, z * (x2 - y2), 2.f * xz, -2.f * yz, x2 - y2);
-      f(14, x * (x2 - 3.f * y2), 3.f * (x2 - y2), -6.f * xy, 0.f);
+      f(10, y * t, -R(2) * xy, R(4) * z2 - x2 - R(3) * y2, R(8) * yz);
+      f(11, z * (R(2) * z2 - R(3) * x2 - R(3) * y2), -R(6) * xz, -R(6) * yz, R(6) * z2 - R(3) * x2 - R(3) * y2);
+      f(12, x * t, R(4) * z2 - R(3) * x2 - y2, -R(2) * xy, R(8) * xz);
+      f(13, z * (x2 - y2), R(2) * xz, -R(2) * yz, x2 - y2);
+      f(14, x * (x2 - R(3) * y2), R(3) * (x2 - y2), -R(6) * xy, R(0));
       if constexpr (NC > 15) {
-        const float rho2 = x2 + y2;
-        const float a = 6.f * z2 - rho2;
-        const float b = 4.f * z2 - 3.f * rho2;
-        const float xyz = xy * z;
-        f(15, xy * (x2 - y2), 3.f * x2 * y - y2 * y, x2 * x - 3.f * x * y2, 0.f);
-        f(16, yz * (3.f * x2 - y2), 6.f * xyz, 3.f * z * (x2 - y2), y * (3.f * x2 - y2));
-        f(17, xy * a, y * (6.f * z2 - 3.f * x2 - y2), x * (6.f * z2 - x2 - 3.f * y2), 12.f * xyz);
-        f(18, yz * b, -6.f * xyz, z * (4.f * z2 - 3.f * x2 - 9.f * y2), 3.f * y * (4.f * z2 - rho2));
-        f(19, 8.f * z2 * z2 - 24.f * z2 * rho2 + 3.f * rho2 * rho2, 12.f * x * (rho2 - 4.f * z2),
-          12.f * y * (rho2 - 4.f * z2), 16.f * z * (2.f * z2 - 3.f * rho2));
-        f(20, xz * b, z * (4.f * z2 - 9.f * x2 - 3.f * y2), -6.f * xyz, 3.f * x * (4.f * z2 - rho2));
-        f(21, (x2 - y2) * a, 4.f * x * (3.f * z2 - x2), 4.f * y * (y2 - 3.f * z2), 12.f * z * (x2 - y2));
-        f(22, xz * (x2 - 3.f * y2), 3.f * z * (x2 - y2), -6.f * xyz, x * (x2 - 3.f * y2));
-        f(23, x2 * x2 - 6.f * x2 * y2 + y2 * y2, 4.f * x * (x2 - 3.f * y2), 4.f * y * (y2 - 3.f * x2), 0.f);
+        const R rho2 = x2 + y2;
+        const R a = R(6) * z2 - rho2;
+        const R b = R(4) * z2 - R(3) * rho2;
+        const R xyz = xy * z;
+        f(15, xy * (x2 - y2), R(3) * x2 * y - y2 * y, x2 * x - R(3) * x * y2, R(0));
+        f(16, yz * (R(3) * x2 - y2), R(6) * xyz, R(3) * z * (x2 - y2), y * (R(3) * x2 - y2));
+        f(17, xy * a, y * (R(6) * z2 - R(3) * x2 - y2), x * (R(6) * z2 - x2 - R(3) * y2), R(12) * xyz);
+        f(18, yz * b, -R(6) * xyz, z * (R(4) * z2 - R(3) * x2 - R(9) * y2), R(3) * y * (R(4) * z2 - rho2));
+        f(19, R(8) * z2 * z2 - R(24) * z2 * rho2 + R(3) * rho2 * rho2, R(12) * x * (rho2 - R(4) * z2),
+          R(12) * y * (rho2 - R(4) * z2), R(16) * z * (R(2) * z2 - R(3) * rho2));
+        f(20, xz * b, z * (R(4) * z2 - R(9) * x2 - R(3) * y2), -R(6) * xyz, R(3) * x * (R(4) * z2 - rho2));
+        f(21, (x2 - y2) * a, R(4) * x * (R(3) * z2 - x2), R(4) * y * (y2 - R(3) * z2), R(12) * z * (x2 - y2));
+        f(22, xz * (x2 - R(3) * y2), R(3) * z * (x2 - y2), -R(6) * xyz, x * (x2 - R(3) * y2));
+        f(23, x2 * x2 - R(6) * x2 * y2 + y2 * y2, R(4) * x * (x2 - R(3) * y2), R(4) * y * (y2 - R(3) * x2), R(0));
       }
     }
   }

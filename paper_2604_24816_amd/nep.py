@@ -21,7 +21,9 @@ LIB_PATH = os.path.join(_HERE, "libnep.so")
 
 NEP_FP32 = 0
 NEP_BF16 = 1
-_PREC = {"fp32": NEP_FP32, "bf16": NEP_BF16, NEP_FP32: NEP_FP32, NEP_BF16: NEP_BF16}
+NEP_FP64 = 2   # evaluation only: FP64 throughout, for checks
+_PREC = {"fp32": NEP_FP32, "bf16": NEP_BF16, "fp64": NEP_FP64, NEP_FP32: NEP_FP32, NEP_BF16: NEP_BF16,
+         NEP_FP64: NEP_FP64}
 
 EXPORTED = [
     "nep_param_count", "nep_model_create", "nep_model_destroy", "nep_system_workspace_bytes",

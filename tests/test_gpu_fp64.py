@@ -1,0 +1,83 @@
+"""The FP64 evaluation on the GPU (NEP_FP64): agreement with the FP64 oracle to
+round-off, and central differences of the GPU's own energies at h = 1e-5 A.
+
+Bars: FP64 sums in a different order from the oracle's differ by ~1e-16 relative
+per operation, so per-atom energies (~0.2 eV) and forces (~0.05 eV/A) agree to well
+under 1e-11; the bars are 1e-11 eV per atom and 1e-10 eV/A (virial 1e-11 eV per
+atom). The difference quotient sums per-atom energy changes (each ~0.2 eV, FP64),
+so its rounding noise is ~1e-16 * 0.2 eV * sqrt(200 changed atoms) / 2h ~ 1e-11 eV/A,
+and its truncation error h^2 |F'''| / 6 is far below that at h = 1e-5 A.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_24816_amd import inputs as I
+from tests.gpu_helpers import make_system, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _compare(s, m, at, slot=0):
+    E, W, F, U = s.compute(slot=slot, precision="fp64", per_atom=True)
+    Eo, Wo, Uo, Fo = oracle.evaluate(m, at.x, at.types, at.box)
+    du, de = np.abs(U - Uo).max(), abs(E - Eo) / at.n
+    df, dw = np.abs(F - Fo).max(), np.abs(W - Wo).max() / at.n
+    say(f"  N={at.n} fp64: max|dU|={du:.2e} |dE|/N={de:.2e} max|dF|={df:.2e} max|dW|/N={dw:.2e}")
+    assert du < 1e-11 and de < 1e-11 and df < 1e-10 and dw < 1e-11, (du, de, df, dw)
+
+
+@pytest.mark.parametrize("kind", ["full", "surrogate", "two_species_zbl"])
+def test_fp64_matches_oracle_to_roundoff(kind):
+    if kind == "surrogate":
+        thp = I.FULL_HPARAMS
+        hp = I.SURROGATE_HPARAMS
+        params = I.surrogate_from_teacher(thp, I.random_model(thp, 0), hp, 3)
+        at = I.fcc_box(10, 0.1, 9)
+        caps = (160, 96)
+    elif kind == "two_species_zbl":
+        hp = I.HParams(n_types=2, zbl_outer=2.0, zbl_z=(29.0, 79.0))
+        params = I.random_model(hp, 8)
+        a = I.alloy_box(6, 1, 30, 2, 0.12, 3)
+        at = I.Atoms(x=a.x * 0.82, types=a.types, box=a.box * 0.82, masses=a.masses)
+        caps = (320, 200)
+    else:
+        hp = I.FULL_HPARAMS
+        params = I.random_model(hp, 0)
+        at = I.workload_small()
+        caps = (160, 96)
+    say(f"case: FP64 evaluation, {kind}, N={at.n}")
+    s = make_system(at, hp, params, cap_radial=caps[0], cap_angular=caps[1])
+    _compare(s, oracle.Model.from_hparams(hp, params), at)
+    # the FP32 path still works after an FP64 evaluation clobbered its scratch
+    E, W, F, U = s.compute(per_atom=True)
+    Eo, Wo, Uo, Fo = oracle.evaluate(oracle.Model.from_hparams(hp, params), at.x, at.types, at.box)
+    assert np.abs(F - Fo).max() < 1e-4 + 5e-7 * np.abs(Fo).max()
+
+
+def test_fp64_forces_are_minus_the_energy_gradient():
+    """64 random (atom, component) pairs of a thermally disordered 32,000-atom box."""
+    hp = I.FULL_HPARAMS
+    params = I.random_model(hp, 0)
+    at = I.workload_disordered_frames(20, 1)[0]
+    say(f"case: FP64 central differences, h = 1e-5 A, N={at.n}")
+    s = make_system(at, hp, params)
+    _, _, F, _ = s.compute(precision="fp64", per_atom=True)
+    rng = np.random.default_rng(23)
+    h = 1e-5
+    worst = 0.0
+    for _ in range(64):
+        k, c = int(rng.integers(at.n)), int(rng.integers(3))
+        Us = []
+        for sgn in (1, -1):
+            x = at.x.copy()
+            x[k, c] += sgn * h
+            s.set_positions(x)
+            s.build_neighbors(1.0)
+            Us.append(s.compute(precision="fp64", per_atom=True)[3])
+        fd = -np.sum(Us[0] - Us[1]) / (2 * h)
+        worst = max(worst, abs(fd - F[k, c]))
+    say(f"  max |FD - F| = {worst:.2e} eV/A (max|F| {np.abs(F).max():.2e})")
+    assert worst < 1e-9
