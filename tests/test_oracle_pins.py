@@ -514,6 +514,24 @@ def test_mts_reduces_to_velocity_verlet(full_hp):
     assert np.all(err[:, 0] > 0)
 
 
+def test_mts_time_reversible(full_hp):
+    """r-RESPA is a symmetric splitting: three blocks forward, reverse the velocities,
+    three blocks more return to the start (untrained surrogate, so the slow correction
+    is large)."""
+    hp = full_hp
+    m = oracle.Model.from_hparams(hp, I.random_model(hp, 0))
+    sur_hp = I.SURROGATE_HPARAMS
+    s = oracle.Model.from_hparams(sur_hp, I.surrogate_from_teacher(hp, m.params, sur_hp, 1))
+    at = I.fcc_box(4, 0.1, 21)
+    v = I.maxwell_boltzmann(at, 600.0, 22)
+    x1, v1, _ = oracle.mts(m, s, at.x, v, at.types, at.masses, at.box, 1.0, 4, 3)
+    x2, v2, _ = oracle.mts(m, s, x1, -v1, at.types, at.masses, at.box, 1.0, 4, 3)
+    d = x2 - at.x
+    d -= at.box * np.round(d / at.box)
+    assert np.abs(d).max() < 1e-10 and np.abs(v2 + v).max() < 1e-12
+    assert np.abs(x1 - at.x).max() > 1e-2
+
+
 # ----------------------------------------------------------------------------- gradients, bf16, adam
 
 def test_weight_gradient_fd(full_hp):
