@@ -325,41 +325,46 @@ __device__ __forceinline__ int bin_of(double r2, const BinEdges& be) {
   return k;
 }
 
+// Pair vector x_q - x_p in FP64 followed by the periodic shift of the stencil cell
+// (-L, 0 or +L: the value the minimum-image rule subtracts for every pair that can
+// lie within the cutoff when the dimension holds at least three cells), or by the
+// minimum-image rule itself when some dimension has fewer cells (MINIMG);
+// r^2 = (dx*dx + dy*dy) + dz*dz without FMA.
+template <bool MINIMG>
+__device__ __forceinline__ double cand_r2(const uint4* __restrict__ rec, int64_t q, double xi, double yi, double zi,
+                                          double sx, double sy, double sz, const CellGrid& g) {
+#pragma clang fp contract(off)
+  const uint4 w0 = rec[4 * q], w1 = rec[4 * q + 1];
+  double dx = rec_f64(w0.x, w0.y) - xi, dy = rec_f64(w0.z, w0.w) - yi, dz = rec_f64(w1.x, w1.y) - zi;
+  if constexpr (MINIMG) {
+    dx = g.nc[0] < 3 ? min_image(dx, g.box[0]) : dx + sx;
+    dy = g.nc[1] < 3 ? min_image(dy, g.box[1]) : dy + sy;
+    dz = g.nc[2] < 3 ? min_image(dz, g.box[2]) : dz + sz;
+  } else {
+    dx = dx + sx;
+    dy = dy + sy;
+    dz = dz + sz;
+  }
+  const double sxx = dx * dx;
+  const double syy = dy * dy;
+  const double szz = dz * dz;
+  const double sxy = sxx + syy;
+  return sxy + szz;
+}
+
 // Candidates of one stencil cell, four at a time (their positions are loaded
-// together before any is tested). The pair vector is the FP64 difference x_q - x_p
-// followed by the periodic shift of the stencil cell (-L, 0 or +L, the value the
-// minimum-image rule subtracts for every pair that can lie within the cutoff when
-// the dimension holds at least three cells), or by the minimum-image rule itself
-// in dimensions with fewer cells; r^2 = (dx*dx + dy*dy) + dz*dz without FMA.
-template <class Visit>
+// together before any is tested).
+template <bool MINIMG, class Visit>
 __device__ __forceinline__ void scan_cell(const uint4* __restrict__ rec, int64_t N, int q0, int q1, int64_t p,
                                           double xi, double yi, double zi, double sx, double sy, double sz,
                                           const CellGrid& g, double cut2, Visit&& visit) {
-#pragma clang fp contract(off)
-  const bool mx = g.nc[0] < 3, my = g.nc[1] < 3, mz = g.nc[2] < 3;
   for (int q = q0; q < q1; q += 4) {
-    double px[4], py[4], pz[4];
+    double r2[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t qq = q + u < q1 ? q + u : q1 - 1;
-      const uint4 w0 = rec[4 * qq], w1 = rec[4 * qq + 1];
-      px[u] = rec_f64(w0.x, w0.y);
-      py[u] = rec_f64(w0.z, w0.w);
-      pz[u] = rec_f64(w1.x, w1.y);
-    }
+    for (int u = 0; u < 4; ++u) r2[u] = cand_r2<MINIMG>(rec, q + u < q1 ? q + u : q1 - 1, xi, yi, zi, sx, sy, sz, g);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      double dx = px[u] - xi, dy = py[u] - yi, dz = pz[u] - zi;
-      dx = mx ? min_image(dx, g.box[0]) : dx + sx;
-      dy = my ? min_image(dy, g.box[1]) : dy + sy;
-      dz = mz ? min_image(dz, g.box[2]) : dz + sz;
-      const double sxx = dx * dx;
-      const double syy = dy * dy;
-      const double szz = dz * dz;
-      const double sxy = sxx + syy;
-      const double r2 = sxy + szz;
-      if (q + u < q1 && q + u != p && r2 < cut2) visit(q + u, r2);
-    }
+    for (int u = 0; u < 4; ++u)
+      if (q + u < q1 && q + u != p && r2[u] < cut2) visit(q + u, r2[u]);
   }
 }
 
@@ -407,6 +412,7 @@ __device__ __forceinline__ void stage_flush16(const uint32_t* st, uint4* col, in
 // q | bin << 28 together with its halo-local index; per-bin counts give the bin
 // breakpoints. Stencil cells whose nearest point lies beyond the list cutoff (with a
 // 1e-6 A margin) are skipped. k_place_lists then orders the entries by bin.
+template <bool MINIMG>
 __global__ void __launch_bounds__(kBlock)
 k_build_lists(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_t* __restrict__ start,
               const int32_t* __restrict__ cell_sorted, BinEdges be, int capR, int capA, ListOut lo_,
@@ -460,7 +466,7 @@ k_build_lists(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_
         if (q1 <= q0) continue;
         // halo-local index of sorted atom q is loc0 + q (cells are contiguous in the halo)
         const int loc0 = hok ? halo_index(ht, tile, hcells, q0) - q0 : 0;
-        scan_cell(rec, N, q0, q1, p, xi, yi, zi, sx, sy, sz, g, cut2, [&](int q, double r2) {
+        scan_cell<MINIMG>(rec, N, q0, q1, p, xi, yi, zi, sx, sy, sz, g, cut2, [&](int q, double r2) {
           const int bin = bin_of(r2, be);
           cb.add(bin);
           if ((n + 1) % kPartLen == 0 && (n + 1) / kPartLen < kPlaceParts && n < capR) {
@@ -692,8 +698,14 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, const BinEdges& be, int 
   hipLaunchKernelGGL(k_copy_back, dim3(nb), dim3(kBlock), 0, st, N, x_alt, v_alt, type_alt, perm_alt,
                      x, v, type, perm, rec, flags);
   hipLaunchKernelGGL(k_halo_tables, dim3(nb), dim3(kBlock), 0, st, N, g, cell_sorted, cell_start, ht, flags);
-  hipLaunchKernelGGL(k_build_lists, dim3(nb), dim3(kBlock), 0, st, N, g, rec, cell_start, cell_sorted, be,
-                     capR, capA, lout, ht, sc, flags);
+  // the minimum-image rule inside the candidate loop only for boxes with fewer than
+  // three cells along some dimension
+  if (g.nc[0] < 3 || g.nc[1] < 3 || g.nc[2] < 3)
+    hipLaunchKernelGGL(k_build_lists<true>, dim3(nb), dim3(kBlock), 0, st, N, g, rec, cell_start, cell_sorted, be,
+                       capR, capA, lout, ht, sc, flags);
+  else
+    hipLaunchKernelGGL(k_build_lists<false>, dim3(nb), dim3(kBlock), 0, st, N, g, rec, cell_start, cell_sorted, be,
+                       capR, capA, lout, ht, sc, flags);
   hipLaunchKernelGGL(k_place_lists, dim3(grid_blocks(N, kPlaceAtoms)), dim3(64), 0, st, N, be.nbins, lout, sc,
                      flags);
   hipLaunchKernelGGL(k_count_build, dim3(1), dim3(64), 0, st, flags, be.idxR[0][0], be.idxA[0][0], be.idxR[1][0],
