@@ -350,7 +350,7 @@ BinEdges make_bin_edges(const nep_hparams* hp0, const nep_hparams* hp1, double s
   e.erase(std::unique(e.begin(), e.end()), e.end());
   BinEdges be{};
   be.nbins = (int)e.size();
-  for (int b = 0; b < be.nbins; ++b) be.e2[b] = e[b] * e[b];
+  for (int b = 0; b < kMaxBins; ++b) be.e2[b] = b < be.nbins ? e[b] * e[b] : INFINITY;  // no pair reaches unused edges
   const nep_hparams* hp[2] = {hp0, hp1 ? hp1 : hp0};
   for (int m = 0; m < 2; ++m)
     for (int k = 0; k < kFracs; ++k) {

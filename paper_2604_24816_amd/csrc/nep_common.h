@@ -50,7 +50,7 @@ __host__ __device__ constexpr float bin_frac(int k) {
 }
 constexpr int kMaxBins = 2 * kFracs;
 struct BinEdges {
-  double e2[kMaxBins];       // squared edges, ascending; e2[nbins - 1] = (rc_radial + skin)^2
+  double e2[kMaxBins];       // squared edges, ascending; e2[nbins - 1] = (rc_radial + skin)^2, then infinity
   int nbins;
   int idxR[2][kFracs];       // per model: first bin whose upper edge is >= rc_radial + f_k skin
   int idxA[2][kFracs];       // per model: the same for rc_angular + f_k skin

@@ -317,11 +317,12 @@ __device__ __forceinline__ int halo_index(const HaloTables& ht, int tile, int nc
   return ho[lo] + (q - hs[lo]);
 }
 
-// Distance bin of a pair inside the list cutoff: the number of interior edges <= r^2.
+// Distance bin of a pair inside the list cutoff: the number of interior edges <= r^2
+// (the outer edge and the unused ones, set to infinity, are never reached).
 __device__ __forceinline__ int bin_of(double r2, const BinEdges& be) {
   int k = 0;
 #pragma unroll
-  for (int m = 0; m < kMaxBins - 1; ++m) k += (m < be.nbins - 1 && r2 >= be.e2[m]) ? 1 : 0;
+  for (int m = 0; m < kMaxBins - 1; ++m) k += r2 >= be.e2[m] ? 1 : 0;
   return k;
 }
 
