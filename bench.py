@@ -28,6 +28,8 @@ if ROOT not in sys.path:
 
 PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X published FP32 vector peak (packed FMA)
 PEAK_HBM_GBS = 8000.0
+PEAK_FP32_MFMA_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
+PEAK_BF16_MFMA_TFLOPS = 2500.0    # MI355X dense bfloat16 matrix peak (no sparsity)
 
 # Static FLOP counts per unit (FMA = 2 flops), from the kernel source of the full
 # model (n_max 4, basis 8, l_max 4 + four-body, 30 hidden): see the kernel notes
@@ -236,6 +238,31 @@ def run_forms(args):
     print(json.dumps(out))
 
 
+def network_mfma(hp, n, desc_ms, precision):
+    """MFMA use of the network inside the descriptor kernel: the forward product W0 q~ and
+    the backward product W0^T (w1 (1 - t^2)), 2 * 2 * H * D flops per atom (unpadded),
+    over the whole descriptor+network launch, against the dense MFMA peak of the
+    operand type."""
+    flops = 4.0 * hp.n_hidden * hp.n_desc
+    achieved = flops * n / (desc_ms * 1e-3) / 1e12
+    peak = PEAK_BF16_MFMA_TFLOPS if precision == "bf16" else PEAK_FP32_MFMA_TFLOPS
+    return {"kernel": "k_desc_net (network part)", "flops_per_atom": flops, "achieved": achieved,
+            "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak}
+
+
+def integrator_hbm(n, integrate, steps):
+    """HBM bandwidth of the velocity-Verlet kernels: k_kick_drift reads type, v, F, x and
+    the build positions and writes v, x and the record's position (88 + 72 B per atom);
+    k_kick reads type, F, v and writes v (40 + 24 B)."""
+    total_ms, launches = integrate
+    per_step_s = total_ms * 1e-3 / steps
+    nbytes = 224.0 * n
+    achieved = nbytes / per_step_s / 1e9
+    return {"kernels": "k_kick_drift + k_kick", "bytes_per_atom_step": 224, "achieved": achieved,
+            "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+            "timed_segments": launches}
+
+
 def copy_calibration(nbytes=1 << 30, reps=3):
     """A plain copy of known size: reads nbytes and writes nbytes per launch."""
     import torch
@@ -342,6 +369,8 @@ def main():
                      "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": force_traffic(),
                      "flops_per_atom": force_f, "avg_launch_ms": avg_force_s * 1e3},
+        "network_mfma": network_mfma(hp, n, desc_ms / desc_cnt, args.precision),
+        "integrator_hbm": integrator_hbm(n, prof["integrate"], args.steps),
         "kernels_ms_per_launch": {k: (v[0] / v[1] if v[1] else None) for k, v in prof.items()},
         "pairs_per_atom": {"radial": pairs_r / n, "angular": pairs_a / n, "skin_list": skin_entries},
         "flops_per_atom_step": desc_f + force_f,
