@@ -175,7 +175,6 @@ int64_t layout(nep_system* s, char* base, int64_t N, int capR, int capA, int max
   S.selfl = c.take<uint16_t>(N);
   S.lsc.q = c.take<uint4>((int64_t)((capR + 15) / 16) * N * 4);
   S.lsc.l = c.take<uint4>((int64_t)((capR + 15) / 16) * N * 2);
-  S.lsc.cum = c.take<uint4>((int64_t)(kPlaceParts - 1) * N * 2);
   {
     const int64_t nt = grid_blocks(N);
     S.ht.info = c.take<int32_t>(4 * nt);

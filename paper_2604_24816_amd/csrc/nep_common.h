@@ -127,7 +127,6 @@ struct ListOut {
 struct ListScratch {
   uint4* q;
   uint4* l;
-  uint4* cum;  // [kPlaceParts - 1][N][2]: per-bin counts of the first 32, 64, 96 entries
 };
 constexpr int kPlaceParts = 4;   // lanes per atom in the placement; part h starts at entry 32 h
 constexpr int kPartLen = 32;

@@ -410,9 +410,9 @@ __device__ __forceinline__ void stage_flush16(const uint32_t* st, uint4* col, in
 
 // One thread per atom, one pass over the 27-cell stencil. Every candidate inside the
 // list cutoff is appended, in stencil order, to the atom's scratch column as
-// q | bin << 28 together with its halo-local index; per-bin counts give the bin
-// breakpoints. Stencil cells whose nearest point lies beyond the list cutoff (with a
-// 1e-6 A margin) are skipped. k_place_lists then orders the entries by bin.
+// q | bin << 28 together with its halo-local index. Stencil cells whose nearest point
+// lies beyond the list cutoff (with a 1e-6 A margin) are skipped. k_place_lists then
+// counts the entries per bin and orders them by bin.
 template <bool MINIMG>
 __global__ void __launch_bounds__(kBlock)
 k_build_lists(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_t* __restrict__ start,
@@ -441,7 +441,6 @@ k_build_lists(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_
     dlo[d] = fmax(pos3[d] - cc3[d] * h - 1e-6, 0.0);
     dhi[d] = fmax((cc3[d] + 1) * h - pos3[d] - 1e-6, 0.0);
   }
-  BinCounts cb;
   int n = 0;
   __shared__ uint32_t stage_q[kBlock * kStageStride], stage_l[kBlock * kStageStride];
   uint32_t* sq = stage_q + threadIdx.x * kStageStride;
@@ -468,21 +467,8 @@ k_build_lists(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_
         // halo-local index of sorted atom q is loc0 + q (cells are contiguous in the halo)
         const int loc0 = hok ? halo_index(ht, tile, hcells, q0) - q0 : 0;
         scan_cell<MINIMG>(rec, N, q0, q1, p, xi, yi, zi, sx, sy, sz, g, cut2, [&](int q, double r2) {
-          const int bin = bin_of(r2, be);
-          cb.add(bin);
-          if ((n + 1) % kPartLen == 0 && (n + 1) / kPartLen < kPlaceParts && n < capR) {
-            // per-bin counts of the first n + 1 entries: where part (n + 1) / 32 of the
-            // placement starts
-            uint4* c = sc.cum + ((int64_t)((n + 1) / kPartLen - 1) * N + p) * 2;
-            static_assert(BinCounts::kWords <= 4, "bin counters fit two 16-byte words");
-            uint64_t w4[4] = {0, 0, 0, 0};
-#pragma unroll
-            for (int k = 0; k < BinCounts::kWords; ++k) w4[k] = cb.w[k];
-            c[0] = make_uint4((uint32_t)w4[0], (uint32_t)(w4[0] >> 32), (uint32_t)w4[1], (uint32_t)(w4[1] >> 32));
-            c[1] = make_uint4((uint32_t)w4[2], (uint32_t)(w4[2] >> 32), (uint32_t)w4[3], (uint32_t)(w4[3] >> 32));
-          }
           if (n < capR) {
-            sq[n % kStage] = (uint32_t)q | ((uint32_t)bin << 28);
+            sq[n % kStage] = (uint32_t)q | ((uint32_t)bin_of(r2, be) << 28);
             sl[n % kStage] = hok ? (uint32_t)(loc0 + q) : (uint32_t)kNoLocal;
             if (n % kStage == kStage - 1) {
               stage_flush32(sq, sc.q, N, p, n);
@@ -498,37 +484,28 @@ k_build_lists(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_
     stage_flush32(sq, sc.q, N, p, n);
     stage_flush16(sl, sc.l, N, p, n);
   }
-  // cumulative breakpoints; angular candidates are the bins up to idxA[kFracs - 1]
-  int t = 0, na = 0;
-#pragma unroll
-  for (int k = 0; k < kMaxBins; ++k) {
-    if (k < be.nbins) {
-      t += cb.get(k);
-      if (k == be.idxA[0][kFracs - 1]) na = t;
-      lo_.bp[(int64_t)k * N + p] = t < capR ? t : capR;
-    }
-  }
   lo_.cnt[p] = n < capR ? n : capR;
   if (n > capR) atomicMax(&flags[FLAG_OVF_R], n);
-  if (na > capA) atomicMax(&flags[FLAG_OVF_A], na);
 }
 
-// One wavefront per 16 atoms, four lanes per atom: orders each atom's scratch
-// entries by bin (stable inside a bin) and writes the list and its halo-local
-// indices row by row, 16 consecutive atoms (64 bytes) per store, through LDS tiles of
-// kPlaceRows rows; longer lists take further rounds. Lane h places entries
-// [32 h, 32 (h + 1)) (the last lane the rest), starting each bin after the entries
-// of earlier parts (their per-bin counts were saved by the list build). Entries
-// outside the current round go to a spare row.
+// One wavefront per 16 atoms, four lanes per atom: counts each atom's scratch
+// entries per bin, writes the bin breakpoints, and orders the entries by bin (stable
+// inside a bin), writing the list and its halo-local indices row by row, 16
+// consecutive atoms (64 bytes) per store, through LDS tiles of kPlaceRows rows;
+// longer lists take further rounds. Lane h counts and places entries [32 h, 32 (h + 1))
+// (the last lane the rest), starting each bin after the entries of earlier parts.
+// Entries outside the current round go to a spare row.
 constexpr int kPlaceRows = 127;
 constexpr int kPlaceAtoms = 64 / kPlaceParts;
 
 __global__ void __launch_bounds__(64)
-k_place_lists(int64_t N, int nbins, ListOut lo_, ListScratch sc, const int32_t* __restrict__ flags) {
+k_place_lists(int64_t N, int nbins, int binA, int capR, int capA, ListOut lo_, ListScratch sc,
+              int32_t* __restrict__ flags) {
   if (flags[FLAG_REBUILD] == 0) return;
   __shared__ uint32_t tile[(kPlaceRows + 1) * kPlaceAtoms];
   __shared__ uint16_t ltile[(kPlaceRows + 1) * kPlaceAtoms];
   __shared__ uint16_t off[kMaxBins * 64];  // next position of each bin, per lane
+  __shared__ uint64_t parts[kPlaceParts][BinCounts::kWords][kPlaceAtoms];  // per-bin counts of each part
   __shared__ int red[64];
   const int lane = threadIdx.x;
   const int a = lane % kPlaceAtoms;  // atom of the wavefront
@@ -547,25 +524,51 @@ k_place_lists(int64_t N, int nbins, ListOut lo_, ListScratch sc, const int32_t* 
     __syncthreads();
   }
   const int rows_max = red[0];
-  // per-bin counts of the entries before this part
-  uint64_t before[4] = {0, 0, 0, 0};
-  if (work && h > 0) {
-    const uint4* c = sc.cum + ((int64_t)(h - 1) * N + p) * 2;
-    const uint4 c0 = c[0], c1 = c[1];
-    before[0] = ((uint64_t)c0.y << 32) | c0.x;
-    before[1] = ((uint64_t)c0.w << 32) | c0.z;
-    before[2] = ((uint64_t)c1.y << 32) | c1.x;
-    before[3] = ((uint64_t)c1.w << 32) | c1.z;
+  // per-bin counts of this lane's part (16-bit fields), then of the parts before it
+  // and of the whole list
+  BinCounts mine;
+  if (work) {
+    for (int g = g_lo; g < g_hi; g += kStage) {
+      const uint4* src = sc.q + ((int64_t)(g / kStage) * N + p) * (kStage / 4);
+#pragma unroll
+      for (int j = 0; j < kStage / 4; ++j) {
+        const uint4 w = src[j];
+        const uint32_t t[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (g + 4 * j + u < g_hi) mine.add((int)(t[u] >> 28));
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < BinCounts::kWords; ++k) parts[h][k][a] = mine.w[k];
+  __syncthreads();
+  BinCounts before, total;
+#pragma unroll
+  for (int q = 0; q < kPlaceParts; ++q)
+#pragma unroll
+    for (int k = 0; k < BinCounts::kWords; ++k) {
+      const uint64_t c = parts[q][k][a];
+      total.w[k] += c;
+      before.w[k] += q < h ? c : 0;
+    }
+  // bin breakpoints (cumulative counts); angular candidates are the bins up to binA
+  int bstart[kMaxBins];
+  {
+    int t = 0;
+#pragma unroll
+    for (int k = 0; k < kMaxBins; ++k) {
+      bstart[k] = t;
+      t += k < nbins ? total.get(k) : 0;
+      if (valid && h == 0 && k < nbins) lo_.bp[(int64_t)k * N + p] = t < capR ? t : capR;
+      if (valid && h == 0 && k == binA && t > capA) atomicMax(&flags[FLAG_OVF_A], t);
+    }
   }
   constexpr int rows = kPlaceRows;  // row `rows` of the tiles is the spare row
   for (int r0 = 0; r0 < rows_max; r0 += rows) {
     if (work) {
 #pragma unroll
-      for (int k = 0; k < kMaxBins; ++k) {
-        const int start = k == 0 || k >= nbins ? 0 : lo_.bp[(int64_t)(k - 1) * N + p];
-        const int prior = (int)((before[k >> 2] >> (16 * (k & 3))) & 0xffffu);
-        off[k * 64 + lane] = (uint16_t)(start + prior);
-      }
+      for (int k = 0; k < kMaxBins; ++k) off[k * 64 + lane] = (uint16_t)(bstart[k] + before.get(k));
       for (int g = g_lo; g < g_hi; g += kStage) {
         uint32_t v[kStage], hl[kStage];
         const uint4* src = sc.q + ((int64_t)(g / kStage) * N + p) * (kStage / 4);
@@ -707,8 +710,8 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, const BinEdges& be, int 
   else
     hipLaunchKernelGGL(k_build_lists<false>, dim3(nb), dim3(kBlock), 0, st, N, g, rec, cell_start, cell_sorted, be,
                        capR, capA, lout, ht, sc, flags);
-  hipLaunchKernelGGL(k_place_lists, dim3(grid_blocks(N, kPlaceAtoms)), dim3(64), 0, st, N, be.nbins, lout, sc,
-                     flags);
+  hipLaunchKernelGGL(k_place_lists, dim3(grid_blocks(N, kPlaceAtoms)), dim3(64), 0, st, N, be.nbins,
+                     be.idxA[0][kFracs - 1], capR, capA, lout, sc, flags);
   hipLaunchKernelGGL(k_count_build, dim3(1), dim3(64), 0, st, flags, be.idxR[0][0], be.idxA[0][0], be.idxR[1][0],
                      be.idxA[1][0]);
   return hipGetLastError();
