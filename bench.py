@@ -118,20 +118,22 @@ def cpu_baseline(hp, params, at, seconds):
 
 
 def run_form(form, hp, params, at, steps, warmup, sur=None, judge_fraction=0.75):
-    """Time one form on one box: 'fp32', 'bf16' or 'mts' (surrogate inner steps, k = 4)."""
+    """Time one form on one box: 'fp32', 'bf16', 'mts' (surrogate inner steps, k = 4) or
+    'mts_bf16' (the same with the bfloat16 network in both models)."""
+    mts = form.startswith("mts")
     import torch
     from paper_2604_24816_amd import nep
     from paper_2604_24816_amd import surrogate as SG
     shp, sp = sur if sur is not None else (None, None)
     s = nep.NEPSystem(nep.NEPModel(hp, params), at.n, at.box,
-                      surrogate=nep.NEPModel(shp, sp) if form == "mts" else None)
+                      surrogate=nep.NEPModel(shp, sp) if mts else None)
     s.set_state(at.x, at.types, at.masses, at.v)
     s.build_neighbors(1.0)
-    prec = "bf16" if form == "bf16" else "fp32"
-    k = 4 if form == "mts" else 0
+    prec = "bf16" if form in ("bf16", "mts_bf16") else "fp32"
+    k = 4 if mts else 0
     kw = dict(dt=1.0, rebuild_every=10, skin=1.0, precision=prec, mts_k=k)
     extra = {}
-    if form == "mts":
+    if mts:
         # each block is judged against its own full-model force scale
         _, _, rms = SG.judge_thresholds(s, judge_fraction)
         kw.update(fallback_rms=judge_fraction, fallback_max=10.0, relative_judge=True)
@@ -148,19 +150,19 @@ def run_form(form, hp, params, at, steps, warmup, sur=None, judge_fraction=0.75)
     s.profile(False)
     n = at.n
     pr, pa, sk = s.pair_counts()
-    model_name = "surrogate" if form == "mts" else "full"
-    grp = "force_surrogate" if form == "mts" else "force"
+    model_name = "surrogate" if mts else "full"
+    grp = "force_surrogate" if mts else "force"
     desc_f, force_f = flops_per_atom(pr / n, pa / n, sk / n, model_name)
     fms, fcnt = prof[grp]
     out = {"atom_steps_per_s": n * steps / elapsed, "s_per_step_per_atom": elapsed / (n * steps),
            "ms_per_step": 1e3 * elapsed / steps, "n_atoms": n, "steps": steps,
            "kernels_ms_per_launch": {kk: (v[0] / v[1] if v[1] else None) for kk, v in prof.items()},
-           "roofline": {"bound": "alu", "kernel": "k_force" + ("<surrogate>" if form == "mts" else ""),
+           "roofline": {"bound": "alu", "kernel": "k_force" + ("<surrogate>" if mts else ""),
                         "achieved": force_f * n / (fms / fcnt / 1e3) / 1e12, "peak": PEAK_FP32_VECTOR_TFLOPS,
                         "unit": "TFLOP/s"},
            "energy_drift_per_atom": float((th[-1, 1] + th[-1, 2] - th[0, 1] - th[0, 2]) / n) if len(th) > 1 else None}
     out["roofline"]["frac"] = out["roofline"]["achieved"] / PEAK_FP32_VECTOR_TFLOPS
-    if form == "mts":
+    if mts:
         st = s.stats()
         out.update(extra)
         out["surrogate_force_error_rms_mean"] = float(np.mean(th[:, 5]))
@@ -216,8 +218,10 @@ def run_forms(args):
     wm = 4 * max(1, args.warmup // 4)
     for name, sur in (("mts_trained_coeffs", (shp, res_c.params)), ("mts_trained", (shp, res.params)),
                       ("mts_untrained", (shp, sur0)), ("mts_short_trained_coeffs", (shp_s, res_sc.params)),
-                      ("mts_short_trained", (shp_s, res_s.params)), ("mts_short_untrained", (shp_s, sur0_s))):
-        forms[name] = run_form("mts", hp, params, at, args.steps, wm, sur=sur)
+                      ("mts_short_trained", (shp_s, res_s.params)), ("mts_short_untrained", (shp_s, sur0_s)),
+                      ("mts_short_trained_coeffs_bf16", (shp_s, res_sc.params))):
+        forms[name] = run_form("mts_bf16" if name.endswith("_bf16") else "mts", hp, params, at, args.steps, wm,
+                               sur=sur)
         print(f"form {name}: {forms[name]['atom_steps_per_s']:.3e} atom-steps/s, "
               f"{forms[name]['mts_blocks']} MTS / {forms[name]['fallback_blocks']} fallback blocks",
               file=sys.stderr, flush=True)
