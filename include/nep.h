@@ -181,6 +181,11 @@ int nep_step(nep_system* s, int64_t n_steps, double dt_fs, int32_t rebuild_every
  * mts_k > 0 while a thermostat is set. Synchronises. */
 int nep_set_thermostat(nep_system* s, double temperature, double tau_fs, int32_t chain_length);
 
+/* Restores a chain state (host arrays of chain_length values, as returned by
+ * nep_get_thermostat) after nep_set_thermostat, to resume an NVT run from a
+ * checkpoint together with nep_set_state. Synchronises. */
+int nep_set_thermostat_state(nep_system* s, const double* eta, const double* v_eta);
+
 /* The chain state (host arrays of chain_length values, nullable) and its share
  * of the conserved energy, Nf kT eta_1 + kT sum_{k>=2} eta_k + sum_k Q_k v_k^2 / 2
  * (eV, nullable); PE + KE + that share is conserved by the NVT dynamics.

@@ -905,6 +905,21 @@ int nep_set_thermostat(nep_system* s, double temperature, double tau_fs, int32_t
   return NEP_OK;
 }
 
+int nep_set_thermostat_state(nep_system* s, const double* eta, const double* v_eta) {
+  if (!s || !eta || !v_eta) return fail(s, NEP_ERR_ARG, "bad argument");
+  if (s->nvt_M < 1) return fail(s, NEP_ERR_ARG, "no thermostat set");
+  double h[kNhcDoubles] = {0};
+  for (int k = 0; k < s->nvt_M; ++k) {
+    if (!std::isfinite(eta[k]) || !std::isfinite(v_eta[k])) return fail(s, NEP_ERR_NONFINITE, "non-finite chain state");
+    h[k] = eta[k];
+    h[kMaxChain + k] = v_eta[k];
+  }
+  h[2 * kMaxChain] = 1.0;
+  HIPCHK(hipMemcpyAsync(s->nhc, h, sizeof(h), hipMemcpyHostToDevice, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  return NEP_OK;
+}
+
 int nep_get_thermostat(nep_system* s, double* eta, double* v_eta, double* chain_energy) {
   if (!s) return NEP_ERR_ARG;
   double h[kNhcDoubles];

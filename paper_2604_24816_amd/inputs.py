@@ -15,6 +15,7 @@ workloads (radial 6 A, angular 5 A).
 from __future__ import annotations
 
 import dataclasses
+import json
 from typing import Optional, Tuple
 
 import numpy as np
@@ -191,6 +192,26 @@ class HParams:
             out[k] = (off, off + v)
             off += v
         return out
+
+
+def save_model(path: str, hp: HParams, params: np.ndarray) -> None:
+    """Write a model as .npz: the hyperparameters as JSON text and the packed FP64
+    parameters (no pickled objects, so np.load's default allow_pickle=False reads it)."""
+    params = np.ascontiguousarray(params, dtype=np.float64)
+    if params.size != hp.n_params():
+        raise ValueError(f"{params.size} parameters for a model of {hp.n_params()}")
+    np.savez(path, hparams=np.array(json.dumps(dataclasses.asdict(hp))), params=params)
+
+
+def load_model(path: str) -> tuple[HParams, np.ndarray]:
+    with np.load(path) as d:
+        fields = json.loads(str(d["hparams"]))
+        fields["zbl_z"] = tuple(fields["zbl_z"])
+        hp = HParams(**fields)
+        params = np.array(d["params"], dtype=np.float64)
+    if params.size != hp.n_params():
+        raise ValueError(f"{path}: {params.size} parameters for a model of {hp.n_params()}")
+    return hp, params
 
 
 FULL_HPARAMS = HParams()

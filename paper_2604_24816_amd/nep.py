@@ -29,7 +29,8 @@ EXPORTED = [
     "nep_param_count", "nep_model_create", "nep_model_destroy", "nep_system_workspace_bytes",
     "nep_system_create", "nep_system_destroy", "nep_system_set_params", "nep_set_state",
     "nep_build_neighbors", "nep_export_neighbors", "nep_compute_energy_forces_virial", "nep_step",
-    "nep_set_judge", "nep_set_thermostat", "nep_get_thermostat", "nep_get_state", "nep_get_stats",
+    "nep_set_judge", "nep_set_thermostat", "nep_set_thermostat_state", "nep_get_thermostat", "nep_get_state",
+    "nep_get_stats",
     "nep_train_forward", "nep_train_backward", "nep_train_forward_params", "nep_train_backward_params",
     "nep_adam_update",
     "nep_surrogate_error", "nep_status_string", "nep_last_error", "nep_profile", "nep_profile_read",
@@ -80,6 +81,7 @@ def load_library(path: str = LIB_PATH):
         "nep_set_judge": [vp, i32],
         "nep_set_thermostat": [vp, f64, f64, i32],
         "nep_get_thermostat": [vp, vp, vp, vp],
+        "nep_set_thermostat_state": [vp, vp, vp],
         "nep_get_stats": [vp, vp],
         "nep_train_forward": [vp, i32, vp, vp, vp],
         "nep_train_backward": [vp, i32, vp, f64, vp, vp, i32],
@@ -282,6 +284,15 @@ class NEPSystem:
         """NVT with a Nose-Hoover chain (chain = 0: back to NVE); resets the chain state."""
         self._check(self.lib.nep_set_thermostat(self.handle, float(temperature), float(tau), int(chain)))
         self._chain = int(chain)
+
+    def set_thermostat_state(self, eta, v_eta):
+        """Restore the chain state (after set_thermostat), e.g. from a checkpoint."""
+        eta = np.ascontiguousarray(eta, dtype=np.float64)
+        ve = np.ascontiguousarray(v_eta, dtype=np.float64)
+        m = getattr(self, "_chain", 0)
+        if eta.size != m or ve.size != m:
+            raise ValueError(f"the chain has {m} thermostats")
+        self._check(self.lib.nep_set_thermostat_state(self.handle, _np_ptr(eta), _np_ptr(ve)))
 
     def get_thermostat(self):
         """(eta, v_eta, chain energy in eV) of the Nose-Hoover chain."""

@@ -79,3 +79,15 @@ def test_zbl_hparams_validated_on_the_host(lib, zbl, ok):
     assert (st == 0) == ok
     if ok:
         assert n.value == I.HParams().n_params()   # ZBL adds no parameters
+
+
+def test_model_file_round_trip(tmp_path):
+    from paper_2604_24816_amd import inputs as I
+    for hp in (I.FULL_HPARAMS, I.SURROGATE_SHORT_HPARAMS, I.HParams(n_types=2, zbl_outer=2.0, zbl_z=(29.0, 79.0))):
+        p = I.random_model(hp, 3)
+        f = tmp_path / "m.npz"
+        I.save_model(str(f), hp, p)
+        hp2, p2 = I.load_model(str(f))
+        assert hp2 == hp and np.array_equal(p2, p)
+    with pytest.raises(ValueError):
+        I.save_model(str(tmp_path / "bad.npz"), I.FULL_HPARAMS, np.zeros(5))
