@@ -70,14 +70,18 @@ __global__ void k_kick_drift(int64_t N, double dt, CellGrid g, const float* __re
 // k = first bin fraction with bin_frac(k) * skin >= 2 * (largest displacement since the
 // build); the evaluation visits the bins up to the edges rc_radial + f_k skin and
 // rc_angular + f_k skin. A rebuild later in the same step resets them to k = 0.
-__global__ void k_select_bin(const double* __restrict__ partial, int nblocks, int32_t* flags, double skin,
-                             BinEdges be) {
-  __shared__ double sh[kBlock];
+constexpr int kSelBlock = 1024;  // one workgroup reads every partial: many loads in flight
+
+__global__ void __launch_bounds__(kSelBlock)
+k_select_bin(const double* __restrict__ partial, int nblocks, int32_t* flags, double skin, BinEdges be) {
+  __shared__ double sh[kSelBlock];
   double m = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += kBlock) m = fmax(m, partial[(int64_t)b * kPartialStride + P_MAXD2]);
+#pragma unroll 4
+  for (int b = threadIdx.x; b < nblocks; b += kSelBlock)
+    m = fmax(m, partial[(int64_t)b * kPartialStride + P_MAXD2]);
   sh[threadIdx.x] = m;
   __syncthreads();
-  for (int off = kBlock / 2; off > 0; off >>= 1) {
+  for (int off = kSelBlock / 2; off > 0; off >>= 1) {
     if (threadIdx.x < (unsigned)off) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + off]);
     __syncthreads();
   }
@@ -322,7 +326,7 @@ hipError_t launch_kick_drift(int64_t N, double dt, CellGrid g, const float* F, c
 
 hipError_t launch_select_bin(const double* partial, int nblocks, int32_t* flags, double skin,
                              const BinEdges& be, hipStream_t st) {
-  hipLaunchKernelGGL(k_select_bin, dim3(1), dim3(kBlock), 0, st, partial, nblocks, flags, skin, be);
+  hipLaunchKernelGGL(k_select_bin, dim3(1), dim3(kSelBlock), 0, st, partial, nblocks, flags, skin, be);
   return hipGetLastError();
 }
 

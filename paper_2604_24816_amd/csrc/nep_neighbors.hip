@@ -497,6 +497,7 @@ k_build_lists(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_
 // Entries outside the current round go to a spare row.
 constexpr int kPlaceRows = 127;
 constexpr int kPlaceAtoms = 64 / kPlaceParts;
+constexpr int kPlaceGrid = 16384;  // workgroups of the placement (grid-stride over atom groups)
 
 __global__ void __launch_bounds__(64)
 k_place_lists(int64_t N, int nbins, int binA, int capR, int capA, ListOut lo_, ListScratch sc,
@@ -510,113 +511,119 @@ k_place_lists(int64_t N, int nbins, int binA, int capR, int capA, ListOut lo_, L
   const int lane = threadIdx.x;
   const int a = lane % kPlaceAtoms;  // atom of the wavefront
   const int h = lane / kPlaceAtoms;  // which part of its column
-  const int64_t p = (int64_t)blockIdx.x * kPlaceAtoms + a;
-  const bool valid = p < N;
-  const int cnt = valid ? lo_.cnt[p] : 0;
-  const int g_lo = h * kPartLen;
-  const int g_hi = h == kPlaceParts - 1 ? cnt : (g_lo + kPartLen < cnt ? g_lo + kPartLen : cnt);
-  const bool work = valid && g_lo < cnt;
-  // longest list of the wavefront (uniform loop bounds for the row writes)
-  red[lane] = cnt;
-  __syncthreads();
-  for (int o = 32; o > 0; o >>= 1) {
-    if (lane < o) red[lane] = max(red[lane], red[lane + o]);
+  // groups of kPlaceAtoms atoms, strided over a capped grid: a step without a rebuild
+  // then dispatches few workgroups
+  const int64_t ngroups = (N + kPlaceAtoms - 1) / kPlaceAtoms;
+  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const int64_t p = grp * kPlaceAtoms + a;
+    const bool valid = p < N;
+    const int cnt = valid ? lo_.cnt[p] : 0;
+    const int g_lo = h * kPartLen;
+    const int g_hi = h == kPlaceParts - 1 ? cnt : (g_lo + kPartLen < cnt ? g_lo + kPartLen : cnt);
+    const bool work = valid && g_lo < cnt;
+    // longest list of the wavefront (uniform loop bounds for the row writes)
+    red[lane] = cnt;
     __syncthreads();
-  }
-  const int rows_max = red[0];
-  // per-bin counts of this lane's part (16-bit fields), then of the parts before it
-  // and of the whole list
-  BinCounts mine;
-  if (work) {
-    for (int g = g_lo; g < g_hi; g += kStage) {
-      const uint4* src = sc.q + ((int64_t)(g / kStage) * N + p) * (kStage / 4);
-#pragma unroll
-      for (int j = 0; j < kStage / 4; ++j) {
-        const uint4 w = src[j];
-        const uint32_t t[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (g + 4 * j + u < g_hi) mine.add((int)(t[u] >> 28));
-      }
+    for (int o = 32; o > 0; o >>= 1) {
+      if (lane < o) red[lane] = max(red[lane], red[lane + o]);
+      __syncthreads();
     }
-  }
-#pragma unroll
-  for (int k = 0; k < BinCounts::kWords; ++k) parts[h][k][a] = mine.w[k];
-  __syncthreads();
-  BinCounts before, total;
-#pragma unroll
-  for (int q = 0; q < kPlaceParts; ++q)
-#pragma unroll
-    for (int k = 0; k < BinCounts::kWords; ++k) {
-      const uint64_t c = parts[q][k][a];
-      total.w[k] += c;
-      before.w[k] += q < h ? c : 0;
-    }
-  // bin breakpoints (cumulative counts); angular candidates are the bins up to binA
-  int bstart[kMaxBins];
-  {
-    int t = 0;
-#pragma unroll
-    for (int k = 0; k < kMaxBins; ++k) {
-      bstart[k] = t;
-      t += k < nbins ? total.get(k) : 0;
-      if (valid && h == 0 && k < nbins) lo_.bp[(int64_t)k * N + p] = t < capR ? t : capR;
-      if (valid && h == 0 && k == binA && t > capA) atomicMax(&flags[FLAG_OVF_A], t);
-    }
-  }
-  constexpr int rows = kPlaceRows;  // row `rows` of the tiles is the spare row
-  for (int r0 = 0; r0 < rows_max; r0 += rows) {
+    const int rows_max = red[0];
+    // per-bin counts of this lane's part (16-bit fields), then of the parts before it
+    // and of the whole list
+    BinCounts mine;
     if (work) {
-#pragma unroll
-      for (int k = 0; k < kMaxBins; ++k) off[k * 64 + lane] = (uint16_t)(bstart[k] + before.get(k));
       for (int g = g_lo; g < g_hi; g += kStage) {
-        uint32_t v[kStage], hl[kStage];
         const uint4* src = sc.q + ((int64_t)(g / kStage) * N + p) * (kStage / 4);
-#pragma unroll
+  #pragma unroll
         for (int j = 0; j < kStage / 4; ++j) {
           const uint4 w = src[j];
-          v[4 * j] = w.x;
-          v[4 * j + 1] = w.y;
-          v[4 * j + 2] = w.z;
-          v[4 * j + 3] = w.w;
-        }
-        const uint4* ls = sc.l + ((int64_t)(g / kStage) * N + p) * (kStage / 8);
-#pragma unroll
-        for (int j = 0; j < kStage / 8; ++j) {
-          const uint4 w = ls[j];
           const uint32_t t[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            hl[8 * j + 2 * u] = t[u] & 0xffffu;
-            hl[8 * j + 2 * u + 1] = t[u] >> 16;
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < kStage; ++u) {
-          const bool live = g + u < g_hi;
-          const int oi = (int)(v[u] >> 28) * 64 + lane;
-          int pos = -1;
-          if (live) {
-            pos = off[oi];
-            off[oi] = (uint16_t)(pos + 1);
-          }
-          pos -= r0;
-          const int slot = (live && pos >= 0 && pos < rows ? pos : rows) * kPlaceAtoms + a;
-          tile[slot] = v[u] & 0x0fffffffu;
-          ltile[slot] = (uint16_t)hl[u];
+  #pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (g + 4 * j + u < g_hi) mine.add((int)(t[u] >> 28));
         }
       }
     }
+  #pragma unroll
+    for (int k = 0; k < BinCounts::kWords; ++k) parts[h][k][a] = mine.w[k];
     __syncthreads();
-    // the kPlaceParts lane groups write interleaved rows
-    const int nrow = rows_max - r0 < rows ? rows_max - r0 : rows;
-    for (int r = h; r < nrow; r += kPlaceParts) {
-      if (valid && r0 + r < cnt) {
-        lo_.nbr[(int64_t)(r0 + r) * N + p] = (int32_t)tile[r * kPlaceAtoms + a];
-        lo_.nbrl[(int64_t)(r0 + r) * N + p] = ltile[r * kPlaceAtoms + a];
+    BinCounts before, total;
+  #pragma unroll
+    for (int q = 0; q < kPlaceParts; ++q)
+  #pragma unroll
+      for (int k = 0; k < BinCounts::kWords; ++k) {
+        const uint64_t c = parts[q][k][a];
+        total.w[k] += c;
+        before.w[k] += q < h ? c : 0;
+      }
+    // bin breakpoints (cumulative counts); angular candidates are the bins up to binA
+    int bstart[kMaxBins];
+    {
+      int t = 0;
+  #pragma unroll
+      for (int k = 0; k < kMaxBins; ++k) {
+        bstart[k] = t;
+        t += k < nbins ? total.get(k) : 0;
+        if (valid && h == 0 && k < nbins) lo_.bp[(int64_t)k * N + p] = t < capR ? t : capR;
+        if (valid && h == 0 && k == binA && t > capA) atomicMax(&flags[FLAG_OVF_A], t);
       }
     }
-    __syncthreads();
+    constexpr int rows = kPlaceRows;  // row `rows` of the tiles is the spare row
+    for (int r0 = 0; r0 < rows_max; r0 += rows) {
+      if (work) {
+  #pragma unroll
+        for (int k = 0; k < kMaxBins; ++k) off[k * 64 + lane] = (uint16_t)(bstart[k] + before.get(k));
+        for (int g = g_lo; g < g_hi; g += kStage) {
+          uint32_t v[kStage], hl[kStage];
+          const uint4* src = sc.q + ((int64_t)(g / kStage) * N + p) * (kStage / 4);
+  #pragma unroll
+          for (int j = 0; j < kStage / 4; ++j) {
+            const uint4 w = src[j];
+            v[4 * j] = w.x;
+            v[4 * j + 1] = w.y;
+            v[4 * j + 2] = w.z;
+            v[4 * j + 3] = w.w;
+          }
+          const uint4* ls = sc.l + ((int64_t)(g / kStage) * N + p) * (kStage / 8);
+  #pragma unroll
+          for (int j = 0; j < kStage / 8; ++j) {
+            const uint4 w = ls[j];
+            const uint32_t t[4] = {w.x, w.y, w.z, w.w};
+  #pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              hl[8 * j + 2 * u] = t[u] & 0xffffu;
+              hl[8 * j + 2 * u + 1] = t[u] >> 16;
+            }
+          }
+  #pragma unroll
+          for (int u = 0; u < kStage; ++u) {
+            const bool live = g + u < g_hi;
+            const int oi = (int)(v[u] >> 28) * 64 + lane;
+            int pos = -1;
+            if (live) {
+              pos = off[oi];
+              off[oi] = (uint16_t)(pos + 1);
+            }
+            pos -= r0;
+            const int slot = (live && pos >= 0 && pos < rows ? pos : rows) * kPlaceAtoms + a;
+            tile[slot] = v[u] & 0x0fffffffu;
+            ltile[slot] = (uint16_t)hl[u];
+          }
+        }
+      }
+      __syncthreads();
+      // the kPlaceParts lane groups write interleaved rows
+      const int nrow = rows_max - r0 < rows ? rows_max - r0 : rows;
+      for (int r = h; r < nrow; r += kPlaceParts) {
+        if (valid && r0 + r < cnt) {
+          lo_.nbr[(int64_t)(r0 + r) * N + p] = (int32_t)tile[r * kPlaceAtoms + a];
+          lo_.nbrl[(int64_t)(r0 + r) * N + p] = ltile[r * kPlaceAtoms + a];
+        }
+      }
+      __syncthreads();
+    }
+    __syncthreads();  // the LDS tiles are reused by the next group
   }
 }
 
@@ -710,7 +717,9 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, const BinEdges& be, int 
   else
     hipLaunchKernelGGL(k_build_lists<false>, dim3(nb), dim3(kBlock), 0, st, N, g, rec, cell_start, cell_sorted, be,
                        capR, capA, lout, ht, sc, flags);
-  hipLaunchKernelGGL(k_place_lists, dim3(grid_blocks(N, kPlaceAtoms)), dim3(64), 0, st, N, be.nbins,
+  const int place_groups = grid_blocks(N, kPlaceAtoms);
+  hipLaunchKernelGGL(k_place_lists, dim3(place_groups < kPlaceGrid ? place_groups : kPlaceGrid), dim3(64), 0, st,
+                     N, be.nbins,
                      be.idxA[0][kFracs - 1], capR, capA, lout, sc, flags);
   hipLaunchKernelGGL(k_count_build, dim3(1), dim3(64), 0, st, flags, be.idxR[0][0], be.idxA[0][0], be.idxR[1][0],
                      be.idxA[1][0]);
