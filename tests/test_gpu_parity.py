@@ -243,3 +243,25 @@ def test_each_descriptor_block_separately(block):
     assert rel < 2e-5
     assert np.abs(U - Uo).max() < E_ATOM_TOL
     assert np.abs(W - Wo).max() < 2e-5 * np.abs(Wo).max() + 1e-9
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7])
+def test_tiny_and_sparse_systems(full, n):
+    """A lone atom (empty lists), a far-apart pair, a trimer and a sparse cluster in a
+    box much larger than the cutoffs: energies, forces and virial as the oracle's."""
+    hp, params, m = full
+    rng = np.random.default_rng(60 + n)
+    box = np.array([20.0, 21.0, 22.0])
+    if n == 2:
+        x = np.array([[1.0, 1.0, 1.0], [11.0, 11.5, 12.0]])       # farther apart than 7 A
+    else:
+        x = 10.0 + rng.normal(0.0, 1.2, size=(n, 3))              # a loose cluster
+    at = I.Atoms(x=I.wrap(x, box), types=np.zeros(n, np.int32), box=box, masses=np.array([63.546]))
+    say(f"case: tiny system, N={n}")
+    s = make_system(at, hp, params)
+    E, W, F, U = s.compute(per_atom=True)
+    Eo, Wo, Uo, Fo = oracle.evaluate(m, at.x, at.types, at.box)
+    assert np.abs(U - Uo).max() < E_ATOM_TOL and np.abs(F - Fo).max() < F_TOL
+    assert np.abs(W - Wo).max() < W_ATOM_TOL * max(n, 1) + 1e-6
+    s.step(3)
+    assert np.isfinite(s.get_state()[0]).all()
