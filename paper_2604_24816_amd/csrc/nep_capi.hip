@@ -336,20 +336,37 @@ int reduce_ew(nep_system* s, int base) {
   return NEP_OK;
 }
 
-// Merged, sorted distance-bin edges of the list (see BinEdges): the full model's
-// radial and angular edges; each model's bounds are the first edges at or beyond
-// its own cutoffs plus f_k skin.
+// Merged, sorted distance-bin edges of the list (see BinEdges): r_c + f_k skin for the
+// radial and angular cutoffs of both models, so that each model's evaluation visits
+// only the entries it can need; each model's bounds are the first edges at or beyond
+// its own cutoffs plus f_k skin. If the union exceeded kMaxBins edges, the full
+// model's edges alone are used (the surrogate then visits a few more entries).
 BinEdges make_bin_edges(const nep_hparams* hp0, const nep_hparams* hp1, double skin) {
+  auto edges = [&](const nep_hparams* h, std::vector<double>& e) {
+    for (int k = 0; k < kFracs; ++k) {
+      e.push_back(h->rc_angular + (double)bin_frac(k) * skin);
+      e.push_back(h->rc_radial + (double)bin_frac(k) * skin);
+    }
+  };
+  auto finish = [](std::vector<double>& e) {
+    std::sort(e.begin(), e.end());
+    e.erase(std::unique(e.begin(), e.end()), e.end());
+  };
   std::vector<double> e;
-  for (int k = 0; k < kFracs; ++k) {
-    e.push_back(hp0->rc_angular + (double)bin_frac(k) * skin);
-    e.push_back(hp0->rc_radial + (double)bin_frac(k) * skin);
+  edges(hp0, e);
+  if (hp1) edges(hp1, e);
+  finish(e);
+  // the list cutoff is the full model's largest edge; edges beyond it cannot be used
+  const double outer = hp0->rc_radial + (double)bin_frac(kFracs - 1) * skin;
+  while (!e.empty() && e.back() > outer) e.pop_back();
+  if ((int)e.size() > kMaxBins) {
+    e.clear();
+    edges(hp0, e);
+    finish(e);
   }
-  std::sort(e.begin(), e.end());
-  e.erase(std::unique(e.begin(), e.end()), e.end());
   BinEdges be{};
   be.nbins = (int)e.size();
-  for (int b = 0; b < kMaxBins; ++b) be.e2[b] = b < be.nbins ? e[b] * e[b] : INFINITY;  // no pair reaches unused edges
+  for (int b = 0; b < kMaxBins; ++b) be.e2[b] = b < be.nbins ? e[b] * e[b] : INFINITY;
   const nep_hparams* hp[2] = {hp0, hp1 ? hp1 : hp0};
   for (int m = 0; m < 2; ++m)
     for (int k = 0; k < kFracs; ++k) {

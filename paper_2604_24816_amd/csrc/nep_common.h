@@ -48,7 +48,7 @@ constexpr int kFracs = 5;
 __host__ __device__ constexpr float bin_frac(int k) {
   return k == 0 ? 0.f : (k == 1 ? 0.05f : (k == 2 ? 0.15f : (k == 3 ? 0.35f : 1.0f)));
 }
-constexpr int kMaxBins = 2 * kFracs;
+constexpr int kMaxBins = 16;  // distinct edges of both models' cutoffs; bins fit in 4 bits
 struct BinEdges {
   double e2[kMaxBins];       // squared edges, ascending; e2[nbins - 1] = (rc_radial + skin)^2, then infinity
   int nbins;

@@ -317,14 +317,20 @@ __device__ __forceinline__ int halo_index(const HaloTables& ht, int tile, int nc
   return ho[lo] + (q - hs[lo]);
 }
 
-// Distance bin of a pair inside the list cutoff: the number of interior edges <= r^2
-// (the outer edge and the unused ones, set to infinity, are never reached).
+// Distance bin of a pair inside the list cutoff: the number of interior edges <= r^2,
+// testing the first NE edges (the outer edge and the unused ones, set to infinity, are
+// never reached; NE >= nbins - 1).
+template <int NE>
 __device__ __forceinline__ int bin_of(double r2, const BinEdges& be) {
   int k = 0;
 #pragma unroll
-  for (int m = 0; m < kMaxBins - 1; ++m) k += r2 >= be.e2[m] ? 1 : 0;
+  for (int m = 0; m < NE; ++m) k += r2 >= be.e2[m] ? 1 : 0;
   return k;
 }
+// Edge tests of the list build: one model's nine interior edges, or the union of two
+// models' edges.
+constexpr int kEdgesOne = 2 * kFracs - 1;
+constexpr int kEdgesTwo = kMaxBins - 1;
 
 // Pair vector x_q - x_p in FP64 followed by the periodic shift of the stencil cell
 // (-L, 0 or +L: the value the minimum-image rule subtracts for every pair that can
@@ -413,7 +419,7 @@ __device__ __forceinline__ void stage_flush16(const uint32_t* st, uint4* col, in
 // q | bin << 28 together with its halo-local index. Stencil cells whose nearest point
 // lies beyond the list cutoff (with a 1e-6 A margin) are skipped. k_place_lists then
 // counts the entries per bin and orders them by bin.
-template <bool MINIMG>
+template <bool MINIMG, int NE>
 __global__ void __launch_bounds__(kBlock)
 k_build_lists(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_t* __restrict__ start,
               const int32_t* __restrict__ cell_sorted, BinEdges be, int capR, int capA, ListOut lo_,
@@ -468,7 +474,7 @@ k_build_lists(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_
         const int loc0 = hok ? halo_index(ht, tile, hcells, q0) - q0 : 0;
         scan_cell<MINIMG>(rec, N, q0, q1, p, xi, yi, zi, sx, sy, sz, g, cut2, [&](int q, double r2) {
           if (n < capR) {
-            sq[n % kStage] = (uint32_t)q | ((uint32_t)bin_of(r2, be) << 28);
+            sq[n % kStage] = (uint32_t)q | ((uint32_t)bin_of<NE>(r2, be) << 28);
             sl[n % kStage] = hok ? (uint32_t)(loc0 + q) : (uint32_t)kNoLocal;
             if (n % kStage == kStage - 1) {
               stage_flush32(sq, sc.q, N, p, n);
@@ -711,12 +717,12 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, const BinEdges& be, int 
   hipLaunchKernelGGL(k_halo_tables, dim3(nb), dim3(kBlock), 0, st, N, g, cell_sorted, cell_start, ht, flags);
   // the minimum-image rule inside the candidate loop only for boxes with fewer than
   // three cells along some dimension
-  if (g.nc[0] < 3 || g.nc[1] < 3 || g.nc[2] < 3)
-    hipLaunchKernelGGL(k_build_lists<true>, dim3(nb), dim3(kBlock), 0, st, N, g, rec, cell_start, cell_sorted, be,
-                       capR, capA, lout, ht, sc, flags);
-  else
-    hipLaunchKernelGGL(k_build_lists<false>, dim3(nb), dim3(kBlock), 0, st, N, g, rec, cell_start, cell_sorted, be,
-                       capR, capA, lout, ht, sc, flags);
+  const bool small = g.nc[0] < 3 || g.nc[1] < 3 || g.nc[2] < 3;
+  const bool one = be.nbins - 1 <= kEdgesOne;
+  auto kern = small ? (one ? k_build_lists<true, kEdgesOne> : k_build_lists<true, kEdgesTwo>)
+                    : (one ? k_build_lists<false, kEdgesOne> : k_build_lists<false, kEdgesTwo>);
+  hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, N, g, rec, cell_start, cell_sorted, be, capR, capA, lout,
+                     ht, sc, flags);
   const int place_groups = grid_blocks(N, kPlaceAtoms);
   hipLaunchKernelGGL(k_place_lists, dim3(place_groups < kPlaceGrid ? place_groups : kPlaceGrid), dim3(64), 0, st,
                      N, be.nbins,
