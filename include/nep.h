@@ -102,7 +102,7 @@ int nep_model_create(const nep_hparams* hp, const double* params, int64_t n_para
 void nep_model_destroy(nep_model* m);
 
 /* Bytes of device workspace a system needs. surrogate may be NULL.
- * n_atoms: 1 .. 2^28 - 1 (list entries carry a 3-bit distance bin above the
+ * n_atoms: 1 .. 2^28 - 1 (list entries carry a 4-bit distance bin above the
  * 28-bit atom index while the lists are built); cap_radial, cap_angular: 1 .. 4096.
  * cap_radial / cap_angular: per-atom capacities of the lists with skin
  * (radial cutoff + skin, angular cutoff + skin). */
@@ -144,7 +144,7 @@ int nep_export_neighbors(nep_system* s, int32_t which, int64_t* offsets, int32_t
 
 /* Energy, virial and (optionally) forces and per-atom energies at the current
  * positions, for model slot 0 (full) or 1 (surrogate), with precision
- * NEP_FP32 or NEP_BF16. energy, virial9 (row-major 3x3,
+ * NEP_FP32, NEP_BF16 or NEP_FP64 (checks only). energy, virial9 (row-major 3x3,
  * W_ab = -sum_i sum_j (r_ij)_a (dU_i/dr_ij)_b) are host pointers and always
  * written (FP64 reductions on the device). forces [N][3] and per_atom_energy
  * [N] (FP64, original order) may be NULL; on_device says whether they are
@@ -160,8 +160,11 @@ int nep_compute_energy_forces_virial(nep_system* s, int32_t slot, int32_t precis
  * velocity Verlet with the full model. mts_k >= 1: multiple time stepping with
  * the surrogate as the fast force and the full model applied every mts_k
  * steps (n_steps must be a multiple of mts_k); when the surrogate's force
- * error against the full model exceeds fallback_rms or fallback_max (eV/A),
- * the next blocks fall back to the full model. thermo (host, nullable):
+ * error against the full model exceeds fallback_rms or fallback_max (eV/A, or
+ * multiples of the block's rms full-model force after nep_set_judge(s, 1)),
+ * the next blocks fall back to the full model until 10 blocks in a row pass.
+ * precision: NEP_FP32 or NEP_BF16. With a thermostat set (nep_set_thermostat)
+ * the steps are NVT and mts_k must be 0. thermo (host, nullable):
  * rows of 8 doubles {step, potential, kinetic, temperature, pressure (eV/A^3),
  * surrogate rms error, surrogate max error, fallback flag} every thermo_every
  * steps (and the final step), at most max_rows rows. Synchronises at the end,
