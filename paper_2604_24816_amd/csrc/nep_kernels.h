@@ -179,6 +179,11 @@ struct Shape {
   static constexpr bool FB = FB_;
   static constexpr int NC = L3 * (L3 + 2);
   static constexpr int D = NR + NA * L3 + (FB ? NA : 0);
+  // neighbour records in flight ahead of the pair the descriptor pass works on: with
+  // l <= 2 that pass does too little arithmetic per pair to hide one record's latency
+  // (the force passes gather 64-byte records and stay at one ahead: a deeper queue there
+  // loses more to memory contention than it hides)
+  static constexpr int DESC_AHEAD = L3 <= 2 ? 2 : 1;
   static_assert(D <= 32 && H <= 32, "network tiles hold at most 32 descriptors and 32 hidden units");
   static_assert(NR <= 10 && KR <= 10, "the neighbour record holds 10 radial coefficients");
   static_assert(!FB || L3 >= 2, "the four-body term uses the l = 2 accumulators");
@@ -213,29 +218,39 @@ __device__ __forceinline__ bool inside(double xj, double yj, double zj, double x
 }
 
 // Visits entries [0, k) of atom i's slot-major list, calling body(p, j, w) with the
-// first W 16-byte words of neighbour j's record. The index of entry p + 2 and the
-// record words of entry p + 1 are loaded before the body of entry p runs, so their
-// latency overlaps the pair arithmetic (the last loads repeat entry k - 1: every
-// address stays inside the list and the records).
-template <int W, class Body>
+// first W 16-byte words of neighbour j's record. The records of entries p + 1 .. p + AHEAD
+// and the index of entry p + AHEAD + 1 are in flight while the body of entry p runs, so
+// their latency overlaps the pair arithmetic; a body with little arithmetic per pair
+// needs the deeper queue (the last loads repeat entry k - 1: every address stays inside
+// the list and the records).
+template <int W, int AHEAD = 1, class Body>
 __device__ __forceinline__ void for_each_rec(const int32_t* __restrict__ nbr, const uint4* __restrict__ rec,
                                              int64_t N, int64_t i, int k, Body&& body) {
+  static_assert(AHEAD >= 1 && AHEAD <= 3, "prefetch depth");
   if (k <= 0) return;
-  int32_t j = nbr[i];
-  int32_t jn = nbr[(int64_t)(k > 1 ? 1 : 0) * N + i];
-  uint4 cur[W];
+  int32_t jq[AHEAD + 1];  // indices of entries p .. p + AHEAD
 #pragma unroll
-  for (int w = 0; w < W; ++w) cur[w] = rec[4 * (int64_t)j + w];
+  for (int a = 0; a <= AHEAD; ++a) jq[a] = nbr[(int64_t)(a < k ? a : k - 1) * N + i];
+  uint4 rq[AHEAD][W];  // records of entries p .. p + AHEAD - 1
+#pragma unroll
+  for (int a = 0; a < AHEAD; ++a)
+#pragma unroll
+    for (int w = 0; w < W; ++w) rq[a][w] = rec[4 * (int64_t)jq[a] + w];
   for (int p = 0; p < k; ++p) {
-    const int32_t jnn = nbr[(int64_t)(p + 2 < k ? p + 2 : k - 1) * N + i];
-    uint4 nxt[W];
+    const int32_t jn = nbr[(int64_t)(p + AHEAD + 1 < k ? p + AHEAD + 1 : k - 1) * N + i];
+    uint4 rn[W];
 #pragma unroll
-    for (int w = 0; w < W; ++w) nxt[w] = rec[4 * (int64_t)jn + w];
-    body(p, j, cur);
-    j = jn;
-    jn = jnn;
+    for (int w = 0; w < W; ++w) rn[w] = rec[4 * (int64_t)jq[AHEAD] + w];
+    body(p, jq[0], rq[0]);
 #pragma unroll
-    for (int w = 0; w < W; ++w) cur[w] = nxt[w];
+    for (int a = 0; a < AHEAD; ++a) jq[a] = jq[a + 1];
+    jq[AHEAD] = jn;
+#pragma unroll
+    for (int a = 0; a + 1 < AHEAD; ++a)
+#pragma unroll
+      for (int w = 0; w < W; ++w) rq[a][w] = rq[a + 1][w];
+#pragma unroll
+    for (int w = 0; w < W; ++w) rq[AHEAD - 1][w] = rn[w];
   }
 }
 
@@ -394,7 +409,7 @@ __device__ __forceinline__ void desc_accumulate(const ModelDev& m, const EvalBuf
   for (int k = 0; k < S::KR; ++k) Qb[k] = 0.f;
   // one pass over the list: radial terms for every pair inside rc_radial, angular
   // terms for the pairs of the angular prefix inside rc_angular
-  for_each_rec<2>(b.nbr, b.rec, N, i, kR, [&](int p, int32_t j, const uint4* w) {
+  for_each_rec<2, S::DESC_AHEAD>(b.nbr, b.rec, N, i, kR, [&](int p, int32_t j, const uint4* w) {
     double ex, ey, ez;
     const double r2 = pair_r2_64(rec_f64(w[0].x, w[0].y), rec_f64(w[0].z, w[0].w), rec_f64(w[1].x, w[1].y),
                                  xi, yi, zi, Lx, Ly, Lz, ex, ey, ez);
