@@ -89,7 +89,10 @@ __host__ __device__ inline bool cell_coords(const CellGrid& g, int lin, int& cx,
 constexpr int kTileCellsMax = 48;     // cells a tile may touch
 constexpr int kCandMax = 2048;        // >= 27 * kTileCellsMax, power of two
 constexpr int kHaloCellsMax = 512;    // cells per halo
-constexpr int kHaloMax = 4096;        // atoms per halo held in LDS
+// atoms per halo held in LDS: 3840 keeps the force kernel's LDS (halo forces and
+// tables, 52 KB) within a third of a CU's 160 KB, so three workgroups fit where the
+// registers allow it; FCC boxes at metallic density need at most ~3,400
+constexpr int kHaloMax = 3840;
 constexpr uint16_t kNoLocal = 0xffff; // tile without an LDS halo
 struct HaloTables {
   int32_t* info;   // [ntiles][4] = {ncells, natoms, ok, 0}

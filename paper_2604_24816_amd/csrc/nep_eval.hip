@@ -324,8 +324,13 @@ __device__ void flush_halo(const HaloLds& h, float* __restrict__ F, int64_t N) {
 }
 
 // ------------------------------------------------------------------------ forces
+// Waves per SIMD the force kernel is compiled for: the l <= 2 shapes fit three in
+// registers and in LDS (the halo takes a third of a CU's LDS); four would spill.
+template <class S>
+constexpr int force_waves() { return S::L3 <= 2 ? 3 : 2; }
+
 template <class S, bool MULTI>
-__global__ void __launch_bounds__(kBlock, 2) k_force(ModelDev m, EvalBuffers b) {
+__global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, EvalBuffers b) {
   __shared__ double red[kBlock];
   __shared__ HaloLds halo;
   constexpr int NR = S::NR, NA = S::NA, NC = S::NC;
