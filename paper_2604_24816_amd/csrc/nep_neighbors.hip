@@ -419,7 +419,8 @@ __device__ __forceinline__ void stage_flush16(const uint32_t* st, uint4* col, in
 // q | bin << 28 together with its halo-local index. Stencil cells whose nearest point
 // lies beyond the list cutoff (with a 1e-6 A margin) are skipped. k_place_lists then
 // counts the entries per bin and orders them by bin.
-template <bool MINIMG, int NE>
+// With MARKED, only the atoms that k_build_cells left to it (cnt = -1) are built.
+template <bool MINIMG, int NE, bool MARKED = false>
 __global__ void __launch_bounds__(kBlock)
 k_build_lists(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_t* __restrict__ start,
               const int32_t* __restrict__ cell_sorted, BinEdges be, int capR, int capA, ListOut lo_,
@@ -427,6 +428,7 @@ k_build_lists(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_
   if (flags[FLAG_REBUILD] == 0) return;
   const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (p >= N) return;
+  if (MARKED && lo_.cnt[p] != -1) return;
   const int tile = (int)(p / kBlock);
   const bool hok = ht.info[4 * tile + 2] != 0;
   const int hcells = ht.info[4 * tile + 0];
@@ -492,6 +494,179 @@ k_build_lists(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_
   }
   lo_.cnt[p] = n < capR ? n : capR;
   if (n > capR) atomicMax(&flags[FLAG_OVF_R], n);
+}
+
+// One workgroup per cell (boxes with at least three cells along every dimension):
+// the positions of the 27 stencil cells' atoms are staged in LDS once, in stencil
+// order and by sorted index inside a cell, and each wavefront takes the cell's atoms
+// in turn, its 64 lanes testing 64 candidates at a time. The accepted candidates are
+// compacted (ballot and prefix count) into a per-wavefront LDS queue in candidate
+// order; only those are binned and written, 64 entries per pass, to the atom's
+// scratch column. The scratch therefore holds the same entries in the same order as
+// the per-atom kernel writes, with the FP64 distance computed the same way. Cells
+// whose stencil holds more than kCellCand atoms mark their atoms (cnt = -1) for
+// k_build_lists<false, NE, true>.
+constexpr int kCellCand = 1024;  // stencil atoms a workgroup stages in LDS
+constexpr int kCellQueue = 128;  // accepted candidates queued per wavefront
+
+template <int NE>
+__global__ void __launch_bounds__(kBlock)
+k_build_cells(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_t* __restrict__ start,
+              BinEdges be, int capR, ListOut lo_, HaloTables ht, ListScratch sc, int32_t* __restrict__ flags) {
+#pragma clang fp contract(off)
+  if (flags[FLAG_REBUILD] == 0) return;
+  const int c = xcd_tile(blockIdx.x, gridDim.x);
+  const int s0 = start[c], s1 = start[c + 1];
+  if (s1 <= s0) return;  // empty cell or brick slot outside the grid
+  int cx, cy, cz;
+  cell_coords(g, c, cx, cy, cz);
+  __shared__ double X[kCellCand], Y[kCellCand], Z[kCellCand];
+  __shared__ int32_t Q[kCellCand];
+  __shared__ uint8_t C[kCellCand];
+  __shared__ int cq0[27], cum[28];
+  __shared__ double shift[3][27];
+  __shared__ uint32_t qk[kBlock / 64][kCellQueue];
+  __shared__ double qr[kBlock / 64][kCellQueue];
+  __shared__ int loc0s[2][27];  // halo offset of each stencil cell for the cell's first two tiles
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int tile0 = s0 / kBlock;
+  int cnt_s = 0;
+  if (t < 27) {  // stencil cell t = 9 a + 3 b + e: z offset a - 1, y offset b - 1, x offset e - 1
+    const int r3[3] = {cx + t % 3 - 1, cy + (t / 3) % 3 - 1, cz + t / 9 - 1};
+    int w3[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      w3[d] = (r3[d] + g.nc[d]) % g.nc[d];
+      shift[d][t] = r3[d] < 0 ? -g.box[d] : (r3[d] >= g.nc[d] ? g.box[d] : 0.0);
+    }
+    const int cc = cell_lin(g, w3[0], w3[1], w3[2]);
+    cq0[t] = start[cc];
+    cnt_s = start[cc + 1] - start[cc];
+    cum[t] = cnt_s;
+  }
+  __syncthreads();
+  if (t == 0) {
+    int acc = 0;
+    for (int k = 0; k < 27; ++k) {
+      const int v = cum[k];
+      cum[k] = acc;
+      acc += v;
+    }
+    cum[27] = acc;
+  }
+  __syncthreads();
+  const int nc = cum[27];
+  if (nc > kCellCand) {
+    for (int p = s0 + t; p < s1; p += kBlock) lo_.cnt[p] = -1;
+    return;
+  }
+  // halo-local offsets for the tile of the cell's first atom and the next tile if it
+  // holds atoms of the cell (other tiles, for cells of more than 256 atoms, are
+  // looked up when reached); computed while the positions load
+  if (t >= 64 && t < 64 + 54) {
+    const int u = t - 64, tl = tile0 + u / 27, sc = u % 27;
+    int v = 0;
+    if (tl * kBlock < s1 && ht.info[4 * tl + 2] != 0 && cum[sc + 1] > cum[sc])
+      v = halo_index(ht, tl, ht.info[4 * tl + 0], cq0[sc]) - cq0[sc];
+    loc0s[u / 27][sc] = v;
+  }
+  for (int k = t; k < nc; k += kBlock) {
+    int sidx = 0;
+#pragma unroll
+    for (int m = 1; m < 27; ++m) sidx += k >= cum[m] ? 1 : 0;
+    const int q = cq0[sidx] + (k - cum[sidx]);
+    const uint4 w0 = rec[4 * (int64_t)q], w1 = rec[4 * (int64_t)q + 1];
+    X[k] = rec_f64(w0.x, w0.y);
+    Y[k] = rec_f64(w0.z, w0.w);
+    Z[k] = rec_f64(w1.x, w1.y);
+    Q[k] = q;
+    C[k] = (uint8_t)sidx;
+  }
+  __syncthreads();
+  // a cell away from the periodic boundary has no image shifts
+  const bool shifted = cx == 0 || cy == 0 || cz == 0 || cx == g.nc[0] - 1 || cy == g.nc[1] - 1 ||
+                       cz == g.nc[2] - 1;
+  const double cut2 = be.e2[be.nbins - 1];
+  uint32_t* scq = reinterpret_cast<uint32_t*>(sc.q);
+  uint16_t* scl = reinterpret_cast<uint16_t*>(sc.l);
+  int cached_tile = -1, hok = 0, hcells = 0, loc0 = 0;  // loc0: of stencil cell `lane`, for the atom's tile
+  for (int p = s0 + w; p < s1; p += kBlock / 64) {  // wave-uniform
+    const int tile = p / kBlock;
+    if (tile != cached_tile) {
+      cached_tile = tile;
+      hcells = ht.info[4 * tile + 0];
+      hok = ht.info[4 * tile + 2] != 0;
+      loc0 = 0;
+      if (tile - tile0 < 2) {
+        if (lane < 27) loc0 = loc0s[tile - tile0][lane];
+      } else if (hok && lane < 27 && cum[lane + 1] > cum[lane]) {
+        loc0 = halo_index(ht, tile, hcells, cq0[lane]) - cq0[lane];
+      }
+    }
+    // the atom lies in its own cell, stencil cell 13
+    const int self_off = __shfl(loc0, 13);
+    if (lane == 0) lo_.selfl[p] = hok ? (uint16_t)(self_off + p) : kNoLocal;
+    const int ks = cum[13] + (p - s0);  // the atom's own slot (stencil cell 13 is its cell)
+    const double xi = X[ks], yi = Y[ks], zi = Z[ks];
+    int nw = 0, nq = 0;  // entries written, entries queued (wave-uniform)
+    auto drain = [&]() {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int j0 = 0; j0 < nq; j0 += 64) {
+        const int j = j0 + lane;
+        const bool v = j < nq;
+        const int k = v ? (int)qk[w][j] : 0;
+        const int sidx = C[k];
+        const int lc = __shfl(loc0, sidx);
+        const int e = nw + j;
+        if (v && e < capR) {
+          const int q = Q[k];
+          const int64_t o = ((int64_t)(e / kStage) * N + p) * kStage + e % kStage;
+          scq[o] = (uint32_t)q | ((uint32_t)bin_of<NE>(qr[w][j], be) << 28);
+          scl[o] = hok ? (uint16_t)(lc + q) : kNoLocal;
+        }
+      }
+      nw += nq;
+      nq = 0;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    for (int k0 = 0; k0 < nc; k0 += 64) {
+      const int k = k0 + lane;
+      bool acc = false;
+      double r2 = 0.0;
+      if (k < nc && k != ks) {
+        double dx = X[k] - xi, dy = Y[k] - yi, dz = Z[k] - zi;
+        if (shifted) {
+          const int sidx = C[k];
+          dx = dx + shift[0][sidx];
+          dy = dy + shift[1][sidx];
+          dz = dz + shift[2][sidx];
+        }
+        const double sxx = dx * dx;
+        const double syy = dy * dy;
+        const double szz = dz * dz;
+        const double sxy = sxx + syy;
+        r2 = sxy + szz;
+        acc = r2 < cut2;
+      }
+      const uint64_t m = __ballot(acc);
+      const int pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+      if (acc) {
+        qk[w][nq + pre] = (uint32_t)k;
+        qr[w][nq + pre] = r2;
+      }
+      nq += __popcll(m);
+      if (nq > kCellQueue - 64) drain();
+    }
+    drain();
+    if (lane == 0) {
+      lo_.cnt[p] = nw < capR ? nw : capR;
+      if (nw > capR) atomicMax(&flags[FLAG_OVF_R], nw);
+    }
+  }
 }
 
 // One wavefront per 16 atoms, four lanes per atom: counts each atom's scratch
@@ -719,10 +894,19 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, const BinEdges& be, int 
   // three cells along some dimension
   const bool small = g.nc[0] < 3 || g.nc[1] < 3 || g.nc[2] < 3;
   const bool one = be.nbins - 1 <= kEdgesOne;
-  auto kern = small ? (one ? k_build_lists<true, kEdgesOne> : k_build_lists<true, kEdgesTwo>)
-                    : (one ? k_build_lists<false, kEdgesOne> : k_build_lists<false, kEdgesTwo>);
-  hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, N, g, rec, cell_start, cell_sorted, be, capR, capA, lout,
-                     ht, sc, flags);
+  if (small) {
+    auto kern = one ? k_build_lists<true, kEdgesOne> : k_build_lists<true, kEdgesTwo>;
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, N, g, rec, cell_start, cell_sorted, be, capR, capA,
+                       lout, ht, sc, flags);
+  } else {
+    auto cells = one ? k_build_cells<kEdgesOne> : k_build_cells<kEdgesTwo>;
+    hipLaunchKernelGGL(cells, dim3(ncell), dim3(kBlock), 0, st, N, g, rec, cell_start, be, capR, lout, ht, sc,
+                       flags);
+    // atoms of cells whose stencil did not fit in LDS
+    auto rest = one ? k_build_lists<false, kEdgesOne, true> : k_build_lists<false, kEdgesTwo, true>;
+    hipLaunchKernelGGL(rest, dim3(nb), dim3(kBlock), 0, st, N, g, rec, cell_start, cell_sorted, be, capR, capA,
+                       lout, ht, sc, flags);
+  }
   const int place_groups = grid_blocks(N, kPlaceAtoms);
   hipLaunchKernelGGL(k_place_lists, dim3(place_groups < kPlaceGrid ? place_groups : kPlaceGrid), dim3(64), 0, st,
                      N, be.nbins,
