@@ -77,6 +77,52 @@ def test_neighbor_lists_bit_exact_random_tiny_boxes(full, box, n, seed):
         assert ok, (which, msg)
 
 
+def _stencil_sizes(x, box, cut):
+    """Atoms in each occupied cell's 27-cell stencil, for the library's cell grid
+    (the most cells per side whose width is at least the list cutoff)."""
+    nc = [max(int(np.floor(L / cut)), 1) for L in box]
+    nc = [n - 1 if n > 1 and L / n < cut * (1 + 1e-10) else n for n, L in zip(nc, box)]
+    c = np.minimum((x / (np.array(box) / nc)).astype(int), np.array(nc) - 1)
+    cnt = np.zeros(nc, int)
+    np.add.at(cnt, (c[:, 0], c[:, 1], c[:, 2]), 1)
+    tot = sum(np.roll(cnt, (a, b, e), axis=(0, 1, 2)) for a in (-1, 0, 1) for b in (-1, 0, 1) for e in (-1, 0, 1))
+    return nc, tot[cnt > 0]
+
+
+@pytest.mark.parametrize("case", ["overfull", "blob"])
+def test_neighbor_lists_bit_exact_cell_build(full, case):
+    """Boxes of at least three cells per side take the workgroup-per-cell build; a cell
+    whose stencil holds more than 1000 atoms is built by the per-atom kernel instead.
+    'overfull': every stencil is over that size; 'blob': a dense cluster in a uniform
+    box, so both kernels build part of the lists."""
+    hp, params, m = full
+    rng = np.random.default_rng(11 if case == "overfull" else 12)
+    if case == "overfull":
+        box = np.array([21.5, 22.3, 29.0])
+        x = rng.uniform(0, 1, size=(1500, 3)) * box
+    else:
+        box = np.array([36.0, 36.5, 37.0])
+        u = rng.uniform(0, 1, size=(3000, 3)) * box
+        d = rng.normal(size=(700, 3))
+        blob = np.array([12.0, 20.0, 25.0]) + d / np.linalg.norm(d, axis=1)[:, None] * \
+            (5.0 * rng.uniform(0, 1, size=(700, 1)) ** (1 / 3))
+        x = np.concatenate([u, blob])
+    x = I.wrap(x, box)
+    n = len(x)
+    nc, tot = _stencil_sizes(x, box, 7.0)
+    say(f"case: lists, {case}, box {box.tolist()} ({nc} cells), n={n}, stencil sizes {tot.min()}..{tot.max()}")
+    assert min(nc) >= 3 and tot.max() > 1000
+    if case == "blob":
+        assert tot.min() <= 1000
+    at = I.Atoms(x=x, types=np.zeros(n, np.int32), box=box, masses=np.array([63.546]))
+    s = make_system(at, hp, params, cap_radial=1200, cap_angular=1000)
+    for which, cut in [(0, 7.0), (1, 6.0)]:
+        off, idx = s.export_neighbors(which)
+        cnt, oidx = oracle.neighbors(x, box, cut, cap=1300)
+        ok, msg = lists_equal(off, idx, cnt, oidx)
+        assert ok, (which, msg)
+
+
 def test_energy_forces_virial_4000_atoms(full):
     hp, params, m = full
     at = I.workload_small()
