@@ -117,9 +117,10 @@ def cpu_baseline(hp, params, at, seconds):
                       f"({setup:.1f} s)"}
 
 
-def run_form(form, hp, params, at, steps, warmup, sur=None, judge_fraction=0.75):
-    """Time one form on one box: 'fp32', 'bf16', 'mts' (surrogate inner steps, k = 4) or
-    'mts_bf16' (the same with the bfloat16 network in both models)."""
+def run_form(form, hp, params, at, steps, warmup, sur=None, judge_fraction=0.75, mts_k=4):
+    """Time one form on one box: 'fp32', 'bf16', 'mts' (mts_k surrogate inner steps per
+    full-model step) or 'mts_bf16' (the same with the bfloat16 network in both models).
+    An MTS run times the largest multiple of mts_k not above `steps`."""
     mts = form.startswith("mts")
     import torch
     from paper_2604_24816_amd import nep
@@ -130,7 +131,10 @@ def run_form(form, hp, params, at, steps, warmup, sur=None, judge_fraction=0.75)
     s.set_state(at.x, at.types, at.masses, at.v)
     s.build_neighbors(1.0)
     prec = "bf16" if form in ("bf16", "mts_bf16") else "fp32"
-    k = 4 if mts else 0
+    k = mts_k if mts else 0
+    if mts:
+        steps = k * (steps // k)
+        warmup = k * max(1, warmup // k)
     kw = dict(dt=1.0, rebuild_every=10, skin=1.0, precision=prec, mts_k=k)
     extra = {}
     if mts:
@@ -161,6 +165,8 @@ def run_form(form, hp, params, at, steps, warmup, sur=None, judge_fraction=0.75)
                         "achieved": force_f * n / (fms / fcnt / 1e3) / 1e12, "peak": PEAK_FP32_VECTOR_TFLOPS,
                         "unit": "TFLOP/s"},
            "energy_drift_per_atom": float((th[-1, 1] + th[-1, 2] - th[0, 1] - th[0, 2]) / n) if len(th) > 1 else None}
+    if mts:
+        out["mts_k"] = k
     out["roofline"]["frac"] = out["roofline"]["achieved"] / PEAK_FP32_VECTOR_TFLOPS
     if mts:
         st = s.stats()
@@ -219,9 +225,11 @@ def run_forms(args):
     for name, sur in (("mts_trained_coeffs", (shp, res_c.params)), ("mts_trained", (shp, res.params)),
                       ("mts_untrained", (shp, sur0)), ("mts_short_trained_coeffs", (shp_s, res_sc.params)),
                       ("mts_short_trained", (shp_s, res_s.params)), ("mts_short_untrained", (shp_s, sur0_s)),
-                      ("mts_short_trained_coeffs_bf16", (shp_s, res_sc.params))):
+                      ("mts_short_trained_coeffs_bf16", (shp_s, res_sc.params)),
+                      ("mts_short_trained_coeffs_k8", (shp_s, res_sc.params))):
+        # the last form: the full model every 8 steps instead of 4 (same judge)
         forms[name] = run_form("mts_bf16" if name.endswith("_bf16") else "mts", hp, params, at, args.steps, wm,
-                               sur=sur)
+                               sur=sur, mts_k=8 if name.endswith("_k8") else 4)
         print(f"form {name}: {forms[name]['atom_steps_per_s']:.3e} atom-steps/s, "
               f"{forms[name]['mts_blocks']} MTS / {forms[name]['fallback_blocks']} fallback blocks",
               file=sys.stderr, flush=True)

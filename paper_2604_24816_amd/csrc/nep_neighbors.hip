@@ -676,7 +676,7 @@ k_build_cells(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_
 // longer lists take further rounds. Lane h counts and places entries [32 h, 32 (h + 1))
 // (the last lane the rest), starting each bin after the entries of earlier parts.
 // Entries outside the current round go to a spare row.
-constexpr int kPlaceRows = 127;
+constexpr int kPlaceRows = 159;  // one round for lists up to 159 entries (FCC metals at 7 A: ~135-150)
 constexpr int kPlaceAtoms = 64 / kPlaceParts;
 constexpr int kPlaceGrid = 16384;  // workgroups of the placement (grid-stride over atom groups)
 
