@@ -200,6 +200,8 @@ def run_forms(args):
     n_frames = int(fr.x.shape[0])
     shp_s = I.SURROGATE_SHORT_HPARAMS   # the same surrogate with 5 / 4 A cutoffs (fewer pairs per step)
     sur0_s = I.surrogate_from_teacher(hp, params, shp_s, 1)
+    shp_t = I.SURROGATE_SHORTER_HPARAMS  # 4 / 3 A: two radial shells, one angular shell
+    sur0_t = I.surrogate_from_teacher(hp, params, shp_t, 1)
 
     def train(label, h, p0, coeffs):
         def log(msg):
@@ -214,6 +216,7 @@ def run_forms(args):
     res_c = train("6/5 A, coefficients", shp, sur0, True)
     res_s = train("5/4 A", shp_s, sur0_s, False)
     res_sc = train("5/4 A, coefficients", shp_s, sur0_s, True)
+    res_tc = train("4/3 A, coefficients", shp_t, sur0_t, True)
     del fr
     torch.cuda.empty_cache()
     at = I.workload_32m(args.cells)
@@ -226,7 +229,9 @@ def run_forms(args):
                       ("mts_untrained", (shp, sur0)), ("mts_short_trained_coeffs", (shp_s, res_sc.params)),
                       ("mts_short_trained", (shp_s, res_s.params)), ("mts_short_untrained", (shp_s, sur0_s)),
                       ("mts_short_trained_coeffs_bf16", (shp_s, res_sc.params)),
-                      ("mts_short_trained_coeffs_k8", (shp_s, res_sc.params))):
+                      ("mts_short_trained_coeffs_k8", (shp_s, res_sc.params)),
+                      ("mts_shorter_trained_coeffs", (shp_t, res_tc.params)),
+                      ("mts_shorter_untrained", (shp_t, sur0_t))):
         # the last form: the full model every 8 steps instead of 4 (same judge)
         forms[name] = run_form("mts_bf16" if name.endswith("_bf16") else "mts", hp, params, at, args.steps, wm,
                                sur=sur, mts_k=8 if name.endswith("_k8") else 4)
@@ -245,7 +250,8 @@ def run_forms(args):
                                   "val_force_rmse_init": r.val_force_rmse_init, "val_force_rmse": r.val_force_rmse,
                                   "val_energy_mae_init": r.val_energy_mae_init, "val_energy_mae": r.val_energy_mae}
                            for name, r in (("teacher_cutoffs", res), ("teacher_cutoffs_coeffs", res_c),
-                                           ("short_cutoffs", res_s), ("short_cutoffs_coeffs", res_sc))}},
+                                           ("short_cutoffs", res_s), ("short_cutoffs_coeffs", res_sc),
+                                           ("shorter_cutoffs_coeffs", res_tc))}},
            "forms": forms}
     print(json.dumps(out))
 

@@ -339,31 +339,48 @@ int reduce_ew(nep_system* s, int base) {
 // Merged, sorted distance-bin edges of the list (see BinEdges): r_c + f_k skin for the
 // radial and angular cutoffs of both models, so that each model's evaluation visits
 // only the entries it can need; each model's bounds are the first edges at or beyond
-// its own cutoffs plus f_k skin. If the union exceeded kMaxBins edges, the full
-// model's edges alone are used (the surrogate then visits a few more entries).
+// its own cutoffs plus f_k skin. Any subset of edges that keeps the outer one gives
+// correct bounds (a missing edge only makes a model visit the entries up to the next
+// one), so when the union exceeds kMaxBins edges the least useful are dropped: the
+// largest skin fractions first (they serve only late in a rebuild interval), the
+// surrogate's before the full model's at equal fraction; the exact cutoffs (f = 0)
+// and the outer edge are always kept.
 BinEdges make_bin_edges(const nep_hparams* hp0, const nep_hparams* hp1, double skin) {
-  auto edges = [&](const nep_hparams* h, std::vector<double>& e) {
+  struct Edge {
+    double r;
+    int rank;  // removal order: higher goes first; -1 = never removed
+  };
+  std::vector<Edge> c;
+  const nep_hparams* hps[2] = {hp0, hp1};
+  for (int m = 0; m < (hp1 ? 2 : 1); ++m)
     for (int k = 0; k < kFracs; ++k) {
-      e.push_back(h->rc_angular + (double)bin_frac(k) * skin);
-      e.push_back(h->rc_radial + (double)bin_frac(k) * skin);
+      const int rank = k == 0 ? -1 : 2 * k + m;  // f_k skin, surrogate (m = 1) first at equal k
+      c.push_back({hps[m]->rc_angular + (double)bin_frac(k) * skin, rank});
+      c.push_back({hps[m]->rc_radial + (double)bin_frac(k) * skin, rank});
     }
-  };
-  auto finish = [](std::vector<double>& e) {
-    std::sort(e.begin(), e.end());
-    e.erase(std::unique(e.begin(), e.end()), e.end());
-  };
-  std::vector<double> e;
-  edges(hp0, e);
-  if (hp1) edges(hp1, e);
-  finish(e);
   // the list cutoff is the full model's largest edge; edges beyond it cannot be used
   const double outer = hp0->rc_radial + (double)bin_frac(kFracs - 1) * skin;
-  while (!e.empty() && e.back() > outer) e.pop_back();
-  if ((int)e.size() > kMaxBins) {
-    e.clear();
-    edges(hp0, e);
-    finish(e);
+  std::sort(c.begin(), c.end(), [](const Edge& x, const Edge& y) { return x.r < y.r; });
+  std::vector<Edge> u;  // distinct edges up to the outer one, each with its most useful rank
+  for (const Edge& x : c) {
+    if (x.r > outer) break;
+    if (!u.empty() && u.back().r == x.r) {
+      const int a = u.back().rank, b = x.rank;
+      u.back().rank = (a < 0 || b < 0) ? -1 : std::min(a, b);
+    } else {
+      u.push_back(x);
+    }
   }
+  u.back().rank = -1;  // the outer edge
+  while ((int)u.size() > kMaxBins) {
+    int worst = -1;
+    for (int i = 0; i < (int)u.size(); ++i)
+      if (u[i].rank >= 0 && (worst < 0 || u[i].rank > u[worst].rank)) worst = i;
+    if (worst < 0) break;  // cannot happen: at most four exact cutoffs and the outer edge
+    u.erase(u.begin() + worst);
+  }
+  std::vector<double> e;
+  for (const Edge& x : u) e.push_back(x.r);
   BinEdges be{};
   be.nbins = (int)e.size();
   for (int b = 0; b < kMaxBins; ++b) be.e2[b] = b < be.nbins ? e[b] * e[b] : INFINITY;

@@ -218,6 +218,8 @@ FULL_HPARAMS = HParams()
 SURROGATE_HPARAMS = HParams(l_max_3b=2, l_max_4b=0, n_hidden=8)
 # The same surrogate with 5 / 4 A cutoffs: fewer pairs, so a cheaper inner step.
 SURROGATE_SHORT_HPARAMS = HParams(rc_radial=5.0, rc_angular=4.0, l_max_3b=2, l_max_4b=0, n_hidden=8)
+# 4 / 3 A: two radial neighbour shells and one angular shell of FCC Cu (a = 3.615 A).
+SURROGATE_SHORTER_HPARAMS = HParams(rc_radial=4.0, rc_angular=3.0, l_max_3b=2, l_max_4b=0, n_hidden=8)
 
 # Descriptor scaler of the synthetic models, one constant per descriptor block
 # (radial, angular l = 1..4, four-body). The constants were chosen once so that

@@ -19,11 +19,12 @@ def models():
     return hp, teacher, shp, sur
 
 
-@pytest.mark.parametrize("cutoffs", ["teacher", "short"])
+@pytest.mark.parametrize("cutoffs", ["teacher", "short", "shorter"])
 def test_mts_blocks_match_oracle_rrespa(models, cutoffs):
+    """'shorter' (4 / 3 A) brings the two models' bin edges to 17, so the list keeps 16."""
     hp, teacher, shp, sur = models
-    if cutoffs == "short":
-        shp = I.SURROGATE_SHORT_HPARAMS
+    if cutoffs != "teacher":
+        shp = I.SURROGATE_SHORT_HPARAMS if cutoffs == "short" else I.SURROGATE_SHORTER_HPARAMS
         sur = I.surrogate_from_teacher(hp, teacher, shp, 1)
     at = I.workload_small()
     say(f"case: MTS k=4, 3 blocks, 4000 atoms, untrained surrogate ({cutoffs} cutoffs), no fallback")

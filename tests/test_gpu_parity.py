@@ -145,12 +145,14 @@ def test_two_species_alloy_with_vacancies():
     assert ok, msg
 
 
-@pytest.mark.parametrize("cutoffs", ["teacher", "short"])
+@pytest.mark.parametrize("cutoffs", ["teacher", "short", "shorter"])
 def test_surrogate_shape(full, cutoffs):
-    """The surrogate in slot 1 of a system built around the full model; with 5 / 4 A
-    cutoffs it visits only the bins of the shared list up to its own cutoffs."""
+    """The surrogate in slot 1 of a system built around the full model; with 5 / 4 or
+    4 / 3 A cutoffs it visits only the bins of the shared list up to its own cutoffs
+    (4 / 3 A: 17 candidate edges, of which the list keeps 16)."""
     hp, params, m = full
-    shp = I.SURROGATE_HPARAMS if cutoffs == "teacher" else I.SURROGATE_SHORT_HPARAMS
+    shp = {"teacher": I.SURROGATE_HPARAMS, "short": I.SURROGATE_SHORT_HPARAMS,
+           "shorter": I.SURROGATE_SHORTER_HPARAMS}[cutoffs]
     sp = I.surrogate_from_teacher(hp, params, shp, 1)
     ms = oracle.Model.from_hparams(shp, sp)
     at = I.fcc_box(5, 0.12, 9)
