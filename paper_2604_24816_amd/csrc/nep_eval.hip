@@ -361,6 +361,7 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
 #pragma unroll
     for (int k = 0; k < NA * NC; ++k) G[k] = b.G[(int64_t)k * N + i];
     const double rcR2 = m.rcR64 * m.rcR64, rcA2 = m.rcA64 * m.rcA64;
+    const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
     const int kR = radial_bound(b, i), kA = angular_bound(b, i);
     ZblSeenFor<MULTI> zs;  // pairs inside the ZBL radius
     // One pass over the list. Radial pairs: gather, F_i += (dU_i/dr_ij + dU_j/dr_ji) along u,
@@ -370,7 +371,8 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
     for_each_rec<4>(b.nbr, b.rec, N, i, kR, [&](int p, int32_t j, const uint4* rw) {
       double ex, ey, ez;
       const double r2 = pair_r2_64(rec_f64(rw[0].x, rw[0].y), rec_f64(rw[0].z, rw[0].w),
-                                   rec_f64(rw[1].x, rw[1].y), xi, yi, zi, Lx, Ly, Lz, ex, ey, ez);
+                                   rec_f64(rw[1].x, rw[1].y), xi, yi, zi, Lx, Ly, Lz, iLx, iLy, iLz, ex, ey,
+                                   ez);
       if (!(r2 < rcR2)) return;
       const float dx = (float)ex, dy = (float)ey, dz = (float)ez;
       const bool ang = p < kA && r2 < rcA2;

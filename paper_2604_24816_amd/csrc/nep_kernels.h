@@ -318,13 +318,22 @@ __device__ __forceinline__ void zbl_pair(const ModelDev& m, int tp, double r, do
   de = dphi * sw + phi * dsw;
 }
 
-// FP64 minimum-image vector of a pair whose position is loaded and its r^2.
+// Minimum image of a list pair's FP64 component as d - L rint(d / L) (one multiply,
+// one rounding, one fused multiply-add instead of two compares and selects of 64-bit
+// values). L rint(d / L) is 0 or +-L exactly, so the result is the rule's d, d - L or
+// d + L rounded once, as the rule gives it, except when |d| is within rounding of L/2;
+// there both candidates lie at L/2 >= rc + skin from the center, outside every cutoff.
+__device__ __forceinline__ double min_image_list(double d, double L, double inv_L) {
+  return fma(-L, rint(d * inv_L), d);
+}
+
+// FP64 minimum-image vector of a list pair whose position is loaded and its r^2.
 __device__ __forceinline__ double pair_r2_64(double xj, double yj, double zj, double xi, double yi, double zi,
-                                             double Lx, double Ly, double Lz, double& ex, double& ey,
-                                             double& ez) {
-  ex = min_image(xj - xi, Lx);
-  ey = min_image(yj - yi, Ly);
-  ez = min_image(zj - zi, Lz);
+                                             double Lx, double Ly, double Lz, double iLx, double iLy, double iLz,
+                                             double& ex, double& ey, double& ez) {
+  ex = min_image_list(xj - xi, Lx, iLx);
+  ey = min_image_list(yj - yi, Ly, iLy);
+  ez = min_image_list(zj - zi, Lz, iLz);
   return ex * ex + ey * ey + ez * ez;
 }
 
@@ -399,6 +408,7 @@ __device__ __forceinline__ void desc_accumulate(const ModelDev& m, const EvalBuf
   const int64_t N = b.N;
   const float rcR_inv = 1.f / m.rcR, rcA_inv = 1.f / m.rcA;
   const double rcR2 = m.rcR64 * m.rcR64, rcA2 = m.rcA64 * m.rcA64;
+  const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
   nr = 0;
   na = 0;
   const float* cR = m.cR + (MULTI ? 0 : (ti * m.T) * NR * S::KR);
@@ -412,7 +422,7 @@ __device__ __forceinline__ void desc_accumulate(const ModelDev& m, const EvalBuf
   for_each_rec<2, S::DESC_AHEAD>(b.nbr, b.rec, N, i, kR, [&](int p, int32_t j, const uint4* w) {
     double ex, ey, ez;
     const double r2 = pair_r2_64(rec_f64(w[0].x, w[0].y), rec_f64(w[0].z, w[0].w), rec_f64(w[1].x, w[1].y),
-                                 xi, yi, zi, Lx, Ly, Lz, ex, ey, ez);
+                                 xi, yi, zi, Lx, Ly, Lz, iLx, iLy, iLz, ex, ey, ez);
     if (!(r2 < rcR2)) return;
     const float dx = (float)ex, dy = (float)ey, dz = (float)ez;
     ++nr;
