@@ -228,19 +228,24 @@ __device__ __forceinline__ void for_each_rec(const int32_t* __restrict__ nbr, co
                                              int64_t N, int64_t i, int k, Body&& body) {
   static_assert(AHEAD >= 1 && AHEAD <= 3, "prefetch depth");
   if (k <= 0) return;
+  // slots, indices and N fit in 32 bits (N < 2^28): 32 x 32 -> 64-bit offsets
+  const int32_t* __restrict__ col = nbr + i;
+  const uint32_t n32 = (uint32_t)N;
+  auto slot = [&](int s) { return col[(uint64_t)(uint32_t)s * n32]; };
+  auto record = [&](int32_t j, int w) { return rec[((uint64_t)(uint32_t)j << 2) + w]; };
   int32_t jq[AHEAD + 1];  // indices of entries p .. p + AHEAD
 #pragma unroll
-  for (int a = 0; a <= AHEAD; ++a) jq[a] = nbr[(int64_t)(a < k ? a : k - 1) * N + i];
+  for (int a = 0; a <= AHEAD; ++a) jq[a] = slot(a < k ? a : k - 1);
   uint4 rq[AHEAD][W];  // records of entries p .. p + AHEAD - 1
 #pragma unroll
   for (int a = 0; a < AHEAD; ++a)
 #pragma unroll
-    for (int w = 0; w < W; ++w) rq[a][w] = rec[4 * (int64_t)jq[a] + w];
+    for (int w = 0; w < W; ++w) rq[a][w] = record(jq[a], w);
   for (int p = 0; p < k; ++p) {
-    const int32_t jn = nbr[(int64_t)(p + AHEAD + 1 < k ? p + AHEAD + 1 : k - 1) * N + i];
+    const int32_t jn = slot(p + AHEAD + 1 < k ? p + AHEAD + 1 : k - 1);
     uint4 rn[W];
 #pragma unroll
-    for (int w = 0; w < W; ++w) rn[w] = rec[4 * (int64_t)jq[AHEAD] + w];
+    for (int w = 0; w < W; ++w) rn[w] = record(jq[AHEAD], w);
     body(p, jq[0], rq[0]);
 #pragma unroll
     for (int a = 0; a < AHEAD; ++a) jq[a] = jq[a + 1];
