@@ -153,6 +153,10 @@ def run_form(form, hp, params, at, steps, warmup, sur=None, judge_fraction=0.75,
     prof = s.profile_read()
     s.profile(False)
     n = at.n
+    if mts:
+        # pair counts are those of the last evaluation, which in an MTS run is the full
+        # model's; the surrogate's roofline needs its own, at its own cutoffs
+        s.compute(slot=1, precision=prec, on_device=True)
     pr, pa, sk = s.pair_counts()
     model_name = "surrogate" if mts else "full"
     grp = "force_surrogate" if mts else "force"
