@@ -31,9 +31,10 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_MFMA_TFLOPS = 157.3     # MI355X dense FP32 matrix peak
 PEAK_BF16_MFMA_TFLOPS = 2500.0    # MI355X dense bfloat16 matrix peak (no sparsity)
 
-# Static FLOP counts per unit (FMA = 2 flops), from the kernel source of the full
-# model (n_max 4, basis 8, l_max 4 + four-body, 30 hidden): see the kernel notes
-# in the design doc. Units are pairs inside the true cutoffs and atoms.
+# Static FLOP counts per unit (FMA = 2 flops) of the method's definition, counted per
+# pair inside the true cutoff or per atom (the basis and its derivative, the channel
+# contractions, harmonics and their gradients, the network). Units are pairs inside
+# the true cutoffs and atoms.
 FLOPS = {
     "full": {
         "force_radial_pair": 346,
@@ -357,7 +358,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              f"(the path shards by spatial decomposition, see DESIGN.md)", file=sys.stderr)
+              f"(the library computes one GPU's share; the spatial decomposition with a halo "
+              f"exchange across GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     if args.copy_calibration:

@@ -3,7 +3,7 @@
 Bars: neighbour lists bit-exact as sorted index sets; FP32 energies within
 1e-6 eV per atom (max over atoms and total / N), forces within 1e-4 eV/A,
 virial within 1e-6 eV per atom per component; bfloat16 network against the
-oracle's bfloat16 model within the FP32-accumulation slack derived in the design doc.
+oracle's bfloat16 model within the bound of one rounding flip (see that test).
 """
 import numpy as np
 import pytest
