@@ -101,7 +101,10 @@ int nep_model_create(const nep_hparams* hp, const double* params, int64_t n_para
                      nep_model** out);
 void nep_model_destroy(nep_model* m);
 
-/* Bytes of device workspace a system needs. surrogate may be NULL.
+/* Bytes of device workspace a system needs. surrogate may be NULL; otherwise it
+ * has the full model's number of species and cutoffs no larger than the full
+ * model's (it reads the full model's lists, visiting only their distance bins up to
+ * its own cutoffs), else NEP_ERR_ARG; nep_system_create checks the same.
  * n_atoms: 1 .. 2^28 - 1 (list entries carry a 4-bit distance bin above the
  * 28-bit atom index while the lists are built); cap_radial, cap_angular: 1 .. 4096.
  * cap_radial / cap_angular: per-atom capacities of the lists with skin
