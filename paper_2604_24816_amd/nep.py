@@ -197,15 +197,25 @@ class NEPSystem:
         p = np.ascontiguousarray(params, dtype=np.float64)
         self._check(self.lib.nep_system_set_params(self.handle, slot, _np_ptr(p), p.size))
 
+    def _shape(self, a, shape, name):
+        if tuple(a.shape) != shape:
+            raise ValueError(f"{name} has shape {tuple(a.shape)}, expected {shape}")
+
     def set_state(self, x, types, masses, v=None):
+        """Positions [N][3] (A), species [N], one mass per species (amu), velocities [N][3]
+        (A/fs, optional): host arrays, or device tensors for x, types and v."""
         self.generation += 1
-        masses = np.ascontiguousarray(masses, dtype=np.float64)
-        self._types = types
-        self._masses = masses
+        masses = np.ascontiguousarray(masses, dtype=np.float64).reshape(-1)
+        self._shape(masses, (self.full.hp.n_types,), "masses")
         if isinstance(x, torch.Tensor):
             xt = x.to(self.device, torch.float64).contiguous()
             tt = torch.as_tensor(types, device=self.device, dtype=torch.int32).contiguous()
-            vt = None if v is None else v.to(self.device, torch.float64).contiguous()
+            vt = None if v is None else torch.as_tensor(v).to(self.device, torch.float64).contiguous()
+            self._shape(xt, (self.n, 3), "x")
+            self._shape(tt, (self.n,), "types")
+            if vt is not None:
+                self._shape(vt, (self.n, 3), "v")
+            self._types, self._masses = types, masses
             self._check(self.lib.nep_set_state(self.handle, _t_ptr(xt), _t_ptr(vt) if vt is not None else None,
                                                _t_ptr(tt), _np_ptr(masses), 1))
             torch.cuda.synchronize(self.device)
@@ -213,7 +223,11 @@ class NEPSystem:
         x = np.ascontiguousarray(x, dtype=np.float64)
         t = np.ascontiguousarray(types, dtype=np.int32)
         vv = None if v is None else np.ascontiguousarray(v, dtype=np.float64)
-        assert x.shape == (self.n, 3) and t.shape == (self.n,)
+        self._shape(x, (self.n, 3), "x")
+        self._shape(t, (self.n,), "types")
+        if vv is not None:
+            self._shape(vv, (self.n, 3), "v")
+        self._types, self._masses = types, masses
         self._check(self.lib.nep_set_state(self.handle, _np_ptr(x), _np_ptr(vv) if vv is not None else None,
                                            _np_ptr(t), _np_ptr(masses), 0))
 
@@ -363,19 +377,28 @@ class NEPSystem:
         self._check(fn(self.handle, slot, _t_ptr(theta), ctypes.byref(E), _t_ptr(F)))
         return E.value, F
 
+    def _device_f32(self, a, n, name):
+        if not (isinstance(a, torch.Tensor) and a.dtype == torch.float32 and a.is_contiguous()
+                and a.device == self.device and a.numel() == n):
+            raise ValueError(f"{name} must be a contiguous float32 tensor of {n} values on {self.device}")
+
     def _train_backward(self, fn, slot, theta, gE, gF, out, all_params):
         theta = self._expect(slot, theta, all_params)
         acc = out is not None
+        if acc:
+            self._device_f32(out, theta.numel(), "out")
         grad = out if acc else torch.empty_like(theta)
         gFc = None if gF is None else gF.detach().to(self.device, torch.float32).contiguous()
+        if gFc is not None:
+            self._shape(gFc, (self.n, 3), "gF")
         self._check(fn(self.handle, slot, _t_ptr(theta), float(gE), _t_ptr(gFc) if gFc is not None else None,
                        _t_ptr(grad), 1 if acc else 0))
         return grad
 
     def adam(self, theta: torch.Tensor, grad: torch.Tensor, m1: torch.Tensor, m2: torch.Tensor, t: int,
              lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
-        for a in (theta, grad, m1, m2):
-            assert a.dtype == torch.float32 and a.is_contiguous() and a.device == self.device
+        for a, name in ((theta, "theta"), (grad, "grad"), (m1, "m1"), (m2, "m2")):
+            self._device_f32(a, theta.numel(), name)
         self._check(self.lib.nep_adam_update(self.handle, _t_ptr(theta), _t_ptr(grad), _t_ptr(m1), _t_ptr(m2),
                                              theta.numel(), int(t), lr, beta1, beta2, eps))
 
