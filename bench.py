@@ -60,12 +60,16 @@ TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_force_fcc4m_fp32_hbm_traffic
 
 
 def force_sources_digest():
-    """SHA-256 of the sources the force kernel is compiled from."""
+    """SHA-256 of the code the force kernel is compiled from: its sources with // comments
+    and blank lines removed, so that a comment edit does not disown the measured counters."""
     import hashlib
     h = hashlib.sha256()
     for name in FORCE_SOURCES:
-        with open(os.path.join(ROOT, "paper_2604_24816_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_2604_24816_amd", "csrc", name), encoding="utf-8") as f:
+            for line in f:
+                code = line.split("//", 1)[0].rstrip()
+                if code:
+                    h.update(code.encode("utf-8") + b"\n")
     return h.hexdigest()
 
 

@@ -41,8 +41,9 @@ enum {
 // since the build, so an evaluation visits the radial pairs up to the edge
 // rc_radial + f_k skin and the angular pairs up to rc_angular + f_k skin for the
 // first k with f_k skin >= 2 d; every visited pair is still tested against the
-// true cutoff. The edges come from the full model's cutoffs; a surrogate with
-// shorter cutoffs visits the bins up to the first edge beyond its own.
+// true cutoff. The edges come from both models' cutoffs (at most kMaxBins; beyond
+// that the largest skin fractions are dropped, the surrogate's first), and each
+// model visits the bins up to the first edges at or beyond its own.
 // bp[b][i] = number of entries of atom i in bins 0..b.
 constexpr int kFracs = 5;
 __host__ __device__ constexpr float bin_frac(int k) {
