@@ -25,6 +25,13 @@ NEP_FP64 = 2   # evaluation only: FP64 throughout, for checks
 _PREC = {"fp32": NEP_FP32, "bf16": NEP_BF16, "fp64": NEP_FP64, NEP_FP32: NEP_FP32, NEP_BF16: NEP_BF16,
          NEP_FP64: NEP_FP64}
 
+
+def _prec(p) -> int:
+    try:
+        return _PREC[p]
+    except (KeyError, TypeError):
+        raise ValueError(f"precision {p!r}: expected 'fp32', 'bf16' or 'fp64'") from None
+
 EXPORTED = [
     "nep_param_count", "nep_model_create", "nep_model_destroy", "nep_system_workspace_bytes",
     "nep_system_create", "nep_system_destroy", "nep_system_set_params", "nep_set_state",
@@ -274,7 +281,7 @@ class NEPSystem:
             fp = _np_ptr(F) if F is not None else None
             up = _np_ptr(U) if U is not None else None
         self._check(self.lib.nep_compute_energy_forces_virial(
-            self.handle, slot, _PREC[precision], ctypes.byref(E), _np_ptr(W), fp, up, 1 if on_device else 0))
+            self.handle, slot, _prec(precision), ctypes.byref(E), _np_ptr(W), fp, up, 1 if on_device else 0))
         return E.value, W.reshape(3, 3), F, U
 
     def step(self, n_steps: int, dt: float = 1.0, rebuild_every: int = 10, skin: float = 1.0,
@@ -284,12 +291,13 @@ class NEPSystem:
 
         With ``relative_judge`` the MTS fallback thresholds are multiples of each block's rms
         full-model force instead of eV/A."""
+        prec = _prec(precision)
         self.generation += 1
         self._check(self.lib.nep_set_judge(self.handle, 1 if relative_judge else 0))
         rows = ctypes.c_int64()
         th = np.zeros((max_rows, 8)) if thermo_every > 0 else None
         self._check(self.lib.nep_step(self.handle, int(n_steps), float(dt), int(rebuild_every), float(skin),
-                                      int(mts_k), float(fallback_rms), float(fallback_max), _PREC[precision],
+                                      int(mts_k), float(fallback_rms), float(fallback_max), prec,
                                       _np_ptr(th) if th is not None else None, int(max(thermo_every, 1)),
                                       int(max_rows), ctypes.byref(rows)))
         return th[: rows.value].copy() if th is not None else None
@@ -340,7 +348,7 @@ class NEPSystem:
 
     def surrogate_error(self, precision="fp32"):
         e = np.zeros(2)
-        self._check(self.lib.nep_surrogate_error(self.handle, _PREC[precision], _np_ptr(e)))
+        self._check(self.lib.nep_surrogate_error(self.handle, _prec(precision), _np_ptr(e)))
         return float(e[0]), float(e[1])
 
     # ------------------------------------------------------------------ training

@@ -78,3 +78,12 @@ def test_adam_checks_sizes_and_dtypes():
     assert s.lib.calls == []
     s.adam(a, torch.zeros(10), torch.zeros(10), torch.zeros(10), 1)
     assert s.lib.calls[-1][0] == "nep_adam_update"
+
+
+def test_unknown_precision_is_refused():
+    s = shell()
+    with pytest.raises(ValueError):
+        s.compute(precision="fp16")
+    with pytest.raises(ValueError):
+        s.step(4, precision="half")
+    assert s.lib.calls == []
