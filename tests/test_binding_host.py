@@ -87,3 +87,13 @@ def test_unknown_precision_is_refused():
     with pytest.raises(ValueError):
         s.step(4, precision="half")
     assert s.lib.calls == []
+
+
+def test_valid_calls_reach_the_library():
+    s = shell()
+    E, W, F, U = s.compute(precision="bf16", per_atom=True)
+    assert F.shape == (4, 3) and U.shape == (4,) and W.shape == (3, 3)
+    assert s.lib.calls[-1][0] == "nep_compute_energy_forces_virial" and s.lib.calls[-1][1][2] == nep.NEP_BF16
+    th = s.step(8, mts_k=4, thermo_every=4, relative_judge=True)
+    names = [c[0] for c in s.lib.calls]
+    assert names[-2:] == ["nep_set_judge", "nep_step"] and th.shape == (0, 8)
