@@ -146,7 +146,10 @@ int nep_export_neighbors(nep_system* s, int32_t which, int64_t* offsets, int32_t
                          int64_t cap_total);
 
 /* Energy, virial and (optionally) forces and per-atom energies at the current
- * positions, for model slot 0 (full) or 1 (surrogate), with precision
+ * positions (Section III.B: the total energy is the sum of the per-atom network
+ * outputs U_i of the descriptors q^i, and the forces F_i = sum_j (dU_i/dr_ij -
+ * dU_j/dr_ji) and the virial follow from the derivatives of U_i with respect to
+ * the pair vectors r_ij = x_j - x_i), for model slot 0 (full) or 1 (surrogate), with precision
  * NEP_FP32, NEP_BF16 or NEP_FP64 (checks only). energy, virial9 (row-major 3x3,
  * W_ab = -sum_i sum_j (r_ij)_a (dU_i/dr_ij)_b) are host pointers and always
  * written (FP64 reductions on the device). forces [N][3] and per_atom_energy
@@ -167,7 +170,13 @@ int nep_compute_energy_forces_virial(nep_system* s, int32_t slot, int32_t precis
  * multiples of the block's rms full-model force after nep_set_judge(s, 1)),
  * the next blocks fall back to the full model until 10 blocks in a row pass.
  * precision: NEP_FP32 or NEP_BF16. With a thermostat set (nep_set_thermostat)
- * the steps are NVT and mts_k must be 0. thermo (host, nullable):
+ * the steps are NVT and mts_k must be 0. The list flags are checked after
+ * every rebuild_every-th step and after every MTS block: a list that overflowed
+ * its capacity at a build stops the run at the first such check with
+ * NEP_ERR_NEIGHBOR_OVERFLOW (at most rebuild_every steps, or one block, after
+ * the build); the state is that of the step reached (nep_get_state), the
+ * steps since the overflowing build used truncated lists and are void, and
+ * the next call rebuilds the lists. thermo (host, nullable):
  * rows of 8 doubles {step, potential, kinetic, temperature, pressure (eV/A^3),
  * surrogate rms error, surrogate max error, fallback flag} every thermo_every
  * steps (and the final step), at most max_rows rows. Synchronises at the end,
@@ -210,6 +219,15 @@ int nep_get_state(nep_system* s, double* x, double* v, int64_t* step, int32_t on
 
 /* Counters since creation: {list builds, MTS blocks, fallback blocks, steps}. */
 int nep_get_stats(nep_system* s, int64_t* stats4);
+
+/* Force-halo tables of the last list build (host int64 stats4): {workgroup tiles
+ * of 256 cell-sorted atoms, tiles whose halo does not fit the force kernel's LDS
+ * copy (more than 3,840 atoms, 512 cells, or a tile spanning more than 48 cells)
+ * and therefore scatter their angular reaction forces with global atomics (the
+ * consolidated three-body backward of Section V.B, Optimization 1, without the
+ * LDS stage), the largest halo in atoms and in cells over the tiles whose tables
+ * were built}. Requires a built list (NEP_ERR_STALE_LIST). Synchronises. */
+int nep_halo_stats(nep_system* s, int64_t* stats4);
 
 /* ---------------------------------------------------------------- training
  * Differentiation of E and F with respect to the network parameters

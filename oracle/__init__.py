@@ -61,6 +61,11 @@ def num_threads() -> int:
     return int(_load().orc_num_threads())
 
 
+def set_num_threads(n: int) -> None:
+    """OpenMP threads for the following oracle calls."""
+    _check(_load().orc_set_num_threads(ctypes.c_int32(int(n))), "set_num_threads")
+
+
 class Model:
     """Hyperparameters (8 ints, 2 reals) plus the packed FP64 parameter vector."""
 

@@ -692,6 +692,16 @@ extern "C" {
 
 int orc_num_threads() { return nthreads(); }
 
+// Number of OpenMP threads for the following calls (n >= 1), to time the oracle on
+// one core and on all of them.
+int orc_set_num_threads(int32_t n) {
+  if (n < 1) return ERR_ARG;
+#ifdef _OPENMP
+  omp_set_num_threads(n);
+#endif
+  return OK;
+}
+
 int orc_n_params(const int32_t* ip, int64_t* n_params, int32_t* n_desc) {
   if (!ip) return ERR_ARG;
   Model m;

@@ -861,6 +861,9 @@ int nep_step(nep_system* s, int64_t n_steps, double dt_fs, int32_t rebuild_every
       if (s->nvt_M > 0 && (st = nhc_half(s, dt_fs))) return st;
       if ((st = vv_step(s, 0, precision, dt_fs, rebuild_every, skin))) return st;
       if (s->nvt_M > 0 && (st = nhc_half(s, dt_fs))) return st;
+      // a list that overflowed at a build (scheduled, or early since the last check)
+      // stops the run here rather than after n_steps of truncated lists
+      if (rebuild_every > 0 && s->step % rebuild_every == 0 && (st = check_flags(s))) return st;
       if (want_row(k == n_steps - 1)) {
         if ((st = reduce_ew(s, 0))) return st;
         if ((st = thermo_row(s, thermo + 8 * rows, 0.0, 0.0, 0))) return st;
@@ -916,6 +919,8 @@ int nep_step(nep_system* s, int64_t n_steps, double dt_fs, int32_t rebuild_every
         if ((st = thermo_row(s, thermo + 8 * rows, rms, mx, fallback))) return st;
         ++rows;
       }
+      // the block has synchronised already: stop at the first overflowing build
+      if ((st = check_flags(s))) return st;
     }
   }
   if (rows_written) *rows_written = rows;
@@ -1011,6 +1016,26 @@ int nep_get_stats(nep_system* s, int64_t* stats4) {
   stats4[1] = s->n_mts_blocks;
   stats4[2] = s->n_fallback_blocks;
   stats4[3] = s->n_steps_total;
+  return NEP_OK;
+}
+
+int nep_halo_stats(nep_system* s, int64_t* stats4) {
+  if (!s || !stats4) return NEP_ERR_ARG;
+  if (!s->have_list) return fail(s, NEP_ERR_STALE_LIST, "build the neighbour lists first");
+  const int64_t nt = grid_blocks(s->N);
+  std::vector<int32_t> info((size_t)(4 * nt));
+  HIPCHK(hipMemcpyAsync(info.data(), s->ht.info, 4 * nt * sizeof(int32_t), hipMemcpyDeviceToHost, s->st));
+  HIPCHK(hipStreamSynchronize(s->st));
+  int64_t global = 0, max_atoms = 0, max_cells = 0;
+  for (int64_t t = 0; t < nt; ++t) {
+    if (info[4 * t + 2] == 0) ++global;
+    max_cells = std::max<int64_t>(max_cells, info[4 * t + 0]);
+    max_atoms = std::max<int64_t>(max_atoms, info[4 * t + 1]);
+  }
+  stats4[0] = nt;
+  stats4[1] = global;
+  stats4[2] = max_atoms;
+  stats4[3] = max_cells;
   return NEP_OK;
 }
 

@@ -37,7 +37,7 @@ EXPORTED = [
     "nep_system_create", "nep_system_destroy", "nep_system_set_params", "nep_set_state",
     "nep_build_neighbors", "nep_export_neighbors", "nep_compute_energy_forces_virial", "nep_step",
     "nep_set_judge", "nep_set_thermostat", "nep_set_thermostat_state", "nep_get_thermostat", "nep_get_state",
-    "nep_get_stats",
+    "nep_get_stats", "nep_halo_stats",
     "nep_train_forward", "nep_train_backward", "nep_train_forward_params", "nep_train_backward_params",
     "nep_adam_update",
     "nep_surrogate_error", "nep_status_string", "nep_last_error", "nep_profile", "nep_profile_read",
@@ -90,6 +90,7 @@ def load_library(path: str = LIB_PATH):
         "nep_get_thermostat": [vp, vp, vp, vp],
         "nep_set_thermostat_state": [vp, vp, vp],
         "nep_get_stats": [vp, vp],
+        "nep_halo_stats": [vp, vp],
         "nep_train_forward": [vp, i32, vp, vp, vp],
         "nep_train_backward": [vp, i32, vp, f64, vp, vp, i32],
         "nep_train_forward_params": [vp, i32, vp, vp, vp],
@@ -328,6 +329,14 @@ class NEPSystem:
         self._check(self.lib.nep_get_stats(self.handle, _np_ptr(s)))
         return {"list_builds": int(s[0]), "mts_blocks": int(s[1]), "fallback_blocks": int(s[2]),
                 "steps": int(s[3])}
+
+    def halo_stats(self) -> dict:
+        """Force-halo tables of the last list build: tiles, tiles on the global-atomic
+        scatter (halo too large for LDS), largest halo in atoms and in cells."""
+        s = np.zeros(4, np.int64)
+        self._check(self.lib.nep_halo_stats(self.handle, _np_ptr(s)))
+        return {"tiles": int(s[0]), "global_atomic_tiles": int(s[1]), "max_halo_atoms": int(s[2]),
+                "max_halo_cells": int(s[3])}
 
     def profile(self, enable: bool):
         self._check(self.lib.nep_profile(self.handle, 1 if enable else 0))

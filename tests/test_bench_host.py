@@ -17,17 +17,24 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert "one GPU" in r.stderr and r.stdout == ""
 
 
-def test_traffic_is_reported_only_for_the_sources_it_was_measured_on(tmp_path, monkeypatch):
-    rec = {"kernel": "k_force", "bytes_per_launch": 123.0, "sources_sha256": bench.force_sources_digest()}
+def test_traffic_is_reported_only_for_the_sources_and_box_it_was_measured_on(tmp_path, monkeypatch):
+    rec = {"kernel": "k_force", "bytes_per_launch": 123.0, "sources_sha256": bench.force_sources_digest(),
+           "n_atoms": 4 * 200 ** 3}
     summary = tmp_path / "traffic.md"
     summary.write_text("# summary\n\ntraffic-json: " + json.dumps(rec) + "\n")
-    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(summary))
-    assert bench.force_traffic() == 123.0
+    monkeypatch.setattr(bench, "traffic_summary_path", lambda cells: str(summary))
+    assert bench.force_traffic(200) == 123.0
+    assert bench.force_traffic(100) is None          # counters of another box
     rec["sources_sha256"] = "0" * 64  # counters taken on other sources
     summary.write_text("traffic-json: " + json.dumps(rec) + "\n")
-    assert bench.force_traffic() is None
-    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(tmp_path / "missing.md"))
-    assert bench.force_traffic() is None
+    assert bench.force_traffic(200) is None
+    monkeypatch.setattr(bench, "traffic_summary_path", lambda cells: str(tmp_path / "missing.md"))
+    assert bench.force_traffic(200) is None
+
+
+def test_summary_names_follow_the_box():
+    assert bench.traffic_summary_path(200).endswith("k_force_fcc32m_fp32_hbm_traffic.md")
+    assert bench.traffic_summary_path(100).endswith("k_force_fcc4m_fp32_hbm_traffic.md")
 
 
 def test_flop_counts_scale_with_each_models_own_pairs():

@@ -132,3 +132,33 @@ def test_coefficient_training_beats_network_only(models):
     a, b = o["sigma"]
     assert np.array_equal(co.params[a:b], sur0[a:b])              # the scaler stays fixed
     assert np.abs(co.params[:a] - sur0[:a]).max() > 1e-3          # the coefficients moved
+
+
+def test_shorter_surrogate_is_accepted_once_trained(models):
+    """The 4/3 A surrogate of the MTS form (the two nearest radial shells, the nearest
+    angular one), coefficients and network trained on the GPU, in r-RESPA with k = 4 on a
+    600 K 10^3-cell box under the relative judge (block rms error <= 0.75 x the block's rms
+    full-model force, max <= 10 x): accepted in all 6 blocks, while the untrained one
+    fails the first block and falls back to the full model for the rest."""
+    from paper_2604_24816_amd import surrogate as SG
+    hp, teacher, _, _ = models
+    shp = I.SURROGATE_SHORTER_HPARAMS
+    sur0 = I.surrogate_from_teacher(hp, teacher, shp, 1)
+    say("case: 4/3 A surrogate, coefficients + network trained (100 x 10 frames, 30 epochs), relative judge")
+    fr = SG.generate_frames(hp, teacher, n_traj=100, cells=10, steps=100, every=10)
+    res = SG.train_surrogate(fr, shp, sur0, epochs=30, batch=8, lr=1e-2, lr_end=1e-4, train_coeffs=True)
+    say(f"  held-out force RMSE {res.val_force_rmse_init:.4e} -> {res.val_force_rmse:.4e} eV/A ({res.seconds:.1f} s)")
+    at = I.fcc_box(10, 0.08, 61)
+    at.v = I.maxwell_boltzmann(at, 600.0, 62)
+    runs = {}
+    for name, p in (("untrained", sur0), ("trained", res.params)):
+        s = make_system(at, hp, teacher, shp, p)
+        th = s.step(24, mts_k=4, fallback_rms=0.75, fallback_max=10.0, thermo_every=4, relative_judge=True)
+        runs[name] = (s.stats(), th)
+        say(f"  {name}: stats {runs[name][0]}, block rms errors {np.round(th[:, 5], 5).tolist()}, "
+            f"fallback flags {th[:, 7].astype(int).tolist()}")
+    st, th = runs["trained"]
+    assert st["mts_blocks"] == 6 and st["fallback_blocks"] == 0
+    st0, th0 = runs["untrained"]
+    assert st0["mts_blocks"] == 1 and st0["fallback_blocks"] == 5 and th0[0, 7] == 1
+    assert th[:, 5].mean() < 0.5 * th0[:, 5].mean()

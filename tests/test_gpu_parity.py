@@ -48,6 +48,24 @@ def test_mfma_network_and_forces_small_box(full):
     _check_efw(s, m, at)
 
 
+@pytest.mark.parametrize("scale,mixed", [(0.85, True), (0.8, False)])
+def test_force_global_atomic_fallback_compressed_box(full, scale, mixed):
+    """FCC compressed to `scale` of the Cu lattice constant (12^3 cells; 1.63x and 1.95x
+    the Cu density): some (0.85) or all (0.8) 256-atom tiles have force halos larger than
+    the 3,840 atoms the force kernel keeps in LDS, and scatter their angular reaction
+    forces into global memory with atomics; energies, forces and virial at the standard
+    bounds."""
+    hp, params, m = full
+    at = I.fcc_box(12, 0.05 * scale, 5, a=I.CU_LATTICE_A * scale)
+    say(f"case: compressed FCC 12^3 cells, scale {scale}, N={at.n}, caps 320/224, fp32")
+    s = make_system(at, hp, params, cap_radial=320, cap_angular=224)
+    hs = s.halo_stats()
+    say(f"  halo tables: {hs}")
+    assert hs["global_atomic_tiles"] > 0
+    assert (hs["global_atomic_tiles"] < hs["tiles"]) == mixed
+    _check_efw(s, m, at)
+
+
 def test_neighbor_lists_bit_exact_4000_atoms(full):
     hp, params, m = full
     at = I.workload_small()
@@ -254,6 +272,33 @@ def test_error_paths(full):
     with pytest.raises(nep.NEPError) as e:
         s.build_neighbors(2.0)  # 14.46 A box < 2 (6 + 2)
     assert e.value.status == -2
+
+
+def test_step_stops_at_the_first_overflowing_rebuild(full):
+    """A shell of 20 atoms at 7.8 A around a center, moving inwards at 0.4 A/fs: the
+    lists fit a capacity of 16 at the start, and an early rebuild (displacement beyond
+    half the skin) two or three steps later overflows it. nep_step checks the list flags
+    after every 10th step, so a 40-step run stops at step 10 with the overflow status
+    instead of running on with truncated lists."""
+    from paper_2604_24816_amd import nep
+    hp, params, m = full
+    rng = np.random.default_rng(9)
+    d = rng.normal(size=(20, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    c = np.array([15.0, 15.0, 15.0])
+    x = np.concatenate([c[None], c + 7.8 * d])
+    v = np.concatenate([np.zeros((1, 3)), -0.4 * d])
+    box = np.array([30.0, 30.0, 30.0])
+    at = I.Atoms(x=x, types=np.zeros(21, np.int32), box=box, masses=np.array([63.546]))
+    at.v = v
+    cnt, _ = oracle.neighbors(x, box, 7.0, cap=32)
+    say(f"case: overflow during nep_step, 21 atoms, largest initial list {cnt.max()}, cap_radial 16")
+    assert cnt.max() <= 16
+    s = make_system(at, hp, params, cap_radial=16, cap_angular=96)
+    with pytest.raises(nep.NEPError) as e:
+        s.step(40, dt=1.0, rebuild_every=10, skin=1.0)
+    assert e.value.status == -3 and "capacity" in str(e.value)
+    assert s.get_state()[2] == 10
 
 
 def _block_model(hp, block, seed=5):

@@ -27,10 +27,19 @@ def _noisy(hp, params, seed, std=0.01):
     return p
 
 
-def _compare(g_gpu, g_ref, label, rel=2e-4):
-    err = np.abs(g_gpu - g_ref).max() / np.abs(g_ref).max()
-    say(f"  {label}: max|grad|={np.abs(g_ref).max():.3e} rel err={err:.2e}")
-    assert err < rel, (label, err)
+def _compare(g_gpu, g_ref, label, rel=1e-4, floor=1e-5):
+    """Entry by entry: |g - ref| <= rel |ref| + floor max|ref|. The floor is for entries
+    that cancel to almost nothing over the atoms, where the FP32 per-atom terms leave an
+    absolute error of the block's scale rather than a relative one."""
+    scale = np.abs(g_ref).max()
+    err = np.abs(g_gpu - g_ref)
+    bound = rel * np.abs(g_ref) + floor * scale
+    big = np.abs(g_ref) >= 0.01 * scale
+    rel_big = float((err[big] / np.abs(g_ref[big])).max())
+    k = int(np.argmax(err / bound))
+    say(f"  {label}: {g_ref.size} entries, max|grad|={scale:.3e}, max rel err over entries above 1% of it "
+        f"{rel_big:.2e}, worst entry {k}: {g_gpu[k]:.6e} vs {g_ref[k]:.6e} ({err[k] / bound[k]:.2f} of its bound)")
+    assert (err <= bound).all(), (label, k, g_gpu[k], g_ref[k])
 
 
 @pytest.mark.parametrize("kind", ["full", "two_species", "surrogate"])
@@ -139,7 +148,9 @@ def test_autograd_function_energy_force_loss_16_frames():
     loss.backward()
     g_gpu = theta.grad.detach().cpu().numpy()
     say(f"  loss={float(loss):.6e}")
-    _compare(g_gpu, ref, "16-frame loss", rel=1e-3)
+    # the loss residuals F_student - F_teacher come from FP32 forces on the GPU and FP64 on the
+    # oracle, and they are 1e-3 of the forces themselves (the student is the teacher plus noise)
+    _compare(g_gpu, ref, "16-frame loss", rel=1e-3, floor=1e-4)
 
 
 def test_position_gradient_is_minus_force():
