@@ -129,6 +129,18 @@ def round_bf16(v: float) -> float:
     return float(_load().orc_round_bf16(float(v)))
 
 
+def network(model: Model, q, bf16=False):
+    """U and dU/dq of the network on one descriptor vector q [D] (bf16: the bfloat16 form)."""
+    q = _f64(q)
+    if q.size != model.n_desc:
+        raise ValueError(f"q has {q.size} values, expected {model.n_desc}")
+    U = ctypes.c_double()
+    Fp = np.zeros(model.n_desc)
+    st = _load().orc_network(*model._args(), _p(q), ctypes.c_int32(1 if bf16 else 0), ctypes.byref(U), _p(Fp))
+    _check(st, "network")
+    return U.value, Fp
+
+
 def descriptors(model: Model, x, types, box, centers=None, path=0):
     x = _f64(x)
     types = np.ascontiguousarray(types, np.int32)

@@ -29,6 +29,16 @@
 //   four-body: S_n = sum_j g_n(r_ij) (u u^T - I/3),  q4_n = tr(S_n^3)
 // Descriptor order: [radial n | angular, l-major then n | four-body n].
 // Build: g++ -O2 -ffp-contract=off -fopenmp (no fast-math, no FMA contraction).
+//
+// Parity pins: every function here is checked in the CPU test suite against closed
+// forms, library routines, brute force, invariances or finite differences, with one
+// partial exception. The ZBL term's universal screening constants (the four weights
+// c_m and exponents d_m, the 0.8854 a_0 screening length and the 0.23 power, from
+// J. F. Ziegler, J. P. Biersack and U. Littmark, "The Stopping and Range of Ions in
+// Solids", Pergamon, 1985) are PARITY UNPINNED as values: the tests fix the weights'
+// sum (the bare-Coulomb limit r -> 0), the switch, and forces and virial against
+// central differences, but a mistyped exponent or screening length would pass them,
+// since neither the paper nor any fixture here prints the function's values.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -336,6 +346,43 @@ double round_bf16(double v) {
   return std::ldexp(r, e - 8);
 }
 
+// Network of Section III.B on one descriptor vector q [D]:
+//   U = sum_mu w1_mu tanh(h_mu) - b1,  h = W0 q~ - b0,  q~ = q * sigma,
+//   Fp = dU/dq = sigma * W0^T (w1 * (1 - tanh^2 h)),
+// with h [H] returned too. bf16 != 0 is the bfloat16 form: q~, W0 and w1 (1 - tanh^2 h)
+// are rounded to bfloat16 before the products that use them (FP64 accumulation).
+void network(const Model& m, const double* q, int bf16, double& U, std::vector<double>& Fp,
+             std::vector<double>& h) {
+  const int D = m.D, H = m.H;
+  std::vector<double> qs(D), Wr(H * D);
+  for (int v = 0; v < D; ++v) qs[v] = q[v] * m.sigma[v];
+  for (int k = 0; k < H * D; ++k) Wr[k] = m.W0[k];
+  if (bf16) {
+    for (int v = 0; v < D; ++v) qs[v] = round_bf16(qs[v]);
+    for (int k = 0; k < H * D; ++k) Wr[k] = round_bf16(Wr[k]);
+  }
+  h.assign(H, 0.0);
+  std::vector<double> a1(H);
+  U = 0;
+  for (int mu = 0; mu < H; ++mu) {
+    double s = 0;
+    for (int v = 0; v < D; ++v) s += Wr[mu * D + v] * qs[v];
+    const double hh = s - m.b0[mu];
+    h[mu] = hh;
+    const double t = std::tanh(hh);
+    U += m.w1[mu] * t;
+    a1[mu] = m.w1[mu] * (1.0 - t * t);
+    if (bf16) a1[mu] = round_bf16(a1[mu]);
+  }
+  U -= m.b1;
+  Fp.assign(D, 0.0);
+  for (int v = 0; v < D; ++v) {
+    double s = 0;
+    for (int mu = 0; mu < H; ++mu) s += Wr[mu * D + v] * a1[mu];
+    Fp[v] = m.sigma[v] * s;
+  }
+}
+
 // ------------------------------------------------------------------ per-center terms
 struct PairGeom {
   int32_t j;
@@ -506,34 +553,8 @@ void center_terms(const Model& m, const CellGrid* g, int64_t n, const double* x,
     tab->dPjk = dPjk;
     tab->S = S;
   }
-  // Network: U = sum_mu w1 tanh(sum_nu W0 qs - b0) - b1, qs = q * sigma.
-  std::vector<double> qs(D), Wr(H * D);
-  for (int v = 0; v < D; ++v) qs[v] = ct.q[v] * m.sigma[v];
-  for (int k = 0; k < H * D; ++k) Wr[k] = m.W0[k];
-  if (precision_bf16) {
-    for (int v = 0; v < D; ++v) qs[v] = round_bf16(qs[v]);
-    for (int k = 0; k < H * D; ++k) Wr[k] = round_bf16(Wr[k]);
-  }
-  ct.h.assign(H, 0.0);
-  std::vector<double> a1(H);
-  double U = 0;
-  for (int mu = 0; mu < H; ++mu) {
-    double s = 0;
-    for (int v = 0; v < D; ++v) s += Wr[mu * D + v] * qs[v];
-    const double hh = s - m.b0[mu];
-    ct.h[mu] = hh;
-    const double t = std::tanh(hh);
-    U += m.w1[mu] * t;
-    a1[mu] = m.w1[mu] * (1.0 - t * t);
-    if (precision_bf16) a1[mu] = round_bf16(a1[mu]);
-  }
-  ct.U = U - m.b1 + Uz;
-  ct.Fp.assign(D, 0.0);
-  for (int v = 0; v < D; ++v) {
-    double s = 0;
-    for (int mu = 0; mu < H; ++mu) s += Wr[mu * D + v] * a1[mu];
-    ct.Fp[v] = m.sigma[v] * s;
-  }
+  network(m, ct.q.data(), precision_bf16, ct.U, ct.Fp, ct.h);
+  ct.U += Uz;
   if (jac_for == -2) return;
   // Jacobian dq_nu / d r_ij for the requested radial neighbours.
   ct.J.assign((size_t)np * D * 3, 0.0);
@@ -760,6 +781,19 @@ int orc_sph_harm(int32_t l, const double* u, double* Y) {
 }
 
 double orc_round_bf16(double v) { return round_bf16(v); }
+
+// The network alone on a given descriptor vector q [D]: U and Fp = dU/dq [D].
+int orc_network(const int32_t* ip, const double* dp, const double* params, int64_t n_params, const double* q,
+                int32_t bf16, double* U, double* Fp) {
+  Model m;
+  int st = parse_model(ip, dp, params, n_params, m);
+  if (st) return st;
+  if (!q || !U || !Fp) return ERR_ARG;
+  std::vector<double> fp, h;
+  network(m, q, bf16, *U, fp, h);
+  for (int v = 0; v < m.D; ++v) Fp[v] = fp[v];
+  return OK;
+}
 
 // Descriptors q[ncent][D] of the listed centers. path 0: Legendre double sum (the
 // path the oracle's forces use); path 1: spherical-harmonic sums s_nlm contracted

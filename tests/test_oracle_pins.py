@@ -713,6 +713,69 @@ def test_bf16_model_error_is_bf16_sized(full_model):
     assert np.abs(Fb - F).max() < 0.05 * np.abs(F).max()
 
 
+def test_bf16_network_worked_example():
+    """One hidden unit, values chosen so that each of the three bfloat16 roundings of the
+    form (scaled descriptor, W0, w1 (1 - tanh^2)) moves a known bit: the expected U and
+    dU/dq follow from the rounded values typed in below (8 significant bits each, so every
+    product is exact in FP64), with the rounding of w1 (1 - tanh^2) taken by torch."""
+    import math
+    import torch
+    hp = I.HParams(l_max_3b=2, l_max_4b=0, n_hidden=1)
+    D = hp.n_desc
+    p = np.zeros(hp.n_params())
+    o = hp.offsets()
+    sig = np.ones(D)
+    sig[0] = 0.25
+    sig[3] = 3.0
+    p[o["sigma"][0]:o["sigma"][1]] = sig
+    W0 = np.zeros(D)
+    W0[0] = 0.5 + 2 ** -10 + 2 ** -12          # bf16: 0.5 (0.31 ulp below the midpoint)
+    W0[3] = 1.0 - 2 ** -9 - 2 ** -12           # bf16: 1 - 2^-8
+    p[o["W0"][0]:o["W0"][1]] = W0
+    p[o["b0"][0]] = 0.1
+    p[o["w1"][0]] = 1.7
+    p[o["b1"][0]] = 0.3
+    q = np.zeros(D)
+    q[0] = 4.0 * (1.0 + 2 ** -8 + 2 ** -20)    # q~ = 1 + 2^-8 + 2^-20 -> bf16 1 + 2^-7
+    q[3] = -(0.25 + 2 ** -11)                  # q~ = -(0.75 + 3 2^-11) -> bf16 -0.75
+    m = oracle.Model.from_hparams(hp, p)
+    U, Fp = oracle.network(m, q, bf16=True)
+    h = 0.5 * (1.0 + 2 ** -7) + (1.0 - 2 ** -8) * (-0.75) - 0.1
+    t = math.tanh(h)
+    a1 = 1.7 * (1.0 - t * t)
+    a1r = float(torch.tensor(a1, dtype=torch.float64).to(torch.float32).to(torch.bfloat16).double())
+    assert abs(a1r - a1) > 1e-4 * a1        # the rounding of a1 matters at this scale
+    U_ref = 1.7 * t - 0.3
+    Fp_ref = np.zeros(D)
+    Fp_ref[0] = 0.25 * 0.5 * a1r
+    Fp_ref[3] = 3.0 * (1.0 - 2 ** -8) * a1r
+    assert abs(U - U_ref) <= 4e-16 * abs(U_ref)
+    assert np.array_equal(Fp, Fp_ref)
+    # the same model without rounding gives a different U and dU/dq
+    U64, Fp64 = oracle.network(m, q)
+    assert abs(U64 - U) > 1e-3 and abs(Fp64[0] - Fp[0]) > 1e-4 and abs(Fp64[3] - Fp[3]) > 1e-4
+
+
+@pytest.mark.parametrize("betas,eps", [((0.9, 0.999), 1e-8), ((0.5, 0.9), 1e-8), ((0.95, 0.6), 1e-3)])
+def test_adam_matches_torch_over_several_steps(betas, eps):
+    """Seven Adam steps on non-uniform gradients against torch.optim.Adam in FP64 (the bias
+    corrections of later steps, the order of beta1 and beta2 and where eps enters)."""
+    import torch
+    rng = np.random.default_rng(17)
+    n = 37
+    theta = rng.normal(size=n)
+    grads = [rng.normal(size=n) * rng.uniform(0.01, 3.0, size=n) for _ in range(7)]
+    pt = torch.tensor(theta.copy(), dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([pt], lr=0.01, betas=betas, eps=eps, foreach=False)
+    m1 = np.zeros(n)
+    m2 = np.zeros(n)
+    for t, g in enumerate(grads, start=1):
+        pt.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        oracle.adam(theta, g, m1, m2, t, lr=0.01, beta1=betas[0], beta2=betas[1], eps=eps)
+        assert np.abs(theta - pt.detach().numpy()).max() < 1e-14, t
+
+
 def test_adam_first_step_is_signed_lr():
     theta = np.array([1.0, -2.0, 0.5])
     g = np.array([3.0, -1e-3, 0.2])
