@@ -129,6 +129,8 @@ struct nep_system {
   double *partial, *gpart, *res, *staging;
   int32_t* flags;
   float* mparams[2];
+  float* mderived[2];     // derived radial tables of each model
+  float* tderived;        // the same for a parameter vector of the training calls
   uint16_t* mbf[2];
   double* mparams64[2];
   Model64 m64[2];
@@ -145,6 +147,7 @@ struct nep_system {
 namespace {
 
 constexpr int kGradMax = 32 * 32 + 2 * 32 + 1;  // equals train_grad_stride()
+constexpr int kDerivedMax = 10;                 // channels and basis functions the derived tables hold
 
 // Lays out every buffer; with base == nullptr it only measures.
 int64_t layout(nep_system* s, char* base, int64_t N, int capR, int capA, int max_ncell, const int64_t* np,
@@ -197,7 +200,11 @@ int64_t layout(nep_system* s, char* base, int64_t N, int capR, int capA, int max
   S.staging = c.take<double>(3 * N);
   S.flags = c.take<int32_t>(FLAG_COUNT);
   S.nhc = c.take<double>(kNhcDoubles);
+  // derived radial tables: at most kMaxTypes^2 species pairs of kDerivedMax channels and basis functions
+  const int64_t nder = derived_coeff_floats(kMaxTypes, kDerivedMax, kDerivedMax, kDerivedMax, kDerivedMax);
+  S.tderived = c.take<float>(nder);
   for (int k = 0; k < 2; ++k) {
+    S.mderived[k] = c.take<float>(nder);
     S.mparams[k] = c.take<float>(np[k] > 0 ? np[k] : 1);
     S.mbf[k] = c.take<uint16_t>(HD[k] > 0 ? HD[k] : 1);
     S.mparams64[k] = c.take<double>(np[k] > 0 ? np[k] : 1);
@@ -222,21 +229,27 @@ int fail(nep_system* s, int code, const std::string& msg) {
   return code;
 }
 
-// Upload one model's parameters (FP32 copy + bfloat16 copy of W0).
-int upload_model(nep_system* s, int slot) {
-  const nep_model& m = s->model[slot];
-  std::vector<float> f(m.params.size());
-  for (size_t k = 0; k < f.size(); ++k) f[k] = (float)m.params[k];
+// Upload one model's parameters (FP32 copy + bfloat16 copy of W0) into slot `slot`
+// (s->model[slot].hp must hold the model's hyperparameters). Host staging uses fixed-size
+// arrays, so an upload allocates nothing.
+constexpr int kMaxParams = 4096;   // more than any model of a compiled shape (at most 1,921)
+constexpr int kMaxNet = 32 * 32;   // network tiles: D <= 32, H <= 32
+int upload_model(nep_system* s, int slot, const nep_model& m) {
   const int T = m.hp.n_types, nR = m.hp.n_max_radial + 1, nA = m.hp.n_max_angular + 1;
   const int kR = m.hp.basis_radial + 1, kA = m.hp.basis_angular + 1, H = m.hp.n_hidden, D = m.D;
+  if (nR > kDerivedMax || kR > kDerivedMax || nA > kDerivedMax || kA > kDerivedMax || m.n_params > kMaxParams ||
+      H * D > kMaxNet)
+    return fail(s, NEP_ERR_UNSUPPORTED, "model shape has no compiled kernel");
+  float f[kMaxParams];
+  for (int64_t k = 0; k < m.n_params; ++k) f[k] = (float)m.params[k];
   const int64_t offW0 = (int64_t)T * T * nR * kR + (int64_t)T * T * nA * kA + D;
-  std::vector<uint16_t> bf((size_t)H * D);
+  uint16_t bf[kMaxNet];
   for (int k = 0; k < H * D; ++k) bf[k] = f64_to_bf16_bits(m.params[offW0 + k]);
-  HIPCHK(hipMemcpyAsync(s->mparams[slot], f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice, s->st));
-  HIPCHK(hipMemcpyAsync(s->mbf[slot], bf.data(), bf.size() * sizeof(uint16_t), hipMemcpyHostToDevice, s->st));
-  HIPCHK(hipMemcpyAsync(s->mparams64[slot], m.params.data(), m.params.size() * sizeof(double),
+  HIPCHK(hipMemcpyAsync(s->mparams[slot], f, m.n_params * sizeof(float), hipMemcpyHostToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(s->mbf[slot], bf, H * D * sizeof(uint16_t), hipMemcpyHostToDevice, s->st));
+  HIPCHK(hipMemcpyAsync(s->mparams64[slot], m.params.data(), m.n_params * sizeof(double),
                         hipMemcpyHostToDevice, s->st));
-  HIPCHK(hipStreamSynchronize(s->st));  // host vectors go out of scope
+  HIPCHK(hipStreamSynchronize(s->st));  // the host staging arrays go out of scope
   ModelDev& d = s->mdev[slot];
   d.T = T;
   d.nR = nR;
@@ -260,6 +273,10 @@ int upload_model(nep_system* s, int slot) {
   d.w1 = d.b0 + H;
   d.b1 = d.w1 + H;
   d.W0bf = s->mbf[slot];
+  d.hR = s->mderived[slot];
+  d.hA = s->mderived[slot] + (int64_t)T * T * nR * (2 * kR - 1);
+  d.hscratch = s->tderived;
+  HIPCHK(launch_derive_coeffs(T, nR, kR, nA, kA, d.cR, d.cA, s->mderived[slot], const_cast<float*>(d.hA), s->st));
   {
     Model64& q = s->m64[slot];
     const double* p64 = s->mparams64[slot];
@@ -350,47 +367,56 @@ BinEdges make_bin_edges(const nep_hparams* hp0, const nep_hparams* hp1, double s
     double r;
     int rank;  // removal order: higher goes first; -1 = never removed
   };
-  std::vector<Edge> c;
+  // fixed-size arrays: at most two models x kFracs fractions x two cutoffs
+  constexpr int kCand = 2 * kFracs * 2;
+  Edge c[kCand];
+  int nc = 0;
   const nep_hparams* hps[2] = {hp0, hp1};
   for (int m = 0; m < (hp1 ? 2 : 1); ++m)
     for (int k = 0; k < kFracs; ++k) {
       const int rank = k == 0 ? -1 : 2 * k + m;  // f_k skin, surrogate (m = 1) first at equal k
-      c.push_back({hps[m]->rc_angular + (double)bin_frac(k) * skin, rank});
-      c.push_back({hps[m]->rc_radial + (double)bin_frac(k) * skin, rank});
+      c[nc++] = {hps[m]->rc_angular + (double)bin_frac(k) * skin, rank};
+      c[nc++] = {hps[m]->rc_radial + (double)bin_frac(k) * skin, rank};
     }
   // the list cutoff is the full model's largest edge; edges beyond it cannot be used
   const double outer = hp0->rc_radial + (double)bin_frac(kFracs - 1) * skin;
-  std::sort(c.begin(), c.end(), [](const Edge& x, const Edge& y) { return x.r < y.r; });
-  std::vector<Edge> u;  // distinct edges up to the outer one, each with its most useful rank
-  for (const Edge& x : c) {
+  for (int a = 1; a < nc; ++a)  // insertion sort by radius (stable)
+    for (int b = a; b > 0 && c[b].r < c[b - 1].r; --b) std::swap(c[b], c[b - 1]);
+  Edge u[kCand];  // distinct edges up to the outer one, each with its most useful rank
+  int nu = 0;
+  for (int a = 0; a < nc; ++a) {
+    const Edge& x = c[a];
     if (x.r > outer) break;
-    if (!u.empty() && u.back().r == x.r) {
-      const int a = u.back().rank, b = x.rank;
-      u.back().rank = (a < 0 || b < 0) ? -1 : std::min(a, b);
+    if (nu > 0 && u[nu - 1].r == x.r) {
+      const int ra = u[nu - 1].rank, rb = x.rank;
+      u[nu - 1].rank = (ra < 0 || rb < 0) ? -1 : std::min(ra, rb);
     } else {
-      u.push_back(x);
+      u[nu++] = x;
     }
   }
-  u.back().rank = -1;  // the outer edge
-  while ((int)u.size() > kMaxBins) {
+  u[nu - 1].rank = -1;  // the outer edge
+  while (nu > kMaxBins) {
     int worst = -1;
-    for (int i = 0; i < (int)u.size(); ++i)
-      if (u[i].rank >= 0 && (worst < 0 || u[i].rank > u[worst].rank)) worst = i;
+    for (int a = 0; a < nu; ++a)
+      if (u[a].rank >= 0 && (worst < 0 || u[a].rank > u[worst].rank)) worst = a;
     if (worst < 0) break;  // cannot happen: at most four exact cutoffs and the outer edge
-    u.erase(u.begin() + worst);
+    for (int a = worst; a + 1 < nu; ++a) u[a] = u[a + 1];
+    --nu;
   }
-  std::vector<double> e;
-  for (const Edge& x : u) e.push_back(x.r);
   BinEdges be{};
-  be.nbins = (int)e.size();
-  for (int b = 0; b < kMaxBins; ++b) be.e2[b] = b < be.nbins ? e[b] * e[b] : INFINITY;
+  be.nbins = nu;
+  for (int b = 0; b < kMaxBins; ++b) be.e2[b] = b < be.nbins ? u[b].r * u[b].r : INFINITY;
+  // index of the first edge >= r (the last edge if none)
+  auto first_at_or_above = [&](double r) {
+    int b = 0;
+    while (b < nu && u[b].r < r) ++b;
+    return std::min(nu - 1, b);
+  };
   const nep_hparams* hp[2] = {hp0, hp1 ? hp1 : hp0};
   for (int m = 0; m < 2; ++m)
     for (int k = 0; k < kFracs; ++k) {
-      const double er = hp[m]->rc_radial + (double)bin_frac(k) * skin;
-      const double ea = hp[m]->rc_angular + (double)bin_frac(k) * skin;
-      be.idxR[m][k] = std::min(be.nbins - 1, (int)(std::lower_bound(e.begin(), e.end(), er) - e.begin()));
-      be.idxA[m][k] = std::min(be.nbins - 1, (int)(std::lower_bound(e.begin(), e.end(), ea) - e.begin()));
+      be.idxR[m][k] = first_at_or_above(hp[m]->rc_radial + (double)bin_frac(k) * skin);
+      be.idxA[m][k] = first_at_or_above(hp[m]->rc_angular + (double)bin_frac(k) * skin);
     }
   return be;
 }
@@ -584,7 +610,7 @@ int nep_system_create(const nep_model* full, const nep_model* sur, int64_t n_ato
   }
   for (int k = 0; k < 2; ++k) {
     if (!s->has_model[k]) continue;
-    const int st = upload_model(s, k);
+    const int st = upload_model(s, k, s->model[k]);
     if (st) {
       delete s;
       return st;
@@ -619,7 +645,7 @@ int nep_system_set_params(nep_system* s, int32_t slot, const double* params, int
   for (int64_t k = 0; k < n_params; ++k)
     if (!std::isfinite(params[k])) return fail(s, NEP_ERR_NONFINITE, "non-finite parameter");
   s->model[slot].params.assign(params, params + n_params);
-  return upload_model(s, slot);
+  return upload_model(s, slot, s->model[slot]);
 }
 
 int nep_set_state(nep_system* s, const double* x, const double* v, const int32_t* types, const double* masses,
@@ -1181,5 +1207,6 @@ int nep_pair_counts(nep_system* s, int64_t* counts3) {
   for (int k = 0; k < 3; ++k) counts3[k] = (int64_t)r[k];
   return NEP_OK;
 }
+
 
 }  // extern "C"

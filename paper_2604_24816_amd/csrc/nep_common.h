@@ -152,6 +152,13 @@ struct ModelDev {
   const float* w1;
   const float* b1;
   const uint16_t* W0bf;  // [H][D] bfloat16 bits, rounded from the FP64 parameters
+  // Radial coefficient tables derived from cR and cA (one [n][2 basis - 1] block per
+  // species pair, see nep_fast.h), built on the device by launch_derive_coeffs from the
+  // FP32 coefficients in use; hscratch holds the tables of a parameter vector passed to
+  // the training calls.
+  const float* hR;
+  const float* hA;
+  float* hscratch;
   // ZBL repulsion: pairs with r^2 < zbl_o2 (0: no ZBL term), switched between
   // zbl_ri and zbl_ro; per species pair (t_i * T + t_j) k_e Z_i Z_j and 1 / a_ij
   double zbl_o2;
@@ -225,6 +232,11 @@ struct EvalBuffers {
   int flag_r, flag_a;    // flag words holding this model's last radial / angular bin
 };
 bool eval_supported(const ModelDev& m);
+// Floats of the derived radial tables of one model (radial then angular blocks).
+int64_t derived_coeff_floats(int T, int nR, int kR, int nA, int kA);
+// Derived tables of the coefficients cR, cA (FP32, model layout) into hR, hA.
+hipError_t launch_derive_coeffs(int T, int nR, int kR, int nA, int kA, const float* cR, const float* cA, float* hR,
+                                float* hA, hipStream_t st);
 // ev (nullable): three events recorded before the descriptor kernel, between the
 // two kernels and after the force kernel.
 hipError_t launch_eval(const ModelDev& m, int precision, const EvalBuffers& b, hipStream_t st,

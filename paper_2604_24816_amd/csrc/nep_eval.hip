@@ -1,27 +1,27 @@
 // NEP energy/force evaluation on gfx950: two kernels per force evaluation.
 //
 //   k_desc_net  (one thread per center, 256-thread workgroups)
-//     0. compaction: the neighbours inside the true cutoffs are picked out of
-//        the skin list once per evaluation, so the descriptor and force loops
-//        below run over exactly the pairs that contribute;
-//     1. radial descriptors q_n = sum_j g_n(r_ij) (Section III.B);
-//     2. angular accumulators s_nlm = sum_j g_n(r_ij) P_lm(u_ij) for every
-//        channel n in one neighbour pass (Algorithm 1's geometry reuse with the
-//        channel tile equal to all n_max+1 channels), and from them
-//        q_nl = sum_m W_lm s_nlm^2 and the four-body invariant tr(S_n^3);
-//     3. the network U_i = w1 . tanh(W0 q~ - b0) - b1 and its gradient
+//     1. radial descriptors q_n = sum_j g_n(r_ij) (Section III.B) and angular
+//        accumulators s_nlm = sum_j g_n(r_ij) P_lm(u_ij) for every channel n in one
+//        pass over the center's list with skin, each visited entry tested against
+//        the true cutoffs in FP64 (Algorithm 1's geometry reuse with the channel tile
+//        equal to all n_max+1 channels); from them q_nl = sum_m W_lm s_nlm^2 and the
+//        four-body invariant tr(S_n^3);
+//     2. the network U_i = w1 . tanh(W0 q~ - b0) - b1 and its gradient
 //        dU/dq~ = W0^T (w1 (1 - tanh^2)) as two 64-row MFMA products per
 //        wavefront (Section V.B Optimization 1, Fig. 2c), operands staged
 //        through LDS; FP32 MFMA or bfloat16 MFMA with FP32 accumulation;
-//     4. per-atom dU/ds_nlm is written for the force kernel.
+//     3. per-atom dU/ds_nlm is written for the force kernel, and the radial force
+//        coefficients into the atom's neighbour record.
 //   k_force
 //     radial pair forces by gather (F_i += sum_j [dU_i/dr_ij - dU_j/dr_ji]
-//     with the neighbour's dU/dq_n read from HBM), angular and four-body pair
-//     forces from dU/ds by scatter with FP32 atomics into the neighbour
-//     (Section V.B Optimization 1: no temporary per-pair force buffer), and the
-//     virial W_ab = -sum r_a dU_i/dr_b; energy and virial are reduced per
-//     workgroup in FP64.
-#include "nep_kernels.h"
+//     with the neighbour's radial coefficients read from its record), angular and
+//     four-body pair forces from dU/ds by scatter into the neighbours (Section V.B
+//     Optimization 1: no temporary per-pair force buffer; an LDS copy of the tile's
+//     halo, or global atomics where it does not fit), and the virial
+//     W_ab = -sum r_a dU_i/dr_b; energy and virial are reduced per workgroup in FP64.
+//   Pair arithmetic in both comes from nep_fast.h.
+#include "nep_fast.h"
 
 namespace nep {
 namespace {
@@ -29,9 +29,14 @@ namespace {
 using namespace kern;
 
 // ------------------------------------------------------------------------ network
+// Row stride of the per-wavefront operand tile: 37 words keep a lane's own row (stride
+// odd) and the MFMA operand and result patterns (lane (lr, lk) at 37 lr + lk and
+// 148 lk + lr) within two passes of the 64 LDS banks.
+constexpr int kNetStride = 37;
+
 // One wavefront evaluates the network for its 64 centers. qs[lane][v] holds the
 // scaled descriptor of the lane's center on entry; on exit fp[v] = dU/dq~ and the
-// return value is U. lds: this wavefront's 64 x 33 float tile.
+// return value is U. lds: this wavefront's 64 x kNetStride float tile.
 template <class S, int PREC>
 __device__ __forceinline__ float network_wave(const ModelDev& m, const float* qs, float* fp, float* lds,
                                               const float* __restrict__ W0, const float* __restrict__ b0,
@@ -39,7 +44,7 @@ __device__ __forceinline__ float network_wave(const ModelDev& m, const float* qs
   const int lane = threadIdx.x & 63;
   const int lr = lane & 15;   // row / column within a 16-wide tile
   const int lk = lane >> 4;   // k group
-  float* row = lds + lane * kLdsStride;
+  float* row = lds + lane * kNetStride;
 #pragma unroll
   for (int v = 0; v < 32; ++v) row[v] = v < S::D ? qs[v] : 0.f;
   __syncthreads();
@@ -61,7 +66,7 @@ __device__ __forceinline__ float network_wave(const ModelDev& m, const float* qs
       }
 #pragma unroll
       for (int R = 0; R < 4; ++R) {
-        const float aop = lds[(16 * R + lr) * kLdsStride + dcol];
+        const float aop = lds[(16 * R + lr) * kNetStride + dcol];
 #pragma unroll
         for (int C = 0; C < 2; ++C)
           acc[R][C] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop[C], acc[R][C], 0, 0, 0);
@@ -83,7 +88,7 @@ __device__ __forceinline__ float network_wave(const ModelDev& m, const float* qs
       bf16x8 aop;
 #pragma unroll
       for (int e = 0; e < 8; ++e)
-        aop[e] = bits_to_bf16(f32_to_bf16_bits(lds[(16 * R + lr) * kLdsStride + 8 * lk + e]));
+        aop[e] = bits_to_bf16(f32_to_bf16_bits(lds[(16 * R + lr) * kNetStride + 8 * lk + e]));
 #pragma unroll
       for (int C = 0; C < 2; ++C)
         acc[R][C] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop[C], acc[R][C], 0, 0, 0);
@@ -96,7 +101,7 @@ __device__ __forceinline__ float network_wave(const ModelDev& m, const float* qs
 #pragma unroll
     for (int C = 0; C < 2; ++C)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) lds[(16 * R + 4 * lk + r) * kLdsStride + 16 * C + lr] = acc[R][C][r];
+      for (int r = 0; r < 4; ++r) lds[(16 * R + 4 * lk + r) * kNetStride + 16 * C + lr] = acc[R][C][r];
   __syncthreads();
   float U = -b1;
   float a1[32];
@@ -131,7 +136,7 @@ __device__ __forceinline__ float network_wave(const ModelDev& m, const float* qs
       }
 #pragma unroll
       for (int R = 0; R < 4; ++R) {
-        const float aop = lds[(16 * R + lr) * kLdsStride + hid];
+        const float aop = lds[(16 * R + lr) * kNetStride + hid];
 #pragma unroll
         for (int C = 0; C < 2; ++C)
           acc[R][C] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop[C], acc[R][C], 0, 0, 0);
@@ -153,7 +158,7 @@ __device__ __forceinline__ float network_wave(const ModelDev& m, const float* qs
       bf16x8 aop;
 #pragma unroll
       for (int e = 0; e < 8; ++e)
-        aop[e] = bits_to_bf16(f32_to_bf16_bits(lds[(16 * R + lr) * kLdsStride + 8 * lk + e]));
+        aop[e] = bits_to_bf16(f32_to_bf16_bits(lds[(16 * R + lr) * kNetStride + 8 * lk + e]));
 #pragma unroll
       for (int C = 0; C < 2; ++C)
         acc[R][C] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop[C], acc[R][C], 0, 0, 0);
@@ -165,17 +170,109 @@ __device__ __forceinline__ float network_wave(const ModelDev& m, const float* qs
 #pragma unroll
     for (int C = 0; C < 2; ++C)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) lds[(16 * R + 4 * lk + r) * kLdsStride + 16 * C + lr] = acc[R][C][r];
+      for (int r = 0; r < 4; ++r) lds[(16 * R + 4 * lk + r) * kNetStride + 16 * C + lr] = acc[R][C][r];
   __syncthreads();
 #pragma unroll
   for (int v = 0; v < S::D; ++v) fp[v] = row[v];
   return U;
 }
 
+// ------------------------------------------------------------------------ descriptors
+// Radial descriptors q[0..NR) and angular accumulators s[NA][NC] of center i over the
+// pairs inside the true cutoffs, all channels in one pass over the list with skin
+// (geometry computed once per pair and reused for every n). One species: the radial
+// descriptors are linear in the basis sums, q_n = sum_k c_nk sum_j f_k(r_ij), with
+// sum_j f_k = (sum_j f_c T_k + sum_j f_c) / 2, so a pair adds f_c and f_c T_k (k >= 1).
+// Returns the pair counts and the pairs inside the ZBL radius (zs).
+template <class S, bool MULTI>
+__device__ __forceinline__ void desc_pass(const ModelDev& m, const EvalBuffers& b, int64_t i, int ti, double xi,
+                                          double yi, double zi, double Lx, double Ly, double Lz, float* q, float* s,
+                                          ZblSeenFor<MULTI>& zs, int& nr, int& na) {
+  constexpr int NR = S::NR, NA = S::NA, NC = S::NC, KR = S::KR, KA = S::KA;
+  const int64_t N = b.N;
+  const float rcR_inv = 1.f / m.rcR, rcA_inv = 1.f / m.rcA;
+  const double rcR2 = m.rcR64 * m.rcR64, rcA2 = m.rcA64 * m.rcA64;
+  const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
+  nr = 0;
+  na = 0;
+  const int kR = radial_bound(b, i), kA = angular_bound(b, i);
+  float Qf = 0.f, QT[KR];  // sum_j f_c and sum_j f_c T_k (one species)
+#pragma unroll
+  for (int k = 0; k < KR; ++k) QT[k] = 0.f;
+  // the radial term of a pair inside rc_radial
+  auto radial_term = [&](int p, int32_t j, double r2, float r) {
+    ++nr;
+    if (r2 < m.zbl_o2) zs.add(p);
+    const RadialArg ra = radial_arg(r * rcR_inv);
+    if constexpr (MULTI) {
+      float g[NR];
+      radial_g<NR, KR>(r, rcR_inv, m.cR + (ti * m.T + b.type[j]) * NR * KR, g);
+#pragma unroll
+      for (int n = 0; n < NR; ++n) q[n] += g[n];
+    } else {
+      // T_k by the recurrence T_{k+1} = 2x T_k - T_{k-1}
+      Qf += ra.fc;
+      const float x2 = ra.x + ra.x;
+      float Tm = 1.f, T = ra.x;
+#pragma unroll
+      for (int k = 1; k < KR; ++k) {
+        QT[k] = fmaf(ra.fc, T, QT[k]);
+        const float Tn = fmaf(x2, T, -Tm);
+        Tm = T;
+        T = Tn;
+      }
+    }
+  };
+  // one entry: the radial term, and for the angular candidates inside rc_angular the angular one
+  auto pair_both = [&](int p, int32_t j, const uint4* w) {
+    double ex, ey, ez;
+    const double r2 = pair_r2_64(rec_f64(w[0].x, w[0].y), rec_f64(w[0].z, w[0].w), rec_f64(w[1].x, w[1].y),
+                                 xi, yi, zi, Lx, Ly, Lz, iLx, iLy, iLz, ex, ey, ez);
+    if (!(r2 < rcR2)) return;
+    const float dx = (float)ex, dy = (float)ey, dz = (float)ez;
+    float r, rinv;
+    pair_r(dx, dy, dz, r, rinv);
+    radial_term(p, j, r2, r);
+    if (p < kA && r2 < rcA2) {
+      ++na;
+      float g[NA];
+      if constexpr (MULTI) {
+        radial_g<NA, KA>(r, rcA_inv, m.cA + (ti * m.T + b.type[j]) * NA * KA, g);
+      } else {
+        const RadialArg ra = radial_arg(r * rcA_inv);
+        radial_g_fast<NA, KA>(ra.fc, ra.x, uniform_coeffs(m.hA), g);
+      }
+      for_each_poly<NC>(dx * rinv, dy * rinv, dz * rinv, [&](int lm, float P) {
+#pragma unroll
+        for (int n = 0; n < NA; ++n) s[n * NC + lm] = fmaf(g[n], P, s[n * NC + lm]);
+      });
+    }
+  };
+  // the angular candidates are the list's prefix [0, kA)
+  if constexpr (MULTI)
+    for_each_rec_span<2, S::DESC_AHEAD>(b.nbr, b.rec, N, i, 0, kR, pair_both);
+  else
+    for_each_rec_fast<2, S::DESC_AHEAD>(b.nbr, b.rec, N, i, 0, kR, pair_both);
+  if constexpr (!MULTI) {
+    const cfloat_ptr c = uniform_coeffs(m.cR);
+    float Qb[KR];
+    Qb[0] = Qf;
+#pragma unroll
+    for (int k = 1; k < KR; ++k) Qb[k] = 0.5f * (QT[k] + Qf);
+#pragma unroll
+    for (int n = 0; n < NR; ++n) {
+      float a = 0.f;
+#pragma unroll
+      for (int k = 0; k < KR; ++k) a = fmaf(c[n * KR + k], Qb[k], a);
+      q[n] += a;
+    }
+  }
+}
+
 // ------------------------------------------------------------------------ descriptor + network
 template <class S, int PREC, bool MULTI>
 __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers b) {
-  __shared__ float lds[kBlock / 64][64 * kLdsStride];
+  __shared__ float lds[kBlock / 64][64 * kNetStride];
   __shared__ double red[kBlock];
   constexpr int NR = S::NR, NA = S::NA, NC = S::NC, D = S::D;
   const int64_t N = b.N;
@@ -200,7 +297,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers 
     yi = rec_f64(w0.z, w0.w);
     zi = rec_f64(w1.x, w1.y);
     int nr = 0, na = 0;
-    desc_accumulate<S, MULTI>(m, b, i, ti, xi, yi, zi, Lx, Ly, Lz, q, s, zs, nr, na);
+    desc_pass<S, MULTI>(m, b, i, ti, xi, yi, zi, Lx, Ly, Lz, q, s, zs, nr, na);
     b.nactR[i] = nr;
     b.nactA[i] = na;
     desc_finish<S>(s, q);
@@ -215,23 +312,28 @@ __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers 
 
   if (valid) {
     {
-      // neighbour record words 1.zw, 2, 3: w_k = sum_n (dU/dq_n) c_nk for one species
-      // (the radial force of a pair then needs only the basis derivatives), dU/dq_n otherwise
-      float t[12];
+      // neighbour record words 1.zw, 2, 3: for one species w_k = sum_n (dU/dq_n) c_nk (k < 9)
+      // and their sum (the radial force of a pair is then a Chebyshev series in w_i + w_j),
+      // dU/dq_n otherwise
+      static_assert(S::KR <= 9, "the record holds 9 radial coefficients and their sum");
+      float t[10];
       if constexpr (MULTI) {
 #pragma unroll
-        for (int k = 0; k < 12; ++k) t[k] = k < NR ? fp[k] : 0.f;
+        for (int k = 0; k < 10; ++k) t[k] = k < NR ? fp[k] : 0.f;
       } else {
         const cfloat_ptr c = uniform_coeffs(m.cR);
+        float sum = 0.f;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) {
+        for (int k = 0; k < 9; ++k) {
           float a = 0.f;
           if (k < S::KR) {
 #pragma unroll
             for (int n = 0; n < NR; ++n) a = fmaf(fp[n], c[n * S::KR + k], a);
           }
           t[k] = a;
+          sum += a;
         }
+        t[9] = sum;
       }
       uint4* r = b.rec + 4 * i;
       reinterpret_cast<float2*>(r + 1)[1] = make_float2(t[0], t[1]);
@@ -350,13 +452,12 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
     const uint4 r0 = ri[0], r1 = ri[1], r2w = ri[2], r3 = ri[3];
     const double xi = rec_f64(r0.x, r0.y), yi = rec_f64(r0.z, r0.w), zi = rec_f64(r1.x, r1.y);
     const int ti = MULTI ? b.type[i] : 0;
-    // own radial coefficients (w_k for one species, dU/dq_n for several)
+    // own radial coefficients (w_k and their sum for one species, dU/dq_n for several)
     const float wi[10] = {__uint_as_float(r1.z), __uint_as_float(r1.w), __uint_as_float(r2w.x),
                           __uint_as_float(r2w.y), __uint_as_float(r2w.z), __uint_as_float(r2w.w),
                           __uint_as_float(r3.x), __uint_as_float(r3.y), __uint_as_float(r3.z),
                           __uint_as_float(r3.w)};
-    const float* cR = m.cR;
-    const float* cA = m.cA;
+    constexpr int KR = S::KR, KA = S::KA;
     float G[NA * NC];
 #pragma unroll
     for (int k = 0; k < NA * NC; ++k) G[k] = b.G[(int64_t)k * N + i];
@@ -365,10 +466,13 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
     const int kR = radial_bound(b, i), kA = angular_bound(b, i);
     ZblSeenFor<MULTI> zs;  // pairs inside the ZBL radius
     // One pass over the list. Radial pairs: gather, F_i += (dU_i/dr_ij + dU_j/dr_ji) along u,
-    // with the neighbour's radial coefficients read from its record.
+    // with the neighbour's radial coefficients read from its record; the virial takes half
+    // of that pair term (the lists are symmetric, so the pair's other half comes from j).
     // Angular and four-body pairs (the angular prefix inside rc_angular): scatter
     // dU_i/dr_ij into this atom and -dU_i/dr_ij into the neighbour.
-    for_each_rec<4>(b.nbr, b.rec, N, i, kR, [&](int p, int32_t j, const uint4* rw) {
+    // one entry: the radial term, and for the angular candidates inside rc_angular the
+    // angular and four-body term, scattered into the neighbour
+    auto pair_both = [&](int p, int32_t j, const uint4* rw) {
       double ex, ey, ez;
       const double r2 = pair_r2_64(rec_f64(rw[0].x, rw[0].y), rec_f64(rw[0].z, rw[0].w),
                                    rec_f64(rw[1].x, rw[1].y), xi, yi, zi, Lx, Ly, Lz, iLx, iLy, iLz, ex, ey,
@@ -377,44 +481,42 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
       const float dx = (float)ex, dy = (float)ey, dz = (float)ez;
       const bool ang = p < kA && r2 < rcA2;
       const int lj = (ang && lds) ? (int)b.nbrl[(int64_t)p * N + i] : 0;
+      float r, rinv;
+      pair_r(dx, dy, dz, r, rinv);
+      const int tj = MULTI ? b.type[j] : 0;
       const float wj[10] = {__uint_as_float(rw[1].z), __uint_as_float(rw[1].w), __uint_as_float(rw[2].x),
                             __uint_as_float(rw[2].y), __uint_as_float(rw[2].z), __uint_as_float(rw[2].w),
                             __uint_as_float(rw[3].x), __uint_as_float(rw[3].y), __uint_as_float(rw[3].z),
                             __uint_as_float(rw[3].w)};
-      float r, rinv;
-      pair_r(dx, dy, dz, r, rinv);
-      const int tj = MULTI ? b.type[j] : 0;
-      float si = 0.f, sj = 0.f;
+      float st;  // dU_i/dr_ij + dU_j/dr_ji along u
       if constexpr (MULTI) {
-        float g[NR], dg[NR];
-        radial_g_dg<NR, S::KR>(r, rcR_inv, cR + (ti * m.T + tj) * NR * S::KR, g, dg);
-        float g2[NR], dg2[NR];
-        radial_g_dg<NR, S::KR>(r, rcR_inv, cR + (tj * m.T + ti) * NR * S::KR, g2, dg2);
+        float g[NR], dg[NR], g2[NR], dg2[NR];
+        radial_g_dg<NR, KR>(r, rcR_inv, m.cR + (ti * m.T + tj) * NR * KR, g, dg);
+        radial_g_dg<NR, KR>(r, rcR_inv, m.cR + (tj * m.T + ti) * NR * KR, g2, dg2);
+        float si = 0.f, sj = 0.f;
 #pragma unroll
         for (int n = 0; n < NR; ++n) {
           si = fmaf(wi[n], dg[n], si);
           sj = fmaf(wj[n], dg2[n], sj);
         }
+        st = si + sj;
       } else {
-        // one species: dU/dr along u = sum_k w_k e_k with the basis derivatives e_k
-        float e[S::KR];
-        radial_basis_deriv<S::KR>(r, rcR_inv, e);
+        // one species: sum_k (w_ik + w_jk) f_k'(r)
+        const RadialArgD ra = radial_arg_d(r * rcR_inv, rcR_inv);
+        float W[KR];
 #pragma unroll
-        for (int k = 0; k < S::KR; ++k) {
-          si = fmaf(wi[k], e[k], si);
-          sj = fmaf(wj[k], e[k], sj);
-        }
+        for (int k = 0; k < KR; ++k) W[k] = wi[k] + wj[k];
+        st = radial_series_deriv<KR>(ra, W, wi[9] + wj[9]);
       }
       if (r2 < m.zbl_o2) zs.add(p);
       const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
-      const float st = (si + sj);
       fx = fmaf(st, ux, fx);
       fy = fmaf(st, uy, fy);
       fz = fmaf(st, uz, fz);
-      // virial of dU_i/dr_ij = si u
       {
+        const float hs = 0.5f * st;
         const float d[3] = {dx, dy, dz};
-        const float f[3] = {si * ux, si * uy, si * uz};
+        const float f[3] = {hs * ux, hs * uy, hs * uz};
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -422,27 +524,29 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
       }
       if (!ang) return;
       float g[NA], dg[NA];
-      if constexpr (MULTI)
-        radial_g_dg<NA, S::KA>(r, rcA_inv, cA + (ti * m.T + tj) * NA * S::KA, g, dg);
-      else
-        radial_g_dg<NA, S::KA>(r, rcA_inv, uniform_coeffs(cA), g, dg);
+      if constexpr (MULTI) {
+        radial_g_dg<NA, KA>(r, rcA_inv, m.cA + (ti * m.T + tj) * NA * KA, g, dg);
+      } else {
+        const RadialArgD rb = radial_arg_d(r * rcA_inv, rcA_inv);
+        radial_g_dg_fast<NA, KA>(rb, uniform_coeffs(m.hA), g, dg);
+      }
       // F_ij = sum_lm [ A_lm P_lm u + B_lm (grad P_lm - l P_lm u) / r ] with
       // A_lm = sum_n G_nlm g'_n and B_lm = sum_n G_nlm g_n; the l P B terms are
       // summed per l and scaled once.
       float sA = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
       float sB[4] = {0.f, 0.f, 0.f, 0.f};
-      for_each_poly_grad<NC>(ux, uy, uz, [&](int lm, float P, float px, float py, float pz) {
-        float A = 0.f, B = 0.f;
+      for_each_poly_grad<NC>(ux, uy, uz, [&](int lm, float P, auto px, auto py, auto pz) {
+        float A = G[lm] * dg[0], B = G[lm] * g[0];
 #pragma unroll
-        for (int n = 0; n < NA; ++n) {
+        for (int n = 1; n < NA; ++n) {
           A = fmaf(G[n * NC + lm], dg[n], A);
           B = fmaf(G[n * NC + lm], g[n], B);
         }
         sA = fmaf(P, A, sA);
         sB[comp_l(lm) - 1] = fmaf(P, B, sB[comp_l(lm) - 1]);
-        vx = fmaf(B, px, vx);
-        vy = fmaf(B, py, vy);
-        vz = fmaf(B, pz, vz);
+        vx = fmac(B, px, vx);
+        vy = fmac(B, py, vy);
+        vz = fmac(B, pz, vz);
       });
       const float lPB = fmaf(4.f, sB[3], fmaf(3.f, sB[2], fmaf(2.f, sB[1], sB[0])));
       const float sc = fmaf(-rinv, lPB, sA);
@@ -467,7 +571,13 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
       for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int c = 0; c < 3; ++c) w[a * 3 + c] = fmaf(-d[a], f[c], w[a * 3 + c]);
-    });
+    };
+    // One pass over the list. Radial pairs: gather, F_i += (dU_i/dr_ij + dU_j/dr_ji) along u,
+    // with the neighbour's radial coefficients read from its record; the virial takes half
+    // of that pair term (the lists are symmetric, so the pair's other half comes from j).
+    // Angular and four-body pairs (the angular prefix [0, kA) inside rc_angular): scatter
+    // dU_i/dr_ij into this atom and -dU_i/dr_ij into the neighbour.
+    for_each_rec_span<4, 1>(b.nbr, b.rec, N, i, 0, kR, pair_both);
     if (zs.n) {
       float f[3] = {fx, fy, fz};
       zbl_center<MULTI>(m, b, i, ti, xi, yi, zi, zs, nullptr, f, w);
@@ -518,7 +628,36 @@ hipError_t launch_shape(const ModelDev& m, int precision, const EvalBuffers& b, 
 }
 
 
+// Derived radial tables (nep_fast.h) of nblk coefficient blocks [nblk][N][K]: one thread
+// per (block, channel) writes h_n0 = (c_n0 + sum_k c_nk) / 2, h_nk = c_nk / 2 and
+// d_n(k-1) = k c_nk / 2 into that block's [N][2K - 1] table.
+__global__ void k_derive_coeffs(const float* __restrict__ c, int nblk, int N, int K, float* __restrict__ h) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nblk * N) return;
+  const int blk = t / N, n = t % N;
+  const float* cn = c + ((int64_t)blk * N + n) * K;
+  float* hb = h + (int64_t)blk * N * (2 * K - 1);
+  float sum = 0.f;
+  for (int k = 0; k < K; ++k) sum += cn[k];
+  hb[n * K] = 0.5f * (cn[0] + sum);
+  for (int k = 1; k < K; ++k) {
+    hb[n * K + k] = 0.5f * cn[k];
+    hb[N * K + n * (K - 1) + k - 1] = (0.5f * (float)k) * cn[k];
+  }
+}
+
 }  // namespace
+
+int64_t derived_coeff_floats(int T, int nR, int kR, int nA, int kA) {
+  return (int64_t)T * T * (nR * (2 * kR - 1) + nA * (2 * kA - 1));
+}
+
+hipError_t launch_derive_coeffs(int T, int nR, int kR, int nA, int kA, const float* cR, const float* cA, float* hR,
+                                float* hA, hipStream_t st) {
+  hipLaunchKernelGGL(k_derive_coeffs, dim3(1), dim3(64), 0, st, cR, T * T, nR, kR, hR);
+  hipLaunchKernelGGL(k_derive_coeffs, dim3(1), dim3(64), 0, st, cA, T * T, nA, kA, hA);
+  return hipGetLastError();
+}
 
 bool eval_supported(const ModelDev& m) { return is_shape<FullShape>(m) || is_shape<SurShape>(m); }
 

@@ -1,0 +1,249 @@
+// Pair arithmetic of the evaluation kernels (k_desc_net, k_force), written for the
+// fewest VALU instructions per pair: the cutoff function from short Taylor series on
+// the one interval it needs, the Chebyshev basis through the recurrences of both kinds
+// with model-derived coefficient tables, the single-species radial force by Clenshaw's
+// recurrence, and a neighbour loop whose prefetch buffers rotate without copies.
+// The training kernels keep the direct forms of nep_kernels.h.
+#pragma once
+
+#include "nep_kernels.h"
+
+namespace nep {
+namespace kern {
+
+// ---------------------------------------------------------------- cutoff function
+// f_c = (1 + cos(pi t)) / 2 for t = r / r_c in [0, 1) (the cosine cutoff: value and slope
+// vanish at r_c). With psi = pi t - pi/2 in [-pi/2, pi/2): cos(pi t) = -sin(psi) and
+// sin(pi t) = cos(psi). sin and cos of psi come from their Taylor series through psi^13
+// and psi^14; on |psi| <= pi/2 the remainders are below |psi|^15 / 15! < 7e-10 and
+// |psi|^16 / 16! < 7e-11, under the FP32 rounding of the result.
+constexpr float kHalfPiF = 1.57079632679489661923f;
+
+__device__ __forceinline__ float taylor_sin(float psi, float p2) {
+  float a = (float)(1.0 / 6227020800.0);  // 1/13!
+  a = fmaf(a, p2, (float)(-1.0 / 39916800.0));
+  a = fmaf(a, p2, (float)(1.0 / 362880.0));
+  a = fmaf(a, p2, (float)(-1.0 / 5040.0));
+  a = fmaf(a, p2, (float)(1.0 / 120.0));
+  a = fmaf(a, p2, (float)(-1.0 / 6.0));
+  return fmaf(psi * p2, a, psi);
+}
+
+__device__ __forceinline__ float taylor_cos(float p2) {
+  float a = (float)(-1.0 / 87178291200.0);  // -1/14!
+  a = fmaf(a, p2, (float)(1.0 / 479001600.0));
+  a = fmaf(a, p2, (float)(-1.0 / 3628800.0));
+  a = fmaf(a, p2, (float)(1.0 / 40320.0));
+  a = fmaf(a, p2, (float)(-1.0 / 720.0));
+  a = fmaf(a, p2, (float)(1.0 / 24.0));
+  a = fmaf(a, p2, -0.5f);
+  return fmaf(a, p2, 1.f);
+}
+
+// Geometry of one pair at scaled distance t = r / r_c: f_c, and the Chebyshev argument
+// x = 2 (t - 1)^2 - 1 of the radial basis.
+struct RadialArg {
+  float fc, x;
+};
+__device__ __forceinline__ RadialArg radial_arg(float t) {
+  const float psi = fmaf(kPiF, t, -kHalfPiF);
+  const float s = taylor_sin(psi, psi * psi);
+  const float y = t - 1.f;
+  return {fmaf(-0.5f, s, 0.5f), fmaf(y + y, y, -1.f)};
+}
+
+// The same with the r-derivatives: dfc = d f_c / dr and dx = d x / dr (rc_inv = 1 / r_c).
+struct RadialArgD {
+  float fc, dfc, x, dx;
+};
+__device__ __forceinline__ RadialArgD radial_arg_d(float t, float rc_inv) {
+  const float psi = fmaf(kPiF, t, -kHalfPiF);
+  const float p2 = psi * psi;
+  const float s = taylor_sin(psi, p2), c = taylor_cos(p2);
+  const float y = t - 1.f;
+  return {fmaf(-0.5f, s, 0.5f), (-kHalfPiF * rc_inv) * c, fmaf(y + y, y, -1.f), (4.f * rc_inv) * y};
+}
+
+// Derived coefficient table of one (center type, neighbour type) block of N channels
+// and K basis functions, [N][2K - 1] floats: h_n0 = (c_n0 + sum_k c_nk) / 2,
+// h_nk = c_nk / 2 (k >= 1), then d_n(k-1) = k c_nk / 2 (k >= 1). With them
+//   g_n  = f_c (h_n0 + sum_{k>=1} h_nk T_k(x))                       = f_c C_n
+//   g_n' = f_c' C_n + f_c x' sum_{k>=1} d_n(k-1) U_{k-1}(x)          = f_c' C_n + f_c x' D_n
+// which are sum_k c_nk f_k and its r-derivative for f_k = f_c (T_k + 1) / 2.
+template <int N, int K>
+constexpr int derived_block() { return N * (2 * K - 1); }
+
+// Both run over k outermost with the recurrences rolled along, so that only the channel
+// sums and three terms of each recurrence are live.
+template <int N, int K, class CP>
+__device__ __forceinline__ void radial_g_fast(float fc, float x, CP h, float* g) {
+  float a[N];
+#pragma unroll
+  for (int n = 0; n < N; ++n) a[n] = h[n * K];
+  const float x2 = x + x;
+  float Tm = 1.f, T = x;  // T_{k-1}, T_k
+#pragma unroll
+  for (int k = 1; k < K; ++k) {
+#pragma unroll
+    for (int n = 0; n < N; ++n) a[n] = fmaf(h[n * K + k], T, a[n]);
+    const float Tn = fmaf(x2, T, -Tm);
+    Tm = T;
+    T = Tn;
+  }
+#pragma unroll
+  for (int n = 0; n < N; ++n) g[n] = fc * a[n];
+}
+
+template <int N, int K, class CP>
+__device__ __forceinline__ void radial_g_dg_fast(const RadialArgD& ra, CP h, float* g, float* dg) {
+  float a[N], d[N];
+#pragma unroll
+  for (int n = 0; n < N; ++n) {
+    a[n] = h[n * K];                // k = 0 of C_n
+    d[n] = h[N * K + n * (K - 1)];  // k = 1 of D_n (U_0 = 1)
+  }
+  const float x2 = ra.x + ra.x;
+  float Tm = 1.f, T = ra.x;  // T_{k-1}, T_k
+  float Um = 1.f, Uc = x2;   // U_{k-2}, U_{k-1} for the D term of index k + 1
+#pragma unroll
+  for (int k = 1; k < K; ++k) {
+#pragma unroll
+    for (int n = 0; n < N; ++n) a[n] = fmaf(h[n * K + k], T, a[n]);
+    if (k + 1 < K) {
+      // D_n term k + 1: d_nk U_k, with U_k in Uc
+#pragma unroll
+      for (int n = 0; n < N; ++n) d[n] = fmaf(h[N * K + n * (K - 1) + k], Uc, d[n]);
+      const float Un = fmaf(x2, Uc, -Um);
+      Um = Uc;
+      Uc = Un;
+    }
+    const float Tn = fmaf(x2, T, -Tm);
+    Tm = T;
+    T = Tn;
+  }
+  const float fcdx = ra.fc * ra.dx;
+#pragma unroll
+  for (int n = 0; n < N; ++n) {
+    if (g) g[n] = ra.fc * a[n];
+    dg[n] = fmaf(ra.dfc, a[n], fcdx * d[n]);
+  }
+}
+
+// d/dr sum_k W_k f_k(r) for f_k = f_c (T_k + 1) / 2, given Wsum = sum_k W_k:
+//   sum_k W_k f_k = f_c (C(x) + Wsum) / 2 with the Chebyshev series C(x) = sum_k W_k T_k(x),
+// so the derivative is (f_c' (C + Wsum) + f_c x' C'(x)) / 2. C and C' by Clenshaw's
+// recurrence b_k = W_k + 2x b_{k+1} - b_{k+2} and its x-derivative
+// d_k = 2 b_{k+1} + 2x d_{k+1} - d_{k+2}: C = W_0 + x b_1 - b_2, C' = b_1 + x d_1 - d_2.
+template <int K>
+__device__ __forceinline__ float radial_series_deriv(const RadialArgD& ra, const float* W, float Wsum) {
+  const float x2 = ra.x + ra.x;
+  float b1 = 0.f, b2 = 0.f, d1 = 0.f, d2 = 0.f;
+#pragma unroll
+  for (int k = K - 1; k >= 1; --k) {
+    const float bk = fmaf(x2, b1, W[k] - b2);
+    const float dk = fmaf(x2, d1, fmaf(2.f, b1, -d2));
+    b2 = b1;
+    b1 = bk;
+    d2 = d1;
+    d1 = dk;
+  }
+  const float C = fmaf(ra.x, b1, W[0] - b2);
+  const float Cp = fmaf(ra.x, d1, b1 - d2);
+  return 0.5f * fmaf(ra.dfc, C + Wsum, (ra.fc * ra.dx) * Cp);
+}
+
+// ---------------------------------------------------------------- neighbour loops
+// Both visit entries [k0, k1) of atom i's slot-major list, calling body(p, j, w) with the
+// first W 16-byte words of neighbour j's record. The records of entries p + 1 .. p + AHEAD
+// and the index of entry p + AHEAD + 1 are in flight while the body of entry p runs, so
+// their latency overlaps the pair arithmetic; bodies with little arithmetic per pair need
+// the deeper queue. The last loads repeat entry k1 - 1: every address stays inside the
+// list and the records.
+//
+// for_each_rec_span moves the queue along by register copies; for_each_rec_fast is
+// unrolled AHEAD + 1 times so that each record is loaded straight into the buffer the
+// body later reads (a rotation by index, not by copies), at the cost of a few more live
+// registers.
+template <int W, int AHEAD, class Body>
+__device__ __forceinline__ void for_each_rec_span(const int32_t* __restrict__ nbr, const uint4* __restrict__ rec,
+                                                  int64_t N, int64_t i, int k0, int k1, Body&& body) {
+  static_assert(AHEAD >= 1 && AHEAD <= 4, "prefetch depth");
+  if (k1 <= k0) return;
+  // slots, indices and N fit in 32 bits (N < 2^28): 32 x 32 -> 64-bit offsets
+  const int32_t* __restrict__ col = nbr + i;
+  const uint32_t n32 = (uint32_t)N;
+  auto slot = [&](int s) { return col[(uint64_t)(uint32_t)s * n32]; };
+  auto record = [&](int32_t j, int w) { return rec[((uint64_t)(uint32_t)j << 2) + w]; };
+  const int last = k1 - 1;
+  int32_t jq[AHEAD + 1];  // indices of entries p .. p + AHEAD
+#pragma unroll
+  for (int a = 0; a <= AHEAD; ++a) jq[a] = slot(k0 + a < last ? k0 + a : last);
+  uint4 rq[AHEAD][W];  // records of entries p .. p + AHEAD - 1
+#pragma unroll
+  for (int a = 0; a < AHEAD; ++a)
+#pragma unroll
+    for (int w = 0; w < W; ++w) rq[a][w] = record(jq[a], w);
+  for (int p = k0; p < k1; ++p) {
+    const int32_t jn = slot(p + AHEAD + 1 < last ? p + AHEAD + 1 : last);
+    uint4 rn[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) rn[w] = record(jq[AHEAD], w);
+    body(p, jq[0], rq[0]);
+#pragma unroll
+    for (int a = 0; a < AHEAD; ++a) jq[a] = jq[a + 1];
+    jq[AHEAD] = jn;
+#pragma unroll
+    for (int a = 0; a + 1 < AHEAD; ++a)
+#pragma unroll
+      for (int w = 0; w < W; ++w) rq[a][w] = rq[a + 1][w];
+#pragma unroll
+    for (int w = 0; w < W; ++w) rq[AHEAD - 1][w] = rn[w];
+  }
+}
+
+template <int W, int AHEAD, class Body>
+__device__ __forceinline__ void for_each_rec_fast(const int32_t* __restrict__ nbr, const uint4* __restrict__ rec,
+                                                  int64_t N, int64_t i, int k0, int k1, Body&& body) {
+  static_assert(AHEAD >= 1 && AHEAD <= 3, "prefetch depth");
+  constexpr int U = AHEAD + 1;
+  if (k1 <= k0) return;
+  const int32_t* __restrict__ col = nbr + i;
+  const uint32_t n32 = (uint32_t)N;
+  auto slot = [&](int s) { return col[(uint64_t)(uint32_t)s * n32]; };
+  auto record = [&](int32_t j, int w) { return rec[((uint64_t)(uint32_t)j << 2) + w]; };
+  const int last = k1 - 1;
+  int32_t jq[AHEAD + 1];  // indices of entries p .. p + AHEAD
+#pragma unroll
+  for (int a = 0; a <= AHEAD; ++a) jq[a] = slot(k0 + a < last ? k0 + a : last);
+  uint4 rq[U][W];  // record buffers; entry p sits in buffer (p - k0) % U
+#pragma unroll
+  for (int a = 0; a < AHEAD; ++a)
+#pragma unroll
+    for (int w = 0; w < W; ++w) rq[a][w] = record(jq[a], w);
+  for (int p0 = k0; p0 < k1; p0 += U) {
+#pragma unroll
+    for (int ph = 0; ph < U; ++ph) {
+      const int p = p0 + ph;
+      if (p < k1) {
+        const int32_t jn = slot(p + AHEAD + 1 < last ? p + AHEAD + 1 : last);
+#pragma unroll
+        for (int w = 0; w < W; ++w) rq[(ph + AHEAD) % U][w] = record(jq[AHEAD], w);
+        body(p, jq[0], rq[ph]);
+#pragma unroll
+        for (int a = 0; a < AHEAD; ++a) jq[a] = jq[a + 1];
+        jq[AHEAD] = jn;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- structural zeros
+// Gradient components of the harmonic polynomials that vanish identically are passed as
+// Zero, so that their products drop out at compile time (an FP32 product with a literal
+// 0.0 cannot be removed by the compiler, since it must keep NaN and signed-zero results).
+__device__ __forceinline__ float fmac(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ float fmac(float, Zero, float c) { return c; }
+__device__ __forceinline__ float fmac(Zero, float, float c) { return c; }
+
+}  // namespace kern
+}  // namespace nep

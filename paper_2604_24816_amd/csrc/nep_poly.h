@@ -22,6 +22,13 @@ __device__ constexpr float kW[24] = {
     8.75f, 4.375f, 1.25f, 0.625f, 0.015625f, 0.625f, 0.3125f, 4.375f, 0.546875f  // l = 4
 };
 
+// A gradient component that vanishes identically. It converts to 0 where a caller takes
+// plain numbers; callers that overload on it drop the products with it.
+struct Zero {
+  __host__ __device__ constexpr operator float() const { return 0.f; }
+  __host__ __device__ constexpr operator double() const { return 0.0; }
+};
+
 __host__ __device__ constexpr int comp_l(int lm) {
   return lm < 3 ? 1 : (lm < 8 ? 2 : (lm < 15 ? 3 : 4));
 }
@@ -67,35 +74,35 @@ __device__ __forceinline__ void for_each_poly(R x, R y, R z, Fn&& f) {
 }
 
 // Calls f(lm, P, dP/dx, dP/dy, dP/dz) with the gradient of the homogeneous
-// polynomial evaluated at u.
+// polynomial evaluated at u; components that vanish identically are passed as Zero.
 template <int NC, typename R, typename Fn>
 __device__ __forceinline__ void for_each_poly_grad(R x, R y, R z, Fn&& f) {
-  f(0, y, R(0), R(1), R(0));
-  f(1, z, R(0), R(0), R(1));
-  f(2, x, R(1), R(0), R(0));
+  f(0, y, Zero{}, R(1), Zero{});
+  f(1, z, Zero{}, Zero{}, R(1));
+  f(2, x, R(1), Zero{}, Zero{});
   if constexpr (NC > 3) {
     const R x2 = x * x, y2 = y * y, z2 = z * z;
-    f(3, x * y, y, x, R(0));
-    f(4, y * z, R(0), z, y);
+    f(3, x * y, y, x, Zero{});
+    f(4, y * z, Zero{}, z, y);
     f(5, R(2) * z2 - x2 - y2, -R(2) * x, -R(2) * y, R(4) * z);
-    f(6, x * z, z, R(0), x);
-    f(7, x2 - y2, R(2) * x, -R(2) * y, R(0));
+    f(6, x * z, z, Zero{}, x);
+    f(7, x2 - y2, R(2) * x, -R(2) * y, Zero{});
     if constexpr (NC > 8) {
       const R xy = x * y, xz = x * z, yz = y * z;
       const R t = R(4) * z2 - x2 - y2;
-      f(8, y * (R(3) * x2 - y2), R(6) * xy, R(3) * (x2 - y2), R(0));
+      f(8, y * (R(3) * x2 - y2), R(6) * xy, R(3) * (x2 - y2), Zero{});
       f(9, xy * z, yz, xz, xy);
       f(10, y * t, -R(2) * xy, R(4) * z2 - x2 - R(3) * y2, R(8) * yz);
       f(11, z * (R(2) * z2 - R(3) * x2 - R(3) * y2), -R(6) * xz, -R(6) * yz, R(6) * z2 - R(3) * x2 - R(3) * y2);
       f(12, x * t, R(4) * z2 - R(3) * x2 - y2, -R(2) * xy, R(8) * xz);
       f(13, z * (x2 - y2), R(2) * xz, -R(2) * yz, x2 - y2);
-      f(14, x * (x2 - R(3) * y2), R(3) * (x2 - y2), -R(6) * xy, R(0));
+      f(14, x * (x2 - R(3) * y2), R(3) * (x2 - y2), -R(6) * xy, Zero{});
       if constexpr (NC > 15) {
         const R rho2 = x2 + y2;
         const R a = R(6) * z2 - rho2;
         const R b = R(4) * z2 - R(3) * rho2;
         const R xyz = xy * z;
-        f(15, xy * (x2 - y2), R(3) * x2 * y - y2 * y, x2 * x - R(3) * x * y2, R(0));
+        f(15, xy * (x2 - y2), R(3) * x2 * y - y2 * y, x2 * x - R(3) * x * y2, Zero{});
         f(16, yz * (R(3) * x2 - y2), R(6) * xyz, R(3) * z * (x2 - y2), y * (R(3) * x2 - y2));
         f(17, xy * a, y * (R(6) * z2 - R(3) * x2 - y2), x * (R(6) * z2 - x2 - R(3) * y2), R(12) * xyz);
         f(18, yz * b, -R(6) * xyz, z * (R(4) * z2 - R(3) * x2 - R(9) * y2), R(3) * y * (R(4) * z2 - rho2));
@@ -104,7 +111,7 @@ __device__ __forceinline__ void for_each_poly_grad(R x, R y, R z, Fn&& f) {
         f(20, xz * b, z * (R(4) * z2 - R(9) * x2 - R(3) * y2), -R(6) * xyz, R(3) * x * (R(4) * z2 - rho2));
         f(21, (x2 - y2) * a, R(4) * x * (R(3) * z2 - x2), R(4) * y * (y2 - R(3) * z2), R(12) * z * (x2 - y2));
         f(22, xz * (x2 - R(3) * y2), R(3) * z * (x2 - y2), -R(6) * xyz, x * (x2 - R(3) * y2));
-        f(23, x2 * x2 - R(6) * x2 * y2 + y2 * y2, R(4) * x * (x2 - R(3) * y2), R(4) * y * (y2 - R(3) * x2), R(0));
+        f(23, x2 * x2 - R(6) * x2 * y2 + y2 * y2, R(4) * x * (x2 - R(3) * y2), R(4) * y * (y2 - R(3) * x2), Zero{});
       }
     }
   }

@@ -616,7 +616,15 @@ int param_block_offset(const ModelDev& m) {
 
 hipError_t launch_train_forward_params(const ModelDev& m, const float* params, const EvalBuffers& b,
                                        hipStream_t st) {
-  return launch_eval(with_params(m, params), 0, b, st);
+  // the evaluation kernels read the radial coefficients through their derived tables:
+  // build them from this vector's coefficients
+  ModelDev mp = with_params(m, params);
+  mp.hR = m.hscratch;
+  mp.hA = m.hscratch + (int64_t)m.T * m.T * m.nR * (2 * m.kR - 1);
+  hipError_t e = launch_derive_coeffs(m.T, m.nR, m.kR, m.nA, m.kA, mp.cR, mp.cA, m.hscratch,
+                                      const_cast<float*>(mp.hA), st);
+  if (e != hipSuccess) return e;
+  return launch_eval(mp, 0, b, st);
 }
 
 hipError_t launch_train_backward_params(const ModelDev& m, const TrainBuffers& t, hipStream_t st) {
