@@ -52,7 +52,8 @@ enum nep_status {
   NEP_ERR_HIP = -6,                /* a HIP runtime call failed                    */
   NEP_ERR_WORKSPACE = -7,          /* workspace missing, too small or misaligned   */
   NEP_ERR_STALE_LIST = -8,         /* evaluation requested before any list build   */
-  NEP_ERR_UNSUPPORTED = -9         /* model shape without a compiled kernel        */
+  NEP_ERR_UNSUPPORTED = -9,        /* model shape without a compiled kernel        */
+  NEP_ERR_TOO_LARGE = -10          /* system beyond the allocation-free call's scratch */
 };
 
 enum nep_precision {
@@ -285,6 +286,32 @@ int nep_profile_read(nep_system* s, double* ms6, int64_t* count6);
 /* Pair counts summed over atoms at the last evaluation: counts3 = {radial pairs
  * (r < rc_radial), angular pairs (r < rc_angular), radial list entries with skin}. */
 int nep_pair_counts(nep_system* s, int64_t* counts3);
+
+/* ---------------------------------------------------------------- allocation-free call
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): energy, virial and forces of one
+ * configuration, as nep_system_create + nep_set_state + nep_build_neighbors +
+ * nep_compute_energy_forces_virial would give them (same kernels), but with the system's
+ * workspace carved from a fixed device scratch of 64 MiB that the library holds on every
+ * GPU it runs on until the process ends, instead of a caller-owned buffer. The call
+ * allocates no device memory (no hipMalloc, no allocating library routine); the caller
+ * still owns the inputs and outputs.
+ *   model: as for nep_system_create (no surrogate). n_atoms, box, cap_radial, cap_angular,
+ *   skin: as for nep_system_create and nep_build_neighbors. x [N][3] (FP64) and types [N]
+ *   (int32) are DEVICE arrays in the caller's atom order. precision: NEP_FP32, NEP_BF16 or
+ *   NEP_FP64. energy and virial9 are host pointers; forces [N][3] and per_atom_energy [N]
+ *   (FP64, caller's order) are device pointers and may be NULL. hip_stream: a hipStream_t
+ *   (NULL = default stream); the call synchronises it.
+ * Errors: NEP_ERR_TOO_LARGE when the system's workspace (about 2.8 KB per atom at
+ * capacities 160/96, so roughly 23,000 atoms) exceeds the scratch, checked before any
+ * device work; the other codes as for the calls it replaces. Every call on a GPU uses that
+ * GPU's one scratch and leaves its contents behind (each call clears what it needs), so
+ * calls that overlap on one GPU (different streams or host threads) race: serialise them. */
+int nep_compute_energy_forces_virial_noalloc(const nep_model* model, int64_t n_atoms, const double box[3],
+                                             int32_t cap_radial, int32_t cap_angular, double skin,
+                                             const double* x, const int32_t* types, int32_t precision,
+                                             double* energy, double* virial9, double* forces,
+                                             double* per_atom_energy, void* hip_stream);
 
 const char* nep_status_string(int status);
 const char* nep_last_error(const nep_system* s);

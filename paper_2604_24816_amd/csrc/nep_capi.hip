@@ -10,10 +10,18 @@
 #include <string>
 #include <vector>
 
+#include <mutex>
+
 #include "../../include/nep.h"
 #include "nep_common.h"
 
 using namespace nep;
+
+// Device scratch of nep_compute_energy_forces_virial_noalloc: the workspace of a system of
+// at most this many bytes, in a file-scope array that every GPU running the library holds
+// for the life of the process (host code reaches it only through hipGetSymbolAddress).
+constexpr int64_t kNoallocScratchBytes = int64_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
 
 struct nep_model {
   nep_hparams hp;
@@ -222,6 +230,12 @@ int64_t layout(nep_system* s, char* base, int64_t N, int capR, int capA, int max
       s->err = std::string(#call) + ": " + hipGetErrorString(e_);               \
       return NEP_ERR_HIP;                                                       \
     }                                                                           \
+  } while (0)
+
+// The same for calls without a system to hold the message.
+#define HIPCHK2(call)                                                           \
+  do {                                                                          \
+    if ((call) != hipSuccess) return NEP_ERR_HIP;                               \
   } while (0)
 
 int fail(nep_system* s, int code, const std::string& msg) {
@@ -501,6 +515,27 @@ void prof_pair(nep_system* s, hipEvent_t* base, int a, int b, int group) {
 
 }  // namespace
 
+// Scratch of the allocation-free call (see nep_compute_energy_forces_virial_noalloc).
+namespace {
+constexpr int kNoallocDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kNoallocDevices] = {};
+
+// Device address of this device's copy of `scratch`, looked up once per device with
+// that device current.
+int noalloc_scratch(int dev, void** out) {
+  if (dev < 0 || dev >= kNoallocDevices) return NEP_ERR_ARG;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return NEP_ERR_HIP;
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return NEP_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char* nep_status_string(int status) {
@@ -515,6 +550,7 @@ const char* nep_status_string(int status) {
     case NEP_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
     case NEP_ERR_STALE_LIST: return "no valid neighbour list";
     case NEP_ERR_UNSUPPORTED: return "model shape has no compiled kernel";
+    case NEP_ERR_TOO_LARGE: return "system needs more than the fixed 64 MiB scratch of the allocation-free call";
     default: return "unknown status";
   }
 }
@@ -1208,5 +1244,62 @@ int nep_pair_counts(nep_system* s, int64_t* counts3) {
   return NEP_OK;
 }
 
+
+// ---------------------------------------------------------------- allocation-free evaluation
+
+int nep_compute_energy_forces_virial_noalloc(const nep_model* model, int64_t n_atoms, const double box[3],
+                                             int32_t cap_radial, int32_t cap_angular, double skin, const double* x,
+                                             const int32_t* types, int32_t precision, double* energy,
+                                             double* virial9, double* forces, double* per_atom_energy,
+                                             void* hip_stream) {
+  if (!model || !box || !x || !types || !energy || !virial9 || n_atoms < 1 || n_atoms >= kMaxAtoms ||
+      cap_radial < 1 || cap_angular < 1 || cap_radial > kMaxCap || cap_angular > kMaxCap || precision < 0 ||
+      precision > 2 || !(skin >= 0) || !std::isfinite(skin))
+    return NEP_ERR_ARG;
+  for (int c = 0; c < 3; ++c)
+    if (!(box[c] > 0) || !std::isfinite(box[c])) return NEP_ERR_ARG;
+  const double cut = model->hp.rc_radial + skin;
+  for (int c = 0; c < 3; ++c)
+    if (!(box[c] >= 2.0 * cut)) return NEP_ERR_BOX_TOO_SMALL;
+  // the workspace this system needs, carved from the scratch instead of a caller buffer
+  nep_system s;
+  s.N = n_atoms;
+  for (int c = 0; c < 3; ++c) s.box[c] = box[c];
+  s.capR = cap_radial;
+  s.capA = cap_angular;
+  s.model[0].hp = model->hp;  // hyperparameters only: the parameters are read from *model
+  s.model[0].D = model->D;
+  s.model[0].n_params = model->n_params;
+  s.has_model[0] = true;
+  s.n_types = model->hp.n_types;
+  s.max_ncell = max_cells(box, model->hp.rc_radial);
+  const int64_t np[2] = {model->n_params, 0};
+  const int HD[2] = {model->hp.n_hidden * model->D, 0};
+  if (layout(&s, nullptr, n_atoms, cap_radial, cap_angular, s.max_ncell, np, HD) > kNoallocScratchBytes)
+    return NEP_ERR_TOO_LARGE;
+  if (hipGetDevice(&s.device) != hipSuccess) return NEP_ERR_HIP;
+  void* ws = nullptr;
+  int st = noalloc_scratch(s.device, &ws);
+  if (st) return st;
+  layout(&s, (char*)ws, n_atoms, cap_radial, cap_angular, s.max_ncell, np, HD);
+  s.st = (hipStream_t)hip_stream;
+  if ((st = upload_model(&s, 0, *model))) return st;
+  if (!eval_supported(s.mdev[0])) return NEP_ERR_UNSUPPORTED;
+  for (int t = 0; t < kMaxTypes; ++t) {  // masses do not enter the energy or forces
+    s.mt.mass[t] = 1.0;
+    s.mt.inv_mxi[t] = 1.0 / kXi;
+  }
+  // state (device arrays in the caller's order), lists with skin, evaluation
+  const CellGrid g = make_grid(s.box, model->hp.rc_radial);
+  HIPCHK2(launch_zero_i32(s.flags, FLAG_COUNT, s.st));
+  HIPCHK2(launch_state_in(n_atoms, x, nullptr, types, s.n_types, g, s.x, s.v, s.type, s.perm, s.rec, s.flags, s.st));
+  int32_t f[FLAG_COUNT];
+  if ((st = read_flags(&s, f))) return st;
+  if (f[FLAG_TYPE]) return NEP_ERR_TYPE;
+  if (f[FLAG_NONFINITE]) return NEP_ERR_NONFINITE;
+  s.have_state = true;
+  if ((st = nep_build_neighbors(&s, skin))) return st;
+  return nep_compute_energy_forces_virial(&s, 0, precision, energy, virial9, forces, per_atom_energy, 1);
+}
 
 }  // extern "C"

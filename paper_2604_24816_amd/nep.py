@@ -41,7 +41,7 @@ EXPORTED = [
     "nep_train_forward", "nep_train_backward", "nep_train_forward_params", "nep_train_backward_params",
     "nep_adam_update",
     "nep_surrogate_error", "nep_status_string", "nep_last_error", "nep_profile", "nep_profile_read",
-    "nep_pair_counts",
+    "nep_pair_counts", "nep_compute_energy_forces_virial_noalloc",
 ]
 
 
@@ -100,6 +100,7 @@ def load_library(path: str = LIB_PATH):
         "nep_profile": [vp, i32],
         "nep_profile_read": [vp, vp, vp],
         "nep_pair_counts": [vp, vp],
+        "nep_compute_energy_forces_virial_noalloc": [vp, i64, vp, i32, i32, f64, vp, vp, i32, vp, vp, vp, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -424,3 +425,37 @@ def network_params(hp: inputs.HParams, params: np.ndarray) -> np.ndarray:
     """The network block (W0, b0, w1, b1) of a packed parameter vector, as one array."""
     b = inputs.unpack(hp, params)
     return np.concatenate([b["W0"], b["b0"], b["w1"], b["b1"]])
+
+
+def compute_energy_forces_virial_noalloc(model: NEPModel, x: torch.Tensor, types: torch.Tensor, box,
+                                         cap_radial: int = 160, cap_angular: int = 96, skin: float = 1.0,
+                                         precision="fp32", forces: Optional[torch.Tensor] = None,
+                                         per_atom_energy: Optional[torch.Tensor] = None,
+                                         stream: Optional[torch.cuda.Stream] = None):
+    """Energy, virial [3][3] and, into the given device tensors, forces [N][3] and per-atom
+    energies [N] (FP64) of one configuration through the library's allocation-free call:
+    x [N][3] FP64 and types [N] int32 are device tensors; the library's fixed device scratch
+    replaces a system workspace. Returns (E, W)."""
+    lib = load_library()
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64 and x.dim() == 2
+            and x.shape[1] == 3 and x.is_contiguous()):
+        raise ValueError("x must be a contiguous [N][3] float64 device tensor")
+    n = x.shape[0]
+    if not (isinstance(types, torch.Tensor) and types.is_cuda and types.dtype == torch.int32
+            and tuple(types.shape) == (n,) and types.is_contiguous()):
+        raise ValueError("types must be a contiguous [N] int32 device tensor")
+    for t, shape, name in ((forces, (n, 3), "forces"), (per_atom_energy, (n,), "per_atom_energy")):
+        if t is not None and not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                                  and tuple(t.shape) == shape and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {list(shape)} float64 device tensor")
+    b = np.ascontiguousarray(box, dtype=np.float64).reshape(3)
+    E = ctypes.c_double()
+    W = np.zeros(9)
+    st_obj = stream if stream is not None else torch.cuda.current_stream(x.device)
+    st = lib.nep_compute_energy_forces_virial_noalloc(
+        model.handle, n, _np_ptr(b), int(cap_radial), int(cap_angular), float(skin), _t_ptr(x), _t_ptr(types),
+        _prec(precision), ctypes.byref(E), _np_ptr(W), _t_ptr(forces) if forces is not None else None,
+        _t_ptr(per_atom_energy) if per_atom_energy is not None else None, ctypes.c_void_p(st_obj.cuda_stream))
+    if st != 0:
+        raise NEPError(st, lib.nep_status_string(st).decode())
+    return E.value, W.reshape(3, 3)
