@@ -72,7 +72,7 @@ KERNEL_GROUPS = (("desc_net", "full", "desc", "k_desc_net<full>"),
                  ("desc_net_surrogate", "surrogate", "desc", "k_desc_net<surrogate>"),
                  ("force_surrogate", "surrogate", "force", "k_force<surrogate>"))
 
-FORCE_SOURCES = ("nep_eval.hip", "nep_kernels.h", "nep_poly.h", "nep_common.h")
+FORCE_SOURCES = ("nep_eval.hip", "nep_kernels.h", "nep_poly.h", "nep_common.h", "nep_fast.h")
 
 
 def workload_tag(cells):

@@ -101,19 +101,27 @@ struct HaloTables {
   int32_t* off;    // [ntiles][kHaloCellsMax + 1] local offset of each halo cell
 };
 
-// Per-atom neighbour record: 64 bytes ([N][4] 16-byte words) holding what a
-// neighbour's pair terms read, so a gather touches one half cache line.
-// word 0 = (x, y) FP64; word 1 = (z FP64, w0, w1); word 2 = (w2 .. w5);
-// word 3 = (w6, w7, w8, 0). The w are written by the descriptor kernel: for one
-// species w_k = sum_n (dU/dq_n) c_nk (k < 9), with several species w_n = dU/dq_n.
-__device__ __forceinline__ void rec_put_pos(uint4* rec, int64_t i, double x, double y, double z) {
-  const uint64_t bx = __builtin_bit_cast(uint64_t, x), by = __builtin_bit_cast(uint64_t, y),
-                 bz = __builtin_bit_cast(uint64_t, z);
-  rec[4 * i] = make_uint4((uint32_t)bx, (uint32_t)(bx >> 32), (uint32_t)by, (uint32_t)(by >> 32));
-  reinterpret_cast<uint2*>(rec + 4 * i + 1)[0] = make_uint2((uint32_t)bz, (uint32_t)(bz >> 32));
+// Per-atom neighbour record: 64 bytes ([N][4] 16-byte words) holding what a neighbour's
+// pair terms read, so a gather touches as few 16-byte words as possible.
+// word 0 = (qx, qy, qz, v): the position as three 32-bit fractions of the box,
+//   q = round(x 2^32 / L) modulo 2^32, so that the two's-complement difference of two
+//   atoms' fractions is their minimum-image separation in units of L / 2^32 (the
+//   quantum: 1.7e-7 A in a 723 A box); and one radial force coefficient;
+// words 1, 2 = eight more radial force coefficients; word 3 is not read.
+// The FP64 positions stay in the [3][N] position array (integration, list build, ZBL).
+// The coefficients are written by the descriptor kernel: for one species
+// v = w_0 + sum_k w_k and w_1..w_8 (w_k = sum_n (dU/dq_n) c_nk), with several species
+// dU/dq_0..dU/dq_4 in v, w_1..w_4.
+__host__ __device__ inline double box_quantum(double L) { return L * (1.0 / 4294967296.0); }
+__device__ __forceinline__ uint32_t box_fraction(double x, double L) {
+  const double f = rint(x * (4294967296.0 / L));  // in [0, 2^32] for x in [0, L)
+  return (uint32_t)(uint64_t)f;                   // 2^32, the image of 0, wraps to 0
 }
-__device__ __forceinline__ double rec_f64(uint32_t lo, uint32_t hi) {
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+__device__ __forceinline__ void rec_put_pos(uint4* rec, int64_t i, double x, double y, double z,
+                                            const double* box) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(rec + 4 * i);
+  reinterpret_cast<uint2*>(w)[0] = make_uint2(box_fraction(x, box[0]), box_fraction(y, box[1]));
+  w[2] = box_fraction(z, box[2]);
 }
 
 // Outputs of the list build.

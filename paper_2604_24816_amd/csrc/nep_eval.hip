@@ -185,14 +185,13 @@ __device__ __forceinline__ float network_wave(const ModelDev& m, const float* qs
 // sum_j f_k = (sum_j f_c T_k + sum_j f_c) / 2, so a pair adds f_c and f_c T_k (k >= 1).
 // Returns the pair counts and the pairs inside the ZBL radius (zs).
 template <class S, bool MULTI>
-__device__ __forceinline__ void desc_pass(const ModelDev& m, const EvalBuffers& b, int64_t i, int ti, double xi,
-                                          double yi, double zi, double Lx, double Ly, double Lz, float* q, float* s,
-                                          ZblSeenFor<MULTI>& zs, int& nr, int& na) {
+__device__ __forceinline__ void desc_pass(const ModelDev& m, const EvalBuffers& b, int64_t i, int ti, QPos qi,
+                                          float* q, float* s, ZblSeenFor<MULTI>& zs, int& nr, int& na) {
   constexpr int NR = S::NR, NA = S::NA, NC = S::NC, KR = S::KR, KA = S::KA;
   const int64_t N = b.N;
   const float rcR_inv = 1.f / m.rcR, rcA_inv = 1.f / m.rcA;
-  const double rcR2 = m.rcR64 * m.rcR64, rcA2 = m.rcA64 * m.rcA64;
-  const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
+  const float rcR2 = (float)(m.rcR64 * m.rcR64), rcA2 = (float)(m.rcA64 * m.rcA64), zbl2 = (float)m.zbl_o2;
+  const double hx = box_quantum(b.box[0]), hy = box_quantum(b.box[1]), hz = box_quantum(b.box[2]);
   nr = 0;
   na = 0;
   const int kR = radial_bound(b, i), kA = angular_bound(b, i);
@@ -200,9 +199,9 @@ __device__ __forceinline__ void desc_pass(const ModelDev& m, const EvalBuffers& 
 #pragma unroll
   for (int k = 0; k < KR; ++k) QT[k] = 0.f;
   // the radial term of a pair inside rc_radial
-  auto radial_term = [&](int p, int32_t j, double r2, float r) {
+  auto radial_term = [&](int p, int32_t j, float r2, float r) {
     ++nr;
-    if (r2 < m.zbl_o2) zs.add(p);
+    if (r2 < zbl2) zs.add(p);
     const RadialArg ra = radial_arg(r * rcR_inv);
     if constexpr (MULTI) {
       float g[NR];
@@ -225,13 +224,11 @@ __device__ __forceinline__ void desc_pass(const ModelDev& m, const EvalBuffers& 
   };
   // one entry: the radial term, and for the angular candidates inside rc_angular the angular one
   auto pair_both = [&](int p, int32_t j, const uint4* w) {
-    double ex, ey, ez;
-    const double r2 = pair_r2_64(rec_f64(w[0].x, w[0].y), rec_f64(w[0].z, w[0].w), rec_f64(w[1].x, w[1].y),
-                                 xi, yi, zi, Lx, Ly, Lz, iLx, iLy, iLz, ex, ey, ez);
+    float dx, dy, dz;
+    const float r2 = pair_vec_q(w[0], qi, hx, hy, hz, dx, dy, dz);
     if (!(r2 < rcR2)) return;
-    const float dx = (float)ex, dy = (float)ey, dz = (float)ez;
     float r, rinv;
-    pair_r(dx, dy, dz, r, rinv);
+    r_of_r2(r2, r, rinv);
     radial_term(p, j, r2, r);
     if (p < kA && r2 < rcA2) {
       ++na;
@@ -250,9 +247,9 @@ __device__ __forceinline__ void desc_pass(const ModelDev& m, const EvalBuffers& 
   };
   // the angular candidates are the list's prefix [0, kA)
   if constexpr (MULTI)
-    for_each_rec_span<2, S::DESC_AHEAD>(b.nbr, b.rec, N, i, 0, kR, pair_both);
+    for_each_rec_span<1, S::DESC_AHEAD>(b.nbr, b.rec, N, i, 0, kR, pair_both);
   else
-    for_each_rec_fast<2, S::DESC_AHEAD>(b.nbr, b.rec, N, i, 0, kR, pair_both);
+    for_each_rec_fast<1, S::DESC_AHEAD>(b.nbr, b.rec, N, i, 0, kR, pair_both);
   if constexpr (!MULTI) {
     const cfloat_ptr c = uniform_coeffs(m.cR);
     float Qb[KR];
@@ -289,15 +286,11 @@ __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers 
   for (int k = 0; k < NA * NC; ++k) s[k] = 0.f;
   const int ti = valid ? (MULTI ? b.type[i] : 0) : 0;
   ZblSeenFor<MULTI> zs;  // pairs inside the ZBL radius
-  double xi = 0.0, yi = 0.0, zi = 0.0;
 
   if (valid) {
-    const uint4 w0 = b.rec[4 * i], w1 = b.rec[4 * i + 1];
-    xi = rec_f64(w0.x, w0.y);
-    yi = rec_f64(w0.z, w0.w);
-    zi = rec_f64(w1.x, w1.y);
+    const uint4 w0 = b.rec[4 * i];
     int nr = 0, na = 0;
-    desc_pass<S, MULTI>(m, b, i, ti, xi, yi, zi, Lx, Ly, Lz, q, s, zs, nr, na);
+    desc_pass<S, MULTI>(m, b, i, ti, QPos{w0.x, w0.y, w0.z}, q, s, zs, nr, na);
     b.nactR[i] = nr;
     b.nactA[i] = na;
     desc_finish<S>(s, q);
@@ -312,33 +305,31 @@ __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers 
 
   if (valid) {
     {
-      // neighbour record words 1.zw, 2, 3: for one species w_k = sum_n (dU/dq_n) c_nk (k < 9)
-      // and their sum (the radial force of a pair is then a Chebyshev series in w_i + w_j),
-      // dU/dq_n otherwise
-      static_assert(S::KR <= 9, "the record holds 9 radial coefficients and their sum");
-      float t[10];
+      // neighbour record words 0.w, 1, 2: for one species v = w_0 + sum_k w_k and w_1..w_8 with
+      // w_k = sum_n (dU/dq_n) c_nk (the radial force of a pair is then a Chebyshev series in
+      // w_i + w_j), dU/dq_0..dU/dq_4 for several species
+      static_assert(S::KR == 9 && S::NR <= 5, "the record holds nine radial coefficients");
+      float t[9];
       if constexpr (MULTI) {
 #pragma unroll
-        for (int k = 0; k < 10; ++k) t[k] = k < NR ? fp[k] : 0.f;
+        for (int k = 0; k < 9; ++k) t[k] = k < NR ? fp[k] : 0.f;
       } else {
         const cfloat_ptr c = uniform_coeffs(m.cR);
         float sum = 0.f;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
           float a = 0.f;
-          if (k < S::KR) {
 #pragma unroll
-            for (int n = 0; n < NR; ++n) a = fmaf(fp[n], c[n * S::KR + k], a);
-          }
+          for (int n = 0; n < NR; ++n) a = fmaf(fp[n], c[n * S::KR + k], a);
           t[k] = a;
           sum += a;
         }
-        t[9] = sum;
+        t[0] += sum;
       }
       uint4* r = b.rec + 4 * i;
-      reinterpret_cast<float2*>(r + 1)[1] = make_float2(t[0], t[1]);
-      reinterpret_cast<float4*>(r + 2)[0] = make_float4(t[2], t[3], t[4], t[5]);
-      reinterpret_cast<float4*>(r + 3)[0] = make_float4(t[6], t[7], t[8], t[9]);
+      reinterpret_cast<float*>(r)[3] = t[0];
+      reinterpret_cast<float4*>(r + 1)[0] = make_float4(t[1], t[2], t[3], t[4]);
+      reinterpret_cast<float4*>(r + 2)[0] = make_float4(t[5], t[6], t[7], t[8]);
     }
     // 4. dU/ds_nlm = dU/dq_nl * 2 W_lm s_nlm (+ four-body part for l = 2)
     float Gd[NA * NC];
@@ -365,7 +356,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers 
     b.F[N + i] = 0.f;
     b.F[2 * N + i] = 0.f;
     // ZBL energy (half of each close pair), after the descriptors are no longer live
-    if (zs.n) zbl_center<MULTI>(m, b, i, ti, xi, yi, zi, zs, &U, nullptr, nullptr);
+    if (zs.n) zbl_center<MULTI>(m, b, i, ti, b.x[i], b.x[N + i], b.x[2 * N + i], zs, &U, nullptr, nullptr);
     b.U[i] = U;
   }
   const double e = block_sum(valid ? (double)U : 0.0, red);
@@ -441,7 +432,7 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
   const int64_t i = (int64_t)tile * kBlock + threadIdx.x;
   const bool valid = i < N;
   const bool lds = load_halo(b, tile, halo);
-  const double Lx = b.box[0], Ly = b.box[1], Lz = b.box[2];
+  const double hx = box_quantum(b.box[0]), hy = box_quantum(b.box[1]), hz = box_quantum(b.box[2]);
   const float rcR_inv = 1.f / m.rcR, rcA_inv = 1.f / m.rcA;
   float fx = 0.f, fy = 0.f, fz = 0.f;
   float w[9];
@@ -449,20 +440,19 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
   for (int k = 0; k < 9; ++k) w[k] = 0.f;
   if (valid) {
     const uint4* ri = b.rec + 4 * i;
-    const uint4 r0 = ri[0], r1 = ri[1], r2w = ri[2], r3 = ri[3];
-    const double xi = rec_f64(r0.x, r0.y), yi = rec_f64(r0.z, r0.w), zi = rec_f64(r1.x, r1.y);
+    const uint4 r0 = ri[0], r1 = ri[1], r2w = ri[2];
+    const QPos qi{r0.x, r0.y, r0.z};
     const int ti = MULTI ? b.type[i] : 0;
-    // own radial coefficients (w_k and their sum for one species, dU/dq_n for several)
-    const float wi[10] = {__uint_as_float(r1.z), __uint_as_float(r1.w), __uint_as_float(r2w.x),
-                          __uint_as_float(r2w.y), __uint_as_float(r2w.z), __uint_as_float(r2w.w),
-                          __uint_as_float(r3.x), __uint_as_float(r3.y), __uint_as_float(r3.z),
-                          __uint_as_float(r3.w)};
+    // own radial coefficients (v = w_0 + sum_k w_k and w_1..w_8 for one species, dU/dq_n for
+    // several)
+    const float wi[9] = {__uint_as_float(r0.w),  __uint_as_float(r1.x),  __uint_as_float(r1.y),
+                         __uint_as_float(r1.z),  __uint_as_float(r1.w),  __uint_as_float(r2w.x),
+                         __uint_as_float(r2w.y), __uint_as_float(r2w.z), __uint_as_float(r2w.w)};
     constexpr int KR = S::KR, KA = S::KA;
     float G[NA * NC];
 #pragma unroll
     for (int k = 0; k < NA * NC; ++k) G[k] = b.G[(int64_t)k * N + i];
-    const double rcR2 = m.rcR64 * m.rcR64, rcA2 = m.rcA64 * m.rcA64;
-    const double iLx = 1.0 / Lx, iLy = 1.0 / Ly, iLz = 1.0 / Lz;
+    const float rcR2 = (float)(m.rcR64 * m.rcR64), rcA2 = (float)(m.rcA64 * m.rcA64), zbl2 = (float)m.zbl_o2;
     const int kR = radial_bound(b, i), kA = angular_bound(b, i);
     ZblSeenFor<MULTI> zs;  // pairs inside the ZBL radius
     // One pass over the list. Radial pairs: gather, F_i += (dU_i/dr_ij + dU_j/dr_ji) along u,
@@ -473,21 +463,17 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
     // one entry: the radial term, and for the angular candidates inside rc_angular the
     // angular and four-body term, scattered into the neighbour
     auto pair_both = [&](int p, int32_t j, const uint4* rw) {
-      double ex, ey, ez;
-      const double r2 = pair_r2_64(rec_f64(rw[0].x, rw[0].y), rec_f64(rw[0].z, rw[0].w),
-                                   rec_f64(rw[1].x, rw[1].y), xi, yi, zi, Lx, Ly, Lz, iLx, iLy, iLz, ex, ey,
-                                   ez);
+      float dx, dy, dz;
+      const float r2 = pair_vec_q(rw[0], qi, hx, hy, hz, dx, dy, dz);
       if (!(r2 < rcR2)) return;
-      const float dx = (float)ex, dy = (float)ey, dz = (float)ez;
       const bool ang = p < kA && r2 < rcA2;
       const int lj = (ang && lds) ? (int)b.nbrl[(int64_t)p * N + i] : 0;
       float r, rinv;
-      pair_r(dx, dy, dz, r, rinv);
+      r_of_r2(r2, r, rinv);
       const int tj = MULTI ? b.type[j] : 0;
-      const float wj[10] = {__uint_as_float(rw[1].z), __uint_as_float(rw[1].w), __uint_as_float(rw[2].x),
-                            __uint_as_float(rw[2].y), __uint_as_float(rw[2].z), __uint_as_float(rw[2].w),
-                            __uint_as_float(rw[3].x), __uint_as_float(rw[3].y), __uint_as_float(rw[3].z),
-                            __uint_as_float(rw[3].w)};
+      const float wj[9] = {__uint_as_float(rw[0].w), __uint_as_float(rw[1].x), __uint_as_float(rw[1].y),
+                           __uint_as_float(rw[1].z), __uint_as_float(rw[1].w), __uint_as_float(rw[2].x),
+                           __uint_as_float(rw[2].y), __uint_as_float(rw[2].z), __uint_as_float(rw[2].w)};
       float st;  // dU_i/dr_ij + dU_j/dr_ji along u
       if constexpr (MULTI) {
         float g[NR], dg[NR], g2[NR], dg2[NR];
@@ -505,10 +491,10 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
         const RadialArgD ra = radial_arg_d(r * rcR_inv, rcR_inv);
         float W[KR];
 #pragma unroll
-        for (int k = 0; k < KR; ++k) W[k] = wi[k] + wj[k];
-        st = radial_series_deriv<KR>(ra, W, wi[9] + wj[9]);
+        for (int k = 1; k < KR; ++k) W[k] = wi[k] + wj[k];
+        st = radial_series_deriv<KR>(ra, W, wi[0] + wj[0]);
       }
-      if (r2 < m.zbl_o2) zs.add(p);
+      if (r2 < zbl2) zs.add(p);
       const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
       fx = fmaf(st, ux, fx);
       fy = fmaf(st, uy, fy);
@@ -577,10 +563,10 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
     // of that pair term (the lists are symmetric, so the pair's other half comes from j).
     // Angular and four-body pairs (the angular prefix [0, kA) inside rc_angular): scatter
     // dU_i/dr_ij into this atom and -dU_i/dr_ij into the neighbour.
-    for_each_rec_span<4, 1>(b.nbr, b.rec, N, i, 0, kR, pair_both);
+    for_each_rec_span<3, 1>(b.nbr, b.rec, N, i, 0, kR, pair_both);
     if (zs.n) {
       float f[3] = {fx, fy, fz};
-      zbl_center<MULTI>(m, b, i, ti, xi, yi, zi, zs, nullptr, f, w);
+      zbl_center<MULTI>(m, b, i, ti, b.x[i], b.x[N + i], b.x[2 * N + i], zs, nullptr, f, w);
       fx = f[0];
       fy = f[1];
       fz = f[2];

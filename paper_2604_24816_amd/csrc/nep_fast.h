@@ -129,13 +129,14 @@ __device__ __forceinline__ void radial_g_dg_fast(const RadialArgD& ra, CP h, flo
   }
 }
 
-// d/dr sum_k W_k f_k(r) for f_k = f_c (T_k + 1) / 2, given Wsum = sum_k W_k:
-//   sum_k W_k f_k = f_c (C(x) + Wsum) / 2 with the Chebyshev series C(x) = sum_k W_k T_k(x),
-// so the derivative is (f_c' (C + Wsum) + f_c x' C'(x)) / 2. C and C' by Clenshaw's
-// recurrence b_k = W_k + 2x b_{k+1} - b_{k+2} and its x-derivative
-// d_k = 2 b_{k+1} + 2x d_{k+1} - d_{k+2}: C = W_0 + x b_1 - b_2, C' = b_1 + x d_1 - d_2.
+// d/dr sum_k W_k f_k(r) for f_k = f_c (T_k + 1) / 2, given W_1..W_{K-1} and
+// V = W_0 + sum_k W_k: sum_k W_k f_k = f_c (C(x) + sum_k W_k) / 2 with the Chebyshev series
+// C(x) = sum_k W_k T_k(x), so the derivative is (f_c' (C + sum_k W_k) + f_c x' C'(x)) / 2.
+// C and C' by Clenshaw's recurrence b_k = W_k + 2x b_{k+1} - b_{k+2} (k >= 1) and its
+// x-derivative d_k = 2 b_{k+1} + 2x d_{k+1} - d_{k+2}: C = W_0 + x b_1 - b_2, so
+// C + sum_k W_k = V + x b_1 - b_2, and C' = b_1 + x d_1 - d_2 (W_0 enters only through V).
 template <int K>
-__device__ __forceinline__ float radial_series_deriv(const RadialArgD& ra, const float* W, float Wsum) {
+__device__ __forceinline__ float radial_series_deriv(const RadialArgD& ra, const float* W, float V) {
   const float x2 = ra.x + ra.x;
   float b1 = 0.f, b2 = 0.f, d1 = 0.f, d2 = 0.f;
 #pragma unroll
@@ -147,9 +148,31 @@ __device__ __forceinline__ float radial_series_deriv(const RadialArgD& ra, const
     d2 = d1;
     d1 = dk;
   }
-  const float C = fmaf(ra.x, b1, W[0] - b2);
+  const float Cs = fmaf(ra.x, b1, V - b2);
   const float Cp = fmaf(ra.x, d1, b1 - d2);
-  return 0.5f * fmaf(ra.dfc, C + Wsum, (ra.fc * ra.dx) * Cp);
+  return 0.5f * fmaf(ra.dfc, Cs, (ra.fc * ra.dx) * Cp);
+}
+
+// ---------------------------------------------------------------- pair vectors
+// Pair vector x_j - x_i of a list neighbour from the records' 32-bit box fractions (see
+// the neighbour record): the two's-complement difference is the minimum image in units of
+// the quantum; it is converted to FP64 exactly, scaled by the quantum (h = L / 2^32) and
+// rounded once to FP32. Returns r^2 in FP32.
+struct QPos {
+  uint32_t x, y, z;
+};
+__device__ __forceinline__ float pair_vec_q(const uint4& wj, const QPos& qi, double hx, double hy, double hz,
+                                            float& dx, float& dy, float& dz) {
+  dx = (float)((double)(int32_t)(wj.x - qi.x) * hx);
+  dy = (float)((double)(int32_t)(wj.y - qi.y) * hy);
+  dz = (float)((double)(int32_t)(wj.z - qi.z) * hz);
+  return fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+}
+
+// r and 1/r from an FP32 r^2 (hardware reciprocal square root, 1 ulp).
+__device__ __forceinline__ void r_of_r2(float r2, float& r, float& rinv) {
+  rinv = __builtin_amdgcn_rsqf(r2);
+  r = r2 * rinv;
 }
 
 // ---------------------------------------------------------------- neighbour loops

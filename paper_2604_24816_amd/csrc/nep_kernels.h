@@ -376,10 +376,9 @@ __device__ __forceinline__ void zbl_center(const ModelDev& m, const EvalBuffers&
   for (int q = 0; q < kR; ++q) {
     const int p = all ? q : (int)((seen.slots >> (16 * q)) & 0xffffu);
     const int32_t j = b.nbr[(int64_t)p * N + i];
-    const uint4 w0 = b.rec[4 * (int64_t)j], w1 = b.rec[4 * (int64_t)j + 1];
-    const double ex = min_image(rec_f64(w0.x, w0.y) - xi, Lx);
-    const double ey = min_image(rec_f64(w0.z, w0.w) - yi, Ly);
-    const double ez = min_image(rec_f64(w1.x, w1.y) - zi, Lz);
+    const double ex = min_image(b.x[j] - xi, Lx);
+    const double ey = min_image(b.x[N + j] - yi, Ly);
+    const double ez = min_image(b.x[2 * N + j] - zi, Lz);
     const double r2 = ex * ex + ey * ey + ez * ez;
     if (!(r2 < m.zbl_o2)) continue;
     const double r = sqrt(r2);
@@ -423,12 +422,14 @@ __device__ __forceinline__ void desc_accumulate(const ModelDev& m, const EvalBuf
 #pragma unroll
   for (int k = 0; k < S::KR; ++k) Qb[k] = 0.f;
   // one pass over the list: radial terms for every pair inside rc_radial, angular
-  // terms for the pairs of the angular prefix inside rc_angular
-  for_each_rec<2, S::DESC_AHEAD>(b.nbr, b.rec, N, i, kR, [&](int p, int32_t j, const uint4* w) {
+  // terms for the pairs of the angular prefix inside rc_angular; FP64 positions from
+  // the position array (these kernels serve training, not the MD step)
+  for (int p = 0; p < kR; ++p) {
+    const int32_t j = b.nbr[(int64_t)p * N + i];
     double ex, ey, ez;
-    const double r2 = pair_r2_64(rec_f64(w[0].x, w[0].y), rec_f64(w[0].z, w[0].w), rec_f64(w[1].x, w[1].y),
-                                 xi, yi, zi, Lx, Ly, Lz, iLx, iLy, iLz, ex, ey, ez);
-    if (!(r2 < rcR2)) return;
+    const double r2 = pair_r2_64(b.x[j], b.x[N + j], b.x[2 * N + j], xi, yi, zi, Lx, Ly, Lz, iLx, iLy, iLz, ex,
+                                 ey, ez);
+    if (!(r2 < rcR2)) continue;
     const float dx = (float)ex, dy = (float)ey, dz = (float)ez;
     ++nr;
     float r, rinv;
@@ -458,7 +459,7 @@ __device__ __forceinline__ void desc_accumulate(const ModelDev& m, const EvalBuf
         for (int n = 0; n < NA; ++n) s[n * NC + lm] = fmaf(g[n], P, s[n * NC + lm]);
       });
     }
-  });
+  }
   if constexpr (!MULTI) {
     const cfloat_ptr c = uniform_coeffs(cR);
 #pragma unroll

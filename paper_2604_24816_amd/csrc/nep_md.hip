@@ -52,7 +52,7 @@ __global__ void k_kick_drift(int64_t N, double dt, CellGrid g, const float* __re
     const double d = min_image(xx - xb[c * N + p], g.box[c]);
     d2 += d * d;
   }
-  rec_put_pos(rec, p, xn[0], xn[1], xn[2]);
+  rec_put_pos(rec, p, xn[0], xn[1], xn[2], g.box);
   if (!(d2 <= half_skin2)) flags[FLAG_REBUILD] = 1;  // also catches NaN
   if (!(d2 == d2)) d2 = 1e300;
   }
@@ -257,7 +257,7 @@ __global__ void k_state_in(int64_t N, const double* __restrict__ xa, const doubl
     if (!isfinite(vv)) flags[FLAG_NONFINITE] = 1;
     v[c * N + p] = vv;
   }
-  rec_put_pos(rec, p, xn[0], xn[1], xn[2]);
+  rec_put_pos(rec, p, xn[0], xn[1], xn[2], g.box);
   const int t = tin[p];
   if (t < 0 || t >= n_types) flags[FLAG_TYPE] = 1;
   type[p] = (t < 0 || t >= n_types) ? 0 : t;

@@ -168,7 +168,7 @@ __global__ void k_permute(int64_t N, const int32_t* __restrict__ src, const int3
 __global__ void k_copy_back(int64_t N, const double* __restrict__ x2, const double* __restrict__ v2,
                             const int32_t* __restrict__ type2, const int32_t* __restrict__ perm2,
                             double* __restrict__ x, double* __restrict__ v, int32_t* __restrict__ type,
-                            int32_t* __restrict__ perm, uint4* __restrict__ rec,
+                            int32_t* __restrict__ perm, uint4* __restrict__ rec, CellGrid g,
                             const int32_t* __restrict__ flags) {
   if (flags[FLAG_REBUILD] == 0) return;
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -179,7 +179,7 @@ __global__ void k_copy_back(int64_t N, const double* __restrict__ x2, const doub
     x[c * N + p] = xn[c];
     v[c * N + p] = v2[c * N + p];
   }
-  rec_put_pos(rec, p, xn[0], xn[1], xn[2]);
+  rec_put_pos(rec, p, xn[0], xn[1], xn[2], g.box);
   type[p] = type2[p];
   perm[p] = perm2[p];
 }
@@ -338,11 +338,10 @@ constexpr int kEdgesTwo = kMaxBins - 1;
 // minimum-image rule itself when some dimension has fewer cells (MINIMG);
 // r^2 = (dx*dx + dy*dy) + dz*dz without FMA.
 template <bool MINIMG>
-__device__ __forceinline__ double cand_r2(const uint4* __restrict__ rec, int64_t q, double xi, double yi, double zi,
-                                          double sx, double sy, double sz, const CellGrid& g) {
+__device__ __forceinline__ double cand_r2(const double* __restrict__ x, int64_t N, int64_t q, double xi, double yi,
+                                          double zi, double sx, double sy, double sz, const CellGrid& g) {
 #pragma clang fp contract(off)
-  const uint4 w0 = rec[4 * q], w1 = rec[4 * q + 1];
-  double dx = rec_f64(w0.x, w0.y) - xi, dy = rec_f64(w0.z, w0.w) - yi, dz = rec_f64(w1.x, w1.y) - zi;
+  double dx = x[q] - xi, dy = x[N + q] - yi, dz = x[2 * N + q] - zi;
   if constexpr (MINIMG) {
     dx = g.nc[0] < 3 ? min_image(dx, g.box[0]) : dx + sx;
     dy = g.nc[1] < 3 ? min_image(dy, g.box[1]) : dy + sy;
@@ -362,13 +361,13 @@ __device__ __forceinline__ double cand_r2(const uint4* __restrict__ rec, int64_t
 // Candidates of one stencil cell, four at a time (their positions are loaded
 // together before any is tested).
 template <bool MINIMG, class Visit>
-__device__ __forceinline__ void scan_cell(const uint4* __restrict__ rec, int64_t N, int q0, int q1, int64_t p,
+__device__ __forceinline__ void scan_cell(const double* __restrict__ x, int64_t N, int q0, int q1, int64_t p,
                                           double xi, double yi, double zi, double sx, double sy, double sz,
                                           const CellGrid& g, double cut2, Visit&& visit) {
   for (int q = q0; q < q1; q += 4) {
     double r2[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) r2[u] = cand_r2<MINIMG>(rec, q + u < q1 ? q + u : q1 - 1, xi, yi, zi, sx, sy, sz, g);
+    for (int u = 0; u < 4; ++u) r2[u] = cand_r2<MINIMG>(x, N, q + u < q1 ? q + u : q1 - 1, xi, yi, zi, sx, sy, sz, g);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
       if (q + u < q1 && q + u != p && r2[u] < cut2) visit(q + u, r2[u]);
@@ -422,7 +421,7 @@ __device__ __forceinline__ void stage_flush16(const uint32_t* st, uint4* col, in
 // With MARKED, only the atoms that k_build_cells left to it (cnt = -1) are built.
 template <bool MINIMG, int NE, bool MARKED = false>
 __global__ void __launch_bounds__(kBlock)
-k_build_lists(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_t* __restrict__ start,
+k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t* __restrict__ start,
               const int32_t* __restrict__ cell_sorted, BinEdges be, int capR, int capA, ListOut lo_,
               HaloTables ht, ListScratch sc, int32_t* __restrict__ flags) {
   if (flags[FLAG_REBUILD] == 0) return;
@@ -434,8 +433,7 @@ k_build_lists(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_
   const int hcells = ht.info[4 * tile + 0];
   lo_.selfl[p] = hok ? (uint16_t)halo_index(ht, tile, hcells, (int)p) : kNoLocal;
   const double cut2 = be.e2[be.nbins - 1];
-  const uint4 r0w = rec[4 * p], r1w = rec[4 * p + 1];
-  const double xi = rec_f64(r0w.x, r0w.y), yi = rec_f64(r0w.z, r0w.w), zi = rec_f64(r1w.x, r1w.y);
+  const double xi = x[p], yi = x[N + p], zi = x[2 * N + p];
   int cx, cy, cz;
   cell_coords(g, cell_sorted[p], cx, cy, cz);
   const int cc3[3] = {cx, cy, cz};
@@ -474,7 +472,7 @@ k_build_lists(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_
         if (q1 <= q0) continue;
         // halo-local index of sorted atom q is loc0 + q (cells are contiguous in the halo)
         const int loc0 = hok ? halo_index(ht, tile, hcells, q0) - q0 : 0;
-        scan_cell<MINIMG>(rec, N, q0, q1, p, xi, yi, zi, sx, sy, sz, g, cut2, [&](int q, double r2) {
+        scan_cell<MINIMG>(x, N, q0, q1, p, xi, yi, zi, sx, sy, sz, g, cut2, [&](int q, double r2) {
           if (n < capR) {
             sq[n % kStage] = (uint32_t)q | ((uint32_t)bin_of<NE>(r2, be) << 28);
             sl[n % kStage] = hok ? (uint32_t)(loc0 + q) : (uint32_t)kNoLocal;
@@ -511,7 +509,7 @@ constexpr int kCellQueue = 128;  // accepted candidates queued per wavefront
 
 template <int NE>
 __global__ void __launch_bounds__(kBlock)
-k_build_cells(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_t* __restrict__ start,
+k_build_cells(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t* __restrict__ start,
               BinEdges be, int capR, ListOut lo_, HaloTables ht, ListScratch sc, int32_t* __restrict__ flags) {
 #pragma clang fp contract(off)
   if (flags[FLAG_REBUILD] == 0) return;
@@ -575,10 +573,9 @@ k_build_cells(int64_t N, CellGrid g, const uint4* __restrict__ rec, const int32_
 #pragma unroll
     for (int m = 1; m < 27; ++m) sidx += k >= cum[m] ? 1 : 0;
     const int q = cq0[sidx] + (k - cum[sidx]);
-    const uint4 w0 = rec[4 * (int64_t)q], w1 = rec[4 * (int64_t)q + 1];
-    X[k] = rec_f64(w0.x, w0.y);
-    Y[k] = rec_f64(w0.z, w0.w);
-    Z[k] = rec_f64(w1.x, w1.y);
+    X[k] = x[q];
+    Y[k] = x[N + q];
+    Z[k] = x[2 * N + q];
     Q[k] = q;
     C[k] = (uint8_t)sidx;
   }
@@ -888,7 +885,7 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, const BinEdges& be, int 
   hipLaunchKernelGGL(k_permute, dim3(nb), dim3(kBlock), 0, st, N, src, cellid, x, v, type, perm,
                      x_alt, v_alt, type_alt, perm_alt, x_build, cell_sorted, flags);
   hipLaunchKernelGGL(k_copy_back, dim3(nb), dim3(kBlock), 0, st, N, x_alt, v_alt, type_alt, perm_alt,
-                     x, v, type, perm, rec, flags);
+                     x, v, type, perm, rec, g, flags);
   hipLaunchKernelGGL(k_halo_tables, dim3(nb), dim3(kBlock), 0, st, N, g, cell_sorted, cell_start, ht, flags);
   // the minimum-image rule inside the candidate loop only for boxes with fewer than
   // three cells along some dimension
@@ -896,15 +893,15 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, const BinEdges& be, int 
   const bool one = be.nbins - 1 <= kEdgesOne;
   if (small) {
     auto kern = one ? k_build_lists<true, kEdgesOne> : k_build_lists<true, kEdgesTwo>;
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, N, g, rec, cell_start, cell_sorted, be, capR, capA,
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, N, g, x, cell_start, cell_sorted, be, capR, capA,
                        lout, ht, sc, flags);
   } else {
     auto cells = one ? k_build_cells<kEdgesOne> : k_build_cells<kEdgesTwo>;
-    hipLaunchKernelGGL(cells, dim3(ncell), dim3(kBlock), 0, st, N, g, rec, cell_start, be, capR, lout, ht, sc,
+    hipLaunchKernelGGL(cells, dim3(ncell), dim3(kBlock), 0, st, N, g, x, cell_start, be, capR, lout, ht, sc,
                        flags);
     // atoms of cells whose stencil did not fit in LDS
     auto rest = one ? k_build_lists<false, kEdgesOne, true> : k_build_lists<false, kEdgesTwo, true>;
-    hipLaunchKernelGGL(rest, dim3(nb), dim3(kBlock), 0, st, N, g, rec, cell_start, cell_sorted, be, capR, capA,
+    hipLaunchKernelGGL(rest, dim3(nb), dim3(kBlock), 0, st, N, g, x, cell_start, cell_sorted, be, capR, capA,
                        lout, ht, sc, flags);
   }
   const int place_groups = grid_blocks(N, kPlaceAtoms);
