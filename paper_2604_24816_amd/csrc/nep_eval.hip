@@ -178,6 +178,11 @@ __device__ __forceinline__ float network_wave(const ModelDev& m, const float* qs
 }
 
 // ------------------------------------------------------------------------ descriptors
+// The main loops only count the pairs inside the ZBL radius; a center with any visits its
+// whole radial list again afterwards (zbl_center), which keeps the loops free of slot
+// bookkeeping for the common case of no close pairs.
+using EvalZbl = ZblSeen<0>;
+
 // Radial descriptors q[0..NR) and angular accumulators s[NA][NC] of center i over the
 // pairs inside the true cutoffs, all channels in one pass over the list with skin
 // (geometry computed once per pair and reused for every n). One species: the radial
@@ -186,11 +191,13 @@ __device__ __forceinline__ float network_wave(const ModelDev& m, const float* qs
 // Returns the pair counts and the pairs inside the ZBL radius (zs).
 template <class S, bool MULTI>
 __device__ __forceinline__ void desc_pass(const ModelDev& m, const EvalBuffers& b, int64_t i, int ti, QPos qi,
-                                          float* q, float* s, ZblSeenFor<MULTI>& zs, int& nr, int& na) {
+                                          float* q, float* s, EvalZbl& zs, int& nr, int& na) {
   constexpr int NR = S::NR, NA = S::NA, NC = S::NC, KR = S::KR, KA = S::KA;
   const int64_t N = b.N;
   const float rcR_inv = 1.f / m.rcR, rcA_inv = 1.f / m.rcA;
+  const CutConst cutR = cut_const(m.rcR), cutA = cut_const(m.rcA);
   const float rcR2 = (float)(m.rcR64 * m.rcR64), rcA2 = (float)(m.rcA64 * m.rcA64), zbl2 = (float)m.zbl_o2;
+  const bool zbl_on = m.zbl_o2 > 0.0;
   const double hx = box_quantum(b.box[0]), hy = box_quantum(b.box[1]), hz = box_quantum(b.box[2]);
   nr = 0;
   na = 0;
@@ -201,8 +208,7 @@ __device__ __forceinline__ void desc_pass(const ModelDev& m, const EvalBuffers& 
   // the radial term of a pair inside rc_radial
   auto radial_term = [&](int p, int32_t j, float r2, float r) {
     ++nr;
-    if (r2 < zbl2) zs.add(p);
-    const RadialArg ra = radial_arg(r * rcR_inv);
+    zs.n += (zbl_on && r2 < zbl2) ? 1 : 0;
     if constexpr (MULTI) {
       float g[NR];
       radial_g<NR, KR>(r, rcR_inv, m.cR + (ti * m.T + b.type[j]) * NR * KR, g);
@@ -210,6 +216,7 @@ __device__ __forceinline__ void desc_pass(const ModelDev& m, const EvalBuffers& 
       for (int n = 0; n < NR; ++n) q[n] += g[n];
     } else {
       // T_k by the recurrence T_{k+1} = 2x T_k - T_{k-1}
+      const RadialGeo ra = radial_geo<false>(r, cutR);
       Qf += ra.fc;
       const float x2 = ra.x + ra.x;
       float Tm = 1.f, T = ra.x;
@@ -236,7 +243,7 @@ __device__ __forceinline__ void desc_pass(const ModelDev& m, const EvalBuffers& 
       if constexpr (MULTI) {
         radial_g<NA, KA>(r, rcA_inv, m.cA + (ti * m.T + b.type[j]) * NA * KA, g);
       } else {
-        const RadialArg ra = radial_arg(r * rcA_inv);
+        const RadialGeo ra = radial_geo<false>(r, cutA);
         radial_g_fast<NA, KA>(ra.fc, ra.x, uniform_coeffs(m.hA), g);
       }
       for_each_poly<NC>(dx * rinv, dy * rinv, dz * rinv, [&](int lm, float P) {
@@ -285,7 +292,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers 
 #pragma unroll
   for (int k = 0; k < NA * NC; ++k) s[k] = 0.f;
   const int ti = valid ? (MULTI ? b.type[i] : 0) : 0;
-  ZblSeenFor<MULTI> zs;  // pairs inside the ZBL radius
+  EvalZbl zs;  // pairs inside the ZBL radius
 
   if (valid) {
     const uint4 w0 = b.rec[4 * i];
@@ -434,6 +441,11 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
   const bool lds = load_halo(b, tile, halo);
   const double hx = box_quantum(b.box[0]), hy = box_quantum(b.box[1]), hz = box_quantum(b.box[2]);
   const float rcR_inv = 1.f / m.rcR, rcA_inv = 1.f / m.rcA;
+  const CutConst cutR = cut_const(m.rcR), cutA = cut_const(m.rcA);
+  const float kXR = -0.25f * kPiF * cutR.rc_inv;  // X = kXR Z for the radial series (one species)
+  const float kDA = -0.5f * kPiF * cutA.rc_inv;   // f_c' = kDA c (angular cutoff)
+  const float kYA = 4.f * cutA.rc_inv;            // x' = kYA y
+  const bool zbl_on = m.zbl_o2 > 0.0;
   float fx = 0.f, fy = 0.f, fz = 0.f;
   float w[9];
 #pragma unroll
@@ -454,14 +466,13 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
     for (int k = 0; k < NA * NC; ++k) G[k] = b.G[(int64_t)k * N + i];
     const float rcR2 = (float)(m.rcR64 * m.rcR64), rcA2 = (float)(m.rcA64 * m.rcA64), zbl2 = (float)m.zbl_o2;
     const int kR = radial_bound(b, i), kA = angular_bound(b, i);
-    ZblSeenFor<MULTI> zs;  // pairs inside the ZBL radius
-    // One pass over the list. Radial pairs: gather, F_i += (dU_i/dr_ij + dU_j/dr_ji) along u,
-    // with the neighbour's radial coefficients read from its record; the virial takes half
-    // of that pair term (the lists are symmetric, so the pair's other half comes from j).
-    // Angular and four-body pairs (the angular prefix inside rc_angular): scatter
-    // dU_i/dr_ij into this atom and -dU_i/dr_ij into the neighbour.
-    // one entry: the radial term, and for the angular candidates inside rc_angular the
-    // angular and four-body term, scattered into the neighbour
+    EvalZbl zs;  // pairs inside the ZBL radius
+    // One entry: the radial term by gather, F_i += (dU_i/dr_ij + dU_j/dr_ji) along u, with
+    // the neighbour's radial coefficients read from its record, the virial taking half of
+    // that pair term (the lists are symmetric, so the pair's other half comes from j); and
+    // for the angular candidates (the list prefix [0, kA)) inside rc_angular the angular
+    // and four-body term dU_i/dr_ij, added to this atom and scattered, negated, into the
+    // neighbour.
     auto pair_both = [&](int p, int32_t j, const uint4* rw) {
       float dx, dy, dz;
       const float r2 = pair_vec_q(rw[0], qi, hx, hy, hz, dx, dy, dz);
@@ -474,7 +485,7 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
       const float wj[9] = {__uint_as_float(rw[0].w), __uint_as_float(rw[1].x), __uint_as_float(rw[1].y),
                            __uint_as_float(rw[1].z), __uint_as_float(rw[1].w), __uint_as_float(rw[2].x),
                            __uint_as_float(rw[2].y), __uint_as_float(rw[2].z), __uint_as_float(rw[2].w)};
-      float st;  // dU_i/dr_ij + dU_j/dr_ji along u
+      float sr;  // (dU_i/dr_ij + dU_j/dr_ji) / r: the pair force is sr (x_j - x_i)
       if constexpr (MULTI) {
         float g[NR], dg[NR], g2[NR], dg2[NR];
         radial_g_dg<NR, KR>(r, rcR_inv, m.cR + (ti * m.T + tj) * NR * KR, g, dg);
@@ -485,85 +496,112 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
           si = fmaf(wi[n], dg[n], si);
           sj = fmaf(wj[n], dg2[n], sj);
         }
-        st = si + sj;
+        sr = (si + sj) * rinv;
       } else {
         // one species: sum_k (w_ik + w_jk) f_k'(r)
-        const RadialArgD ra = radial_arg_d(r * rcR_inv, rcR_inv);
+        const RadialGeo ra = radial_geo<true>(r, cutR);
         float W[KR];
 #pragma unroll
         for (int k = 1; k < KR; ++k) W[k] = wi[k] + wj[k];
-        st = radial_series_deriv<KR>(ra, W, wi[0] + wj[0]);
+        sr = radial_series_z<KR>(ra, W, wi[0] + wj[0]) * (kXR * rinv);
       }
-      if (r2 < zbl2) zs.add(p);
-      const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
-      fx = fmaf(st, ux, fx);
-      fy = fmaf(st, uy, fy);
-      fz = fmaf(st, uz, fz);
+      zs.n += (zbl_on && r2 < zbl2) ? 1 : 0;
+      fx = fmaf(sr, dx, fx);
+      fy = fmaf(sr, dy, fy);
+      fz = fmaf(sr, dz, fz);
       {
-        const float hs = 0.5f * st;
+        // W_ac -= d_a (sr d_c) / 2
+        const float vs = -0.5f * sr;
         const float d[3] = {dx, dy, dz};
-        const float f[3] = {hs * ux, hs * uy, hs * uz};
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a) {
+          const float vd = vs * d[a];
 #pragma unroll
-          for (int c = 0; c < 3; ++c) w[a * 3 + c] = fmaf(-d[a], f[c], w[a * 3 + c]);
+          for (int c = 0; c < 3; ++c) w[a * 3 + c] = fmaf(vd, d[c], w[a * 3 + c]);
+        }
       }
       if (!ang) return;
-      float g[NA], dg[NA];
-      if constexpr (MULTI) {
-        radial_g_dg<NA, KA>(r, rcA_inv, m.cA + (ti * m.T + tj) * NA * KA, g, dg);
-      } else {
-        const RadialArgD rb = radial_arg_d(r * rcA_inv, rcA_inv);
-        radial_g_dg_fast<NA, KA>(rb, uniform_coeffs(m.hA), g, dg);
-      }
+      const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
       // F_ij = sum_lm [ A_lm P_lm u + B_lm (grad P_lm - l P_lm u) / r ] with
       // A_lm = sum_n G_nlm g'_n and B_lm = sum_n G_nlm g_n; the l P B terms are
       // summed per l and scaled once.
-      float sA = 0.f, vx = 0.f, vy = 0.f, vz = 0.f;
-      float sB[4] = {0.f, 0.f, 0.f, 0.f};
-      for_each_poly_grad<NC>(ux, uy, uz, [&](int lm, float P, auto px, auto py, auto pz) {
-        float A = G[lm] * dg[0], B = G[lm] * g[0];
+      float sc, vx = 0.f, vy = 0.f, vz = 0.f, vscale;
+      if constexpr (MULTI) {
+        float g[NA], dg[NA];
+        radial_g_dg<NA, KA>(r, rcA_inv, m.cA + (ti * m.T + tj) * NA * KA, g, dg);
+        float sA = 0.f;
+        float sB[4] = {0.f, 0.f, 0.f, 0.f};
+        for_each_poly_grad<NC>(ux, uy, uz, [&](int lm, float P, auto px, auto py, auto pz) {
+          float A = G[lm] * dg[0], B = G[lm] * g[0];
 #pragma unroll
-        for (int n = 1; n < NA; ++n) {
-          A = fmaf(G[n * NC + lm], dg[n], A);
-          B = fmaf(G[n * NC + lm], g[n], B);
-        }
-        sA = fmaf(P, A, sA);
-        sB[comp_l(lm) - 1] = fmaf(P, B, sB[comp_l(lm) - 1]);
-        vx = fmac(B, px, vx);
-        vy = fmac(B, py, vy);
-        vz = fmac(B, pz, vz);
-      });
-      const float lPB = fmaf(4.f, sB[3], fmaf(3.f, sB[2], fmaf(2.f, sB[1], sB[0])));
-      const float sc = fmaf(-rinv, lPB, sA);
-      const float f0 = fmaf(ux, sc, vx * rinv);
-      const float f1 = fmaf(uy, sc, vy * rinv);
-      const float f2 = fmaf(uz, sc, vz * rinv);
-      fx += f0;
-      fy += f1;
-      fz += f2;
-      if (lds) {
-        atomicAdd(&halo.F[0][lj], -f0);
-        atomicAdd(&halo.F[1][lj], -f1);
-        atomicAdd(&halo.F[2][lj], -f2);
+          for (int n = 1; n < NA; ++n) {
+            A = fmaf(G[n * NC + lm], dg[n], A);
+            B = fmaf(G[n * NC + lm], g[n], B);
+          }
+          sA = fmaf(P, A, sA);
+          sB[comp_l(lm) - 1] = fmaf(P, B, sB[comp_l(lm) - 1]);
+          vx = fmac(B, px, vx);
+          vy = fmac(B, py, vy);
+          vz = fmac(B, pz, vz);
+        });
+        const float lPB = fmaf(4.f, sB[3], fmaf(3.f, sB[2], fmaf(2.f, sB[1], sB[0])));
+        sc = fmaf(-rinv, lPB, sA);
+        vscale = rinv;
       } else {
-        unsafeAtomicAdd(&b.F[j], -f0);
-        unsafeAtomicAdd(&b.F[N + j], -f1);
-        unsafeAtomicAdd(&b.F[2 * N + j], -f2);
+        // With g_n = f_c C_n and g'_n = f_c' C_n + f_c x' D_n: B_lm = f_c E_lm and
+        // A_lm = f_c' E_lm + f_c x' H_lm for E_lm = sum_n G_nlm C_n, H_lm = sum_n G_nlm D_n,
+        // so f_c, f_c' and f_c x' are applied once to the sums over lm.
+        const RadialGeo rb = radial_geo<true>(r, cutA);
+        float Cn[NA], Dn[NA];
+        radial_cd_fast<NA, KA>(rb.x, uniform_coeffs(m.hA), Cn, Dn);
+        float sH = 0.f;
+        float sE[4] = {0.f, 0.f, 0.f, 0.f};
+        for_each_poly_grad<NC>(ux, uy, uz, [&](int lm, float P, auto px, auto py, auto pz) {
+          float E = G[lm] * Cn[0], H = G[lm] * Dn[0];
+#pragma unroll
+          for (int n = 1; n < NA; ++n) {
+            E = fmaf(G[n * NC + lm], Cn[n], E);
+            H = fmaf(G[n * NC + lm], Dn[n], H);
+          }
+          sH = fmaf(P, H, sH);
+          sE[comp_l(lm) - 1] = fmaf(P, E, sE[comp_l(lm) - 1]);
+          vx = fmac(E, px, vx);
+          vy = fmac(E, py, vy);
+          vz = fmac(E, pz, vz);
+        });
+        const float sPE = (sE[0] + sE[1]) + (sE[2] + sE[3]);
+        const float lPE = fmaf(4.f, sE[3], fmaf(3.f, sE[2], fmaf(2.f, sE[1], sE[0])));
+        const float sA = fmaf(kDA * rb.c, sPE, (rb.fc * (kYA * rb.y)) * sH);
+        vscale = rb.fc * rinv;
+        sc = fmaf(-vscale, lPE, sA);
+      }
+      // n = -dU_i/dr_ij, the force on the neighbour (sign folded into the operands)
+      const float n0 = fmaf(-ux, sc, -(vx * vscale));
+      const float n1 = fmaf(-uy, sc, -(vy * vscale));
+      const float n2 = fmaf(-uz, sc, -(vz * vscale));
+      fx -= n0;
+      fy -= n1;
+      fz -= n2;
+      if (lds) {
+        atomicAdd(&halo.F[0][lj], n0);
+        atomicAdd(&halo.F[1][lj], n1);
+        atomicAdd(&halo.F[2][lj], n2);
+      } else {
+        unsafeAtomicAdd(&b.F[j], n0);
+        unsafeAtomicAdd(&b.F[N + j], n1);
+        unsafeAtomicAdd(&b.F[2 * N + j], n2);
       }
       const float d[3] = {dx, dy, dz};
-      const float f[3] = {f0, f1, f2};
+      const float nf[3] = {n0, n1, n2};
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) w[a * 3 + c] = fmaf(-d[a], f[c], w[a * 3 + c]);
+        for (int c = 0; c < 3; ++c) w[a * 3 + c] = fmaf(d[a], nf[c], w[a * 3 + c]);
     };
-    // One pass over the list. Radial pairs: gather, F_i += (dU_i/dr_ij + dU_j/dr_ji) along u,
-    // with the neighbour's radial coefficients read from its record; the virial takes half
-    // of that pair term (the lists are symmetric, so the pair's other half comes from j).
-    // Angular and four-body pairs (the angular prefix [0, kA) inside rc_angular): scatter
-    // dU_i/dr_ij into this atom and -dU_i/dr_ij into the neighbour.
-    for_each_rec_span<3, 1>(b.nbr, b.rec, N, i, 0, kR, pair_both);
+    if constexpr (MULTI)
+      for_each_rec_span<3, 1>(b.nbr, b.rec, N, i, 0, kR, pair_both);
+    else
+      for_each_rec_fast<3, 1>(b.nbr, b.rec, N, i, 0, kR, pair_both);
     if (zs.n) {
       float f[3] = {fx, fy, fz};
       zbl_center<MULTI>(m, b, i, ti, b.x[i], b.x[N + i], b.x[2 * N + i], zs, nullptr, f, w);

@@ -40,28 +40,37 @@ __device__ __forceinline__ float taylor_cos(float p2) {
   return fmaf(a, p2, 1.f);
 }
 
-// Geometry of one pair at scaled distance t = r / r_c: f_c, and the Chebyshev argument
-// x = 2 (t - 1)^2 - 1 of the radial basis.
-struct RadialArg {
-  float fc, x;
+// Constants of one cutoff radius, uniform over a launch.
+struct CutConst {
+  float rc_inv;     // 1 / r_c rounded to FP32
+  float rc_inv_lo;  // 1 / r_c - rc_inv (the rounding error, for y below)
+  float pi_rc_inv;  // pi / r_c
 };
-__device__ __forceinline__ RadialArg radial_arg(float t) {
-  const float psi = fmaf(kPiF, t, -kHalfPiF);
-  const float s = taylor_sin(psi, psi * psi);
-  const float y = t - 1.f;
-  return {fmaf(-0.5f, s, 0.5f), fmaf(y + y, y, -1.f)};
+__device__ __forceinline__ CutConst cut_const(float rc) {
+  const float hi = 1.f / rc;
+  return {hi, (float)(1.0 / (double)rc - (double)hi), (float)(3.14159265358979323846 / (double)rc)};
 }
 
-// The same with the r-derivatives: dfc = d f_c / dr and dx = d x / dr (rc_inv = 1 / r_c).
-struct RadialArgD {
-  float fc, dfc, x, dx;
+// Geometry of one pair at distance r < r_c, t = r / r_c: f_c, the Chebyshev argument
+// x = 2 (t - 1)^2 - 1 of the radial basis, and for the r-derivatives c = sin(pi t) and
+// y = t - 1, with which d f_c / dr = -(pi / 2) c / r_c and d x / dr = 4 y / r_c.
+// psi and y are taken from r in one rounding each (r pi / r_c - pi / 2, r / r_c - 1);
+// y adds r times the rounding error of 1 / r_c, without which every y would carry the same
+// relative bias (2e-8 at r_c = 6 A) into the Chebyshev argument of every pair.
+struct RadialGeo {
+  float fc, x, c, y;
 };
-__device__ __forceinline__ RadialArgD radial_arg_d(float t, float rc_inv) {
-  const float psi = fmaf(kPiF, t, -kHalfPiF);
+template <bool DERIV>
+__device__ __forceinline__ RadialGeo radial_geo(float r, const CutConst& k) {
+  const float psi = fmaf(r, k.pi_rc_inv, -kHalfPiF);
   const float p2 = psi * psi;
-  const float s = taylor_sin(psi, p2), c = taylor_cos(p2);
-  const float y = t - 1.f;
-  return {fmaf(-0.5f, s, 0.5f), (-kHalfPiF * rc_inv) * c, fmaf(y + y, y, -1.f), (4.f * rc_inv) * y};
+  const float y = fmaf(r, k.rc_inv_lo, fmaf(r, k.rc_inv, -1.f));
+  RadialGeo g;
+  g.fc = fmaf(-0.5f, taylor_sin(psi, p2), 0.5f);
+  g.x = fmaf(y + y, y, -1.f);
+  g.y = y;
+  g.c = DERIV ? taylor_cos(p2) : 0.f;
+  return g;
 }
 
 // Derived coefficient table of one (center type, neighbour type) block of N channels
@@ -73,8 +82,8 @@ __device__ __forceinline__ RadialArgD radial_arg_d(float t, float rc_inv) {
 template <int N, int K>
 constexpr int derived_block() { return N * (2 * K - 1); }
 
-// Both run over k outermost with the recurrences rolled along, so that only the channel
-// sums and three terms of each recurrence are live.
+// g_n = f_c C_n. Runs over k outermost with the recurrence rolled along, so that only
+// the channel sums and three terms of the recurrence are live.
 template <int N, int K, class CP>
 __device__ __forceinline__ void radial_g_fast(float fc, float x, CP h, float* g) {
   float a[N];
@@ -94,25 +103,25 @@ __device__ __forceinline__ void radial_g_fast(float fc, float x, CP h, float* g)
   for (int n = 0; n < N; ++n) g[n] = fc * a[n];
 }
 
+// The channel sums C_n and D_n themselves (the caller applies f_c, f_c' and x').
 template <int N, int K, class CP>
-__device__ __forceinline__ void radial_g_dg_fast(const RadialArgD& ra, CP h, float* g, float* dg) {
-  float a[N], d[N];
+__device__ __forceinline__ void radial_cd_fast(float x, CP h, float* C, float* D) {
 #pragma unroll
   for (int n = 0; n < N; ++n) {
-    a[n] = h[n * K];                // k = 0 of C_n
-    d[n] = h[N * K + n * (K - 1)];  // k = 1 of D_n (U_0 = 1)
+    C[n] = h[n * K];                // k = 0 of C_n
+    D[n] = h[N * K + n * (K - 1)];  // k = 1 of D_n (U_0 = 1)
   }
-  const float x2 = ra.x + ra.x;
-  float Tm = 1.f, T = ra.x;  // T_{k-1}, T_k
+  const float x2 = x + x;
+  float Tm = 1.f, T = x;  // T_{k-1}, T_k
   float Um = 1.f, Uc = x2;   // U_{k-2}, U_{k-1} for the D term of index k + 1
 #pragma unroll
   for (int k = 1; k < K; ++k) {
 #pragma unroll
-    for (int n = 0; n < N; ++n) a[n] = fmaf(h[n * K + k], T, a[n]);
+    for (int n = 0; n < N; ++n) C[n] = fmaf(h[n * K + k], T, C[n]);
     if (k + 1 < K) {
       // D_n term k + 1: d_nk U_k, with U_k in Uc
 #pragma unroll
-      for (int n = 0; n < N; ++n) d[n] = fmaf(h[N * K + n * (K - 1) + k], Uc, d[n]);
+      for (int n = 0; n < N; ++n) D[n] = fmaf(h[N * K + n * (K - 1) + k], Uc, D[n]);
       const float Un = fmaf(x2, Uc, -Um);
       Um = Uc;
       Uc = Un;
@@ -121,36 +130,46 @@ __device__ __forceinline__ void radial_g_dg_fast(const RadialArgD& ra, CP h, flo
     Tm = T;
     T = Tn;
   }
-  const float fcdx = ra.fc * ra.dx;
-#pragma unroll
-  for (int n = 0; n < N; ++n) {
-    if (g) g[n] = ra.fc * a[n];
-    dg[n] = fmaf(ra.dfc, a[n], fcdx * d[n]);
-  }
 }
 
-// d/dr sum_k W_k f_k(r) for f_k = f_c (T_k + 1) / 2, given W_1..W_{K-1} and
-// V = W_0 + sum_k W_k: sum_k W_k f_k = f_c (C(x) + sum_k W_k) / 2 with the Chebyshev series
-// C(x) = sum_k W_k T_k(x), so the derivative is (f_c' (C + sum_k W_k) + f_c x' C'(x)) / 2.
+// Radial pair force of one species. The r-derivative of sum_k W_k f_k(r), for
+// f_k = f_c (T_k(x) + 1) / 2, is X = (f_c' (C + sum_k W_k) + f_c x' C'(x)) / 2 with the
+// Chebyshev series C(x) = sum_k W_k T_k(x); with f_c' and x' from the pair geometry,
+//   X = -(pi / (4 r_c)) Z,   Z = c (C + sum_k W_k) + f_c y S C'(x),   S = -8 / pi.
 // C and C' by Clenshaw's recurrence b_k = W_k + 2x b_{k+1} - b_{k+2} (k >= 1) and its
-// x-derivative d_k = 2 b_{k+1} + 2x d_{k+1} - d_{k+2}: C = W_0 + x b_1 - b_2, so
-// C + sum_k W_k = V + x b_1 - b_2, and C' = b_1 + x d_1 - d_2 (W_0 enters only through V).
+// x-derivative, carried scaled by S: e_k = 2 S b_{k+1} + 2x e_{k+1} - e_{k+2}; then
+// C = W_0 + x b_1 - b_2, C + sum_k W_k = V + x b_1 - b_2 and S C' = S b_1 + x e_1 - e_2.
+// Takes W_1..W_{K-1} and V = W_0 + sum_k W_k; returns Z. The first three steps, where
+// b_K, e_K and e_{K-1} vanish, are written out.
+constexpr float kDerivScale = -8.f / kPiF;
 template <int K>
-__device__ __forceinline__ float radial_series_deriv(const RadialArgD& ra, const float* W, float V) {
-  const float x2 = ra.x + ra.x;
-  float b1 = 0.f, b2 = 0.f, d1 = 0.f, d2 = 0.f;
-#pragma unroll
-  for (int k = K - 1; k >= 1; --k) {
-    const float bk = fmaf(x2, b1, W[k] - b2);
-    const float dk = fmaf(x2, d1, fmaf(2.f, b1, -d2));
+__device__ __forceinline__ float radial_series_z(const RadialGeo& g, const float* W, float V) {
+  static_assert(K >= 4, "three steps are written out");
+  constexpr float S2 = 2.f * kDerivScale;
+  const float x2 = g.x + g.x;
+  float b2 = W[K - 1];                 // b_{K-1}
+  float b1 = fmaf(x2, b2, W[K - 2]);   // b_{K-2}
+  float e1 = S2 * b2, e2;              // e_{K-2} (e_{K-1} = 0)
+  {
+    const float bk = fmaf(x2, b1, W[K - 3] - b2);
+    const float ek = fmaf(x2, e1, S2 * b1);
     b2 = b1;
     b1 = bk;
-    d2 = d1;
-    d1 = dk;
+    e2 = e1;
+    e1 = ek;
   }
-  const float Cs = fmaf(ra.x, b1, V - b2);
-  const float Cp = fmaf(ra.x, d1, b1 - d2);
-  return 0.5f * fmaf(ra.dfc, Cs, (ra.fc * ra.dx) * Cp);
+#pragma unroll
+  for (int k = K - 4; k >= 1; --k) {
+    const float bk = fmaf(x2, b1, W[k] - b2);
+    const float ek = fmaf(x2, e1, fmaf(S2, b1, -e2));
+    b2 = b1;
+    b1 = bk;
+    e2 = e1;
+    e1 = ek;
+  }
+  const float Cs = fmaf(g.x, b1, V - b2);
+  const float Cp = fmaf(g.x, e1, fmaf(kDerivScale, b1, -e2));
+  return fmaf(g.c, Cs, (g.fc * g.y) * Cp);
 }
 
 // ---------------------------------------------------------------- pair vectors
