@@ -42,21 +42,17 @@ __device__ __forceinline__ float taylor_cos(float p2) {
 
 // Constants of one cutoff radius, uniform over a launch.
 struct CutConst {
-  float rc_inv;     // 1 / r_c rounded to FP32
-  float rc_inv_lo;  // 1 / r_c - rc_inv (the rounding error, for y below)
-  float pi_rc_inv;  // pi / r_c
+  float rc_inv;     // 1 / r_c
+  float pi_rc_inv;  // pi / r_c (rounded once from FP64)
 };
 __device__ __forceinline__ CutConst cut_const(float rc) {
-  const float hi = 1.f / rc;
-  return {hi, (float)(1.0 / (double)rc - (double)hi), (float)(3.14159265358979323846 / (double)rc)};
+  return {1.f / rc, (float)(3.14159265358979323846 / (double)rc)};
 }
 
 // Geometry of one pair at distance r < r_c, t = r / r_c: f_c, the Chebyshev argument
 // x = 2 (t - 1)^2 - 1 of the radial basis, and for the r-derivatives c = sin(pi t) and
 // y = t - 1, with which d f_c / dr = -(pi / 2) c / r_c and d x / dr = 4 y / r_c.
-// psi and y are taken from r in one rounding each (r pi / r_c - pi / 2, r / r_c - 1);
-// y adds r times the rounding error of 1 / r_c, without which every y would carry the same
-// relative bias (2e-8 at r_c = 6 A) into the Chebyshev argument of every pair.
+// psi and y are taken from r in one rounding each (r pi / r_c - pi / 2, r / r_c - 1).
 struct RadialGeo {
   float fc, x, c, y;
 };
@@ -64,7 +60,7 @@ template <bool DERIV>
 __device__ __forceinline__ RadialGeo radial_geo(float r, const CutConst& k) {
   const float psi = fmaf(r, k.pi_rc_inv, -kHalfPiF);
   const float p2 = psi * psi;
-  const float y = fmaf(r, k.rc_inv_lo, fmaf(r, k.rc_inv, -1.f));
+  const float y = fmaf(r, k.rc_inv, -1.f);
   RadialGeo g;
   g.fc = fmaf(-0.5f, taylor_sin(psi, p2), 0.5f);
   g.x = fmaf(y + y, y, -1.f);
