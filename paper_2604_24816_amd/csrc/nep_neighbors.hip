@@ -27,6 +27,14 @@ __global__ void k_zero_f64(double* p, int64_t n) {
   if (i < n) p[i] = 0.0;
 }
 
+// Workgroups of the rebuild kernels. Every rebuild kernel is enqueued each step and
+// returns at once when no rebuild is due, so the per-atom and per-cell ones stride over a
+// capped grid (a multiple of the 8 dies, so that a workgroup stays on its die): a step
+// without a rebuild then dispatches a few thousand workgroups, not one per cell or per
+// 256 atoms.
+constexpr int kRebuildGrid = 8192;
+inline int rebuild_grid(int64_t nblocks) { return (int)(nblocks < kRebuildGrid ? nblocks : kRebuildGrid); }
+
 __device__ __forceinline__ int cell_coord(double xv, double L, int n) {
   int c = (int)(xv * ((double)n / L));
   if (c < 0) c = 0;
@@ -37,14 +45,14 @@ __device__ __forceinline__ int cell_coord(double xv, double L, int n) {
 __global__ void k_bin(int64_t N, CellGrid g, const double* __restrict__ x, int32_t* __restrict__ cellid,
                       int32_t* __restrict__ count, const int32_t* __restrict__ flags) {
   if (flags[FLAG_REBUILD] == 0) return;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= N) return;
-  const int cx = cell_coord(x[p], g.box[0], g.nc[0]);
-  const int cy = cell_coord(x[N + p], g.box[1], g.nc[1]);
-  const int cz = cell_coord(x[2 * N + p], g.box[2], g.nc[2]);
-  const int c = cell_lin(g, cx, cy, cz);
-  cellid[p] = c;
-  atomicAdd(&count[c], 1);
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
+    const int cx = cell_coord(x[p], g.box[0], g.nc[0]);
+    const int cy = cell_coord(x[N + p], g.box[1], g.nc[1]);
+    const int cz = cell_coord(x[2 * N + p], g.box[2], g.nc[2]);
+    const int c = cell_lin(g, cx, cy, cz);
+    cellid[p] = c;
+    atomicAdd(&count[c], 1);
+  }
 }
 
 // Exclusive scan, phase 1: each 256-thread block scans 1024 elements.
@@ -115,31 +123,79 @@ __global__ void k_scatter(int64_t N, const int32_t* __restrict__ cellid, const i
                           int32_t* __restrict__ src, int32_t* __restrict__ key,
                           const int32_t* __restrict__ flags) {
   if (flags[FLAG_REBUILD] == 0) return;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= N) return;
-  const int c = cellid[p];
-  const int pos = start[c] + atomicAdd(&fill[c], 1);
-  src[pos] = (int32_t)p;
-  key[pos] = perm[p];
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
+    const int c = cellid[p];
+    const int pos = start[c] + atomicAdd(&fill[c], 1);
+    src[pos] = (int32_t)p;
+    key[pos] = perm[p];
+  }
 }
 
-// Within each cell, order atoms by original id (insertion sort; cells hold tens of atoms).
-__global__ void k_cell_sort(int ncell, const int32_t* __restrict__ start, int32_t* __restrict__ key,
-                            int32_t* __restrict__ src, const int32_t* __restrict__ flags) {
+// Within each cell, order atoms by original id. One wavefront per cell: each lane holds
+// atoms of the cell, counts the cell's smaller keys (the keys are distinct original ids)
+// and moves its atom to that rank, so the result is the stable order whatever order the
+// scatter's atomics left. Cells of more than kSortMax atoms (none at metallic densities)
+// are sorted by one lane by insertion.
+constexpr int kSortMax = 256;
+constexpr int kSortWaves = kBlock / 64;
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ void __launch_bounds__(kBlock) k_cell_sort(int ncell, const int32_t* __restrict__ start,
+                                                      int32_t* __restrict__ key, int32_t* __restrict__ src,
+                                                      const int32_t* __restrict__ flags) {
   if (flags[FLAG_REBUILD] == 0) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncell) return;
-  const int a = start[c], b = start[c + 1];
-  for (int i = a + 1; i < b; ++i) {
-    const int32_t k = key[i], s = src[i];
-    int j = i - 1;
-    while (j >= a && key[j] > k) {
-      key[j + 1] = key[j];
-      src[j + 1] = src[j];
-      --j;
+  __shared__ int32_t kk[kSortWaves][kSortMax];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int U = kSortMax / 64;
+  for (int c = blockIdx.x * kSortWaves + w; c < ncell; c += gridDim.x * kSortWaves) {  // wave-uniform
+    const int a = start[c], n = start[c + 1] - a;
+    if (n <= 1) continue;
+    if (n > kSortMax) {
+      if (lane == 0) {
+        for (int i = a + 1; i < a + n; ++i) {
+          const int32_t k = key[i], s0 = src[i];
+          int j = i - 1;
+          while (j >= a && key[j] > k) {
+            key[j + 1] = key[j];
+            src[j + 1] = src[j];
+            --j;
+          }
+          key[j + 1] = k;
+          src[j + 1] = s0;
+        }
+      }
+      continue;
     }
-    key[j + 1] = k;
-    src[j + 1] = s;
+    int32_t mk[U], ms[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int l = lane + 64 * u;
+      mk[u] = l < n ? key[a + l] : 0;
+      ms[u] = l < n ? src[a + l] : 0;
+      if (l < n) kk[w][l] = mk[u];
+    }
+    wave_lds_sync();
+    int rank[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) rank[u] = 0;
+    for (int m = 0; m < n; ++m) {
+      const int32_t km = kk[w][m];
+#pragma unroll
+      for (int u = 0; u < U; ++u) rank[u] += km < mk[u] ? 1 : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (lane + 64 * u < n) {
+        key[a + rank[u]] = mk[u];
+        src[a + rank[u]] = ms[u];
+      }
+    }
+    wave_lds_sync();
   }
 }
 
@@ -150,18 +206,18 @@ __global__ void k_permute(int64_t N, const int32_t* __restrict__ src, const int3
                           int32_t* __restrict__ perm2, double* __restrict__ xb,
                           int32_t* __restrict__ cell_sorted, const int32_t* __restrict__ flags) {
   if (flags[FLAG_REBUILD] == 0) return;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= N) return;
-  const int64_t s = src[p];
-  for (int c = 0; c < 3; ++c) {
-    const double xv = x[c * N + s];
-    x2[c * N + p] = xv;
-    xb[c * N + p] = xv;
-    v2[c * N + p] = v[c * N + s];
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t s = src[p];
+    for (int c = 0; c < 3; ++c) {
+      const double xv = x[c * N + s];
+      x2[c * N + p] = xv;
+      xb[c * N + p] = xv;
+      v2[c * N + p] = v[c * N + s];
+    }
+    type2[p] = type[s];
+    perm2[p] = perm[s];
+    cell_sorted[p] = cellid[s];
   }
-  type2[p] = type[s];
-  perm2[p] = perm[s];
-  cell_sorted[p] = cellid[s];
 }
 
 // Copy the permuted arrays back to the primary buffers.
@@ -171,17 +227,17 @@ __global__ void k_copy_back(int64_t N, const double* __restrict__ x2, const doub
                             int32_t* __restrict__ perm, uint4* __restrict__ rec, CellGrid g,
                             const int32_t* __restrict__ flags) {
   if (flags[FLAG_REBUILD] == 0) return;
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= N) return;
-  double xn[3];
-  for (int c = 0; c < 3; ++c) {
-    xn[c] = x2[c * N + p];
-    x[c * N + p] = xn[c];
-    v[c * N + p] = v2[c * N + p];
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
+    double xn[3];
+    for (int c = 0; c < 3; ++c) {
+      xn[c] = x2[c * N + p];
+      x[c * N + p] = xn[c];
+      v[c * N + p] = v2[c * N + p];
+    }
+    rec_put_pos(rec, p, xn[0], xn[1], xn[2], g.box);
+    type[p] = type2[p];
+    perm[p] = perm2[p];
   }
-  rec_put_pos(rec, p, xn[0], xn[1], xn[2], g.box);
-  type[p] = type2[p];
-  perm[p] = perm2[p];
 }
 
 // Exclusive prefix sum over the workgroup; returns this thread's prefix, total in *tot.
@@ -203,14 +259,11 @@ __device__ __forceinline__ int block_scan(int v, int* scan, int* tot) {
 // One workgroup per 256-atom tile: the tile's force halo (every non-empty cell within
 // one cell, periodic, of a cell holding tile atoms), sorted by cell id, with local
 // offsets. ok = 0 when the tile or its halo exceeds the LDS tables of the force kernel.
-__global__ void __launch_bounds__(kBlock)
-k_halo_tables(int64_t N, CellGrid g, const int32_t* __restrict__ cell_sorted,
-              const int32_t* __restrict__ cell_start, HaloTables ht, const int32_t* __restrict__ flags) {
-  if (flags[FLAG_REBUILD] == 0) return;
+__device__ void halo_tile(int64_t N, const CellGrid& g, const int32_t* __restrict__ cell_sorted,
+                          const int32_t* __restrict__ cell_start, const HaloTables& ht, int tile) {
   __shared__ int cand[kCandMax];
   __shared__ int scan[kBlock];
   __shared__ int cnt[kHaloCellsMax];
-  const int tile = blockIdx.x;
   const int64_t t0 = (int64_t)tile * kBlock;
   const int64_t t1 = t0 + kBlock < N ? t0 + kBlock : N;
   int32_t* info = ht.info + 4 * tile;
@@ -301,6 +354,17 @@ k_halo_tables(int64_t N, CellGrid g, const int32_t* __restrict__ cell_sorted,
     info[1] = natoms;
     info[2] = natoms <= kHaloMax ? 1 : 0;
     info[3] = 0;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_halo_tables(int64_t N, CellGrid g, const int32_t* __restrict__ cell_sorted,
+              const int32_t* __restrict__ cell_start, HaloTables ht, const int32_t* __restrict__ flags) {
+  if (flags[FLAG_REBUILD] == 0) return;
+  const int ntiles = (int)((N + kBlock - 1) / kBlock);
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    halo_tile(N, g, cell_sorted, cell_start, ht, tile);
+    __syncthreads();  // the LDS tables are reused by the next tile
   }
 }
 
@@ -419,13 +483,11 @@ __device__ __forceinline__ void stage_flush16(const uint32_t* st, uint4* col, in
 // lies beyond the list cutoff (with a 1e-6 A margin) are skipped. k_place_lists then
 // counts the entries per bin and orders them by bin.
 // With MARKED, only the atoms that k_build_cells left to it (cnt = -1) are built.
-template <bool MINIMG, int NE, bool MARKED = false>
-__global__ void __launch_bounds__(kBlock)
-k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t* __restrict__ start,
-              const int32_t* __restrict__ cell_sorted, BinEdges be, int capR, int capA, ListOut lo_,
-              HaloTables ht, ListScratch sc, int32_t* __restrict__ flags) {
-  if (flags[FLAG_REBUILD] == 0) return;
-  const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+template <bool MINIMG, int NE, bool MARKED>
+__device__ void build_list_atom(int64_t N, const CellGrid& g, const double* __restrict__ x,
+                                const int32_t* __restrict__ start, const int32_t* __restrict__ cell_sorted,
+                                const BinEdges& be, int capR, const ListOut& lo_, const HaloTables& ht,
+                                const ListScratch& sc, int32_t* __restrict__ flags, int64_t p) {
   if (p >= N) return;
   if (MARKED && lo_.cnt[p] != -1) return;
   const int tile = (int)(p / kBlock);
@@ -494,6 +556,18 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
   if (n > capR) atomicMax(&flags[FLAG_OVF_R], n);
 }
 
+template <bool MINIMG, int NE, bool MARKED = false>
+__global__ void __launch_bounds__(kBlock)
+k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t* __restrict__ start,
+              const int32_t* __restrict__ cell_sorted, BinEdges be, int capR, int capA, ListOut lo_,
+              HaloTables ht, ListScratch sc, int32_t* __restrict__ flags) {
+  if (flags[FLAG_REBUILD] == 0) return;
+  const int nblocks = (int)((N + kBlock - 1) / kBlock);
+  for (int b = blockIdx.x; b < nblocks; b += gridDim.x)
+    build_list_atom<MINIMG, NE, MARKED>(N, g, x, start, cell_sorted, be, capR, lo_, ht, sc, flags,
+                                        (int64_t)xcd_tile(b, nblocks) * kBlock + threadIdx.x);
+}
+
 // One workgroup per cell (boxes with at least three cells along every dimension):
 // the positions of the 27 stencil cells' atoms are staged in LDS once, in stencil
 // order and by sorted index inside a cell, and each wavefront takes the cell's atoms
@@ -508,12 +582,10 @@ constexpr int kCellCand = 1024;  // stencil atoms a workgroup stages in LDS
 constexpr int kCellQueue = 128;  // accepted candidates queued per wavefront
 
 template <int NE>
-__global__ void __launch_bounds__(kBlock)
-k_build_cells(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t* __restrict__ start,
-              BinEdges be, int capR, ListOut lo_, HaloTables ht, ListScratch sc, int32_t* __restrict__ flags) {
+__device__ void build_cell(int64_t N, const CellGrid& g, const double* __restrict__ x,
+                           const int32_t* __restrict__ start, const BinEdges& be, int capR, const ListOut& lo_,
+                           const HaloTables& ht, const ListScratch& sc, int32_t* __restrict__ flags, int c) {
 #pragma clang fp contract(off)
-  if (flags[FLAG_REBUILD] == 0) return;
-  const int c = xcd_tile(blockIdx.x, gridDim.x);
   const int s0 = start[c], s1 = start[c + 1];
   if (s1 <= s0) return;  // empty cell or brick slot outside the grid
   int cx, cy, cz;
@@ -663,6 +735,17 @@ k_build_cells(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
       lo_.cnt[p] = nw < capR ? nw : capR;
       if (nw > capR) atomicMax(&flags[FLAG_OVF_R], nw);
     }
+  }
+}
+
+template <int NE>
+__global__ void __launch_bounds__(kBlock)
+k_build_cells(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t* __restrict__ start,
+              BinEdges be, int capR, ListOut lo_, HaloTables ht, ListScratch sc, int32_t* __restrict__ flags) {
+  if (flags[FLAG_REBUILD] == 0) return;
+  for (int cb = blockIdx.x; cb < g.ncell; cb += gridDim.x) {
+    build_cell<NE>(N, g, x, start, be, capR, lo_, ht, sc, flags, xcd_tile(cb, g.ncell));
+    __syncthreads();  // the LDS staging is reused by the next cell
   }
 }
 
@@ -870,7 +953,7 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, const BinEdges& be, int 
   hipError_t e;
   if ((e = launch_zero_i32(cell_count, ncell, st)) != hipSuccess) return e;
   if ((e = launch_zero_i32(cell_fill, ncell, st)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bin, dim3(nb), dim3(kBlock), 0, st, N, g, x, cellid, cell_count, flags);
+  hipLaunchKernelGGL(k_bin, dim3(rebuild_grid(nb)), dim3(kBlock), 0, st, N, g, x, cellid, cell_count, flags);
   const int ntiles = (ncell + kScanTile - 1) / kScanTile;
   hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kBlock), 0, st, cell_count, cell_start, ncell,
                      scan_tmp, flags);
@@ -878,30 +961,30 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, const BinEdges& be, int 
                      flags);
   hipLaunchKernelGGL(k_scan_add, dim3(grid_blocks(ncell)), dim3(kBlock), 0, st, cell_start, ncell,
                      scan_tmp, flags);
-  hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, st, N, cellid, cell_start, cell_fill, perm,
+  hipLaunchKernelGGL(k_scatter, dim3(rebuild_grid(nb)), dim3(kBlock), 0, st, N, cellid, cell_start, cell_fill, perm,
                      src, key, flags);
-  hipLaunchKernelGGL(k_cell_sort, dim3(grid_blocks(ncell)), dim3(kBlock), 0, st, ncell, cell_start,
-                     key, src, flags);
-  hipLaunchKernelGGL(k_permute, dim3(nb), dim3(kBlock), 0, st, N, src, cellid, x, v, type, perm,
+  hipLaunchKernelGGL(k_cell_sort, dim3(rebuild_grid(grid_blocks(ncell, kSortWaves))), dim3(kBlock), 0, st, ncell,
+                     cell_start, key, src, flags);
+  hipLaunchKernelGGL(k_permute, dim3(rebuild_grid(nb)), dim3(kBlock), 0, st, N, src, cellid, x, v, type, perm,
                      x_alt, v_alt, type_alt, perm_alt, x_build, cell_sorted, flags);
-  hipLaunchKernelGGL(k_copy_back, dim3(nb), dim3(kBlock), 0, st, N, x_alt, v_alt, type_alt, perm_alt,
+  hipLaunchKernelGGL(k_copy_back, dim3(rebuild_grid(nb)), dim3(kBlock), 0, st, N, x_alt, v_alt, type_alt, perm_alt,
                      x, v, type, perm, rec, g, flags);
-  hipLaunchKernelGGL(k_halo_tables, dim3(nb), dim3(kBlock), 0, st, N, g, cell_sorted, cell_start, ht, flags);
+  hipLaunchKernelGGL(k_halo_tables, dim3(rebuild_grid(nb)), dim3(kBlock), 0, st, N, g, cell_sorted, cell_start, ht, flags);
   // the minimum-image rule inside the candidate loop only for boxes with fewer than
   // three cells along some dimension
   const bool small = g.nc[0] < 3 || g.nc[1] < 3 || g.nc[2] < 3;
   const bool one = be.nbins - 1 <= kEdgesOne;
   if (small) {
     auto kern = one ? k_build_lists<true, kEdgesOne> : k_build_lists<true, kEdgesTwo>;
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(kBlock), 0, st, N, g, x, cell_start, cell_sorted, be, capR, capA,
+    hipLaunchKernelGGL(kern, dim3(rebuild_grid(nb)), dim3(kBlock), 0, st, N, g, x, cell_start, cell_sorted, be, capR, capA,
                        lout, ht, sc, flags);
   } else {
     auto cells = one ? k_build_cells<kEdgesOne> : k_build_cells<kEdgesTwo>;
-    hipLaunchKernelGGL(cells, dim3(ncell), dim3(kBlock), 0, st, N, g, x, cell_start, be, capR, lout, ht, sc,
+    hipLaunchKernelGGL(cells, dim3(rebuild_grid(ncell)), dim3(kBlock), 0, st, N, g, x, cell_start, be, capR, lout, ht, sc,
                        flags);
     // atoms of cells whose stencil did not fit in LDS
     auto rest = one ? k_build_lists<false, kEdgesOne, true> : k_build_lists<false, kEdgesTwo, true>;
-    hipLaunchKernelGGL(rest, dim3(nb), dim3(kBlock), 0, st, N, g, x, cell_start, cell_sorted, be, capR, capA,
+    hipLaunchKernelGGL(rest, dim3(rebuild_grid(nb)), dim3(kBlock), 0, st, N, g, x, cell_start, cell_sorted, be, capR, capA,
                        lout, ht, sc, flags);
   }
   const int place_groups = grid_blocks(N, kPlaceAtoms);
