@@ -277,7 +277,7 @@ __device__ __forceinline__ void desc_pass(const ModelDev& m, const EvalBuffers& 
 template <class S, int PREC, bool MULTI>
 __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers b) {
   __shared__ float lds[kBlock / 64][64 * kNetStride];
-  __shared__ double red[kBlock];
+  __shared__ double red[4];
   constexpr int NR = S::NR, NA = S::NA, NC = S::NC, D = S::D;
   const int64_t N = b.N;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -366,7 +366,9 @@ __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers 
     if (zs.n) zbl_center<MULTI>(m, b, i, ti, b.x[i], b.x[N + i], b.x[2 * N + i], zs, &U, nullptr, nullptr);
     b.U[i] = U;
   }
-  const double e = block_sum(valid ? (double)U : 0.0, red);
+  const double ev = valid ? (double)U : 0.0;
+  double e;
+  block_sum_n<1>(&ev, &e, red);
   if (threadIdx.x == 0) b.partial[(int64_t)tile * kPartialStride + P_ENERGY] = e;
 }
 
@@ -405,20 +407,20 @@ __device__ bool load_halo(const EvalBuffers& b, int tile, HaloLds& h) {
   return true;
 }
 
-// Adds the halo forces to F with one global atomic per halo atom and component.
+// Adds the halo forces to F with one global atomic per halo atom and component that
+// received a force: 16 lanes to a halo cell, whose atoms are contiguous both in the halo
+// and in F.
 __device__ void flush_halo(const HaloLds& h, float* __restrict__ F, int64_t N) {
-  for (int l = threadIdx.x; l < h.natoms; l += kBlock) {
-    int lo = 0, hi = h.ncells - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (h.off[mid] <= l) lo = mid;
-      else hi = mid - 1;
-    }
-    const int64_t g = h.start[lo] + (l - h.off[lo]);
+  const int q = threadIdx.x >> 4, u = threadIdx.x & 15;
+  for (int c = q; c < h.ncells; c += kBlock / 16) {
+    const int o = h.off[c], n = h.off[c + 1] - o;
+    const int64_t g0 = h.start[c];
+    for (int t = u; t < n; t += 16) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float v = h.F[c][l];
-      if (v != 0.f) unsafeAtomicAdd(&F[c * N + g], v);
+      for (int k = 0; k < 3; ++k) {
+        const float v = h.F[k][o + t];
+        if (v != 0.f) unsafeAtomicAdd(&F[k * N + g0 + t], v);
+      }
     }
   }
 }
@@ -431,7 +433,7 @@ constexpr int force_waves() { return S::L3 <= 2 ? 3 : 2; }
 
 template <class S, bool MULTI>
 __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, EvalBuffers b) {
-  __shared__ double red[kBlock];
+  __shared__ double red[4 * 9];
   __shared__ HaloLds halo;
   constexpr int NR = S::NR, NA = S::NA, NC = S::NC;
   const int64_t N = b.N;
@@ -624,11 +626,13 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
     __syncthreads();
     flush_halo(halo, b.F, N);
   }
+  double wd[9], ws[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) {
-    const double t = block_sum((double)w[k], red);
-    if (threadIdx.x == 0) b.partial[(int64_t)tile * kPartialStride + P_VIR + k] = t;
-  }
+  for (int k = 0; k < 9; ++k) wd[k] = (double)w[k];
+  block_sum_n<9>(wd, ws, red);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < 9; ++k) b.partial[(int64_t)tile * kPartialStride + P_VIR + k] = ws[k];
 }
 
 template <class S, int PREC, bool MULTI>

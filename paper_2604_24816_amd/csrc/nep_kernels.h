@@ -160,6 +160,30 @@ __device__ __forceinline__ void pair_vec(const double* __restrict__ x, int64_t N
   dz = (float)min_image(x[2 * N + j] - zi, Lz);
 }
 
+// Deterministic FP64 sums of K values over a 256-thread workgroup: a butterfly over the
+// 64 lanes of each wavefront (cross-lane moves, no barrier), then the four wavefront
+// partials in a fixed order, with one barrier for all K. The result is valid in thread 0.
+// sh holds at least 4 K doubles.
+template <int K>
+__device__ __forceinline__ void block_sum_n(const double* v, double* out, double* sh) {
+  double t[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) t[k] = v[k];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int k = 0; k < K; ++k) t[k] += __shfl_xor(t[k], off, 64);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();  // sh may still be read by an earlier use
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[w * K + k] = t[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = (sh[k] + sh[K + k]) + (sh[2 * K + k] + sh[3 * K + k]);
+}
+
 // Deterministic FP64 sum over a 256-thread workgroup (fixed tree order).
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   __syncthreads();
