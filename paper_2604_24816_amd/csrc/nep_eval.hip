@@ -19,7 +19,8 @@
 //     four-body pair forces from dU/ds by scatter into the neighbours (Section V.B
 //     Optimization 1: no temporary per-pair force buffer; an LDS copy of the tile's
 //     halo, or global atomics where it does not fit), and the virial
-//     W_ab = -sum r_a dU_i/dr_b; energy and virial are reduced per workgroup in FP64.
+//     W_ab = -sum r_a dU_i/dr_b; the tile's energy (the U_i the descriptor kernel
+//     wrote) and virial are summed per workgroup in FP64.
 //   Pair arithmetic in both comes from nep_fast.h.
 #include "nep_fast.h"
 
@@ -34,6 +35,15 @@ using namespace kern;
 // 148 lk + lr) within two passes of the 64 LDS banks.
 constexpr int kNetStride = 37;
 
+// The network's operand tiles are private to a wavefront, so its lanes only have to see
+// each other's LDS writes: an LDS fence and a wavefront barrier, not a workgroup barrier
+// (the wavefronts of a workgroup then leave their descriptor loops independently).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One wavefront evaluates the network for its 64 centers. qs[lane][v] holds the
 // scaled descriptor of the lane's center on entry; on exit fp[v] = dU/dq~ and the
 // return value is U. lds: this wavefront's 64 x kNetStride float tile.
@@ -47,7 +57,7 @@ __device__ __forceinline__ float network_wave(const ModelDev& m, const float* qs
   float* row = lds + lane * kNetStride;
 #pragma unroll
   for (int v = 0; v < 32; ++v) row[v] = v < S::D ? qs[v] : 0.f;
-  __syncthreads();
+  wave_lds_sync();
   floatx4 acc[4][2];
 #pragma unroll
   for (int R = 0; R < 4; ++R)
@@ -94,7 +104,7 @@ __device__ __forceinline__ float network_wave(const ModelDev& m, const float* qs
         acc[R][C] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop[C], acc[R][C], 0, 0, 0);
     }
   }
-  __syncthreads();
+  wave_lds_sync();
   // D layout: lane holds rows 4*lk + r of column lr.
 #pragma unroll
   for (int R = 0; R < 4; ++R)
@@ -102,7 +112,7 @@ __device__ __forceinline__ float network_wave(const ModelDev& m, const float* qs
     for (int C = 0; C < 2; ++C)
 #pragma unroll
       for (int r = 0; r < 4; ++r) lds[(16 * R + 4 * lk + r) * kNetStride + 16 * C + lr] = acc[R][C][r];
-  __syncthreads();
+  wave_lds_sync();
   float U = -b1;
   float a1[32];
 #pragma unroll
@@ -115,10 +125,10 @@ __device__ __forceinline__ float network_wave(const ModelDev& m, const float* qs
       a1[mu] = 0.f;
     }
   }
-  __syncthreads();
+  wave_lds_sync();
 #pragma unroll
   for (int mu = 0; mu < 32; ++mu) row[mu] = a1[mu];
-  __syncthreads();
+  wave_lds_sync();
 #pragma unroll
   for (int R = 0; R < 4; ++R)
 #pragma unroll
@@ -164,14 +174,14 @@ __device__ __forceinline__ float network_wave(const ModelDev& m, const float* qs
         acc[R][C] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop[C], acc[R][C], 0, 0, 0);
     }
   }
-  __syncthreads();
+  wave_lds_sync();
 #pragma unroll
   for (int R = 0; R < 4; ++R)
 #pragma unroll
     for (int C = 0; C < 2; ++C)
 #pragma unroll
       for (int r = 0; r < 4; ++r) lds[(16 * R + 4 * lk + r) * kNetStride + 16 * C + lr] = acc[R][C][r];
-  __syncthreads();
+  wave_lds_sync();
 #pragma unroll
   for (int v = 0; v < S::D; ++v) fp[v] = row[v];
   return U;
@@ -277,7 +287,6 @@ __device__ __forceinline__ void desc_pass(const ModelDev& m, const EvalBuffers& 
 template <class S, int PREC, bool MULTI>
 __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers b) {
   __shared__ float lds[kBlock / 64][64 * kNetStride];
-  __shared__ double red[4];
   constexpr int NR = S::NR, NA = S::NA, NC = S::NC, D = S::D;
   const int64_t N = b.N;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -366,10 +375,6 @@ __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers 
     if (zs.n) zbl_center<MULTI>(m, b, i, ti, b.x[i], b.x[N + i], b.x[2 * N + i], zs, &U, nullptr, nullptr);
     b.U[i] = U;
   }
-  const double ev = valid ? (double)U : 0.0;
-  double e;
-  block_sum_n<1>(&ev, &e, red);
-  if (threadIdx.x == 0) b.partial[(int64_t)tile * kPartialStride + P_ENERGY] = e;
 }
 
 // ------------------------------------------------------------------------ force halo in LDS
@@ -433,7 +438,7 @@ constexpr int force_waves() { return S::L3 <= 2 ? 3 : 2; }
 
 template <class S, bool MULTI>
 __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, EvalBuffers b) {
-  __shared__ double red[4 * 9];
+  __shared__ double red[4 * 10];
   __shared__ HaloLds halo;
   constexpr int NR = S::NR, NA = S::NA, NC = S::NC;
   const int64_t N = b.N;
@@ -626,13 +631,17 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
     __syncthreads();
     flush_halo(halo, b.F, N);
   }
-  double wd[9], ws[9];
+  // the tile's energy (the descriptor kernel's U_i, ZBL included) and virial in FP64
+  double wd[10], ws[10];
+  wd[0] = valid ? (double)b.U[i] : 0.0;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) wd[k] = (double)w[k];
-  block_sum_n<9>(wd, ws, red);
-  if (threadIdx.x == 0)
+  for (int k = 0; k < 9; ++k) wd[1 + k] = (double)w[k];
+  block_sum_n<10>(wd, ws, red);
+  if (threadIdx.x == 0) {
+    b.partial[(int64_t)tile * kPartialStride + P_ENERGY] = ws[0];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) b.partial[(int64_t)tile * kPartialStride + P_VIR + k] = ws[k];
+    for (int k = 0; k < 9; ++k) b.partial[(int64_t)tile * kPartialStride + P_VIR + k] = ws[1 + k];
+  }
 }
 
 template <class S, int PREC, bool MULTI>
