@@ -180,7 +180,7 @@ int64_t layout(nep_system* s, char* base, int64_t N, int capR, int capA, int max
   S.cell_start = c.take<int32_t>(max_ncell + 1);
   S.cell_fill = c.take<int32_t>(max_ncell);
   S.scan_tmp = c.take<int32_t>(max_ncell / 1024 + 2);
-  S.nbr = c.take<int32_t>((int64_t)capR * N);
+  S.nbr = c.take<int32_t>((int64_t)(capR + kListPad) * N);
   S.cnt = c.take<int32_t>(N);
   S.nbrl = c.take<uint16_t>((int64_t)capR * N);
   S.selfl = c.take<uint16_t>(N);
@@ -656,7 +656,8 @@ int nep_system_create(const nep_model* full, const nep_model* sur, int64_t n_ato
       return NEP_ERR_UNSUPPORTED;
     }
   }
-  if (launch_zero_i32(s->flags, FLAG_COUNT, s->st) != hipSuccess) {
+  if (launch_zero_i32(s->flags, FLAG_COUNT, s->st) != hipSuccess ||
+      launch_zero_i32(s->nbr, (int64_t)(cap_radial + kListPad) * n_atoms, s->st) != hipSuccess) {
     delete s;
     return NEP_ERR_HIP;
   }
@@ -1292,6 +1293,7 @@ int nep_compute_energy_forces_virial_noalloc(const nep_model* model, int64_t n_a
   // state (device arrays in the caller's order), lists with skin, evaluation
   const CellGrid g = make_grid(s.box, model->hp.rc_radial);
   HIPCHK2(launch_zero_i32(s.flags, FLAG_COUNT, s.st));
+  HIPCHK2(launch_zero_i32(s.nbr, (int64_t)(cap_radial + kListPad) * n_atoms, s.st));
   HIPCHK2(launch_state_in(n_atoms, x, nullptr, types, s.n_types, g, s.x, s.v, s.type, s.perm, s.rec, s.flags, s.st));
   int32_t f[FLAG_COUNT];
   if ((st = read_flags(&s, f))) return st;

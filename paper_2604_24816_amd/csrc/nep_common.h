@@ -87,6 +87,12 @@ __host__ __device__ inline bool cell_coords(const CellGrid& g, int lin, int& cx,
 // cells within one cell of a cell holding tile atoms, sorted by cell id, so their
 // atom ranges increase. Built once per list build; the angular list carries each
 // neighbour's index inside its tile's halo.
+// Rows of the slot-major neighbour list beyond its capacity. The evaluation loops load the
+// indices of the next entries before they know whether those exist, so the list carries
+// kListPad extra rows, and every row of it always holds an index of an atom of the system
+// (the list is zero-filled when the system is created; a build overwrites entries with
+// other atoms' indices), so that such loads and the record loads that follow stay in bounds.
+constexpr int kListPad = 4;
 constexpr int kTileCellsMax = 48;     // cells a tile may touch
 constexpr int kCandMax = 2048;        // >= 27 * kTileCellsMax, power of two
 constexpr int kHaloCellsMax = 512;    // cells per halo

@@ -118,7 +118,7 @@ __device__ __forceinline__ float network_wave(const ModelDev& m, const float* qs
 #pragma unroll
   for (int mu = 0; mu < 32; ++mu) {
     if (mu < S::H) {
-      const float t = tanhf(row[mu] - b0[mu]);
+      const float t = tanh_fast(row[mu] - b0[mu]);
       U = fmaf(w1[mu], t, U);
       a1[mu] = w1[mu] * (1.f - t * t);
     } else {

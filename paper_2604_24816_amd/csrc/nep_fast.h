@@ -168,6 +168,16 @@ __device__ __forceinline__ float radial_series_z(const RadialGeo& g, const float
   return fmaf(g.c, Cs, (g.fc * g.y) * Cp);
 }
 
+// ---------------------------------------------------------------- activation
+// tanh z = 1 - 2 / (e^{2z} + 1), with e^{2z} = 2^{2 z log2(e)} from the hardware base-2
+// exponential and the hardware reciprocal (about 1 ulp each): absolute error within a few
+// 1e-7 over the whole range, with no branch; for large |z| e^{2z} overflows to infinity or
+// underflows to 0 and the result saturates to +1 or -1 exactly.
+__device__ __forceinline__ float tanh_fast(float z) {
+  const float e = __builtin_amdgcn_exp2f(z * 2.88539008177792681f);  // 2 / ln 2
+  return fmaf(-2.f, __builtin_amdgcn_rcpf(e + 1.f), 1.f);
+}
+
 // ---------------------------------------------------------------- pair vectors
 // Pair vector x_j - x_i of a list neighbour from the records' 32-bit box fractions (see
 // the neighbour record): the two's-complement difference is the minimum image in units of
@@ -195,8 +205,10 @@ __device__ __forceinline__ void r_of_r2(float r2, float& r, float& rinv) {
 // first W 16-byte words of neighbour j's record. The records of entries p + 1 .. p + AHEAD
 // and the index of entry p + AHEAD + 1 are in flight while the body of entry p runs, so
 // their latency overlaps the pair arithmetic; bodies with little arithmetic per pair need
-// the deeper queue. The last loads repeat entry k1 - 1: every address stays inside the
-// list and the records.
+// the deeper queue. The loads run past k1 - 1 by up to AHEAD + 1 rows, into entries that
+// are not visited (later bins, stale entries, or the kListPad rows past the capacity),
+// which hold indices of atoms of the system, so every address stays inside the list and
+// the records; the index loads walk down the column by a pointer step of one row.
 //
 // for_each_rec_span moves the queue along by register copies; for_each_rec_fast is
 // unrolled AHEAD + 1 times so that each record is loaded straight into the buffer the
@@ -205,24 +217,25 @@ __device__ __forceinline__ void r_of_r2(float r2, float& r, float& rinv) {
 template <int W, int AHEAD, class Body>
 __device__ __forceinline__ void for_each_rec_span(const int32_t* __restrict__ nbr, const uint4* __restrict__ rec,
                                                   int64_t N, int64_t i, int k0, int k1, Body&& body) {
-  static_assert(AHEAD >= 1 && AHEAD <= 4, "prefetch depth");
+  static_assert(AHEAD >= 1 && AHEAD + 1 <= kListPad, "prefetch depth within the list's padding");
   if (k1 <= k0) return;
-  // slots, indices and N fit in 32 bits (N < 2^28): 32 x 32 -> 64-bit offsets
-  const int32_t* __restrict__ col = nbr + i;
-  const uint32_t n32 = (uint32_t)N;
-  auto slot = [&](int s) { return col[(uint64_t)(uint32_t)s * n32]; };
+  const uint64_t n64 = (uint64_t)N;
+  const int32_t* __restrict__ col = nbr + i + (uint64_t)(uint32_t)k0 * n64;  // entry k0
   auto record = [&](int32_t j, int w) { return rec[((uint64_t)(uint32_t)j << 2) + w]; };
-  const int last = k1 - 1;
   int32_t jq[AHEAD + 1];  // indices of entries p .. p + AHEAD
 #pragma unroll
-  for (int a = 0; a <= AHEAD; ++a) jq[a] = slot(k0 + a < last ? k0 + a : last);
+  for (int a = 0; a <= AHEAD; ++a) {
+    jq[a] = *col;
+    col += n64;
+  }
   uint4 rq[AHEAD][W];  // records of entries p .. p + AHEAD - 1
 #pragma unroll
   for (int a = 0; a < AHEAD; ++a)
 #pragma unroll
     for (int w = 0; w < W; ++w) rq[a][w] = record(jq[a], w);
   for (int p = k0; p < k1; ++p) {
-    const int32_t jn = slot(p + AHEAD + 1 < last ? p + AHEAD + 1 : last);
+    const int32_t jn = *col;  // entry p + AHEAD + 1
+    col += n64;
     uint4 rn[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) rn[w] = record(jq[AHEAD], w);
@@ -242,17 +255,18 @@ __device__ __forceinline__ void for_each_rec_span(const int32_t* __restrict__ nb
 template <int W, int AHEAD, class Body>
 __device__ __forceinline__ void for_each_rec_fast(const int32_t* __restrict__ nbr, const uint4* __restrict__ rec,
                                                   int64_t N, int64_t i, int k0, int k1, Body&& body) {
-  static_assert(AHEAD >= 1 && AHEAD <= 3, "prefetch depth");
+  static_assert(AHEAD >= 1 && AHEAD <= 3 && AHEAD + 1 <= kListPad, "prefetch depth within the list's padding");
   constexpr int U = AHEAD + 1;
   if (k1 <= k0) return;
-  const int32_t* __restrict__ col = nbr + i;
-  const uint32_t n32 = (uint32_t)N;
-  auto slot = [&](int s) { return col[(uint64_t)(uint32_t)s * n32]; };
+  const uint64_t n64 = (uint64_t)N;
+  const int32_t* __restrict__ col = nbr + i + (uint64_t)(uint32_t)k0 * n64;  // entry k0
   auto record = [&](int32_t j, int w) { return rec[((uint64_t)(uint32_t)j << 2) + w]; };
-  const int last = k1 - 1;
   int32_t jq[AHEAD + 1];  // indices of entries p .. p + AHEAD
 #pragma unroll
-  for (int a = 0; a <= AHEAD; ++a) jq[a] = slot(k0 + a < last ? k0 + a : last);
+  for (int a = 0; a <= AHEAD; ++a) {
+    jq[a] = *col;
+    col += n64;
+  }
   uint4 rq[U][W];  // record buffers; entry p sits in buffer (p - k0) % U
 #pragma unroll
   for (int a = 0; a < AHEAD; ++a)
@@ -263,7 +277,8 @@ __device__ __forceinline__ void for_each_rec_fast(const int32_t* __restrict__ nb
     for (int ph = 0; ph < U; ++ph) {
       const int p = p0 + ph;
       if (p < k1) {
-        const int32_t jn = slot(p + AHEAD + 1 < last ? p + AHEAD + 1 : last);
+        const int32_t jn = *col;  // entry p + AHEAD + 1
+        col += n64;
 #pragma unroll
         for (int w = 0; w < W; ++w) rq[(ph + AHEAD) % U][w] = record(jq[AHEAD], w);
         body(p, jq[0], rq[ph]);
