@@ -848,7 +848,7 @@ int vv_step(nep_system* s, int slot, int prec, double dt, int rebuild_every, dou
   HIPCHK(launch_set_flag(s->flags, FLAG_REBUILD, scheduled, s->st));
   HIPCHK(launch_kick_drift(s->N, dt, s->grid, s->F[slot], s->type, s->mt, s->x, s->v, s->rec, s->x_build,
                            0.25 * skin * skin, s->flags, s->partial, s->st));
-  HIPCHK(launch_select_bin(s->partial, s->nblocks, s->flags, skin, s->be, s->st));
+  HIPCHK(launch_select_bin(s->partial, kick_drift_blocks(s->N), s->flags, skin, s->be, s->st));
   if (ev) HIPCHK(hipEventRecord(ev[1], s->st));
   int st = rebuild(s, skin, 0);
   if (st) return st;

@@ -271,6 +271,8 @@ hipError_t launch_kick_drift(int64_t N, double dt, CellGrid g, const float* F, c
                              double half_skin2, int32_t* flags, double* partial, hipStream_t st);
 // FLAG_BIN_R / FLAG_BIN_A from the per-workgroup displacement maxima the drift
 // kernel left in partial.
+// workgroups of k_kick_drift, whose per-workgroup maxima launch_select_bin reads
+int kick_drift_blocks(int64_t N);
 hipError_t launch_select_bin(const double* partial, int nblocks, int32_t* flags, double skin,
                              const BinEdges& be, hipStream_t st);
 hipError_t launch_kick(int64_t N, double dt, const float* F, const int32_t* type, MassTable mt,

@@ -32,39 +32,45 @@ __device__ __forceinline__ double wrap_coord(double xv, double L) {
 }
 
 // v += dt/2 F/(m xi); x += dt v; wrap; flag a rebuild when |x - x_build| > skin/2.
+// Strides over a capped grid (kIntegrateGrid workgroups), so that the per-workgroup maxima
+// of the squared displacement that k_select_bin reads are few.
+constexpr int kIntegrateGrid = 8192;
+
 __global__ void k_kick_drift(int64_t N, double dt, CellGrid g, const float* __restrict__ F,
                              const int32_t* __restrict__ type, MassTable mt, double* __restrict__ x,
                              double* __restrict__ v, uint4* __restrict__ rec, const double* __restrict__ xb,
                              double half_skin2,
                              int32_t* __restrict__ flags, double* __restrict__ partial) {
-  __shared__ double sh[kBlock];
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double d2 = 0.0;
-  if (p < N) {
-  const double inv = mt.inv_mxi[type[p]];
-  double xn[3];
-  for (int c = 0; c < 3; ++c) {
-    double vv = v[c * N + p] + 0.5 * dt * (double)F[c * N + p] * inv;
-    double xx = wrap_coord(x[c * N + p] + dt * vv, g.box[c]);
-    v[c * N + p] = vv;
-    x[c * N + p] = xx;
-    xn[c] = xx;
-    const double d = min_image(xx - xb[c * N + p], g.box[c]);
-    d2 += d * d;
+  __shared__ double sh[kBlock / 64];
+  double d2max = 0.0;
+  bool moved = false;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
+    const double inv = mt.inv_mxi[type[p]];
+    double xn[3];
+    double d2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const double vv = v[c * N + p] + 0.5 * dt * (double)F[c * N + p] * inv;
+      const double xx = wrap_coord(x[c * N + p] + dt * vv, g.box[c]);
+      v[c * N + p] = vv;
+      x[c * N + p] = xx;
+      xn[c] = xx;
+      const double d = min_image(xx - xb[c * N + p], g.box[c]);
+      d2 += d * d;
+    }
+    rec_put_pos(rec, p, xn[0], xn[1], xn[2], g.box);
+    if (!(d2 <= half_skin2)) moved = true;  // also catches NaN
+    if (!(d2 == d2)) d2 = 1e300;
+    d2max = fmax(d2max, d2);
   }
-  rec_put_pos(rec, p, xn[0], xn[1], xn[2], g.box);
-  if (!(d2 <= half_skin2)) flags[FLAG_REBUILD] = 1;  // also catches NaN
-  if (!(d2 == d2)) d2 = 1e300;
-  }
+  if (moved) flags[FLAG_REBUILD] = 1;
   // largest squared displacement since the build, per workgroup
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) d2max = fmax(d2max, __shfl_xor(d2max, off, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = d2max;
   __syncthreads();
-  sh[threadIdx.x] = d2;
-  __syncthreads();
-  for (int off = kBlock / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < (unsigned)off) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + off]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * kPartialStride + P_MAXD2] = sh[0];
+  if (threadIdx.x == 0)
+    partial[(int64_t)blockIdx.x * kPartialStride + P_MAXD2] =
+        fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
 }
 
 // k = first bin fraction with bin_frac(k) * skin >= 2 * (largest displacement since the
@@ -316,10 +322,15 @@ hipError_t launch_max_partials(const double* partial, int nblocks, int slot, dou
   return hipGetLastError();
 }
 
+int kick_drift_blocks(int64_t N) {
+  const int nb = grid_blocks(N);
+  return nb < kIntegrateGrid ? nb : kIntegrateGrid;
+}
+
 hipError_t launch_kick_drift(int64_t N, double dt, CellGrid g, const float* F, const int32_t* type,
                              MassTable mt, double* x, double* v, uint4* rec, const double* x_build,
                              double half_skin2, int32_t* flags, double* partial, hipStream_t st) {
-  hipLaunchKernelGGL(k_kick_drift, dim3(grid_blocks(N)), dim3(kBlock), 0, st, N, dt, g, F, type, mt, x, v,
+  hipLaunchKernelGGL(k_kick_drift, dim3(kick_drift_blocks(N)), dim3(kBlock), 0, st, N, dt, g, F, type, mt, x, v,
                      rec, x_build, half_skin2, flags, partial);
   return hipGetLastError();
 }

@@ -768,7 +768,6 @@ k_place_lists(int64_t N, int nbins, int binA, int capR, int capA, ListOut lo_, L
   __shared__ uint16_t ltile[(kPlaceRows + 1) * kPlaceAtoms];
   __shared__ uint16_t off[kMaxBins * 64];  // next position of each bin, per lane
   __shared__ uint64_t parts[kPlaceParts][BinCounts::kWords][kPlaceAtoms];  // per-bin counts of each part
-  __shared__ int red[64];
   const int lane = threadIdx.x;
   const int a = lane % kPlaceAtoms;  // atom of the wavefront
   const int h = lane / kPlaceAtoms;  // which part of its column
@@ -783,27 +782,42 @@ k_place_lists(int64_t N, int nbins, int binA, int capR, int capA, ListOut lo_, L
     const int g_hi = h == kPlaceParts - 1 ? cnt : (g_lo + kPartLen < cnt ? g_lo + kPartLen : cnt);
     const bool work = valid && g_lo < cnt;
     // longest list of the wavefront (uniform loop bounds for the row writes)
-    red[lane] = cnt;
-    __syncthreads();
-    for (int o = 32; o > 0; o >>= 1) {
-      if (lane < o) red[lane] = max(red[lane], red[lane + o]);
-      __syncthreads();
-    }
-    const int rows_max = red[0];
+    int rows_max = cnt;
+  #pragma unroll
+    for (int o = 32; o > 0; o >>= 1) rows_max = max(rows_max, __shfl_xor(rows_max, o, 64));
     // per-bin counts of this lane's part (16-bit fields), then of the parts before it
     // and of the whole list
+    // this lane's part of the scratch column: the first two 16-entry chunks stay in
+    // registers from the counting pass to the placement (parts hold 32 entries, the last
+    // part the rest), later chunks are read again
+    auto load_q = [&](int g, uint32_t* v) {
+      const uint4* src = sc.q + ((int64_t)(g / kStage) * N + p) * (kStage / 4);
+  #pragma unroll
+      for (int j = 0; j < kStage / 4; ++j) {
+        const uint4 w = src[j];
+        v[4 * j] = w.x;
+        v[4 * j + 1] = w.y;
+        v[4 * j + 2] = w.z;
+        v[4 * j + 3] = w.w;
+      }
+    };
     BinCounts mine;
+    auto count_chunk = [&](int g, const uint32_t* v) {
+  #pragma unroll
+      for (int u = 0; u < kStage; ++u)
+        if (g + u < g_hi) mine.add((int)(v[u] >> 28));
+    };
+    uint32_t c0[kStage], c1[kStage];
+    const bool two = work && g_lo + kStage < g_hi;
     if (work) {
-      for (int g = g_lo; g < g_hi; g += kStage) {
-        const uint4* src = sc.q + ((int64_t)(g / kStage) * N + p) * (kStage / 4);
-  #pragma unroll
-        for (int j = 0; j < kStage / 4; ++j) {
-          const uint4 w = src[j];
-          const uint32_t t[4] = {w.x, w.y, w.z, w.w};
-  #pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (g + 4 * j + u < g_hi) mine.add((int)(t[u] >> 28));
-        }
+      load_q(g_lo, c0);
+      if (two) load_q(g_lo + kStage, c1);
+      count_chunk(g_lo, c0);
+      if (two) count_chunk(g_lo + kStage, c1);
+      for (int g = g_lo + 2 * kStage; g < g_hi; g += kStage) {
+        uint32_t t[kStage];
+        load_q(g, t);
+        count_chunk(g, t);
       }
     }
   #pragma unroll
@@ -835,17 +849,8 @@ k_place_lists(int64_t N, int nbins, int binA, int capR, int capA, ListOut lo_, L
       if (work) {
   #pragma unroll
         for (int k = 0; k < kMaxBins; ++k) off[k * 64 + lane] = (uint16_t)(bstart[k] + before.get(k));
-        for (int g = g_lo; g < g_hi; g += kStage) {
-          uint32_t v[kStage], hl[kStage];
-          const uint4* src = sc.q + ((int64_t)(g / kStage) * N + p) * (kStage / 4);
-  #pragma unroll
-          for (int j = 0; j < kStage / 4; ++j) {
-            const uint4 w = src[j];
-            v[4 * j] = w.x;
-            v[4 * j + 1] = w.y;
-            v[4 * j + 2] = w.z;
-            v[4 * j + 3] = w.w;
-          }
+        auto place_chunk = [&](int g, const uint32_t* v) {
+          uint32_t hl[kStage];
           const uint4* ls = sc.l + ((int64_t)(g / kStage) * N + p) * (kStage / 8);
   #pragma unroll
           for (int j = 0; j < kStage / 8; ++j) {
@@ -871,6 +876,13 @@ k_place_lists(int64_t N, int nbins, int binA, int capR, int capA, ListOut lo_, L
             tile[slot] = v[u] & 0x0fffffffu;
             ltile[slot] = (uint16_t)hl[u];
           }
+        };
+        place_chunk(g_lo, c0);
+        if (two) place_chunk(g_lo + kStage, c1);
+        for (int g = g_lo + 2 * kStage; g < g_hi; g += kStage) {
+          uint32_t t[kStage];
+          load_q(g, t);
+          place_chunk(g, t);
         }
       }
       __syncthreads();
