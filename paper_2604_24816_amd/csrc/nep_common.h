@@ -181,6 +181,14 @@ struct ModelDev {
   double zbl_ainv[kMaxTypes * kMaxTypes];
 };
 
+// Makes the LDS writes of a wavefront's lanes visible to its other lanes: an LDS fence and
+// a wavefront barrier (for LDS data private to one wavefront; no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // XCD-aware mapping of a workgroup id to a contiguous tile index: workgroups
 // are dispatched round-robin over the 8 dies, so consecutive tiles (which share
 // neighbour atoms) are given to the same die and its L2.

@@ -36,13 +36,8 @@ using namespace kern;
 constexpr int kNetStride = 37;
 
 // The network's operand tiles are private to a wavefront, so its lanes only have to see
-// each other's LDS writes: an LDS fence and a wavefront barrier, not a workgroup barrier
-// (the wavefronts of a workgroup then leave their descriptor loops independently).
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+// each other's LDS writes (wave_lds_sync), not a workgroup barrier: the wavefronts of a
+// workgroup leave their descriptor loops independently.
 
 // One wavefront evaluates the network for its 64 centers. qs[lane][v] holds the
 // scaled descriptor of the lane's center on entry; on exit fp[v] = dU/dq~ and the

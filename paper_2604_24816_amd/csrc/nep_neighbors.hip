@@ -139,12 +139,6 @@ __global__ void k_scatter(int64_t N, const int32_t* __restrict__ cellid, const i
 constexpr int kSortMax = 256;
 constexpr int kSortWaves = kBlock / 64;
 
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 __global__ void __launch_bounds__(kBlock) k_cell_sort(int ncell, const int32_t* __restrict__ start,
                                                       int32_t* __restrict__ key, int32_t* __restrict__ src,
                                                       const int32_t* __restrict__ flags) {
@@ -679,9 +673,7 @@ __device__ void build_cell(int64_t N, const CellGrid& g, const double* __restric
     const double xi = X[ks], yi = Y[ks], zi = Z[ks];
     int nw = 0, nq = 0;  // entries written, entries queued (wave-uniform)
     auto drain = [&]() {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      wave_lds_sync();
       for (int j0 = 0; j0 < nq; j0 += 64) {
         const int j = j0 + lane;
         const bool v = j < nq;
@@ -698,9 +690,7 @@ __device__ void build_cell(int64_t N, const CellGrid& g, const double* __restric
       }
       nw += nq;
       nq = 0;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      wave_lds_sync();
     };
     for (int k0 = 0; k0 < nc; k0 += 64) {
       const int k = k0 + lane;
