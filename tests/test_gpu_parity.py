@@ -48,6 +48,23 @@ def test_mfma_network_and_forces_small_box(full):
     _check_efw(s, m, at)
 
 
+def test_lists_filled_to_capacity(full):
+    """Radial capacity set to the longest list of the box: the atoms with that many
+    entries have full lists, so the evaluation loops' look-ahead loads run into the
+    padding rows past the capacity; energies, forces and virial at the standard bounds."""
+    hp, params, m = full
+    at = I.workload_small()
+    s = make_system(at, hp, params)
+    offsets, _ = s.export_neighbors(0)
+    longest = int(np.diff(offsets).max())
+    s.close()
+    say(f"case: 4000 atoms, cap_radial = longest list = {longest}, fp32")
+    s = make_system(at, hp, params, cap_radial=longest)
+    offsets, _ = s.export_neighbors(0)
+    assert int(np.diff(offsets).max()) == longest
+    _check_efw(s, m, at)
+
+
 @pytest.mark.parametrize("scale,mixed", [(0.85, True), (0.8, False)])
 def test_force_global_atomic_fallback_compressed_box(full, scale, mixed):
     """FCC compressed to `scale` of the Cu lattice constant (12^3 cells; 1.63x and 1.95x
