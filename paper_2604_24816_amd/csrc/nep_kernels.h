@@ -184,18 +184,6 @@ __device__ __forceinline__ void block_sum_n(const double* v, double* out, double
     for (int k = 0; k < K; ++k) out[k] = (sh[k] + sh[K + k]) + (sh[2 * K + k] + sh[3 * K + k]);
 }
 
-// Deterministic FP64 sum over a 256-thread workgroup (fixed tree order).
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  __syncthreads();
-  sh[threadIdx.x] = v;
-  __syncthreads();
-#pragma unroll
-  for (int off = kBlock / 2; off > 0; off >>= 1) {
-    if (threadIdx.x < (unsigned)off) sh[threadIdx.x] += sh[threadIdx.x + off];
-    __syncthreads();
-  }
-  return sh[0];
-}
 
 template <int NR_, int KR_, int NA_, int KA_, int L3_, bool FB_, int H_>
 struct Shape {
