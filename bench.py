@@ -453,6 +453,8 @@ def main():
     ap.add_argument("--zbl", type=float, default=0.0,
                     help="fp32 form only, with the ZBL repulsion of this outer radius in A (the paper's Cu "
                          "model uses 2.0)")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="fp32 form only, with fixed-order force accumulation (no atomics)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy three times (the reference kernel "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -480,16 +482,21 @@ def main():
     params = I.random_model(hp, 0)
     at = I.workload_4m(args.cells) if args.cells == 100 else I.workload_32m(args.cells)
     n = at.n
-    variant = (f"nvt_{args.nvt:g}K" if args.nvt > 0 else "nve") + (f"_zbl_{args.zbl:g}A" if args.zbl > 0 else "")
+    variant = ((f"nvt_{args.nvt:g}K" if args.nvt > 0 else "nve") + (f"_zbl_{args.zbl:g}A" if args.zbl > 0 else "")
+               + ("_deterministic" if args.deterministic else ""))
     say(f"bench: {n} atoms ({args.cells}^3 FCC cells), {args.steps} timed + {args.warmup} warm-up steps")
     forms = {}
-    if args.nvt > 0:
+    if args.nvt > 0 or args.deterministic:
         from paper_2604_24816_amd import nep
-        # NVT: the fp32 form with a Nose-Hoover chain, timed like the others
+        # NVT (a Nose-Hoover chain) or deterministic accumulation: the fp32 form alone,
+        # timed like the others
         s = nep.NEPSystem(nep.NEPModel(hp, params), n, at.box)
         s.set_state(at.x, at.types, at.masses, at.v)
         s.build_neighbors(1.0)
-        s.set_thermostat(args.nvt, tau=100.0, chain=3)
+        if args.nvt > 0:
+            s.set_thermostat(args.nvt, tau=100.0, chain=3)
+        if args.deterministic:
+            s.set_deterministic(True)
         s.step(args.warmup)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -215,6 +215,19 @@ int nep_get_thermostat(nep_system* s, double* eta, double* v_eta, double* chain_
  * disorders. It changes only the fallback decision. */
 int nep_set_judge(nep_system* s, int32_t relative);
 
+/* Order of the force accumulation for every later evaluation and step
+ * (Section III.B: F_i gathers dU_i/dr_ij from its own pair terms and -dU_j/dr_ji
+ * from each neighbour j's). deterministic = 0 (the default): each center adds its
+ * angular terms to its neighbours with atomic additions, so the order of the FP32
+ * sums, and the last bits of the forces, can change from run to run.
+ * deterministic = 1: no atomics; every atom sums its own terms and then, in list
+ * order, the angular terms of its neighbours, each recomputed from that
+ * neighbour's dU/ds; the same list, positions and model then give bitwise the
+ * same forces, energy and virial on every run. It costs a second pass over the
+ * angular lists in the force kernel. Energies are unchanged; forces agree with
+ * the default mode to FP32 rounding. Returns NEP_ERR_ARG for other values. */
+int nep_set_deterministic(nep_system* s, int32_t deterministic);
+
 /* Positions and velocities [N][3] in original order, and the step counter. */
 int nep_get_state(nep_system* s, double* x, double* v, int64_t* step, int32_t on_device);
 

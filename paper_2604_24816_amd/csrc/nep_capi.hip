@@ -117,6 +117,7 @@ struct nep_system {
   int64_t step = 0;
   int64_t n_mts_blocks = 0, n_fallback_blocks = 0, n_steps_total = 0;
   int judge_relative = 0;  // nep_set_judge
+  int deterministic = 0;   // nep_set_deterministic
   // NVT (nep_set_thermostat): Nose-Hoover chain length (0 = NVE), target and period
   int nvt_M = 0;
   double nvt_T = 0, nvt_tau = 0;
@@ -343,6 +344,7 @@ EvalBuffers eval_buffers(nep_system* s, int slot) {
   b.flags = s->flags;
   b.flag_r = slot == 0 ? FLAG_BIN_R : FLAG_BIN_R1;
   b.flag_a = slot == 0 ? FLAG_BIN_A : FLAG_BIN_A1;
+  b.deterministic = s->deterministic;
   return b;
 }
 
@@ -1048,6 +1050,12 @@ int nep_get_thermostat(nep_system* s, double* eta, double* v_eta, double* chain_
 int nep_set_judge(nep_system* s, int32_t relative) {
   if (!s || relative < 0 || relative > 1) return fail(s, NEP_ERR_ARG, "bad argument");
   s->judge_relative = relative;
+  return NEP_OK;
+}
+
+int nep_set_deterministic(nep_system* s, int32_t deterministic) {
+  if (!s || deterministic < 0 || deterministic > 1) return fail(s, NEP_ERR_ARG, "bad argument");
+  s->deterministic = deterministic;
   return NEP_OK;
 }
 

@@ -252,6 +252,7 @@ struct EvalBuffers {
   double* partial;       // [nblocks][kPartialStride]
   int32_t* flags;
   int flag_r, flag_a;    // flag words holding this model's last radial / angular bin
+  int deterministic;     // 1: forces gathered in a fixed order, no atomics (k_force<..., true>)
 };
 bool eval_supported(const ModelDev& m);
 // Floats of the derived radial tables of one model (radial then angular blocks).

@@ -278,6 +278,26 @@ __device__ __forceinline__ void desc_pass(const ModelDev& m, const EvalBuffers& 
   }
 }
 
+// dU/ds of one atom as a row (the deterministic form's layout): NA * NC values padded
+// to a multiple of four, so that a row is read with 16-byte loads.
+template <class S>
+constexpr int g_row() {
+  static_assert(((S::NA * S::NC + 3) & ~3) <= 5 * 24, "a row must fit the system's dU/ds buffer");
+  return (S::NA * S::NC + 3) & ~3;
+}
+template <class S>
+__device__ __forceinline__ void load_g_row(const float* row, float* g) {
+  const float4* r4 = reinterpret_cast<const float4*>(row);
+#pragma unroll
+  for (int k = 0; k < g_row<S>() / 4; ++k) {
+    const float4 v = r4[k];
+    g[4 * k] = v.x;
+    if (4 * k + 1 < S::NA * S::NC) g[4 * k + 1] = v.y;
+    if (4 * k + 2 < S::NA * S::NC) g[4 * k + 2] = v.z;
+    if (4 * k + 3 < S::NA * S::NC) g[4 * k + 3] = v.w;
+  }
+}
+
 // ------------------------------------------------------------------------ descriptor + network
 template <class S, int PREC, bool MULTI>
 __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers b) {
@@ -361,8 +381,17 @@ __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers 
         for (int k = 0; k < 5; ++k) Gd[n * NC + 3 + k] = fmaf(f4, d5[k], Gd[n * NC + 3 + k]);
       }
     }
+    if (b.deterministic) {
+      // atom-major rows for the force kernel's gathers of the neighbours' dU/ds
+      float4* g4 = reinterpret_cast<float4*>(b.G + i * g_row<S>());
 #pragma unroll
-    for (int k = 0; k < NA * NC; ++k) b.G[(int64_t)k * N + i] = Gd[k];
+      for (int k = 0; k < g_row<S>() / 4; ++k)
+        g4[k] = make_float4(Gd[4 * k], 4 * k + 1 < NA * NC ? Gd[4 * k + 1] : 0.f,
+                            4 * k + 2 < NA * NC ? Gd[4 * k + 2] : 0.f, 4 * k + 3 < NA * NC ? Gd[4 * k + 3] : 0.f);
+    } else {
+#pragma unroll
+      for (int k = 0; k < NA * NC; ++k) b.G[(int64_t)k * N + i] = Gd[k];
+    }
     b.F[i] = 0.f;
     b.F[N + i] = 0.f;
     b.F[2 * N + i] = 0.f;
@@ -431,7 +460,94 @@ __device__ void flush_halo(const HaloLds& h, float* __restrict__ F, int64_t N) {
 template <class S>
 constexpr int force_waves() { return S::L3 <= 2 ? 3 : 2; }
 
-template <class S, bool MULTI>
+// Constants of the angular pair force (uniform over a launch).
+struct AngConst {
+  float rcA_inv;
+  CutConst cutA;
+  float kDA;  // f_c' = kDA c (angular cutoff)
+  float kYA;  // x' = kYA y
+};
+__device__ __forceinline__ AngConst ang_const(const ModelDev& m) {
+  AngConst a;
+  a.rcA_inv = 1.f / m.rcA;
+  a.cutA = cut_const(m.rcA);
+  a.kDA = -0.5f * kPiF * a.cutA.rc_inv;
+  a.kYA = 4.f * a.cutA.rc_inv;
+  return a;
+}
+
+// Angular and four-body force of center c on a neighbour k inside rc_angular, n = -dU_c/dr_ck,
+// for the unit vector u from c to k at distance r, from the center's dU/ds (Gc(q) returns
+// component q < NA * NC, channel-major) and the pair's types (center tc, neighbour tk):
+// F_ck = sum_lm [ A_lm P_lm u + B_lm (grad P_lm - l P_lm u) / r ] with A_lm = sum_n G_nlm g'_n
+// and B_lm = sum_n G_nlm g_n; the l P B terms are summed per l and scaled once.
+template <class S, bool MULTI, class GF>
+__device__ __forceinline__ void angular_pair_force(const ModelDev& m, const AngConst& ac, GF&& Gc, int tc, int tk,
+                                                   float ux, float uy, float uz, float r, float rinv, float& n0,
+                                                   float& n1, float& n2) {
+  constexpr int NA = S::NA, NC = S::NC, KA = S::KA;
+  float sc, vx = 0.f, vy = 0.f, vz = 0.f, vscale;
+  if constexpr (MULTI) {
+    float g[NA], dg[NA];
+    radial_g_dg<NA, KA>(r, ac.rcA_inv, m.cA + (tc * m.T + tk) * NA * KA, g, dg);
+    float sA = 0.f;
+    float sB[4] = {0.f, 0.f, 0.f, 0.f};
+    for_each_poly_grad<NC>(ux, uy, uz, [&](int lm, float P, auto px, auto py, auto pz) {
+      float A = Gc(lm) * dg[0], B = Gc(lm) * g[0];
+#pragma unroll
+      for (int n = 1; n < NA; ++n) {
+        A = fmaf(Gc(n * NC + lm), dg[n], A);
+        B = fmaf(Gc(n * NC + lm), g[n], B);
+      }
+      sA = fmaf(P, A, sA);
+      sB[comp_l(lm) - 1] = fmaf(P, B, sB[comp_l(lm) - 1]);
+      vx = fmac(B, px, vx);
+      vy = fmac(B, py, vy);
+      vz = fmac(B, pz, vz);
+    });
+    const float lPB = fmaf(4.f, sB[3], fmaf(3.f, sB[2], fmaf(2.f, sB[1], sB[0])));
+    sc = fmaf(-rinv, lPB, sA);
+    vscale = rinv;
+  } else {
+    // With g_n = f_c C_n and g'_n = f_c' C_n + f_c x' D_n: B_lm = f_c E_lm and
+    // A_lm = f_c' E_lm + f_c x' H_lm for E_lm = sum_n G_nlm C_n, H_lm = sum_n G_nlm D_n,
+    // so f_c, f_c' and f_c x' are applied once to the sums over lm.
+    const RadialGeo rb = radial_geo<true>(r, ac.cutA);
+    float Cn[NA], Dn[NA];
+    radial_cd_fast<NA, KA>(rb.x, uniform_coeffs(m.hA), Cn, Dn);
+    float sH = 0.f;
+    float sE[4] = {0.f, 0.f, 0.f, 0.f};
+    for_each_poly_grad<NC>(ux, uy, uz, [&](int lm, float P, auto px, auto py, auto pz) {
+      float E = Gc(lm) * Cn[0], H = Gc(lm) * Dn[0];
+#pragma unroll
+      for (int n = 1; n < NA; ++n) {
+        E = fmaf(Gc(n * NC + lm), Cn[n], E);
+        H = fmaf(Gc(n * NC + lm), Dn[n], H);
+      }
+      sH = fmaf(P, H, sH);
+      sE[comp_l(lm) - 1] = fmaf(P, E, sE[comp_l(lm) - 1]);
+      vx = fmac(E, px, vx);
+      vy = fmac(E, py, vy);
+      vz = fmac(E, pz, vz);
+    });
+    const float sPE = (sE[0] + sE[1]) + (sE[2] + sE[3]);
+    const float lPE = fmaf(4.f, sE[3], fmaf(3.f, sE[2], fmaf(2.f, sE[1], sE[0])));
+    const float sA = fmaf(ac.kDA * rb.c, sPE, (rb.fc * (ac.kYA * rb.y)) * sH);
+    vscale = rb.fc * rinv;
+    sc = fmaf(-vscale, lPE, sA);
+  }
+  // n = -dU_c/dr_ck (sign folded into the operands)
+  n0 = fmaf(-ux, sc, -(vx * vscale));
+  n1 = fmaf(-uy, sc, -(vy * vscale));
+  n2 = fmaf(-uz, sc, -(vz * vscale));
+}
+
+// DET: the deterministic form. Nothing is scattered: each atom adds, after its own pair
+// terms, the angular forces of the centers that have it as an angular neighbour, each
+// recomputed from that center's dU/ds in list order (the angular sets are symmetric: the
+// same bin and the same exactly negated pair vector decide both), and stores its force.
+// The terms are bitwise those the scattering form adds, in a fixed order.
+template <class S, bool MULTI, bool DET>
 __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, EvalBuffers b) {
   __shared__ double red[4 * 10];
   __shared__ HaloLds halo;
@@ -440,13 +556,13 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t i = (int64_t)tile * kBlock + threadIdx.x;
   const bool valid = i < N;
-  const bool lds = load_halo(b, tile, halo);
+  bool lds = false;
+  if constexpr (!DET) lds = load_halo(b, tile, halo);
   const double hx = box_quantum(b.box[0]), hy = box_quantum(b.box[1]), hz = box_quantum(b.box[2]);
-  const float rcR_inv = 1.f / m.rcR, rcA_inv = 1.f / m.rcA;
-  const CutConst cutR = cut_const(m.rcR), cutA = cut_const(m.rcA);
+  const float rcR_inv = 1.f / m.rcR;
+  const CutConst cutR = cut_const(m.rcR);
   const float kXR = -0.25f * kPiF * cutR.rc_inv;  // X = kXR Z for the radial series (one species)
-  const float kDA = -0.5f * kPiF * cutA.rc_inv;   // f_c' = kDA c (angular cutoff)
-  const float kYA = 4.f * cutA.rc_inv;            // x' = kYA y
+  const AngConst ac = ang_const(m);
   const bool zbl_on = m.zbl_o2 > 0.0;
   float fx = 0.f, fy = 0.f, fz = 0.f;
   float w[9];
@@ -464,8 +580,12 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
                          __uint_as_float(r2w.y), __uint_as_float(r2w.z), __uint_as_float(r2w.w)};
     constexpr int KR = S::KR, KA = S::KA;
     float G[NA * NC];
+    if constexpr (DET) {
+      load_g_row<S>(b.G + i * g_row<S>(), G);
+    } else {
 #pragma unroll
-    for (int k = 0; k < NA * NC; ++k) G[k] = b.G[(int64_t)k * N + i];
+      for (int k = 0; k < NA * NC; ++k) G[k] = b.G[(int64_t)k * N + i];
+    }
     const float rcR2 = (float)(m.rcR64 * m.rcR64), rcA2 = (float)(m.rcA64 * m.rcA64), zbl2 = (float)m.zbl_o2;
     const int kR = radial_bound(b, i), kA = angular_bound(b, i);
     EvalZbl zs;  // pairs inside the ZBL radius
@@ -480,7 +600,7 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
       const float r2 = pair_vec_q(rw[0], qi, hx, hy, hz, dx, dy, dz);
       if (!(r2 < rcR2)) return;
       const bool ang = p < kA && r2 < rcA2;
-      const int lj = (ang && lds) ? (int)b.nbrl[(int64_t)p * N + i] : 0;
+      const int lj = (!DET && ang && lds) ? (int)b.nbrl[(int64_t)p * N + i] : 0;
       float r, rinv;
       r_of_r2(r2, r, rinv);
       const int tj = MULTI ? b.type[j] : 0;
@@ -524,74 +644,21 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
       }
       if (!ang) return;
       const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
-      // F_ij = sum_lm [ A_lm P_lm u + B_lm (grad P_lm - l P_lm u) / r ] with
-      // A_lm = sum_n G_nlm g'_n and B_lm = sum_n G_nlm g_n; the l P B terms are
-      // summed per l and scaled once.
-      float sc, vx = 0.f, vy = 0.f, vz = 0.f, vscale;
-      if constexpr (MULTI) {
-        float g[NA], dg[NA];
-        radial_g_dg<NA, KA>(r, rcA_inv, m.cA + (ti * m.T + tj) * NA * KA, g, dg);
-        float sA = 0.f;
-        float sB[4] = {0.f, 0.f, 0.f, 0.f};
-        for_each_poly_grad<NC>(ux, uy, uz, [&](int lm, float P, auto px, auto py, auto pz) {
-          float A = G[lm] * dg[0], B = G[lm] * g[0];
-#pragma unroll
-          for (int n = 1; n < NA; ++n) {
-            A = fmaf(G[n * NC + lm], dg[n], A);
-            B = fmaf(G[n * NC + lm], g[n], B);
-          }
-          sA = fmaf(P, A, sA);
-          sB[comp_l(lm) - 1] = fmaf(P, B, sB[comp_l(lm) - 1]);
-          vx = fmac(B, px, vx);
-          vy = fmac(B, py, vy);
-          vz = fmac(B, pz, vz);
-        });
-        const float lPB = fmaf(4.f, sB[3], fmaf(3.f, sB[2], fmaf(2.f, sB[1], sB[0])));
-        sc = fmaf(-rinv, lPB, sA);
-        vscale = rinv;
-      } else {
-        // With g_n = f_c C_n and g'_n = f_c' C_n + f_c x' D_n: B_lm = f_c E_lm and
-        // A_lm = f_c' E_lm + f_c x' H_lm for E_lm = sum_n G_nlm C_n, H_lm = sum_n G_nlm D_n,
-        // so f_c, f_c' and f_c x' are applied once to the sums over lm.
-        const RadialGeo rb = radial_geo<true>(r, cutA);
-        float Cn[NA], Dn[NA];
-        radial_cd_fast<NA, KA>(rb.x, uniform_coeffs(m.hA), Cn, Dn);
-        float sH = 0.f;
-        float sE[4] = {0.f, 0.f, 0.f, 0.f};
-        for_each_poly_grad<NC>(ux, uy, uz, [&](int lm, float P, auto px, auto py, auto pz) {
-          float E = G[lm] * Cn[0], H = G[lm] * Dn[0];
-#pragma unroll
-          for (int n = 1; n < NA; ++n) {
-            E = fmaf(G[n * NC + lm], Cn[n], E);
-            H = fmaf(G[n * NC + lm], Dn[n], H);
-          }
-          sH = fmaf(P, H, sH);
-          sE[comp_l(lm) - 1] = fmaf(P, E, sE[comp_l(lm) - 1]);
-          vx = fmac(E, px, vx);
-          vy = fmac(E, py, vy);
-          vz = fmac(E, pz, vz);
-        });
-        const float sPE = (sE[0] + sE[1]) + (sE[2] + sE[3]);
-        const float lPE = fmaf(4.f, sE[3], fmaf(3.f, sE[2], fmaf(2.f, sE[1], sE[0])));
-        const float sA = fmaf(kDA * rb.c, sPE, (rb.fc * (kYA * rb.y)) * sH);
-        vscale = rb.fc * rinv;
-        sc = fmaf(-vscale, lPE, sA);
-      }
-      // n = -dU_i/dr_ij, the force on the neighbour (sign folded into the operands)
-      const float n0 = fmaf(-ux, sc, -(vx * vscale));
-      const float n1 = fmaf(-uy, sc, -(vy * vscale));
-      const float n2 = fmaf(-uz, sc, -(vz * vscale));
+      float n0, n1, n2;  // -dU_i/dr_ij, the force on the neighbour
+      angular_pair_force<S, MULTI>(m, ac, [&](int q) { return G[q]; }, ti, tj, ux, uy, uz, r, rinv, n0, n1, n2);
       fx -= n0;
       fy -= n1;
       fz -= n2;
-      if (lds) {
-        atomicAdd(&halo.F[0][lj], n0);
-        atomicAdd(&halo.F[1][lj], n1);
-        atomicAdd(&halo.F[2][lj], n2);
-      } else {
-        unsafeAtomicAdd(&b.F[j], n0);
-        unsafeAtomicAdd(&b.F[N + j], n1);
-        unsafeAtomicAdd(&b.F[2 * N + j], n2);
+      if constexpr (!DET) {
+        if (lds) {
+          atomicAdd(&halo.F[0][lj], n0);
+          atomicAdd(&halo.F[1][lj], n1);
+          atomicAdd(&halo.F[2][lj], n2);
+        } else {
+          unsafeAtomicAdd(&b.F[j], n0);
+          unsafeAtomicAdd(&b.F[N + j], n1);
+          unsafeAtomicAdd(&b.F[2 * N + j], n2);
+        }
       }
       const float d[3] = {dx, dy, dz};
       const float nf[3] = {n0, n1, n2};
@@ -611,7 +678,30 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
       fy = f[1];
       fz = f[2];
     }
-    if (lds) {
+    if constexpr (DET) {
+      // the neighbours' angular terms on this atom, in list order
+      const uint64_t n64 = (uint64_t)N;
+      for (int p = 0; p < kA; ++p) {
+        const int32_t j = b.nbr[(uint64_t)(uint32_t)p * n64 + i];
+        float dx, dy, dz;
+        const float r2 = pair_vec_q(b.rec[4 * (int64_t)j], qi, hx, hy, hz, dx, dy, dz);
+        if (!(r2 < rcR2 && r2 < rcA2)) continue;
+        float r, rinv;
+        r_of_r2(r2, r, rinv);
+        const int tj = MULTI ? b.type[j] : 0;
+        float Gj[NA * NC];
+        load_g_row<S>(b.G + (int64_t)j * g_row<S>(), Gj);
+        float n0, n1, n2;  // -dU_j/dr_ji, the force of center j's angular term on this atom
+        angular_pair_force<S, MULTI>(m, ac, [&](int q) { return Gj[q]; }, tj, ti, -(dx * rinv), -(dy * rinv),
+                                     -(dz * rinv), r, rinv, n0, n1, n2);
+        fx += n0;
+        fy += n1;
+        fz += n2;
+      }
+      b.F[i] = fx;
+      b.F[N + i] = fy;
+      b.F[2 * N + i] = fz;
+    } else if (lds) {
       const int li = b.selfl[i];
       atomicAdd(&halo.F[0][li], fx);
       atomicAdd(&halo.F[1][li], fy);
@@ -622,9 +712,11 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
       unsafeAtomicAdd(&b.F[2 * N + i], fz);
     }
   }
-  if (lds) {
-    __syncthreads();
-    flush_halo(halo, b.F, N);
+  if constexpr (!DET) {
+    if (lds) {
+      __syncthreads();
+      flush_halo(halo, b.F, N);
+    }
   }
   // the tile's energy (the descriptor kernel's U_i, ZBL included) and virial in FP64
   double wd[10], ws[10];
@@ -645,7 +737,10 @@ hipError_t launch_pair(const ModelDev& m, const EvalBuffers& b, hipStream_t st, 
   if (ev) (void)hipEventRecord(ev[0], st);
   hipLaunchKernelGGL((k_desc_net<S, PREC, MULTI>), dim3(nb), dim3(kBlock), 0, st, m, b);
   if (ev) (void)hipEventRecord(ev[1], st);
-  hipLaunchKernelGGL((k_force<S, MULTI>), dim3(nb), dim3(kBlock), 0, st, m, b);
+  if (b.deterministic)
+    hipLaunchKernelGGL((k_force<S, MULTI, true>), dim3(nb), dim3(kBlock), 0, st, m, b);
+  else
+    hipLaunchKernelGGL((k_force<S, MULTI, false>), dim3(nb), dim3(kBlock), 0, st, m, b);
   if (ev) (void)hipEventRecord(ev[2], st);
   return hipGetLastError();
 }

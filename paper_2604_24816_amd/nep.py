@@ -36,7 +36,7 @@ EXPORTED = [
     "nep_param_count", "nep_model_create", "nep_model_destroy", "nep_system_workspace_bytes",
     "nep_system_create", "nep_system_destroy", "nep_system_set_params", "nep_set_state",
     "nep_build_neighbors", "nep_export_neighbors", "nep_compute_energy_forces_virial", "nep_step",
-    "nep_set_judge", "nep_set_thermostat", "nep_set_thermostat_state", "nep_get_thermostat", "nep_get_state",
+    "nep_set_judge", "nep_set_deterministic", "nep_set_thermostat", "nep_set_thermostat_state", "nep_get_thermostat", "nep_get_state",
     "nep_get_stats", "nep_halo_stats",
     "nep_train_forward", "nep_train_backward", "nep_train_forward_params", "nep_train_backward_params",
     "nep_adam_update",
@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH):
         "nep_step": [vp, i64, f64, i32, f64, i32, f64, f64, i32, vp, i32, i64, vp],
         "nep_get_state": [vp, vp, vp, vp, i32],
         "nep_set_judge": [vp, i32],
+        "nep_set_deterministic": [vp, i32],
         "nep_set_thermostat": [vp, f64, f64, i32],
         "nep_get_thermostat": [vp, vp, vp, vp],
         "nep_set_thermostat_state": [vp, vp, vp],
@@ -285,6 +286,10 @@ class NEPSystem:
         self._check(self.lib.nep_compute_energy_forces_virial(
             self.handle, slot, _prec(precision), ctypes.byref(E), _np_ptr(W), fp, up, 1 if on_device else 0))
         return E.value, W.reshape(3, 3), F, U
+
+    def set_deterministic(self, on: bool = True):
+        """Fixed-order force accumulation without atomics (bitwise reproducible forces)."""
+        self._check(self.lib.nep_set_deterministic(self.handle, 1 if on else 0))
 
     def step(self, n_steps: int, dt: float = 1.0, rebuild_every: int = 10, skin: float = 1.0,
              mts_k: int = 0, fallback_rms: float = 0.05, fallback_max: float = 1.0, precision="fp32",

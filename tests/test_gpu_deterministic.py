@@ -1,0 +1,138 @@
+"""Deterministic force accumulation (nep_set_deterministic) on the GPU.
+
+In the default mode each center adds its angular reaction forces to its neighbours
+with atomic additions, so the FP32 force sums can differ in their last bits from run
+to run. The deterministic mode gathers those terms per atom in list order instead:
+
+* against the atomic mode: energies, per-atom energies and virial bitwise equal (they
+  never involve atomics), forces within 1e-6 eV/A (FP32 rounding of a reordered sum);
+* against the FP64 oracle at the parity bounds of the default mode;
+* bitwise equal forces on repeated evaluations and across two systems of one state;
+* 10 MD steps against 5 + checkpoint + 5, bitwise equal, when the list rebuilds fall on
+  the checkpoint (rebuild every 5 steps): a resumed run builds its lists at the
+  checkpoint, and lists are ordered by original atom id, so both runs sum every force
+  over the same list in the same order.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_24816_amd import inputs as I
+from tests.gpu_helpers import make_system, say
+
+pytestmark = pytest.mark.gpu
+
+DET_TOL = 1e-6      # eV/A, deterministic against atomic forces
+F_TOL = 1e-4        # eV/A, against the oracle (the parity bound)
+E_ATOM_TOL = 1e-6   # eV per atom
+W_ATOM_TOL = 1e-6   # eV per atom, per virial component
+
+
+@pytest.fixture(scope="module")
+def full():
+    hp = I.FULL_HPARAMS
+    return hp, I.random_model(hp, 0)
+
+
+def _case(name, full):
+    hp, params = full
+    if name == "full":
+        return hp, params, None, None, I.workload_small(), 0, {}
+    if name == "surrogate_short":
+        shp = I.SURROGATE_SHORT_HPARAMS
+        return hp, params, shp, I.surrogate_from_teacher(hp, params, shp, 1), I.fcc_box(6, 0.12, 9), 1, {}
+    if name == "alloy":
+        hp2 = I.HParams(n_types=2)
+        return hp2, I.random_model(hp2, 7), None, None, I.alloy_box(8, 31, 102, 32, 0.05, 33), 0, {}
+    if name == "compressed":
+        at = I.fcc_box(12, 0.05 * 0.85, 5, a=I.CU_LATTICE_A * 0.85)
+        return hp, params, None, None, at, 0, {"cap_radial": 320, "cap_angular": 224}
+    raise ValueError(name)
+
+
+@pytest.mark.parametrize("name", ["full", "surrogate_short", "alloy", "compressed"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_deterministic_against_atomic(full, name, precision):
+    hp, params, shp, sp, at, slot, caps = _case(name, full)
+    say(f"case: {name} (N={at.n}, slot {slot}), {precision}, deterministic against atomic")
+    s = make_system(at, hp, params, shp, sp, **caps)
+    Ea, Wa, Fa, Ua = s.compute(slot=slot, precision=precision, per_atom=True)
+    s.set_deterministic(True)
+    Ed, Wd, Fd, Ud = s.compute(slot=slot, precision=precision, per_atom=True)
+    df = np.abs(Fd - Fa).max()
+    say(f"  max|dF|={df:.2e} |dE|={abs(Ed - Ea):.1e} max|dW|={np.abs(Wd - Wa).max():.1e}")
+    assert Ed == Ea and np.array_equal(Ud, Ua) and np.array_equal(Wd, Wa)
+    assert df < DET_TOL, df
+    s.set_deterministic(False)
+    E2, _, F2, _ = s.compute(slot=slot, precision=precision, per_atom=True)
+    assert E2 == Ea and np.abs(F2 - Fa).max() < DET_TOL
+
+
+@pytest.mark.parametrize("name", ["full", "surrogate_short", "alloy", "compressed"])
+def test_deterministic_against_oracle(full, name):
+    hp, params, shp, sp, at, slot, caps = _case(name, full)
+    mh, mp = (shp, sp) if slot == 1 else (hp, params)
+    m = oracle.Model.from_hparams(mh, mp)
+    say(f"case: {name} (N={at.n}, slot {slot}), fp32 deterministic against the oracle")
+    s = make_system(at, hp, params, shp, sp, **caps)
+    s.set_deterministic(True)
+    E, W, F, U = s.compute(slot=slot, per_atom=True)
+    Eo, Wo, Uo, Fo = oracle.evaluate(m, at.x, at.types, at.box)
+    du, df, dw = np.abs(U - Uo).max(), np.abs(F - Fo).max(), np.abs(W - Wo).max() / at.n
+    say(f"  max|dU|={du:.2e} |dE|/N={abs(E - Eo) / at.n:.2e} max|dF|={df:.2e} max|dW|/N={dw:.2e}")
+    assert du < E_ATOM_TOL and abs(E - Eo) / at.n < E_ATOM_TOL
+    assert df < F_TOL and dw < W_ATOM_TOL
+
+
+def test_deterministic_repeats_bitwise(full):
+    hp, params = full
+    at = I.workload_small()
+    say("case: 4000 atoms, fp32 deterministic, two evaluations and two systems")
+    a = make_system(at, hp, params)
+    a.set_deterministic(True)
+    E1, W1, F1, _ = a.compute()
+    E2, W2, F2, _ = a.compute()
+    b = make_system(at, hp, params)
+    b.set_deterministic(True)
+    E3, W3, F3, _ = b.compute()
+    say(f"  max|dF| repeat={np.abs(F1 - F2).max():.1e} other system={np.abs(F1 - F3).max():.1e}")
+    assert np.array_equal(F1, F2) and np.array_equal(F1, F3)
+    assert E1 == E2 == E3 and np.array_equal(W1, W2) and np.array_equal(W1, W3)
+
+
+@pytest.mark.parametrize("nvt", [False, True])
+def test_deterministic_checkpoint_bitwise(full, nvt):
+    hp, params = full
+    at = I.workload_small()
+    at.v = I.maxwell_boltzmann(at, 600.0, 14)
+    say(f"case: deterministic 10 steps against 5 + checkpoint + 5, {'NVT' if nvt else 'NVE'}, rebuild every 5")
+
+    def system(atoms):
+        s = make_system(atoms, hp, params)
+        s.set_deterministic(True)
+        if nvt:
+            s.set_thermostat(300.0, tau=20.0, chain=3)
+        return s
+
+    a = system(at)
+    a.step(10, rebuild_every=5)
+    xa, va, _ = a.get_state()
+    b = system(at)
+    b.step(5, rebuild_every=5)
+    x5, v5, step5 = b.get_state()
+    assert step5 == 5
+    c = system(I.Atoms(x=x5, types=at.types, box=at.box, masses=at.masses, v=v5))
+    if nvt:
+        eta, ve, _ = b.get_thermostat()
+        c.set_thermostat_state(eta, ve)
+    c.step(5, rebuild_every=5)
+    xc, vc, _ = c.get_state()
+    say(f"  max|dx|={np.abs(xc - xa).max():.1e} max|dv|={np.abs(vc - va).max():.1e}")
+    assert np.array_equal(xc, xa) and np.array_equal(vc, va)
+    Ea, Wa, Fa, _ = a.compute()
+    Ec, Wc, Fc, _ = c.compute()
+    assert Ea == Ec and np.array_equal(Fa, Fc) and np.array_equal(Wa, Wc)
+    if nvt:
+        ea, vea, _ = a.get_thermostat()
+        ec, vec, _ = c.get_thermostat()
+        assert np.array_equal(ea, ec) and np.array_equal(vea, vec)
