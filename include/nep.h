@@ -277,6 +277,22 @@ int nep_train_forward_params(nep_system* s, int32_t slot, const float* params, d
 int nep_train_backward_params(nep_system* s, int32_t slot, const float* params, double gE,
                               const float* gF, float* grad, int32_t accumulate);
 
+/* FP64 form of nep_train_backward_params, for checks: grad = dL/dparams for
+ * L = gE * E + sum_i gF_i . F_i, with E and F those of the NEP_FP64 evaluation of
+ * the slot's own parameters (as given to nep_model_create or
+ * nep_system_set_params) at the current positions and lists, so that central
+ * differences of that evaluation's L check it (Section III.B: the expansion
+ * coefficients c are trainable; the descriptor scaler sigma and the network
+ * weights likewise). Every descriptor, JVP, network and gradient term is FP64;
+ * one thread per center, sums over atoms with FP64 atomics (the last bits
+ * depend on their order). gF: [N][3] device FP64 in original order, or NULL
+ * for no force term. grad: device FP64, n_params values in the packed order
+ * [cR | cA | sigma | W0 | b0 | w1 | b1], overwritten. Uses the sort scratch and
+ * the system's stream; does not synchronise. Returns NEP_ERR_STALE_LIST
+ * without a list and NEP_ERR_UNSUPPORTED for model shapes without a compiled
+ * kernel (those of the FP32 path). */
+int nep_train_backward64(nep_system* s, int32_t slot, double gE, const double* gF, double* grad);
+
 /* One Adam step on device FP32 arrays theta, grad, m1, m2 of length n
  * (t = 1-based step count), on the system's stream. */
 int nep_adam_update(nep_system* s, float* theta, const float* grad, float* m1, float* m2,

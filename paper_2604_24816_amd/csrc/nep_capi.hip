@@ -1197,6 +1197,21 @@ int nep_train_backward_params(nep_system* s, int32_t slot, const float* params, 
   return NEP_OK;
 }
 
+int nep_train_backward64(nep_system* s, int32_t slot, double gE, const double* gF, double* grad) {
+  if (!s || !grad || slot < 0 || slot > 1 || !s->has_model[slot]) return fail(s, NEP_ERR_ARG, "bad argument");
+  if (!s->have_list) return fail(s, NEP_ERR_STALE_LIST, "build the neighbour lists first");
+  if (!eval_supported(s->mdev[slot])) return fail(s, NEP_ERR_UNSUPPORTED, "no compiled kernel for this model shape");
+  // the force weights in sorted order go to the sort scratch (free between list builds)
+  double* w = nullptr;
+  if (gF) {
+    HIPCHK(launch_gather_vec64(s->N, s->perm, gF, s->x_alt, s->st));
+    w = s->x_alt;
+  }
+  HIPCHK(launch_grad64(s->mdev[slot], s->m64[slot], eval_buffers(s, slot), w, gE, grad, s->model[slot].n_params,
+                       s->st));
+  return NEP_OK;
+}
+
 int nep_adam_update(nep_system* s, float* theta, const float* grad, float* m1, float* m2, int64_t n, int64_t t,
                     double lr, double beta1, double beta2, double eps) {
   if (!s || !theta || !grad || !m1 || !m2 || n < 1 || t < 1) return fail(s, NEP_ERR_ARG, "bad argument");

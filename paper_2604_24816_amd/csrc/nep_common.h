@@ -304,6 +304,12 @@ struct Model64 {
 hipError_t launch_eval64(const ModelDev& m, const Model64& p, const EvalBuffers& b, double* U64, double* Fp64,
                          double* F64, hipStream_t st);
 hipError_t launch_scalar_out64(int64_t N, const int32_t* perm, const double* u, double* out, hipStream_t st);
+// FP64 gradient of gE E + sum gF . F with respect to the packed parameters (n_params
+// values, overwritten), gF_sorted [3][N] in sorted order or null.
+hipError_t launch_grad64(const ModelDev& m, const Model64& p, const EvalBuffers& b, const double* gF_sorted,
+                         double gE, double* grad, int64_t n_params, hipStream_t st);
+hipError_t launch_gather_vec64(int64_t N, const int32_t* perm, const double* aos_orig, double* soa_sorted,
+                               hipStream_t st);
 
 // Nose-Hoover chain: at most kMaxChain thermostats; the device state holds
 // {eta[kMaxChain], v_eta[kMaxChain], velocity scale}.

@@ -39,6 +39,7 @@ EXPORTED = [
     "nep_set_judge", "nep_set_deterministic", "nep_set_thermostat", "nep_set_thermostat_state", "nep_get_thermostat", "nep_get_state",
     "nep_get_stats", "nep_halo_stats",
     "nep_train_forward", "nep_train_backward", "nep_train_forward_params", "nep_train_backward_params",
+    "nep_train_backward64",
     "nep_adam_update",
     "nep_surrogate_error", "nep_status_string", "nep_last_error", "nep_profile", "nep_profile_read",
     "nep_pair_counts", "nep_compute_energy_forces_virial_noalloc",
@@ -96,6 +97,7 @@ def load_library(path: str = LIB_PATH):
         "nep_train_backward": [vp, i32, vp, f64, vp, vp, i32],
         "nep_train_forward_params": [vp, i32, vp, vp, vp],
         "nep_train_backward_params": [vp, i32, vp, f64, vp, vp, i32],
+        "nep_train_backward64": [vp, i32, f64, vp, vp],
         "nep_adam_update": [vp, vp, vp, vp, vp, i64, i64, f64, f64, f64, f64],
         "nep_surrogate_error": [vp, i32, vp],
         "nep_profile": [vp, i32],
@@ -384,6 +386,19 @@ class NEPSystem:
                               out: Optional[torch.Tensor] = None):
         """dL/dparams in the packed order, including the expansion coefficients and the scaler."""
         return self._train_backward(self.lib.nep_train_backward_params, slot, params, gE, gF, out, True)
+
+    def train_backward64(self, gE: float, gF=None, slot: int = 0) -> torch.Tensor:
+        """FP64 dL/dparams (packed order) of L = gE E + sum_i gF_i . F_i, with E and F those of
+        the FP64 evaluation of the slot's own parameters; gF [N][3] in original order."""
+        hp = (self.full if slot == 0 else self.surrogate).hp
+        grad = torch.empty(hp.n_params(), dtype=torch.float64, device=self.device)
+        gFc = None
+        if gF is not None:
+            gFc = torch.as_tensor(gF).detach().to(self.device, torch.float64).contiguous()
+            self._shape(gFc, (self.n, 3), "gF")
+        self._check(self.lib.nep_train_backward64(self.handle, slot, float(gE),
+                                                  _t_ptr(gFc) if gFc is not None else None, _t_ptr(grad)))
+        return grad
 
     def _expect(self, slot, theta, all_params):
         hp = (self.full if slot == 0 else self.surrogate).hp

@@ -81,3 +81,69 @@ def test_fp64_forces_are_minus_the_energy_gradient():
         worst = max(worst, abs(fd - F[k, c]))
     say(f"  max |FD - F| = {worst:.2e} eV/A (max|F| {np.abs(F).max():.2e})")
     assert worst < 1e-9
+
+
+def _grad_case(kind):
+    if kind == "surrogate":
+        thp = I.FULL_HPARAMS
+        hp = I.SURROGATE_HPARAMS
+        params = I.surrogate_from_teacher(thp, I.random_model(thp, 0), hp, 3)
+    elif kind == "two_species":
+        hp = I.HParams(n_types=2)
+        params = I.random_model(hp, 8)
+    else:
+        hp = I.FULL_HPARAMS
+        params = I.random_model(hp, 6)
+    at = I.alloy_box(6, 1, 30, 2, 0.17, 3) if kind == "two_species" else I.fcc_box(6, 0.17, 40)
+    return hp, params, at
+
+
+@pytest.mark.parametrize("kind", ["full", "two_species", "surrogate"])
+def test_fp64_parameter_gradient(kind):
+    """The FP64 gradient of L = gE E + sum_i gF_i . F_i with respect to every packed
+    parameter (nep_train_backward64): every entry against the oracle's FP64 gradient
+    (both FP64, summed in different orders: |g - ref| <= 1e-11 |ref| + 1e-13 max|ref|),
+    and against central differences of the GPU's own FP64 evaluation of L on up to six
+    entries of every block, h = 1e-5 max(|p|, 1): |g - FD| <= 1e-8 |g| + 1e-10 max|g|
+    (truncation ~h^2/6 relative; rounding ~1e-16 sqrt(N) |L_i| / h ~ 3e-10 absolute)."""
+    import torch
+    hp, params, at = _grad_case(kind)
+    say(f"case: FP64 parameter gradient, {kind}, N={at.n}")
+    s = make_system(at, hp, params)
+    rng = np.random.default_rng(5)
+    gF = rng.normal(size=(at.n, 3))
+    gE = 0.7
+    m = oracle.Model.from_hparams(hp, params)
+    for with_f in (True, False):
+        g = s.train_backward64(gE, torch.tensor(gF, device="cuda") if with_f else None).cpu().numpy()
+        ref = oracle.param_grad(m, at.x, at.types, at.box, gE, gF if with_f else None)
+        scale = np.abs(ref).max()
+        err = np.abs(g - ref)
+        bound = 1e-11 * np.abs(ref) + 1e-13 * scale
+        k = int(np.argmax(err / bound))
+        say(f"  oracle ({'energy+force' if with_f else 'energy'}): max|grad|={scale:.3e} "
+            f"max|dg|={err.max():.2e}, worst entry {k} at {err[k] / bound[k]:.2f} of its bound")
+        assert (err <= bound).all(), (k, g[k], ref[k])
+    # central differences of the GPU's own FP64 loss
+    g = s.train_backward64(gE, torch.tensor(gF, device="cuda")).cpu().numpy()
+    gscale = np.abs(g).max()
+
+    def loss(p):
+        s.set_params(0, p)
+        E, _, F, _ = s.compute(precision="fp64")
+        return gE * E + float(np.sum(gF * F))
+
+    worst = 0.0
+    for name, (a, b) in hp.offsets().items():
+        picks = rng.choice(np.arange(a, b), size=min(6, b - a), replace=False)
+        for e in picks:
+            h = 1e-5 * max(abs(params[e]), 1.0)
+            pp, pm = params.copy(), params.copy()
+            pp[e] += h
+            pm[e] -= h
+            fd = (loss(pp) - loss(pm)) / (2 * h)
+            r = abs(fd - g[e]) / (1e-8 * abs(g[e]) + 1e-10 * gscale)
+            worst = max(worst, r)
+            assert r <= 1.0, (name, int(e), g[e], fd)
+    s.set_params(0, params)
+    say(f"  central differences: worst entry at {worst:.2f} of its bound (max|grad|={gscale:.3e})")
