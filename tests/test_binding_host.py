@@ -97,3 +97,17 @@ def test_valid_calls_reach_the_library():
     th = s.step(8, mts_k=4, thermo_every=4, relative_judge=True)
     names = [c[0] for c in s.lib.calls]
     assert names[-2:] == ["nep_set_judge", "nep_step"] and th.shape == (0, 8)
+
+
+def test_deterministic_switch_and_fp64_gradient_reach_the_library():
+    s = shell(n=4)
+    s.set_deterministic(True)
+    s.set_deterministic(False)
+    assert [(c[0], c[1][1]) for c in s.lib.calls] == [("nep_set_deterministic", 1), ("nep_set_deterministic", 0)]
+    with pytest.raises(ValueError):
+        s.train_backward64(0.5, np.zeros((3, 3)))
+    assert len(s.lib.calls) == 2
+    g = s.train_backward64(0.5, np.zeros((4, 3)))
+    name, args = s.lib.calls[-1]
+    assert name == "nep_train_backward64" and args[1] == 0 and args[2] == 0.5
+    assert g.dtype == torch.float64 and g.numel() == s.full.hp.n_params()
