@@ -544,9 +544,11 @@ __device__ __forceinline__ void angular_pair_force(const ModelDev& m, const AngC
 
 // DET: the deterministic form. Nothing is scattered: each atom adds, after its own pair
 // terms, the angular forces of the centers that have it as an angular neighbour, each
-// recomputed from that center's dU/ds in list order (the angular sets are symmetric: the
-// same bin and the same exactly negated pair vector decide both), and stores its force.
-// The terms are bitwise those the scattering form adds, in a fixed order.
+// recomputed from that center's dU/ds (atom-major rows) in list order, and stores its
+// force. The sets agree: a pair inside rc_angular lies in both atoms' angular prefixes,
+// and the box-fraction pair vector of (j, i) is the exact negation of that of (i, j), so
+// both sides see the same r^2. The terms are bitwise those the scattering form adds, in
+// a fixed order.
 template <class S, bool MULTI, bool DET>
 __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, EvalBuffers b) {
   __shared__ double red[4 * 10];
