@@ -225,7 +225,9 @@ int nep_set_judge(nep_system* s, int32_t relative);
  * neighbour's dU/ds; the same list, positions and model then give bitwise the
  * same forces, energy and virial on every run. It costs a second pass over the
  * angular lists in the force kernel. Energies are unchanged; forces agree with
- * the default mode to FP32 rounding. Returns NEP_ERR_ARG for other values. */
+ * the default mode to FP32 rounding. Returns NEP_ERR_ARG for other values.
+ * Systems created while the environment variable NEP_DETERMINISTIC is "1" start
+ * in deterministic mode. */
 int nep_set_deterministic(nep_system* s, int32_t deterministic);
 
 /* Positions and velocities [N][3] in original order, and the step counter. */

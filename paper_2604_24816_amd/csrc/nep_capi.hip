@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -642,6 +643,10 @@ int nep_system_create(const nep_model* full, const nep_model* sur, int64_t n_ato
   }
   layout(s, (char*)workspace, n_atoms, cap_radial, cap_angular, s->max_ncell, np, HD);
   s->st = (hipStream_t)hip_stream;
+  {  // NEP_DETERMINISTIC=1 in the environment: deterministic accumulation from the start
+    const char* env = std::getenv("NEP_DETERMINISTIC");
+    s->deterministic = (env && env[0] == '1' && env[1] == '\0') ? 1 : 0;
+  }
   if (hipGetDevice(&s->device) != hipSuccess) {
     delete s;
     return NEP_ERR_HIP;

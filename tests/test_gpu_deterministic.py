@@ -136,3 +136,18 @@ def test_deterministic_checkpoint_bitwise(full, nvt):
         ea, vea, _ = a.get_thermostat()
         ec, vec, _ = c.get_thermostat()
         assert np.array_equal(ea, ec) and np.array_equal(vea, vec)
+
+
+def test_environment_switch(full, monkeypatch):
+    """NEP_DETERMINISTIC=1 at system creation gives the deterministic mode's forces."""
+    hp, params = full
+    at = I.workload_small()
+    say("case: 4000 atoms, NEP_DETERMINISTIC=1 against set_deterministic")
+    a = make_system(at, hp, params)
+    a.set_deterministic(True)
+    _, _, Fa, _ = a.compute()
+    monkeypatch.setenv("NEP_DETERMINISTIC", "1")
+    b = make_system(at, hp, params)
+    monkeypatch.delenv("NEP_DETERMINISTIC")
+    _, _, Fb, _ = b.compute()
+    assert np.array_equal(Fa, Fb)
