@@ -565,7 +565,8 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
 // One workgroup per cell (boxes with at least three cells along every dimension):
 // the positions of the 27 stencil cells' atoms are staged in LDS once, in stencil
 // order and by sorted index inside a cell, and each wavefront takes the cell's atoms
-// in turn, its 64 lanes testing 64 candidates at a time. The accepted candidates are
+// in turn, its 64 lanes testing two chunks of 64 candidates at a time (their staged
+// positions read together, for the latency). The accepted candidates are
 // compacted (ballot and prefix count) into a per-wavefront LDS queue in candidate
 // order; only those are binned and written, 64 entries per pass, to the atom's
 // scratch column. The scratch therefore holds the same entries in the same order as
@@ -573,7 +574,7 @@ k_build_lists(int64_t N, CellGrid g, const double* __restrict__ x, const int32_t
 // whose stencil holds more than kCellCand atoms mark their atoms (cnt = -1) for
 // k_build_lists<false, NE, true>.
 constexpr int kCellCand = 1024;  // stencil atoms a workgroup stages in LDS
-constexpr int kCellQueue = 128;  // accepted candidates queued per wavefront
+constexpr int kCellQueue = 192;  // accepted candidates queued per wavefront (two chunks past a drain)
 
 template <int NE>
 __device__ void build_cell(int64_t N, const CellGrid& g, const double* __restrict__ x,
@@ -692,25 +693,23 @@ __device__ void build_cell(int64_t N, const CellGrid& g, const double* __restric
       nq = 0;
       wave_lds_sync();
     };
-    for (int k0 = 0; k0 < nc; k0 += 64) {
-      const int k = k0 + lane;
-      bool acc = false;
-      double r2 = 0.0;
-      if (k < nc && k != ks) {
-        double dx = X[k] - xi, dy = Y[k] - yi, dz = Z[k] - zi;
-        if (shifted) {
-          const int sidx = C[k];
-          dx = dx + shift[0][sidx];
-          dy = dy + shift[1][sidx];
-          dz = dz + shift[2][sidx];
-        }
-        const double sxx = dx * dx;
-        const double syy = dy * dy;
-        const double szz = dz * dz;
-        const double sxy = sxx + syy;
-        r2 = sxy + szz;
-        acc = r2 < cut2;
+    // the FP64 squared distance to stencil slot k, the expression of the per-atom build
+    auto dist2 = [&](int k) {
+      double dx = X[k] - xi, dy = Y[k] - yi, dz = Z[k] - zi;
+      if (shifted) {
+        const int sidx = C[k];
+        dx = dx + shift[0][sidx];
+        dy = dy + shift[1][sidx];
+        dz = dz + shift[2][sidx];
       }
+      const double sxx = dx * dx;
+      const double syy = dy * dy;
+      const double szz = dz * dz;
+      const double sxy = sxx + syy;
+      return sxy + szz;
+    };
+    // appends the accepted candidates of one 64-candidate chunk, in candidate order
+    auto enqueue = [&](int k, bool acc, double r2) {
       const uint64_t m = __ballot(acc);
       const int pre = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
       if (acc) {
@@ -718,7 +717,23 @@ __device__ void build_cell(int64_t N, const CellGrid& g, const double* __restric
         qr[w][nq + pre] = r2;
       }
       nq += __popcll(m);
-      if (nq > kCellQueue - 64) drain();
+    };
+    // two chunks per pass, their staged positions read together
+    for (int k0 = 0; k0 < nc; k0 += 128) {
+      const int ka = k0 + lane, kb = k0 + 64 + lane;
+      bool acc_a = false, acc_b = false;
+      double ra = 0.0, rb = 0.0;
+      if (ka < nc && ka != ks) {
+        ra = dist2(ka);
+        acc_a = ra < cut2;
+      }
+      if (kb < nc && kb != ks) {
+        rb = dist2(kb);
+        acc_b = rb < cut2;
+      }
+      enqueue(ka, acc_a, ra);
+      enqueue(kb, acc_b, rb);
+      if (nq > kCellQueue - 128) drain();
     }
     drain();
     if (lane == 0) {
