@@ -134,7 +134,7 @@ struct nep_system {
   HaloTables ht;
   ListScratch lsc;
   float *F[2], *U, *G;
-  uint4* rec;
+  uint4 *pos, *rec;
   float *gF, *vjp, *qs;
   double *partial, *gpart, *res, *staging;
   int32_t* flags;
@@ -200,6 +200,7 @@ int64_t layout(nep_system* s, char* base, int64_t N, int capR, int capA, int max
   S.F[0] = c.take<float>(3 * N);
   S.F[1] = c.take<float>(3 * N);
   S.U = c.take<float>(N);
+  S.pos = c.take<uint4>(N);
   S.rec = c.take<uint4>(4 * N);
   S.G = c.take<float>(5 * 24 * N);
   S.gF = c.take<float>(3 * N);
@@ -338,6 +339,7 @@ EvalBuffers eval_buffers(nep_system* s, int slot) {
   b.hstart = s->ht.start;
   b.hoff = s->ht.off;
   b.U = s->U;
+  b.pos = s->pos;
   b.rec = s->rec;
   b.G = s->G;
   b.F = s->F[slot];
@@ -443,7 +445,7 @@ int rebuild(nep_system* s, double skin, int force) {
   const ListOut lists{s->nbr, s->cnt, s->bp, s->nbrl, s->selfl};
   HIPCHK(launch_rebuild(s->N, s->grid, s->be, s->capR, s->capA, s->x, s->v, s->type, s->perm, s->x_alt,
                         s->v_alt, s->type_alt, s->perm_alt, s->x_build, s->cellid, s->cell_sorted, s->src,
-                        s->key, s->cell_count, s->cell_start, s->cell_fill, s->scan_tmp, s->rec, lists, s->ht, s->lsc,
+                        s->key, s->cell_count, s->cell_start, s->cell_fill, s->scan_tmp, s->pos, lists, s->ht, s->lsc,
                         s->flags, s->st));
   (void)force;
   return NEP_OK;
@@ -717,7 +719,7 @@ int nep_set_state(nep_system* s, const double* x, const double* v, const int32_t
     HIPCHK(hipMemcpyAsync(s->type_alt, types, N * sizeof(int32_t), hipMemcpyHostToDevice, s->st));
     td = s->type_alt;
   }
-  HIPCHK(launch_state_in(N, xd, vd, td, s->n_types, g, s->x, s->v, s->type, s->perm, s->rec, s->flags, s->st));
+  HIPCHK(launch_state_in(N, xd, vd, td, s->n_types, g, s->x, s->v, s->type, s->perm, s->pos, s->flags, s->st));
   int32_t f[FLAG_COUNT];
   int st = read_flags(s, f);
   if (st) return st;
@@ -853,7 +855,7 @@ int vv_step(nep_system* s, int slot, int prec, double dt, int rebuild_every, dou
   hipEvent_t* ev = prof_take(s, 4);
   if (ev) HIPCHK(hipEventRecord(ev[0], s->st));
   HIPCHK(launch_set_flag(s->flags, FLAG_REBUILD, scheduled, s->st));
-  HIPCHK(launch_kick_drift(s->N, dt, s->grid, s->F[slot], s->type, s->mt, s->x, s->v, s->rec, s->x_build,
+  HIPCHK(launch_kick_drift(s->N, dt, s->grid, s->F[slot], s->type, s->mt, s->x, s->v, s->pos, s->x_build,
                            0.25 * skin * skin, s->flags, s->partial, s->st));
   HIPCHK(launch_select_bin(s->partial, kick_drift_blocks(s->N), s->flags, skin, s->be, s->st));
   if (ev) HIPCHK(hipEventRecord(ev[1], s->st));
@@ -1322,7 +1324,7 @@ int nep_compute_energy_forces_virial_noalloc(const nep_model* model, int64_t n_a
   const CellGrid g = make_grid(s.box, model->hp.rc_radial);
   HIPCHK2(launch_zero_i32(s.flags, FLAG_COUNT, s.st));
   HIPCHK2(launch_zero_i32(s.nbr, (int64_t)(cap_radial + kListPad) * n_atoms, s.st));
-  HIPCHK2(launch_state_in(n_atoms, x, nullptr, types, s.n_types, g, s.x, s.v, s.type, s.perm, s.rec, s.flags, s.st));
+  HIPCHK2(launch_state_in(n_atoms, x, nullptr, types, s.n_types, g, s.x, s.v, s.type, s.perm, s.pos, s.flags, s.st));
   int32_t f[FLAG_COUNT];
   if ((st = read_flags(&s, f))) return st;
   if (f[FLAG_TYPE]) return NEP_ERR_TYPE;

@@ -107,13 +107,17 @@ struct HaloTables {
   int32_t* off;    // [ntiles][kHaloCellsMax + 1] local offset of each halo cell
 };
 
-// Per-atom neighbour record: 64 bytes ([N][4] 16-byte words) holding what a neighbour's
-// pair terms read, so a gather touches as few 16-byte words as possible.
-// word 0 = (qx, qy, qz, v): the position as three 32-bit fractions of the box,
-//   q = round(x 2^32 / L) modulo 2^32, so that the two's-complement difference of two
-//   atoms' fractions is their minimum-image separation in units of L / 2^32 (the
-//   quantum: 1.7e-7 A in a 723 A box); and one radial force coefficient;
-// words 1, 2 = eight more radial force coefficients; word 3 is not read.
+// Neighbour positions and records, laid out so that every writer stores whole cache
+// lines and every gather touches as few 16-byte words as possible:
+// pos [N] (16 bytes per atom) = (qx, qy, qz, 0): the position as three 32-bit fractions
+//   of the box, q = round(x 2^32 / L) modulo 2^32, so that the two's-complement
+//   difference of two atoms' fractions is their minimum-image separation in units of
+//   L / 2^32 (the quantum: 1.7e-7 A in a 723 A box). Written by the integrator (and the
+//   state upload and list build), gathered by the descriptor pass.
+// rec [N][4] (64 bytes per atom), written whole by the descriptor kernel for its own atom
+//   and gathered by the force pass: word 0 = (qx, qy, qz, v), the position again and one
+//   radial force coefficient; words 1, 2 = eight more radial force coefficients; word 3
+//   is zero.
 // The FP64 positions stay in the [3][N] position array (integration, list build, ZBL).
 // The coefficients are written by the descriptor kernel: for one species
 // v = w_0 + sum_k w_k and w_1..w_8 (w_k = sum_n (dU/dq_n) c_nk), with several species
@@ -123,11 +127,9 @@ __device__ __forceinline__ uint32_t box_fraction(double x, double L) {
   const double f = rint(x * (4294967296.0 / L));  // in [0, 2^32] for x in [0, L)
   return (uint32_t)(uint64_t)f;                   // 2^32, the image of 0, wraps to 0
 }
-__device__ __forceinline__ void rec_put_pos(uint4* rec, int64_t i, double x, double y, double z,
-                                            const double* box) {
-  uint32_t* w = reinterpret_cast<uint32_t*>(rec + 4 * i);
-  reinterpret_cast<uint2*>(w)[0] = make_uint2(box_fraction(x, box[0]), box_fraction(y, box[1]));
-  w[2] = box_fraction(z, box[2]);
+// Atom i's entry of the position array.
+__device__ __forceinline__ void pos_put(uint4* pos, int64_t i, double x, double y, double z, const double* box) {
+  pos[i] = make_uint4(box_fraction(x, box[0]), box_fraction(y, box[1]), box_fraction(z, box[2]), 0u);
 }
 
 // Outputs of the list build.
@@ -223,7 +225,7 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, const BinEdges& be, int 
                           double* v_alt, int32_t* type_alt, int32_t* perm_alt, double* x_build,
                           int32_t* cellid, int32_t* cell_sorted, int32_t* src, int32_t* key,
                           int32_t* cell_count, int32_t* cell_start, int32_t* cell_fill,
-                          int32_t* scan_tmp, uint4* rec, const ListOut& lists, HaloTables ht,
+                          int32_t* scan_tmp, uint4* pos, const ListOut& lists, HaloTables ht,
                           ListScratch sc, int32_t* flags, hipStream_t st);
 // Rows of original ids [o_lo, o_hi), ascending, into rows[(o - o_lo) * cap + k].
 hipError_t launch_export(int64_t N, const int32_t* perm, const int32_t* nbr, const int32_t* cnt,
@@ -246,7 +248,8 @@ struct EvalBuffers {
   const int32_t* hstart;
   const int32_t* hoff;
   float* U;              // [N]
-  uint4* rec;            // [N][4] neighbour records (positions read, w written)
+  uint4* pos;            // [N] box-fraction positions (read)
+  uint4* rec;            // [N][4] neighbour records (written by the descriptor kernel)
   float* G;              // [nA * ncomp][N] dU/ds for the angular accumulators
   float* F;              // [3][N] forces (FP32 accumulation)
   double* partial;       // [nblocks][kPartialStride]
@@ -276,7 +279,7 @@ hipError_t launch_reduce_partials(const double* partial, int nblocks, int first,
 hipError_t launch_max_partials(const double* partial, int nblocks, int slot, double* out,
                                hipStream_t st);
 hipError_t launch_kick_drift(int64_t N, double dt, CellGrid g, const float* F, const int32_t* type,
-                             MassTable mt, double* x, double* v, uint4* rec, const double* x_build,
+                             MassTable mt, double* x, double* v, uint4* pos, const double* x_build,
                              double half_skin2, int32_t* flags, double* partial, hipStream_t st);
 // FLAG_BIN_R / FLAG_BIN_A from the per-workgroup displacement maxima the drift
 // kernel left in partial.
@@ -326,7 +329,7 @@ hipError_t launch_set_flag(int32_t* flags, int idx, int value, hipStream_t st);
 hipError_t launch_sum_i32(int64_t N, const int32_t* a, double* partial, int slot, hipStream_t st);
 hipError_t launch_state_in(int64_t N, const double* x_aos, const double* v_aos,
                            const int32_t* type_in, int n_types, CellGrid g, double* x, double* v,
-                           int32_t* type, int32_t* perm, uint4* rec, int32_t* flags, hipStream_t st);
+                           int32_t* type, int32_t* perm, uint4* pos, int32_t* flags, hipStream_t st);
 hipError_t launch_state_out(int64_t N, const int32_t* perm, const double* soa, double* aos,
                             hipStream_t st);
 hipError_t launch_forces_out(int64_t N, const int32_t* perm, const float* F, double* aos,

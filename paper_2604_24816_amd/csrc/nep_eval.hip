@@ -259,9 +259,9 @@ __device__ __forceinline__ void desc_pass(const ModelDev& m, const EvalBuffers& 
   };
   // the angular candidates are the list's prefix [0, kA)
   if constexpr (MULTI)
-    for_each_rec_span<1, S::DESC_AHEAD>(b.nbr, b.rec, N, i, 0, kR, pair_both);
+    for_each_rec_span<1, S::DESC_AHEAD, 1>(b.nbr, b.pos, N, i, 0, kR, pair_both);
   else
-    for_each_rec_fast<1, S::DESC_AHEAD>(b.nbr, b.rec, N, i, 0, kR, pair_both);
+    for_each_rec_fast<1, S::DESC_AHEAD, 1>(b.nbr, b.pos, N, i, 0, kR, pair_both);
   if constexpr (!MULTI) {
     const cfloat_ptr c = uniform_coeffs(m.cR);
     float Qb[KR];
@@ -319,7 +319,7 @@ __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers 
   EvalZbl zs;  // pairs inside the ZBL radius
 
   if (valid) {
-    const uint4 w0 = b.rec[4 * i];
+    const uint4 w0 = b.pos[i];
     int nr = 0, na = 0;
     desc_pass<S, MULTI>(m, b, i, ti, QPos{w0.x, w0.y, w0.z}, q, s, zs, nr, na);
     b.nactR[i] = nr;
@@ -357,10 +357,13 @@ __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers 
         }
         t[0] += sum;
       }
+      // the whole 64-byte record: position, the nine coefficients, a zero word
+      const uint4 own = b.pos[i];
       uint4* r = b.rec + 4 * i;
-      reinterpret_cast<float*>(r)[3] = t[0];
+      r[0] = make_uint4(own.x, own.y, own.z, __float_as_uint(t[0]));
       reinterpret_cast<float4*>(r + 1)[0] = make_float4(t[1], t[2], t[3], t[4]);
       reinterpret_cast<float4*>(r + 2)[0] = make_float4(t[5], t[6], t[7], t[8]);
+      r[3] = make_uint4(0u, 0u, 0u, 0u);
     }
     // 4. dU/ds_nlm = dU/dq_nl * 2 W_lm s_nlm (+ four-body part for l = 2)
     float Gd[NA * NC];
@@ -670,9 +673,9 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
         for (int c = 0; c < 3; ++c) w[a * 3 + c] = fmaf(d[a], nf[c], w[a * 3 + c]);
     };
     if constexpr (MULTI)
-      for_each_rec_span<3, 1>(b.nbr, b.rec, N, i, 0, kR, pair_both);
+      for_each_rec_span<3, 1, 4>(b.nbr, b.rec, N, i, 0, kR, pair_both);
     else
-      for_each_rec_fast<3, 1>(b.nbr, b.rec, N, i, 0, kR, pair_both);
+      for_each_rec_fast<3, 1, 4>(b.nbr, b.rec, N, i, 0, kR, pair_both);
     if (zs.n) {
       float f[3] = {fx, fy, fz};
       zbl_center<MULTI>(m, b, i, ti, b.x[i], b.x[N + i], b.x[2 * N + i], zs, nullptr, f, w);
@@ -686,7 +689,7 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
       for (int p = 0; p < kA; ++p) {
         const int32_t j = b.nbr[(uint64_t)(uint32_t)p * n64 + i];
         float dx, dy, dz;
-        const float r2 = pair_vec_q(b.rec[4 * (int64_t)j], qi, hx, hy, hz, dx, dy, dz);
+        const float r2 = pair_vec_q(b.pos[j], qi, hx, hy, hz, dx, dy, dz);
         if (!(r2 < rcR2 && r2 < rcA2)) continue;
         float r, rinv;
         r_of_r2(r2, r, rinv);

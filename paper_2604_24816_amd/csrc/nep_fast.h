@@ -202,7 +202,8 @@ __device__ __forceinline__ void r_of_r2(float r2, float& r, float& rinv) {
 
 // ---------------------------------------------------------------- neighbour loops
 // Both visit entries [k0, k1) of atom i's slot-major list, calling body(p, j, w) with the
-// first W 16-byte words of neighbour j's record. The records of entries p + 1 .. p + AHEAD
+// first W 16-byte words of neighbour j's entry in rec (RS words per atom: the position
+// array with RS = 1, the 64-byte records with RS = 4). The records of entries p + 1 .. p + AHEAD
 // and the index of entry p + AHEAD + 1 are in flight while the body of entry p runs, so
 // their latency overlaps the pair arithmetic; bodies with little arithmetic per pair need
 // the deeper queue. The loads run past k1 - 1 by up to AHEAD + 1 rows, into entries that
@@ -214,14 +215,14 @@ __device__ __forceinline__ void r_of_r2(float r2, float& r, float& rinv) {
 // unrolled AHEAD + 1 times so that each record is loaded straight into the buffer the
 // body later reads (a rotation by index, not by copies), at the cost of a few more live
 // registers.
-template <int W, int AHEAD, class Body>
+template <int W, int AHEAD, int RS, class Body>
 __device__ __forceinline__ void for_each_rec_span(const int32_t* __restrict__ nbr, const uint4* __restrict__ rec,
                                                   int64_t N, int64_t i, int k0, int k1, Body&& body) {
   static_assert(AHEAD >= 1 && AHEAD + 1 <= kListPad, "prefetch depth within the list's padding");
   if (k1 <= k0) return;
   const uint64_t n64 = (uint64_t)N;
   const int32_t* __restrict__ col = nbr + i + (uint64_t)(uint32_t)k0 * n64;  // entry k0
-  auto record = [&](int32_t j, int w) { return rec[((uint64_t)(uint32_t)j << 2) + w]; };
+  auto record = [&](int32_t j, int w) { return rec[(uint64_t)(uint32_t)j * RS + w]; };
   int32_t jq[AHEAD + 1];  // indices of entries p .. p + AHEAD
 #pragma unroll
   for (int a = 0; a <= AHEAD; ++a) {
@@ -252,7 +253,7 @@ __device__ __forceinline__ void for_each_rec_span(const int32_t* __restrict__ nb
   }
 }
 
-template <int W, int AHEAD, class Body>
+template <int W, int AHEAD, int RS, class Body>
 __device__ __forceinline__ void for_each_rec_fast(const int32_t* __restrict__ nbr, const uint4* __restrict__ rec,
                                                   int64_t N, int64_t i, int k0, int k1, Body&& body) {
   static_assert(AHEAD >= 1 && AHEAD <= 3 && AHEAD + 1 <= kListPad, "prefetch depth within the list's padding");
@@ -260,7 +261,7 @@ __device__ __forceinline__ void for_each_rec_fast(const int32_t* __restrict__ nb
   if (k1 <= k0) return;
   const uint64_t n64 = (uint64_t)N;
   const int32_t* __restrict__ col = nbr + i + (uint64_t)(uint32_t)k0 * n64;  // entry k0
-  auto record = [&](int32_t j, int w) { return rec[((uint64_t)(uint32_t)j << 2) + w]; };
+  auto record = [&](int32_t j, int w) { return rec[(uint64_t)(uint32_t)j * RS + w]; };
   int32_t jq[AHEAD + 1];  // indices of entries p .. p + AHEAD
 #pragma unroll
   for (int a = 0; a <= AHEAD; ++a) {

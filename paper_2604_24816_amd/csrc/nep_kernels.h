@@ -229,48 +229,6 @@ __device__ __forceinline__ bool inside(double xj, double yj, double zj, double x
   return true;
 }
 
-// Visits entries [0, k) of atom i's slot-major list, calling body(p, j, w) with the
-// first W 16-byte words of neighbour j's record. The records of entries p + 1 .. p + AHEAD
-// and the index of entry p + AHEAD + 1 are in flight while the body of entry p runs, so
-// their latency overlaps the pair arithmetic; a body with little arithmetic per pair
-// needs the deeper queue (the last loads repeat entry k - 1: every address stays inside
-// the list and the records).
-template <int W, int AHEAD = 1, class Body>
-__device__ __forceinline__ void for_each_rec(const int32_t* __restrict__ nbr, const uint4* __restrict__ rec,
-                                             int64_t N, int64_t i, int k, Body&& body) {
-  static_assert(AHEAD >= 1 && AHEAD <= 3, "prefetch depth");
-  if (k <= 0) return;
-  // slots, indices and N fit in 32 bits (N < 2^28): 32 x 32 -> 64-bit offsets
-  const int32_t* __restrict__ col = nbr + i;
-  const uint32_t n32 = (uint32_t)N;
-  auto slot = [&](int s) { return col[(uint64_t)(uint32_t)s * n32]; };
-  auto record = [&](int32_t j, int w) { return rec[((uint64_t)(uint32_t)j << 2) + w]; };
-  int32_t jq[AHEAD + 1];  // indices of entries p .. p + AHEAD
-#pragma unroll
-  for (int a = 0; a <= AHEAD; ++a) jq[a] = slot(a < k ? a : k - 1);
-  uint4 rq[AHEAD][W];  // records of entries p .. p + AHEAD - 1
-#pragma unroll
-  for (int a = 0; a < AHEAD; ++a)
-#pragma unroll
-    for (int w = 0; w < W; ++w) rq[a][w] = record(jq[a], w);
-  for (int p = 0; p < k; ++p) {
-    const int32_t jn = slot(p + AHEAD + 1 < k ? p + AHEAD + 1 : k - 1);
-    uint4 rn[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) rn[w] = record(jq[AHEAD], w);
-    body(p, jq[0], rq[0]);
-#pragma unroll
-    for (int a = 0; a < AHEAD; ++a) jq[a] = jq[a + 1];
-    jq[AHEAD] = jn;
-#pragma unroll
-    for (int a = 0; a + 1 < AHEAD; ++a)
-#pragma unroll
-      for (int w = 0; w < W; ++w) rq[a][w] = rq[a + 1][w];
-#pragma unroll
-    for (int w = 0; w < W; ++w) rq[AHEAD - 1][w] = rn[w];
-  }
-}
-
 // Pair test for one entry of a list with skin: FP64 minimum-image vector, kept when
 // r^2 < cut2 (the true cutoff); the vector is rounded to FP32 after the subtraction.
 __device__ __forceinline__ bool pair_inside(const double* __restrict__ x, int64_t N, int32_t j, double xi,

@@ -38,7 +38,7 @@ constexpr int kIntegrateGrid = 8192;
 
 __global__ void k_kick_drift(int64_t N, double dt, CellGrid g, const float* __restrict__ F,
                              const int32_t* __restrict__ type, MassTable mt, double* __restrict__ x,
-                             double* __restrict__ v, uint4* __restrict__ rec, const double* __restrict__ xb,
+                             double* __restrict__ v, uint4* __restrict__ pos, const double* __restrict__ xb,
                              double half_skin2,
                              int32_t* __restrict__ flags, double* __restrict__ partial) {
   __shared__ double sh[kBlock / 64];
@@ -57,7 +57,7 @@ __global__ void k_kick_drift(int64_t N, double dt, CellGrid g, const float* __re
       const double d = min_image(xx - xb[c * N + p], g.box[c]);
       d2 += d * d;
     }
-    rec_put_pos(rec, p, xn[0], xn[1], xn[2], g.box);
+    pos_put(pos, p, xn[0], xn[1], xn[2], g.box);
     if (!(d2 <= half_skin2)) moved = true;  // also catches NaN
     if (!(d2 == d2)) d2 = 1e300;
     d2max = fmax(d2max, d2);
@@ -246,7 +246,7 @@ __global__ void k_set_flag(int32_t* flags, int idx, int value) {
 __global__ void k_state_in(int64_t N, const double* __restrict__ xa, const double* __restrict__ va,
                            const int32_t* __restrict__ tin, int n_types, CellGrid g, double* __restrict__ x,
                            double* __restrict__ v, int32_t* __restrict__ type, int32_t* __restrict__ perm,
-                           uint4* __restrict__ rec, int32_t* __restrict__ flags) {
+                           uint4* __restrict__ pos, int32_t* __restrict__ flags) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= N) return;
   double xn[3];
@@ -263,7 +263,7 @@ __global__ void k_state_in(int64_t N, const double* __restrict__ xa, const doubl
     if (!isfinite(vv)) flags[FLAG_NONFINITE] = 1;
     v[c * N + p] = vv;
   }
-  rec_put_pos(rec, p, xn[0], xn[1], xn[2], g.box);
+  pos_put(pos, p, xn[0], xn[1], xn[2], g.box);
   const int t = tin[p];
   if (t < 0 || t >= n_types) flags[FLAG_TYPE] = 1;
   type[p] = (t < 0 || t >= n_types) ? 0 : t;
@@ -328,10 +328,10 @@ int kick_drift_blocks(int64_t N) {
 }
 
 hipError_t launch_kick_drift(int64_t N, double dt, CellGrid g, const float* F, const int32_t* type,
-                             MassTable mt, double* x, double* v, uint4* rec, const double* x_build,
+                             MassTable mt, double* x, double* v, uint4* pos, const double* x_build,
                              double half_skin2, int32_t* flags, double* partial, hipStream_t st) {
   hipLaunchKernelGGL(k_kick_drift, dim3(kick_drift_blocks(N)), dim3(kBlock), 0, st, N, dt, g, F, type, mt, x, v,
-                     rec, x_build, half_skin2, flags, partial);
+                     pos, x_build, half_skin2, flags, partial);
   return hipGetLastError();
 }
 
@@ -384,9 +384,9 @@ hipError_t launch_set_flag(int32_t* flags, int idx, int value, hipStream_t st) {
 
 hipError_t launch_state_in(int64_t N, const double* x_aos, const double* v_aos, const int32_t* type_in,
                            int n_types, CellGrid g, double* x, double* v, int32_t* type, int32_t* perm,
-                           uint4* rec, int32_t* flags, hipStream_t st) {
+                           uint4* pos, int32_t* flags, hipStream_t st) {
   hipLaunchKernelGGL(k_state_in, dim3(grid_blocks(N)), dim3(kBlock), 0, st, N, x_aos, v_aos, type_in,
-                     n_types, g, x, v, type, perm, rec, flags);
+                     n_types, g, x, v, type, perm, pos, flags);
   return hipGetLastError();
 }
 

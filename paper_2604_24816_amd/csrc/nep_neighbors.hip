@@ -218,7 +218,7 @@ __global__ void k_permute(int64_t N, const int32_t* __restrict__ src, const int3
 __global__ void k_copy_back(int64_t N, const double* __restrict__ x2, const double* __restrict__ v2,
                             const int32_t* __restrict__ type2, const int32_t* __restrict__ perm2,
                             double* __restrict__ x, double* __restrict__ v, int32_t* __restrict__ type,
-                            int32_t* __restrict__ perm, uint4* __restrict__ rec, CellGrid g,
+                            int32_t* __restrict__ perm, uint4* __restrict__ pos, CellGrid g,
                             const int32_t* __restrict__ flags) {
   if (flags[FLAG_REBUILD] == 0) return;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (int64_t)gridDim.x * blockDim.x) {
@@ -228,7 +228,7 @@ __global__ void k_copy_back(int64_t N, const double* __restrict__ x2, const doub
       x[c * N + p] = xn[c];
       v[c * N + p] = v2[c * N + p];
     }
-    rec_put_pos(rec, p, xn[0], xn[1], xn[2], g.box);
+    pos_put(pos, p, xn[0], xn[1], xn[2], g.box);
     type[p] = type2[p];
     perm[p] = perm2[p];
   }
@@ -963,7 +963,7 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, const BinEdges& be, int 
                           double* v_alt, int32_t* type_alt, int32_t* perm_alt, double* x_build,
                           int32_t* cellid, int32_t* cell_sorted, int32_t* src, int32_t* key,
                           int32_t* cell_count, int32_t* cell_start, int32_t* cell_fill,
-                          int32_t* scan_tmp, uint4* rec, const ListOut& lout, HaloTables ht,
+                          int32_t* scan_tmp, uint4* pos, const ListOut& lout, HaloTables ht,
                           ListScratch sc, int32_t* flags, hipStream_t st) {
   const int nb = grid_blocks(N);
   const int ncell = g.ncell;
@@ -985,7 +985,7 @@ hipError_t launch_rebuild(int64_t N, const CellGrid& g, const BinEdges& be, int 
   hipLaunchKernelGGL(k_permute, dim3(rebuild_grid(nb)), dim3(kBlock), 0, st, N, src, cellid, x, v, type, perm,
                      x_alt, v_alt, type_alt, perm_alt, x_build, cell_sorted, flags);
   hipLaunchKernelGGL(k_copy_back, dim3(rebuild_grid(nb)), dim3(kBlock), 0, st, N, x_alt, v_alt, type_alt, perm_alt,
-                     x, v, type, perm, rec, g, flags);
+                     x, v, type, perm, pos, g, flags);
   hipLaunchKernelGGL(k_halo_tables, dim3(rebuild_grid(nb)), dim3(kBlock), 0, st, N, g, cell_sorted, cell_start, ht, flags);
   // the minimum-image rule inside the candidate loop only for boxes with fewer than
   // three cells along some dimension
