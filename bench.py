@@ -405,13 +405,13 @@ def network_mfma(hp, n, desc_ms, precision):
 
 def integrator_hbm(n, integrate, steps):
     """HBM bandwidth of the velocity-Verlet kernels: k_kick_drift reads type, v, F, x and
-    the build positions and writes v, x and the record's position (88 + 72 B per atom);
-    k_kick reads type, F, v and writes v (40 + 24 B)."""
+    the build positions and writes v, x and the 16-byte box-fraction position (88 + 64 B
+    per atom); k_kick reads type, F, v and writes v (40 + 24 B)."""
     total_ms, launches = integrate
     per_step_s = total_ms * 1e-3 / steps
-    nbytes = 224.0 * n
+    nbytes = 216.0 * n
     achieved = nbytes / per_step_s / 1e9
-    return {"kernels": "k_kick_drift + k_kick", "bytes_per_atom_step": 224, "achieved": achieved,
+    return {"kernels": "k_kick_drift + k_kick", "bytes_per_atom_step": 216, "achieved": achieved,
             "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
             "timed_segments": launches}
 
