@@ -779,10 +779,16 @@ k_place_lists(int64_t N, int nbins, int binA, int capR, int capA, ListOut lo_, L
   // groups of kPlaceAtoms atoms, strided over a capped grid: a step without a rebuild
   // then dispatches few workgroups
   const int64_t ngroups = (N + kPlaceAtoms - 1) / kPlaceAtoms;
+  // the list length of the lane's atom in the next group is loaded one group ahead
+  int cnt_next = (int64_t)blockIdx.x * kPlaceAtoms + a < N ? lo_.cnt[(int64_t)blockIdx.x * kPlaceAtoms + a] : 0;
   for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
     const int64_t p = grp * kPlaceAtoms + a;
     const bool valid = p < N;
-    const int cnt = valid ? lo_.cnt[p] : 0;
+    const int cnt = valid ? cnt_next : 0;
+    {
+      const int64_t pn = (grp + gridDim.x) * kPlaceAtoms + a;
+      cnt_next = grp + gridDim.x < ngroups && pn < N ? lo_.cnt[pn] : 0;
+    }
     const int g_lo = h * kPartLen;
     const int g_hi = h == kPlaceParts - 1 ? cnt : (g_lo + kPartLen < cnt ? g_lo + kPartLen : cnt);
     const bool work = valid && g_lo < cnt;
@@ -806,6 +812,12 @@ k_place_lists(int64_t N, int nbins, int binA, int capR, int capA, ListOut lo_, L
         v[4 * j + 3] = w.w;
       }
     };
+    // the halo indices of a chunk, 16-bit, as two 16-byte words
+    auto load_l = [&](int g, uint4* lw) {
+      const uint4* ls = sc.l + ((int64_t)(g / kStage) * N + p) * (kStage / 8);
+  #pragma unroll
+      for (int j = 0; j < kStage / 8; ++j) lw[j] = ls[j];
+    };
     BinCounts mine;
     auto count_chunk = [&](int g, const uint32_t* v) {
   #pragma unroll
@@ -813,10 +825,15 @@ k_place_lists(int64_t N, int nbins, int binA, int capR, int capA, ListOut lo_, L
         if (g + u < g_hi) mine.add((int)(v[u] >> 28));
     };
     uint32_t c0[kStage], c1[kStage];
+    uint4 l0[kStage / 8], l1[kStage / 8];  // their halo indices, loaded with them
     const bool two = work && g_lo + kStage < g_hi;
     if (work) {
       load_q(g_lo, c0);
-      if (two) load_q(g_lo + kStage, c1);
+      load_l(g_lo, l0);
+      if (two) {
+        load_q(g_lo + kStage, c1);
+        load_l(g_lo + kStage, l1);
+      }
       count_chunk(g_lo, c0);
       if (two) count_chunk(g_lo + kStage, c1);
       for (int g = g_lo + 2 * kStage; g < g_hi; g += kStage) {
@@ -854,12 +871,11 @@ k_place_lists(int64_t N, int nbins, int binA, int capR, int capA, ListOut lo_, L
       if (work) {
   #pragma unroll
         for (int k = 0; k < kMaxBins; ++k) off[k * 64 + lane] = (uint16_t)(bstart[k] + before.get(k));
-        auto place_chunk = [&](int g, const uint32_t* v) {
+        auto place_chunk = [&](int g, const uint32_t* v, const uint4* lw) {
           uint32_t hl[kStage];
-          const uint4* ls = sc.l + ((int64_t)(g / kStage) * N + p) * (kStage / 8);
   #pragma unroll
           for (int j = 0; j < kStage / 8; ++j) {
-            const uint4 w = ls[j];
+            const uint4 w = lw[j];
             const uint32_t t[4] = {w.x, w.y, w.z, w.w};
   #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -882,12 +898,14 @@ k_place_lists(int64_t N, int nbins, int binA, int capR, int capA, ListOut lo_, L
             ltile[slot] = (uint16_t)hl[u];
           }
         };
-        place_chunk(g_lo, c0);
-        if (two) place_chunk(g_lo + kStage, c1);
+        place_chunk(g_lo, c0, l0);
+        if (two) place_chunk(g_lo + kStage, c1, l1);
         for (int g = g_lo + 2 * kStage; g < g_hi; g += kStage) {
           uint32_t t[kStage];
+          uint4 lt[kStage / 8];
           load_q(g, t);
-          place_chunk(g, t);
+          load_l(g, lt);
+          place_chunk(g, t, lt);
         }
       }
       __syncthreads();
