@@ -11,8 +11,9 @@
 //        dU/dq~ = W0^T (w1 (1 - tanh^2)) as two 64-row MFMA products per
 //        wavefront (Section V.B Optimization 1, Fig. 2c), operands staged
 //        through LDS; FP32 MFMA or bfloat16 MFMA with FP32 accumulation;
-//     3. per-atom dU/ds_nlm is written for the force kernel, and the radial force
-//        coefficients into the atom's neighbour record.
+//     3. per-atom dU/ds_nlm is written for the force kernel, and the atom's whole
+//        neighbour record (its position and radial force coefficients).
+//     Neighbour positions are gathered from the 16-byte position array.
 //   k_force
 //     radial pair forces by gather (F_i += sum_j [dU_i/dr_ij - dU_j/dr_ji]
 //     with the neighbour's radial coefficients read from its record), angular and

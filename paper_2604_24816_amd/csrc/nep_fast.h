@@ -179,8 +179,8 @@ __device__ __forceinline__ float tanh_fast(float z) {
 }
 
 // ---------------------------------------------------------------- pair vectors
-// Pair vector x_j - x_i of a list neighbour from the records' 32-bit box fractions (see
-// the neighbour record): the two's-complement difference is the minimum image in units of
+// Pair vector x_j - x_i of a list neighbour from the 32-bit box fractions (of the position
+// array or the records): the two's-complement difference is the minimum image in units of
 // the quantum; it is converted to FP64 exactly, scaled by the quantum (h = L / 2^32) and
 // rounded once to FP32. Returns r^2 in FP32.
 struct QPos {

@@ -191,8 +191,8 @@ struct Shape {
   static constexpr bool FB = FB_;
   static constexpr int NC = L3 * (L3 + 2);
   static constexpr int D = NR + NA * L3 + (FB ? NA : 0);
-  // neighbour records in flight ahead of the pair the descriptor pass works on: with
-  // l <= 2 that pass does too little arithmetic per pair to hide one record's latency
+  // neighbour positions in flight ahead of the pair the descriptor pass works on: with
+  // l <= 2 that pass does too little arithmetic per pair to hide one gather's latency
   // (the force passes gather 64-byte records and stay at one ahead: a deeper queue there
   // loses more to memory contention than it hides)
   static constexpr int DESC_AHEAD = L3 <= 2 ? 2 : 1;
