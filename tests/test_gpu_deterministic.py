@@ -11,7 +11,10 @@ to run. The deterministic mode gathers those terms per atom in list order instea
 * 10 MD steps against 5 + checkpoint + 5, bitwise equal, when the list rebuilds fall on
   the checkpoint (rebuild every 5 steps): a resumed run builds its lists at the
   checkpoint, and lists are ordered by original atom id, so both runs sum every force
-  over the same list in the same order.
+  over the same list in the same order;
+* two r-RESPA runs of one state bitwise equal.
+The cases: the full model, the 5/4 A surrogate, a two-species alloy, a compressed box
+whose tiles take the global-atomic path, and a compressed two-species box with ZBL.
 """
 import numpy as np
 import pytest
@@ -26,6 +29,13 @@ DET_TOL = 1e-6      # eV/A, deterministic against atomic forces
 F_TOL = 1e-4        # eV/A, against the oracle (the parity bound)
 E_ATOM_TOL = 1e-6   # eV per atom
 W_ATOM_TOL = 1e-6   # eV per atom, per virial component
+# relative terms (of the largest |U_i|, |F| or W component) for the compressed ZBL alloy,
+# where one FP32 rounding of an atom's ZBL energy (~30 eV) or force (~90 eV/A) is already
+# above the absolute bars: reordered sums of pair terms several times larger than the net
+# force differ by a few roundings of those terms (16 roundings of the largest force
+# allowed; measured 5), and the oracle bars take the ZBL tests' eight roundings
+DET_REL = 1e-6
+REL = 5e-7
 
 
 @pytest.fixture(scope="module")
@@ -47,10 +57,15 @@ def _case(name, full):
     if name == "compressed":
         at = I.fcc_box(12, 0.05 * 0.85, 5, a=I.CU_LATTICE_A * 0.85)
         return hp, params, None, None, at, 0, {"cap_radial": 320, "cap_angular": 224}
+    if name == "alloy_zbl":
+        hpz = I.HParams(n_types=2, zbl_outer=2.0, zbl_z=(29.0, 79.0))
+        a = I.alloy_box(6, 1, 30, 2, 0.12, 3)
+        at = I.Atoms(x=a.x * 0.82, types=a.types, box=a.box * 0.82, masses=a.masses)
+        return hpz, I.random_model(hpz, 8), None, None, at, 0, {"cap_radial": 320, "cap_angular": 200}
     raise ValueError(name)
 
 
-@pytest.mark.parametrize("name", ["full", "surrogate_short", "alloy", "compressed"])
+@pytest.mark.parametrize("name", ["full", "surrogate_short", "alloy", "compressed", "alloy_zbl"])
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 def test_deterministic_against_atomic(full, name, precision):
     hp, params, shp, sp, at, slot, caps = _case(name, full)
@@ -60,15 +75,16 @@ def test_deterministic_against_atomic(full, name, precision):
     s.set_deterministic(True)
     Ed, Wd, Fd, Ud = s.compute(slot=slot, precision=precision, per_atom=True)
     df = np.abs(Fd - Fa).max()
-    say(f"  max|dF|={df:.2e} |dE|={abs(Ed - Ea):.1e} max|dW|={np.abs(Wd - Wa).max():.1e}")
+    tol = DET_TOL + DET_REL * np.abs(Fa).max()
+    say(f"  max|dF|={df:.2e} (bar {tol:.1e}) |dE|={abs(Ed - Ea):.1e} max|dW|={np.abs(Wd - Wa).max():.1e}")
     assert Ed == Ea and np.array_equal(Ud, Ua) and np.array_equal(Wd, Wa)
-    assert df < DET_TOL, df
+    assert df < tol, df
     s.set_deterministic(False)
     E2, _, F2, _ = s.compute(slot=slot, precision=precision, per_atom=True)
-    assert E2 == Ea and np.abs(F2 - Fa).max() < DET_TOL
+    assert E2 == Ea and np.abs(F2 - Fa).max() < tol
 
 
-@pytest.mark.parametrize("name", ["full", "surrogate_short", "alloy", "compressed"])
+@pytest.mark.parametrize("name", ["full", "surrogate_short", "alloy", "compressed", "alloy_zbl"])
 def test_deterministic_against_oracle(full, name):
     hp, params, shp, sp, at, slot, caps = _case(name, full)
     mh, mp = (shp, sp) if slot == 1 else (hp, params)
@@ -79,9 +95,13 @@ def test_deterministic_against_oracle(full, name):
     E, W, F, U = s.compute(slot=slot, per_atom=True)
     Eo, Wo, Uo, Fo = oracle.evaluate(m, at.x, at.types, at.box)
     du, df, dw = np.abs(U - Uo).max(), np.abs(F - Fo).max(), np.abs(W - Wo).max() / at.n
+    rel = REL if name == "alloy_zbl" else 0.0
+    e_tol = E_ATOM_TOL + rel * np.abs(Uo).max()
+    f_tol = F_TOL + rel * np.abs(Fo).max()
+    w_tol = W_ATOM_TOL + rel * np.abs(Wo).max() / at.n
     say(f"  max|dU|={du:.2e} |dE|/N={abs(E - Eo) / at.n:.2e} max|dF|={df:.2e} max|dW|/N={dw:.2e}")
-    assert du < E_ATOM_TOL and abs(E - Eo) / at.n < E_ATOM_TOL
-    assert df < F_TOL and dw < W_ATOM_TOL
+    assert du < e_tol and abs(E - Eo) / at.n < e_tol
+    assert df < f_tol and dw < w_tol
 
 
 def test_deterministic_repeats_bitwise(full):
@@ -151,3 +171,21 @@ def test_environment_switch(full, monkeypatch):
     monkeypatch.delenv("NEP_DETERMINISTIC")
     _, _, Fb, _ = b.compute()
     assert np.array_equal(Fa, Fb)
+
+
+def test_deterministic_mts_repeats_bitwise(full):
+    """Two r-RESPA runs (k = 4, the 4/3 A surrogate, fallback off) of one state in the
+    deterministic mode end in bitwise the same positions and velocities."""
+    hp, params = full
+    shp = I.SURROGATE_SHORTER_HPARAMS
+    sp = I.surrogate_from_teacher(hp, params, shp, 1)
+    at = I.workload_small()
+    at.v = I.maxwell_boltzmann(at, 600.0, 14)
+    say("case: deterministic MTS, 4000 atoms, 12 steps twice")
+    out = []
+    for _ in range(2):
+        s = make_system(at, hp, params, shp, sp)
+        s.set_deterministic(True)
+        s.step(12, mts_k=4, fallback_rms=1e9, fallback_max=1e9)
+        out.append(s.get_state()[:2])
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
