@@ -308,7 +308,6 @@ __global__ void __launch_bounds__(kBlock, 2) k_desc_net(ModelDev m, EvalBuffers 
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int64_t i = (int64_t)tile * kBlock + threadIdx.x;
   const bool valid = i < N;
-  const double Lx = b.box[0], Ly = b.box[1], Lz = b.box[2];
 
   float q[D];
 #pragma unroll
@@ -584,7 +583,7 @@ __global__ void __launch_bounds__(kBlock, force_waves<S>()) k_force(ModelDev m, 
     const float wi[9] = {__uint_as_float(r0.w),  __uint_as_float(r1.x),  __uint_as_float(r1.y),
                          __uint_as_float(r1.z),  __uint_as_float(r1.w),  __uint_as_float(r2w.x),
                          __uint_as_float(r2w.y), __uint_as_float(r2w.z), __uint_as_float(r2w.w)};
-    constexpr int KR = S::KR, KA = S::KA;
+    constexpr int KR = S::KR;
     float G[NA * NC];
     if constexpr (DET) {
       load_g_row<S>(b.G + i * g_row<S>(), G);
