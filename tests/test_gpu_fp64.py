@@ -91,6 +91,12 @@ def _grad_case(kind):
     elif kind == "two_species":
         hp = I.HParams(n_types=2)
         params = I.random_model(hp, 8)
+    elif kind == "two_species_zbl":
+        # ZBL energies and forces enter L but do not depend on the parameters
+        hp = I.HParams(n_types=2, zbl_outer=2.0, zbl_z=(29.0, 79.0))
+        params = I.random_model(hp, 8)
+        a = I.alloy_box(6, 1, 30, 2, 0.12, 3)
+        return hp, params, I.Atoms(x=a.x * 0.82, types=a.types, box=a.box * 0.82, masses=a.masses)
     else:
         hp = I.FULL_HPARAMS
         params = I.random_model(hp, 6)
@@ -98,18 +104,22 @@ def _grad_case(kind):
     return hp, params, at
 
 
-@pytest.mark.parametrize("kind", ["full", "two_species", "surrogate"])
+@pytest.mark.parametrize("kind", ["full", "two_species", "surrogate", "two_species_zbl"])
 def test_fp64_parameter_gradient(kind):
     """The FP64 gradient of L = gE E + sum_i gF_i . F_i with respect to every packed
     parameter (nep_train_backward64): every entry against the oracle's FP64 gradient
     (both FP64, summed in different orders: |g - ref| <= 1e-11 |ref| + 1e-13 max|ref|),
     and against central differences of the GPU's own FP64 evaluation of L on up to six
     entries of every block, h = 1e-5 max(|p|, 1): |g - FD| <= 1e-8 |g| + 1e-10 max|g|
-    (truncation ~h^2/6 relative; rounding ~1e-16 sqrt(N) |L_i| / h ~ 3e-10 absolute)."""
+    (truncation ~h^2/6 relative; rounding ~1e-16 sqrt(N) |L_i| / h ~ 3e-10 absolute). The
+    compressed ZBL box, whose L carries per-atom ZBL energies of ~30 eV and forces of
+    ~90 eV/A that do not depend on the parameters, takes h = 1e-4 max(|p|, 1) against
+    the tenfold rounding noise (truncation still ~2e-9 relative)."""
     import torch
     hp, params, at = _grad_case(kind)
     say(f"case: FP64 parameter gradient, {kind}, N={at.n}")
-    s = make_system(at, hp, params)
+    caps = {"cap_radial": 320, "cap_angular": 200} if kind == "two_species_zbl" else {}
+    s = make_system(at, hp, params, **caps)
     rng = np.random.default_rng(5)
     gF = rng.normal(size=(at.n, 3))
     gE = 0.7
@@ -137,7 +147,7 @@ def test_fp64_parameter_gradient(kind):
     for name, (a, b) in hp.offsets().items():
         picks = rng.choice(np.arange(a, b), size=min(6, b - a), replace=False)
         for e in picks:
-            h = 1e-5 * max(abs(params[e]), 1.0)
+            h = (1e-4 if kind == "two_species_zbl" else 1e-5) * max(abs(params[e]), 1.0)
             pp, pm = params.copy(), params.copy()
             pp[e] += h
             pm[e] -= h

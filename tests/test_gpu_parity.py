@@ -271,6 +271,12 @@ def test_error_paths(full):
     with pytest.raises(nep.NEPError) as e:
         s.compute()
     assert e.value.status == -8  # stale list
+    with pytest.raises(nep.NEPError) as e:
+        s.train_backward64(1.0)
+    assert e.value.status == -8
+    with pytest.raises(nep.NEPError) as e:
+        s._check(s.lib.nep_set_deterministic(s.handle, 2))
+    assert e.value.status == -1
     s2 = make_system(at, hp, params, cap_radial=8, build=False)
     with pytest.raises(nep.NEPError) as e:
         s2.build_neighbors(1.0)
